@@ -1,0 +1,145 @@
+"""CPU oracle for the RaDiO radiation deposit -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the package's smoke check and the benchmark's CPU-baseline
+leg may import this package.  The GPU library never calls it and shares no
+code with it.  The arithmetic lives in radio_oracle.c (plain IEEE double,
+no FMA contraction, no fast-math); this module builds it with gcc and
+marshals numpy arrays into it.
+
+Functions and the passages they follow:
+  kinematics(u)            Alg. 1: beta = p / sqrt(|p|^2 + 1), 1/gamma^2
+  arrival(x_cell, x, t, c) Eq. 2: t_det = t + |x_part - x_cell| / c
+  field(...)               Eq. 1: Lienard-Wiechert E and B = n x E
+  deposit(...)             Alg. 1 + Alg. 2 with the integrator-detector
+                           definition of Sec. 3.2 (slot value = integral of
+                           the piecewise-constant field over the slot / dt_det)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "radio_oracle.c")
+_LIB = os.path.join(_HERE, "libradio_oracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile radio_oracle.c with gcc into libradio_oracle.so."""
+    global _lib
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared", "-fPIC",
+           "-fvisibility=hidden", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    _lib = None
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i64 = ctypes.c_int64
+        lib.radio_oracle_kinematics.argtypes = [dp, dp, dp]
+        lib.radio_oracle_kinematics.restype = None
+        lib.radio_oracle_arrival.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double]
+        lib.radio_oracle_arrival.restype = ctypes.c_double
+        lib.radio_oracle_field.argtypes = [dp, dp, dp, ctypes.c_double, dp, ctypes.c_double,
+                                           ctypes.c_double, dp, dp]
+        lib.radio_oracle_field.restype = None
+        lib.radio_oracle_deposit.argtypes = [dp, i64, ctypes.c_double, ctypes.c_double, i64,
+                                             ctypes.c_double, i64, i64, ctypes.c_double,
+                                             ctypes.c_double, dp, dp, dp, dp,
+                                             ctypes.POINTER(i64), ctypes.c_int]
+        lib.radio_oracle_deposit.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _dptr(a: Optional[np.ndarray]):
+    if a is None:
+        return ctypes.POINTER(ctypes.c_double)()
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def kinematics(u) -> Tuple[np.ndarray, float]:
+    u = _f64(u)
+    beta = np.empty(3)
+    g2 = ctypes.c_double()
+    _load().radio_oracle_kinematics(_dptr(u), _dptr(beta), ctypes.byref(g2))
+    return beta, g2.value
+
+
+def arrival(x_cell, x_part, t: float, c: float = 1.0) -> float:
+    return _load().radio_oracle_arrival(_dptr(_f64(x_cell)), _dptr(_f64(x_part)), float(t),
+                                        float(c))
+
+
+def field(x_cell, x_part, beta, inv_gamma2: float, betadot, q: float = -1.0,
+          c: float = 1.0) -> Tuple[np.ndarray, np.ndarray]:
+    E = np.empty(3)
+    B = np.empty(3)
+    _load().radio_oracle_field(_dptr(_f64(x_cell)), _dptr(_f64(x_part)), _dptr(_f64(beta)),
+                               float(inv_gamma2), _dptr(_f64(betadot)), float(q), float(c),
+                               _dptr(E), _dptr(B))
+    return E, B
+
+
+def deposit(cells, t0: float, dt_det: float, n_t: int, x, u, q, t_first: float, dt: float,
+            c: float = 1.0, D: Optional[np.ndarray] = None, n_threads: Optional[int] = None,
+            counters: Optional[np.ndarray] = None) -> np.ndarray:
+    """Accumulate one chunk into D[n_cells, n_t, 6] (created zeroed if None)."""
+    cells = _f64(cells).reshape(-1, 3)
+    x = _f64(x)
+    u = _f64(u)
+    n_c = cells.shape[0]
+    if x.ndim != 3 or x.shape[0] != 3 or u.shape != x.shape:
+        raise ValueError("x and u must both have shape (3, S+1, Np)")
+    n_states, n_p = x.shape[1], x.shape[2]
+    qa = None if q is None else _f64(q)
+    if qa is not None and qa.shape != (n_p,):
+        raise ValueError("q must have shape (Np,)")
+    if D is None:
+        D = np.zeros((n_c, n_t, 6))
+    if D.dtype != np.float64 or not D.flags.c_contiguous or D.shape != (n_c, n_t, 6):
+        raise ValueError("D must be a C-contiguous float64 array of shape (n_cells, n_t, 6)")
+    if counters is None:
+        counters = np.zeros(2, dtype=np.int64)
+    if n_threads is None:
+        n_threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rc = _load().radio_oracle_deposit(
+        _dptr(cells), n_c, float(t0), float(dt_det), int(n_t), float(c), n_p, n_states - 1,
+        float(t_first), float(dt), _dptr(x), _dptr(u), _dptr(qa), _dptr(D),
+        counters.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(n_threads))
+    if rc != 0:
+        raise ValueError(f"oracle deposit rejected its arguments (rc={rc})")
+    return D
+
+
+def deposit_workload(detector, chunk, cell_index=None, D=None, n_threads=None, counters=None):
+    """Convenience: deposit a workloads.Chunk on (a subset of) a DetectorSpec's cells."""
+    cells = detector.cells if cell_index is None else detector.cells[np.asarray(cell_index)]
+    return deposit(cells, detector.t0, detector.dt_det, detector.n_t, chunk.x, chunk.u, chunk.q,
+                   chunk.t_first, chunk.dt, c=detector.c, D=D, n_threads=n_threads,
+                   counters=counters)
+
+
+def read(D: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """Split an oracle detector array into E[n_cells, n_t, 3] and B[n_cells, n_t, 3]."""
+    return np.ascontiguousarray(D[..., :3]), np.ascontiguousarray(D[..., 3:])
