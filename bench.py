@@ -1,0 +1,164 @@
+"""Throughput of the radiation deposit on one MI355X.
+
+A step is one pass of the whole hot path over the planar-undulator ensemble
+(10^4 electrons, gamma ~ N(50, 0.5), K = 1, 20 periods in 4096 steps; a
+128 x 128 spherical-cap detector at 1e5 with 2048 time slots): zero the
+detector, deposit every (particle, segment, cell) triple, read E and B back.
+Inputs are resident in HBM before the timed region.  Prints one JSON line.
+
+The timed path is the mixed-precision deposit (`value`); the double-precision
+deposit is timed in the same run and reported under "fp64".  The CPU oracle
+is timed on a bounded sample of cells on the host cores (cpu_baseline).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# algorithmic work of one (particle segment, cell) interaction, counting an FMA as
+# two flops and a sqrt or divide as one: arrival time 16, n - beta and kappa 9,
+# cross products 18, 1/kappa^3 and the two coefficients 7, E 9, B 9, one slot 16
+FLOPS_PER_INTERACTION = 84
+PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}  # MI355X vector FP64 / FP32 (published)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the double-precision leg")
+    ap.add_argument("--cpu-cells", type=int, default=0,
+                    help="cells in the oracle sample (default: two per host thread)")
+    return ap.parse_args()
+
+
+def time_precision(radio, wl, chunk_dev, precision, steps, warmup):
+    import torch
+    det = radio.Detector.from_spec(wl.detector, precision=precision)
+    E = torch.empty((det.n_cells, det.n_t, 3), dtype=torch.float64, device="cuda")
+    B = torch.empty_like(E)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        det.reset(stream)
+        if ev is not None:
+            ev[0].record(stream)
+        det.deposit(chunk_dev, stream)
+        if ev is not None:
+            ev[1].record(stream)
+        det.read(E, B, stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = sum(a.elapsed_time(b) for a, b in evs) / steps
+    det.close()
+    del E, B
+    return wall / steps * 1e3, kernel_ms
+
+
+def cpu_baseline(wl, n_cells):
+    import numpy as np
+
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = max(1, min(threads, os.cpu_count() or 1))
+    if n_cells <= 0:
+        n_cells = 2 * threads
+    n_c = wl.detector.n_cells
+    idx = np.linspace(0, n_c - 1, n_cells).round().astype(np.int64)
+    t0 = time.perf_counter()
+    oracle.deposit_workload(wl.detector, wl.chunk, cell_index=idx, n_threads=threads)
+    el = time.perf_counter() - t0
+    inter = wl.chunk.n_particles * wl.chunk.n_steps * len(idx)
+    return {"value": inter / el, "unit": "interactions/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(idx)} evenly spaced cells x all {wl.chunk.n_particles} particles x "
+                      f"all {wl.chunk.n_steps} segments ({inter:.3e} interactions, {el:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the deposit is measured on a single MI355X "
+              "(see the sharding paragraph of the design notes); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2302_14812_amd as radio
+    from paper_2302_14812_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t_gen = time.perf_counter()
+    wl = W.undulator_workload()
+    gen_s = time.perf_counter() - t_gen
+    print(f"[bench] generated {wl.name} in {gen_s:.1f} s ({wl.interactions:.3e} interactions "
+          "per step)", file=sys.stderr, flush=True)
+    chunk_dev = radio.Chunk.from_numpy(wl.chunk)
+    torch.cuda.synchronize()
+    inter = wl.interactions
+
+    legs = {}
+    order = [args.precision] + ([] if args.no_fp64 or args.precision == "fp64" else ["fp64"])
+    for prec in order:
+        ms, kms = time_precision(radio, wl, chunk_dev, prec, args.steps, args.warmup)
+        flops = inter * FLOPS_PER_INTERACTION
+        legs[prec] = {
+            "value": inter / (ms * 1e-3), "ms_per_step": ms, "deposit_kernel_ms": kms,
+            "roofline": {"bound": "alu", "achieved": flops / (kms * 1e-3) / 1e12,
+                         "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                         "frac": flops / (kms * 1e-3) / 1e12 / PEAK_TFLOPS[prec],
+                         "traffic": None},
+        }
+        print(f"[bench] {prec}: {ms:.1f} ms/step, deposit kernel {kms:.1f} ms, "
+              f"{legs[prec]['value']:.3e} interactions/s", file=sys.stderr, flush=True)
+
+    main_leg = legs[args.precision]
+    out = {
+        "metric": "LW interactions/s (particle-step x cell)",
+        "value": main_leg["value"],
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_leg["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n_particles": wl.chunk.n_particles,
+                   "n_steps": wl.chunk.n_steps, "n_cells": wl.detector.n_cells,
+                   "n_t": wl.detector.n_t, "precision": args.precision,
+                   "interactions_per_step": inter},
+        "roofline": main_leg["roofline"],
+    }
+    if "fp64" in legs and args.precision != "fp64":
+        out["fp64"] = legs["fp64"]
+        out["mixed_vs_fp64_speedup"] = legs["fp64"]["ms_per_step"] / main_leg["ms_per_step"]
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(wl, args.cpu_cells)
+        out["cpu_baseline"] = cb
+        print(f"[bench] cpu oracle: {cb['value']:.3e} interactions/s on {cb['cores']} threads",
+              file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

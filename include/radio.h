@@ -1,0 +1,183 @@
+/*
+ * radio.h -- C interface of the MI355X radiation-deposit library (libradio.so).
+ *
+ * The library computes the spatiotemporal radiation of charged-particle
+ * trajectories the way RaDiO does (Pardal et al., "RaDiO: an efficient
+ * spatiotemporal radiation diagnostic for particle-in-cell codes"):
+ * for every (particle, trajectory segment, detector cell) triple it
+ * evaluates the Lienard-Wiechert fields E and B = n x E (Eq. 1) with the
+ * segment's current state, maps the segment's two end states to detector
+ * arrival times t_det = t + |x_cell - x_part|/c (Eq. 2, Alg. 1), and
+ * deposits the field, held constant between those two arrival times, into
+ * the detector's uniform time slots with the integrator-detector weights of
+ * Sec. 3.2 / Alg. 2: slot j = [t0 + j dt_det, t0 + (j+1) dt_det) receives
+ * the integral of the held field over the slot divided by dt_det.  Parts of
+ * a segment outside the time array are dropped.
+ *
+ * Units follow the paper's normalised Gaussian units: c is a parameter
+ * (1 in normalised units), charges are signed multiples of e, momenta are
+ * u = p/(m c) = gamma beta, and fields come out in charge/length^2.
+ *
+ * Every call returns RADIO_OK (0) or a negative status; no call aborts or
+ * throws across this interface.  On an argument error nothing is modified.
+ * Work is enqueued asynchronously on the caller's HIP stream (`stream` is a
+ * hipStream_t; NULL selects the null stream); the caller keeps device inputs
+ * alive until the stream has passed the call.  All device pointers must
+ * point to memory of the device that was current when the detector was
+ * created.  Calls on one detector must be ordered by the caller (one stream,
+ * or events between streams).
+ */
+#ifndef RADIO_H
+#define RADIO_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define RADIO_API __attribute__((visibility("default")))
+#else
+#define RADIO_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define RADIO_OK 0
+#define RADIO_EINVAL (-1)  /* invalid argument */
+#define RADIO_ENOMEM (-2)  /* device or host allocation failed */
+#define RADIO_EDEVICE (-3) /* a HIP call or kernel launch failed */
+#define RADIO_ESTATE (-4)  /* object in the wrong state (e.g. wrong device) */
+
+/* arithmetic of the deposit */
+#define RADIO_FP64 0  /* every step in IEEE double */
+#define RADIO_MIXED 1 /* arrival time, bin index, n - beta and kappa in double; the
+                         field, weights and slot accumulation in single, merged into
+                         a double accumulator */
+
+/* detector cell geometry (Sec. 3.1: spherical grids centred at the origin and
+   cartesian planes) */
+#define RADIO_GEOM_EXPLICIT 0 /* cells[n_cells][3] given by the caller */
+#define RADIO_GEOM_PLANE 1    /* n1 x n2 cell centres origin + a1 e1 + a2 e2,
+                                 a_i = -half_i + (i + 1/2) 2 half_i / n_i */
+#define RADIO_GEOM_SPHERE 2   /* n1 x n2 cells on a sphere of `radius` about the origin:
+                                 longitude (about axis x e1) and latitude measured from
+                                 `axis`, spanning +-half1 and +-half2 radians, cell centres
+                                 at bin middles: radius*(cos(lat)(cos(lon) axis +
+                                 sin(lon) e1') + sin(lat) e2'), e1' = e1 made orthogonal
+                                 to axis and normalised, e2' = axis x e1' */
+
+typedef struct radio_detector radio_detector; /* opaque, owned by the library */
+
+typedef struct radio_detector_desc {
+    int32_t geometry;     /* RADIO_GEOM_* */
+    int32_t precision;    /* RADIO_FP64 or RADIO_MIXED */
+    int64_t n_cells;      /* EXPLICIT only: number of cells */
+    const double* cells;  /* EXPLICIT only: HOST pointer to [n_cells][3] positions; copied */
+    double origin[3];     /* PLANE: grid centre */
+    double axis[3];       /* SPHERE: direction of the grid centre (need not be unit) */
+    double e1[3];         /* PLANE: first grid axis; SPHERE: longitude direction */
+    double e2[3];         /* PLANE: second grid axis */
+    double radius;        /* SPHERE: radius */
+    int64_t n1, n2;       /* PLANE/SPHERE: cells along e1 and e2; cell index = i2*n1 + i1 */
+    double half1, half2;  /* PLANE: half spans; SPHERE: half apertures in radians */
+    double t0;            /* start of the detector time array */
+    double dt_det;        /* slot width, > 0 */
+    int64_t n_t;          /* number of slots, >= 1 */
+    double c;             /* speed of light, > 0 (1 in normalised units) */
+} radio_detector_desc;
+
+/*
+ * A chunk of trajectory: n_steps + 1 states of n_particles particles, state s
+ * at time t_first + s*dt.  Segment s (1..n_steps) joins states s-1 and s and
+ * carries the field of state s (beta_s, betadot_s = (beta_s - beta_{s-1})/dt),
+ * as Alg. 1 passes the current step's E(n, beta, betadot) to the deposit.
+ * Streaming: consecutive chunks share one state (state 0 of a chunk is the
+ * last state of the previous one), which makes deposits stateless, additive
+ * and order independent.
+ */
+typedef struct radio_chunk {
+    int64_t n_particles;  /* >= 0 (0 deposits nothing) */
+    int64_t n_steps;      /* segments, >= 0 (0 deposits nothing) */
+    double t_first;       /* time of state 0 */
+    double dt;            /* time between states, > 0 */
+    const double* x;      /* DEVICE [3][n_steps+1][n_particles] positions (SoA) */
+    const double* u;      /* DEVICE [3][n_steps+1][n_particles] momenta p/(m c) */
+    const double* q;      /* DEVICE [n_particles] signed charges, or NULL for all -1 */
+} radio_chunk;
+
+typedef struct radio_stats {
+    int64_t interactions; /* (particle segment, cell) pairs deposited so far */
+    int64_t clipped;      /* of those, pairs with some part outside the time array */
+    int64_t nonmonotone;  /* of those, pairs whose arrival time decreases (|dx| > c dt) */
+    int64_t chunks;       /* deposit calls accepted */
+    int64_t bytes;        /* device bytes held by the detector */
+} radio_stats;
+
+/*
+ * Create a detector on the current device: copies the cell positions, allocates
+ * and zeroes the slot accumulator (n_cells * n_t * 6 doubles) with work
+ * enqueued on `stream`.  *out receives the handle.  RADIO_EINVAL for a bad
+ * description, RADIO_ENOMEM if the accumulator does not fit.
+ */
+RADIO_API int radio_detector_create(const radio_detector_desc* desc, void* stream, radio_detector** out);
+
+/* Wait for the device, then free everything the detector holds.  NULL is a no-op. */
+RADIO_API int radio_detector_destroy(radio_detector* det);
+
+/* Zero the accumulated fields and statistics (enqueued on `stream`). */
+RADIO_API int radio_detector_reset(radio_detector* det, void* stream);
+
+/*
+ * Deposit one chunk (Alg. 1 over every particle, cell and segment; Alg. 2 for
+ * each).  Validates the chunk on the host; RADIO_EINVAL (nothing enqueued) for
+ * NULL pointers with a nonempty chunk, dt <= 0, non-finite times or negative
+ * sizes.  Input values are not inspected: NaN positions or momenta give NaN or
+ * dropped deposits, never out-of-bounds writes.
+ */
+RADIO_API int radio_deposit_trajectory_chunk(radio_detector* det, const radio_chunk* chunk, void* stream);
+
+/*
+ * Deposit n independent (detector, chunk) pairs in one persistent launch.
+ * The result equals n separate radio_deposit_trajectory_chunk calls (up to
+ * the order of floating-point additions).  All detectors must live on the
+ * current device; a detector may appear more than once.  On any invalid pair
+ * nothing is enqueued.
+ */
+RADIO_API int radio_deposit_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
+                        void* stream);
+
+/*
+ * Write the detector fields: E and B as DEVICE arrays [n_cells][n_t][3]
+ * (double), slot values as defined above.  Either pointer may be NULL to skip
+ * it.  Does not modify the detector.
+ */
+RADIO_API int radio_read_detector(const radio_detector* det, double* E, double* B, void* stream);
+
+/* Statistics; synchronises the device to read the counters. */
+RADIO_API int radio_detector_stats(const radio_detector* det, radio_stats* out);
+
+/* Shape of a detector: cells, slots, precision (any pointer may be NULL). */
+RADIO_API int radio_detector_shape(const radio_detector* det, int64_t* n_cells, int64_t* n_t,
+                         int32_t* precision);
+
+/* Copy the detector's cell positions to HOST memory out[n_cells][3]. */
+RADIO_API int radio_detector_cells(const radio_detector* det, double* out);
+
+/*
+ * Arrival times t + |x_cell - x|/c (Eq. 2) of n explicit (cell, point, time)
+ * triples, evaluated on the device with exactly the rounding the deposit uses:
+ * t_s = t_first + s*dt is the caller's job; here t is given.  DEVICE arrays:
+ * cells[n][3], points[n][3], t[n], out[n].
+ */
+RADIO_API int radio_arrival_times(const double* cells, const double* points, const double* t, int64_t n,
+                        double c, double* out, void* stream);
+
+/* Human-readable text for a status code (static storage). */
+RADIO_API const char* radio_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RADIO_H */

@@ -38,6 +38,9 @@
  *   |v|^2 = (v0*v0 + v1*v1) + v2*v2 ;  g = |u|^2 + 1 ;  beta_k = u_k / sqrt(g)
  *   t_s  = t_first + (double)s * dt ;  R = sqrt(|x_c - x_s|^2)
  *   tau  = t_s + R * (1/c)          ;  n_k = d_k * (1/R)
+ *   slot coordinate (tau - t0) * (1/dt_det): the time in units of slots, whose
+ *   integer part is the slot of Alg. 2 (a segment much shorter than a slot
+ *   changes length by ulp(coordinate)/length if rounded differently)
  *   kappa = (|n - beta|^2 + 1/g) / 2, which equals 1 - n.beta exactly for a
  *   unit n (|n - beta|^2 = 1 - 2 n.beta + |beta|^2 and 1 - |beta|^2 = 1/g)
  *   but has no cancellation as beta -> 1.
@@ -153,6 +156,7 @@ EXPORT int radio_oracle_deposit(const double* cells, int64_t n_cells, double t0,
     if (!cells || !x || !u || !D || !(dt > 0.0))
         return -1;
     const int64_t n_states = n_steps + 1;
+    const double inv_dt_det = 1.0 / dt_det;
     int64_t clipped = 0, nonmono = 0;
     if (n_threads < 1)
         n_threads = 1;
@@ -180,8 +184,8 @@ EXPORT int radio_oracle_deposit(const double* cells, int64_t n_cells, double t0,
                 double tau = radio_oracle_arrival(xc, x_cur, t_cur, c);
                 double F[6];
                 radio_oracle_field(xc, x_cur, beta, g2, betadot, qp, c, F, F + 3);
-                double a = (tau_prev - t0) / dt_det;
-                double b = (tau - t0) / dt_det;
+                double a = (tau_prev - t0) * inv_dt_det;
+                double b = (tau - t0) * inv_dt_det;
                 double lo = a < b ? a : b;
                 double hi = a < b ? b : a;
                 if (b < a)

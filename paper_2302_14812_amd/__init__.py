@@ -1,0 +1,305 @@
+"""Python binding of libradio, the MI355X radiation-deposit library.
+
+Argument marshalling only: every step of the deposit runs in the library's
+HIP kernels.  PyTorch provides device memory (tensors) and HIP streams;
+this module checks tensor shapes and types, passes raw device pointers and
+the current stream through the C interface declared in include/radio.h, and
+turns status codes into exceptions.  It fails loudly when the library has
+not been built -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libradio.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4
+FP64, MIXED = 0, 1
+GEOM_EXPLICIT, GEOM_PLANE, GEOM_SPHERE = 0, 1, 2
+_PRECISIONS = {"fp64": FP64, "mixed": MIXED}
+
+# every function the C header declares
+EXPORTS = (
+    "radio_detector_create", "radio_detector_destroy", "radio_detector_reset",
+    "radio_deposit_trajectory_chunk", "radio_deposit_batch", "radio_read_detector",
+    "radio_detector_stats", "radio_detector_shape", "radio_detector_cells",
+    "radio_arrival_times", "radio_status_string",
+)
+
+
+class RadioError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        text = _lib().radio_status_string(status).decode() if _LIB is not None else str(status)
+        super().__init__(f"{what}: {text} ({status})")
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [
+        ("geometry", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("n_cells", ctypes.c_int64), ("cells", ctypes.POINTER(ctypes.c_double)),
+        ("origin", ctypes.c_double * 3), ("axis", ctypes.c_double * 3),
+        ("e1", ctypes.c_double * 3), ("e2", ctypes.c_double * 3),
+        ("radius", ctypes.c_double), ("n1", ctypes.c_int64), ("n2", ctypes.c_int64),
+        ("half1", ctypes.c_double), ("half2", ctypes.c_double),
+        ("t0", ctypes.c_double), ("dt_det", ctypes.c_double), ("n_t", ctypes.c_int64),
+        ("c", ctypes.c_double),
+    ]
+
+
+class _Chunk(ctypes.Structure):
+    _fields_ = [
+        ("n_particles", ctypes.c_int64), ("n_steps", ctypes.c_int64),
+        ("t_first", ctypes.c_double), ("dt", ctypes.c_double),
+        ("x", ctypes.c_void_p), ("u", ctypes.c_void_p), ("q", ctypes.c_void_p),
+    ]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("interactions", "clipped", "nonmonotone", "chunks", "bytes")]
+
+
+_LIB = None
+
+
+def _lib():
+    """Load libradio.so (after torch, so both share torch's HIP runtime)."""
+    global _LIB
+    if _LIB is None:
+        import torch  # noqa: F401  -- loads the HIP runtime the library must bind to
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "or python paper_2302_14812_amd/build_lib.py")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        lib.radio_status_string.argtypes = [ctypes.c_int]
+        lib.radio_status_string.restype = ctypes.c_char_p
+        lib.radio_detector_create.argtypes = [ctypes.POINTER(_Desc), vp, ctypes.POINTER(vp)]
+        lib.radio_detector_destroy.argtypes = [vp]
+        lib.radio_detector_reset.argtypes = [vp, vp]
+        lib.radio_deposit_trajectory_chunk.argtypes = [vp, ctypes.POINTER(_Chunk), vp]
+        lib.radio_deposit_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Chunk),
+                                            ctypes.c_int, vp]
+        lib.radio_read_detector.argtypes = [vp, vp, vp, vp]
+        lib.radio_detector_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
+        lib.radio_detector_shape.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                             ctypes.POINTER(ctypes.c_int32)]
+        lib.radio_detector_cells.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        lib.radio_arrival_times.argtypes = [vp, vp, vp, i64, ctypes.c_double, vp, vp]
+        for name in EXPORTS:
+            if name != "radio_status_string":
+                getattr(lib, name).restype = ctypes.c_int
+        _LIB = lib
+    return _LIB
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != OK:
+        raise RadioError(rc, what)
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _dev_f64(t, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Chunk:
+    """Device-resident trajectory chunk: x, u of shape (3, S+1, Np), q of shape (Np,)."""
+
+    def __init__(self, x, u, q=None, t_first: float = 0.0, dt: float = 1.0):
+        import torch
+        if not isinstance(x, torch.Tensor) or x.dim() != 3 or x.shape[0] != 3:
+            raise ValueError("x must be a (3, S+1, Np) tensor")
+        self.x = _dev_f64(x, x.shape, "x")
+        self.u = _dev_f64(u, x.shape, "u")
+        self.q = None if q is None else _dev_f64(q, (x.shape[2],), "q")
+        self.t_first = float(t_first)
+        self.dt = float(dt)
+
+    @classmethod
+    def from_numpy(cls, chunk, device="cuda") -> "Chunk":
+        """Copy a workloads.Chunk (host arrays) to the device."""
+        import torch
+        return cls(torch.from_numpy(np.ascontiguousarray(chunk.x)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(chunk.u)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(chunk.q)).to(device),
+                   chunk.t_first, chunk.dt)
+
+    @property
+    def n_particles(self) -> int:
+        return int(self.x.shape[2])
+
+    @property
+    def n_steps(self) -> int:
+        return int(self.x.shape[1]) - 1
+
+    def _c(self) -> _Chunk:
+        return _Chunk(self.n_particles, self.n_steps, self.t_first, self.dt,
+                      self.x.data_ptr(), self.u.data_ptr(),
+                      None if self.q is None else self.q.data_ptr())
+
+
+class Detector:
+    """A virtual detector resident in device memory (RaDiO Sec. 3.1).
+
+    Create it from explicit cell positions (`cells`, an (Nc, 3) array) or
+    with Detector.plane / Detector.sphere.  Slot j covers
+    [t0 + j dt_det, t0 + (j+1) dt_det), j < n_t.
+    """
+
+    def __init__(self, cells=None, *, t0: float, dt_det: float, n_t: int, c: float = 1.0,
+                 precision: str = "fp64", stream=None, _desc: Optional[_Desc] = None):
+        lib = _lib()
+        d = _desc if _desc is not None else _Desc()
+        keep = None
+        if _desc is None:
+            cells = np.ascontiguousarray(np.asarray(cells, dtype=np.float64).reshape(-1, 3))
+            keep = cells
+            d.geometry = GEOM_EXPLICIT
+            d.n_cells = cells.shape[0]
+            d.cells = cells.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if precision not in _PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(_PRECISIONS)}")
+        d.precision = _PRECISIONS[precision]
+        d.t0, d.dt_det, d.n_t, d.c = float(t0), float(dt_det), int(n_t), float(c)
+        h = ctypes.c_void_p()
+        _check(lib.radio_detector_create(ctypes.byref(d), _stream(stream), ctypes.byref(h)),
+               "radio_detector_create")
+        del keep
+        self._h = h
+        self.precision = precision
+        n_c, nt, prec = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _check(lib.radio_detector_shape(h, ctypes.byref(n_c), ctypes.byref(nt), ctypes.byref(prec)),
+               "radio_detector_shape")
+        self.n_cells, self.n_t = int(n_c.value), int(nt.value)
+        self.t0, self.dt_det, self.c = float(t0), float(dt_det), float(c)
+
+    @classmethod
+    def plane(cls, origin, e1, e2, n1, n2, half1, half2, **kw) -> "Detector":
+        d = _Desc()
+        d.geometry = GEOM_PLANE
+        d.origin[:] = [float(v) for v in origin]
+        d.e1[:] = [float(v) for v in e1]
+        d.e2[:] = [float(v) for v in e2]
+        d.n1, d.n2, d.half1, d.half2 = int(n1), int(n2), float(half1), float(half2)
+        return cls(_desc=d, **kw)
+
+    @classmethod
+    def sphere(cls, radius, axis, e1, n1, n2, half1, half2, **kw) -> "Detector":
+        d = _Desc()
+        d.geometry = GEOM_SPHERE
+        d.radius = float(radius)
+        d.axis[:] = [float(v) for v in axis]
+        d.e1[:] = [float(v) for v in e1]
+        d.n1, d.n2, d.half1, d.half2 = int(n1), int(n2), float(half1), float(half2)
+        return cls(_desc=d, **kw)
+
+    @classmethod
+    def from_spec(cls, spec, precision: str = "fp64", stream=None) -> "Detector":
+        """From a workloads.DetectorSpec."""
+        return cls(spec.cells, t0=spec.t0, dt_det=spec.dt_det, n_t=spec.n_t, c=spec.c,
+                   precision=precision, stream=stream)
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise ValueError("detector has been closed")
+        return self._h
+
+    def deposit(self, chunk: Chunk, stream=None) -> None:
+        c = chunk._c()
+        _check(_lib().radio_deposit_trajectory_chunk(self.handle, ctypes.byref(c), _stream(stream)),
+               "radio_deposit_trajectory_chunk")
+
+    def read(self, E=None, B=None, stream=None) -> Tuple[object, object]:
+        """Return (E, B) device tensors of shape (n_cells, n_t, 3)."""
+        import torch
+        shape = (self.n_cells, self.n_t, 3)
+        if E is None:
+            E = torch.empty(shape, dtype=torch.float64, device="cuda")
+        if B is None:
+            B = torch.empty(shape, dtype=torch.float64, device="cuda")
+        _dev_f64(E, shape, "E")
+        _dev_f64(B, shape, "B")
+        _check(_lib().radio_read_detector(self.handle, E.data_ptr(), B.data_ptr(), _stream(stream)),
+               "radio_read_detector")
+        return E, B
+
+    def reset(self, stream=None) -> None:
+        _check(_lib().radio_detector_reset(self.handle, _stream(stream)), "radio_detector_reset")
+
+    def stats(self) -> dict:
+        s = _Stats()
+        _check(_lib().radio_detector_stats(self.handle, ctypes.byref(s)), "radio_detector_stats")
+        return {n: int(getattr(s, n)) for n, _ in _Stats._fields_}
+
+    def cells(self) -> np.ndarray:
+        out = np.empty((self.n_cells, 3))
+        _check(_lib().radio_detector_cells(self.handle,
+                                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "radio_detector_cells")
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            _check(_lib().radio_detector_destroy(self._h), "radio_detector_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def deposit_batch(detectors: Sequence[Detector], chunks: Sequence[Chunk], stream=None) -> None:
+    """Deposit n independent (detector, chunk) pairs in one launch."""
+    if len(detectors) != len(chunks):
+        raise ValueError("one chunk per detector")
+    n = len(detectors)
+    hs = (ctypes.c_void_p * max(n, 1))(*[d.handle for d in detectors])
+    cs = (_Chunk * max(n, 1))(*[c._c() for c in chunks])
+    _check(_lib().radio_deposit_batch(hs, cs, n, _stream(stream)), "radio_deposit_batch")
+
+
+def arrival_times(cells, points, t, c: float = 1.0, stream=None):
+    """t + |cells - points|/c on the device for (n, 3), (n, 3), (n,) float64 tensors."""
+    import torch
+    n = int(t.shape[0])
+    _dev_f64(cells, (n, 3), "cells")
+    _dev_f64(points, (n, 3), "points")
+    _dev_f64(t, (n,), "t")
+    out = torch.empty(n, dtype=torch.float64, device=t.device)
+    _check(_lib().radio_arrival_times(cells.data_ptr(), points.data_ptr(), t.data_ptr(), n, float(c),
+                                      out.data_ptr(), _stream(stream)), "radio_arrival_times")
+    return out

@@ -1,0 +1,433 @@
+// Host runtime of libradio: the C interface declared in include/radio.h.
+//
+// Owns the detector objects (cell positions and the slot-difference
+// accumulator resident in device memory), validates every call on the host
+// before anything is enqueued, plans the work decomposition and launches the
+// kernels on the caller's stream.
+#include "radio.h"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "radio_internal.h"
+
+struct radio_detector {
+    int device = 0;
+    int32_t precision = RADIO_FP64;
+    int64_t n_c = 0;
+    int64_t n_t = 0;
+    double t0 = 0.0;
+    double dt_det = 1.0;
+    double c = 1.0;
+    double* d_cells = nullptr;
+    double* d_acc = nullptr;
+    unsigned long long* d_counters = nullptr;  // [2] clipped, nonmonotone
+    int64_t interactions = 0;
+    int64_t chunks = 0;
+    std::vector<double> h_cells;
+};
+
+namespace {
+
+constexpr int kTargetBlocks = 3072;  // workgroups per deposit launch (256 CUs, ~3 resident each)
+
+bool finite3(const double v[3])
+{
+    return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+double norm3(const double v[3])
+{
+    return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+}
+
+// cell positions of the generated geometries (radio.h documents the formulas)
+int build_cells(const radio_detector_desc& d, std::vector<double>& out)
+{
+    if (d.geometry == RADIO_GEOM_EXPLICIT) {
+        if (d.n_cells < 1 || !d.cells)
+            return RADIO_EINVAL;
+        out.assign(d.cells, d.cells + 3 * d.n_cells);
+        for (double v : out)
+            if (!std::isfinite(v))
+                return RADIO_EINVAL;
+        return RADIO_OK;
+    }
+    if (d.n1 < 1 || d.n2 < 1 || d.n1 > (int64_t)1 << 20 || d.n2 > (int64_t)1 << 20)
+        return RADIO_EINVAL;
+    if (!std::isfinite(d.half1) || !std::isfinite(d.half2) || d.half1 < 0.0 || d.half2 < 0.0)
+        return RADIO_EINVAL;
+    const int64_t n1 = d.n1, n2 = d.n2;
+    out.resize((size_t)(3 * n1 * n2));
+    if (d.geometry == RADIO_GEOM_PLANE) {
+        if (!finite3(d.origin) || !finite3(d.e1) || !finite3(d.e2))
+            return RADIO_EINVAL;
+        const double l1 = norm3(d.e1), l2 = norm3(d.e2);
+        if (!(l1 > 0.0) || !(l2 > 0.0))
+            return RADIO_EINVAL;
+        const double e1[3] = {d.e1[0] / l1, d.e1[1] / l1, d.e1[2] / l1};
+        const double e2[3] = {d.e2[0] / l2, d.e2[1] / l2, d.e2[2] / l2};
+        for (int64_t i2 = 0; i2 < n2; ++i2) {
+            const double a2 = -d.half2 + ((double)i2 + 0.5) * (2.0 * d.half2 / (double)n2);
+            for (int64_t i1 = 0; i1 < n1; ++i1) {
+                const double a1 = -d.half1 + ((double)i1 + 0.5) * (2.0 * d.half1 / (double)n1);
+                double* p = &out[(size_t)(3 * (i2 * n1 + i1))];
+                for (int k = 0; k < 3; ++k)
+                    p[k] = d.origin[k] + a1 * e1[k] + a2 * e2[k];
+            }
+        }
+        return RADIO_OK;
+    }
+    if (d.geometry == RADIO_GEOM_SPHERE) {
+        if (!finite3(d.axis) || !finite3(d.e1) || !(d.radius > 0.0) || !std::isfinite(d.radius))
+            return RADIO_EINVAL;
+        const double la = norm3(d.axis);
+        if (!(la > 0.0))
+            return RADIO_EINVAL;
+        const double ax[3] = {d.axis[0] / la, d.axis[1] / la, d.axis[2] / la};
+        const double pr = d.e1[0] * ax[0] + d.e1[1] * ax[1] + d.e1[2] * ax[2];
+        double e1[3] = {d.e1[0] - pr * ax[0], d.e1[1] - pr * ax[1], d.e1[2] - pr * ax[2]};
+        const double l1 = norm3(e1);
+        if (!(l1 > 1e-12 * norm3(d.e1)))
+            return RADIO_EINVAL;
+        for (double& v : e1)
+            v /= l1;
+        const double e2[3] = {ax[1] * e1[2] - ax[2] * e1[1], ax[2] * e1[0] - ax[0] * e1[2],
+                              ax[0] * e1[1] - ax[1] * e1[0]};
+        for (int64_t i2 = 0; i2 < n2; ++i2) {
+            const double lat = -d.half2 + ((double)i2 + 0.5) * (2.0 * d.half2 / (double)n2);
+            for (int64_t i1 = 0; i1 < n1; ++i1) {
+                const double lon = -d.half1 + ((double)i1 + 0.5) * (2.0 * d.half1 / (double)n1);
+                double* p = &out[(size_t)(3 * (i2 * n1 + i1))];
+                for (int k = 0; k < 3; ++k)
+                    p[k] = d.radius * (std::cos(lat) * (std::cos(lon) * ax[k] + std::sin(lon) * e1[k]) +
+                                       std::sin(lat) * e2[k]);
+            }
+        }
+        return RADIO_OK;
+    }
+    return RADIO_EINVAL;
+}
+
+// Make det's device current for the duration of a call, restoring the caller's.
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int dev) : ok_(true)
+    {
+        if (hipGetDevice(&prev_) != hipSuccess) {
+            ok_ = false;
+            return;
+        }
+        if (prev_ != dev && hipSetDevice(dev) != hipSuccess)
+            ok_ = false;
+        target_ = dev;
+    }
+    ~DeviceGuard()
+    {
+        if (ok_ && prev_ != target_)
+            (void)hipSetDevice(prev_);
+    }
+    bool ok() const { return ok_; }
+
+  private:
+    int prev_ = 0;
+    int target_ = 0;
+    bool ok_;
+};
+
+int validate_chunk(const radio_chunk* k)
+{
+    if (!k)
+        return RADIO_EINVAL;
+    if (k->n_particles < 0 || k->n_steps < 0)
+        return RADIO_EINVAL;
+    if (!std::isfinite(k->t_first) || !std::isfinite(k->dt) || !(k->dt > 0.0))
+        return RADIO_EINVAL;
+    if (k->n_particles == 0 || k->n_steps == 0)
+        return RADIO_OK;
+    if (!k->x || !k->u)
+        return RADIO_EINVAL;
+    // keep every flattened index inside int64
+    const double states = (double)k->n_steps + 1.0;
+    if (3.0 * states * (double)k->n_particles > 9.0e18)
+        return RADIO_EINVAL;
+    return RADIO_OK;
+}
+
+radio::DepositJob make_job(radio_detector* det, const radio_chunk* k)
+{
+    radio::DepositJob J{};
+    J.cells = det->d_cells;
+    J.acc = det->d_acc;
+    J.counters = det->d_counters;
+    J.x = k->x;
+    J.u = k->u;
+    J.q = k->q;
+    J.n_c = det->n_c;
+    J.n_t = det->n_t;
+    J.n_p = k->n_particles;
+    J.n_s = k->n_steps;
+    J.t_first = k->t_first;
+    J.dt = k->dt;
+    J.t0 = det->t0;
+    J.inv_dt_det = 1.0 / det->dt_det;
+    J.inv_c = 1.0 / det->c;
+    J.c = det->c;
+    radio::plan_job(J, kTargetBlocks);
+    return J;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* radio_status_string(int status)
+{
+    switch (status) {
+    case RADIO_OK:
+        return "ok";
+    case RADIO_EINVAL:
+        return "invalid argument";
+    case RADIO_ENOMEM:
+        return "out of memory";
+    case RADIO_EDEVICE:
+        return "device error";
+    case RADIO_ESTATE:
+        return "invalid state";
+    default:
+        return "unknown status";
+    }
+}
+
+int radio_detector_create(const radio_detector_desc* desc, void* stream, radio_detector** out)
+{
+    if (!desc || !out)
+        return RADIO_EINVAL;
+    if (desc->precision != RADIO_FP64 && desc->precision != RADIO_MIXED)
+        return RADIO_EINVAL;
+    if (!std::isfinite(desc->t0) || !std::isfinite(desc->dt_det) || !(desc->dt_det > 0.0) ||
+        !std::isfinite(1.0 / desc->dt_det))
+        return RADIO_EINVAL;
+    if (desc->n_t < 1 || desc->n_t > (int64_t)1 << 30)
+        return RADIO_EINVAL;
+    if (!std::isfinite(desc->c) || !(desc->c > 0.0))
+        return RADIO_EINVAL;
+    std::vector<double> cells;
+    int rc = build_cells(*desc, cells);
+    if (rc != RADIO_OK)
+        return rc;
+    const int64_t n_c = (int64_t)(cells.size() / 3);
+    if ((double)n_c * (double)desc->n_t * 6.0 > 4.0e18)
+        return RADIO_EINVAL;
+
+    radio_detector* det = new (std::nothrow) radio_detector();
+    if (!det)
+        return RADIO_ENOMEM;
+    if (hipGetDevice(&det->device) != hipSuccess) {
+        delete det;
+        return RADIO_EDEVICE;
+    }
+    det->precision = desc->precision;
+    det->n_c = n_c;
+    det->n_t = desc->n_t;
+    det->t0 = desc->t0;
+    det->dt_det = desc->dt_det;
+    det->c = desc->c;
+    det->h_cells.swap(cells);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t acc_bytes = (size_t)n_c * (size_t)det->n_t * 6 * sizeof(double);
+    if (hipMalloc((void**)&det->d_acc, acc_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        delete det;
+        return RADIO_ENOMEM;
+    }
+    if (hipMalloc((void**)&det->d_cells, (size_t)n_c * 3 * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&det->d_counters, 2 * sizeof(unsigned long long)) != hipSuccess) {
+        (void)hipGetLastError();
+        radio_detector_destroy(det);
+        return RADIO_ENOMEM;
+    }
+    if (hipMemcpyAsync(det->d_cells, det->h_cells.data(), (size_t)n_c * 3 * sizeof(double),
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        radio::launch_zero(det->d_acc, n_c * det->n_t * 6, s) != hipSuccess ||
+        radio::launch_zero_u64(det->d_counters, 2, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {  // h_cells is pageable: finish the copy
+        radio_detector_destroy(det);
+        return RADIO_EDEVICE;
+    }
+    *out = det;
+    return RADIO_OK;
+}
+
+int radio_detector_destroy(radio_detector* det)
+{
+    if (!det)
+        return RADIO_OK;
+    int rc = RADIO_OK;
+    {
+        DeviceGuard g(det->device);
+        if (!g.ok())
+            rc = RADIO_EDEVICE;
+        if (hipDeviceSynchronize() != hipSuccess)
+            rc = RADIO_EDEVICE;
+        if (det->d_acc)
+            (void)hipFree(det->d_acc);
+        if (det->d_cells)
+            (void)hipFree(det->d_cells);
+        if (det->d_counters)
+            (void)hipFree(det->d_counters);
+    }
+    delete det;
+    return rc;
+}
+
+int radio_detector_reset(radio_detector* det, void* stream)
+{
+    if (!det)
+        return RADIO_EINVAL;
+    DeviceGuard g(det->device);
+    if (!g.ok())
+        return RADIO_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    if (radio::launch_zero(det->d_acc, det->n_c * det->n_t * 6, s) != hipSuccess ||
+        radio::launch_zero_u64(det->d_counters, 2, s) != hipSuccess)
+        return RADIO_EDEVICE;
+    det->interactions = 0;
+    det->chunks = 0;
+    return RADIO_OK;
+}
+
+static int enqueue_deposit(radio_detector* det, const radio_chunk* k, hipStream_t s)
+{
+    if (k->n_particles == 0 || k->n_steps == 0)
+        return RADIO_OK;
+    radio::DepositJob J = make_job(det, k);
+    hipError_t e = det->precision == RADIO_MIXED ? radio::launch_deposit_mixed(J, s)
+                                                 : radio::launch_deposit_fp64(J, s);
+    if (e != hipSuccess)
+        return RADIO_EDEVICE;
+    det->interactions += k->n_particles * k->n_steps * det->n_c;
+    return RADIO_OK;
+}
+
+int radio_deposit_trajectory_chunk(radio_detector* det, const radio_chunk* chunk, void* stream)
+{
+    if (!det)
+        return RADIO_EINVAL;
+    int rc = validate_chunk(chunk);
+    if (rc != RADIO_OK)
+        return rc;
+    DeviceGuard g(det->device);
+    if (!g.ok())
+        return RADIO_EDEVICE;
+    rc = enqueue_deposit(det, chunk, (hipStream_t)stream);
+    if (rc == RADIO_OK)
+        det->chunks += 1;
+    return rc;
+}
+
+int radio_deposit_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
+                        void* stream)
+{
+    if (n < 0 || (n > 0 && (!dets || !chunks)))
+        return RADIO_EINVAL;
+    if (n == 0)
+        return RADIO_OK;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return RADIO_EDEVICE;
+    for (int i = 0; i < n; ++i) {
+        if (!dets[i])
+            return RADIO_EINVAL;
+        if (dets[i]->device != dev)
+            return RADIO_ESTATE;
+        int rc = validate_chunk(&chunks[i]);
+        if (rc != RADIO_OK)
+            return rc;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < n; ++i) {
+        int rc = enqueue_deposit(dets[i], &chunks[i], s);
+        if (rc != RADIO_OK)
+            return rc;
+        dets[i]->chunks += 1;
+    }
+    return RADIO_OK;
+}
+
+int radio_read_detector(const radio_detector* det, double* E, double* B, void* stream)
+{
+    if (!det)
+        return RADIO_EINVAL;
+    if (!E && !B)
+        return RADIO_OK;
+    DeviceGuard g(det->device);
+    if (!g.ok())
+        return RADIO_EDEVICE;
+    if (radio::launch_readout(det->d_acc, det->n_c, det->n_t, det->precision == RADIO_MIXED, E, B,
+                              (hipStream_t)stream) != hipSuccess)
+        return RADIO_EDEVICE;
+    return RADIO_OK;
+}
+
+int radio_detector_stats(const radio_detector* det, radio_stats* out)
+{
+    if (!det || !out)
+        return RADIO_EINVAL;
+    DeviceGuard g(det->device);
+    if (!g.ok())
+        return RADIO_EDEVICE;
+    unsigned long long cnt[2] = {0, 0};
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(cnt, det->d_counters, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess)
+        return RADIO_EDEVICE;
+    out->interactions = det->interactions;
+    out->clipped = (int64_t)cnt[0];
+    out->nonmonotone = (int64_t)cnt[1];
+    out->chunks = det->chunks;
+    out->bytes = (int64_t)(det->n_c * det->n_t * 6 * (int64_t)sizeof(double) +
+                           det->n_c * 3 * (int64_t)sizeof(double) +
+                           2 * (int64_t)sizeof(unsigned long long));
+    return RADIO_OK;
+}
+
+int radio_detector_shape(const radio_detector* det, int64_t* n_cells, int64_t* n_t,
+                         int32_t* precision)
+{
+    if (!det)
+        return RADIO_EINVAL;
+    if (n_cells)
+        *n_cells = det->n_c;
+    if (n_t)
+        *n_t = det->n_t;
+    if (precision)
+        *precision = det->precision;
+    return RADIO_OK;
+}
+
+int radio_detector_cells(const radio_detector* det, double* out)
+{
+    if (!det || !out)
+        return RADIO_EINVAL;
+    std::memcpy(out, det->h_cells.data(), det->h_cells.size() * sizeof(double));
+    return RADIO_OK;
+}
+
+int radio_arrival_times(const double* cells, const double* points, const double* t, int64_t n,
+                        double c, double* out, void* stream)
+{
+    if (n < 0 || !std::isfinite(c) || !(c > 0.0))
+        return RADIO_EINVAL;
+    if (n == 0)
+        return RADIO_OK;
+    if (!cells || !points || !t || !out)
+        return RADIO_EINVAL;
+    if (radio::launch_arrival(cells, points, t, n, 1.0 / c, out, (hipStream_t)stream) !=
+        hipSuccess)
+        return RADIO_EDEVICE;
+    return RADIO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,272 @@
+"""GPU parity: the HIP deposit against the CPU oracle on identical seeded inputs.
+
+Bar for the double-precision path: relative L2 <= 1e-12, reported separately
+for E and for B (the larger counts).  Arrival times, which the slot
+coordinate amplifies, must match the oracle bit for bit.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_14812_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-12
+TOL_MIXED = 1e-5
+TOLS = {"fp64": TOL_FP64, "mixed": TOL_MIXED}
+PRECISIONS = pytest.mark.parametrize("precision", ["fp64", "mixed"])
+
+
+@pytest.fixture(scope="module")
+def radio():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2302_14812_amd as radio
+    radio._lib()  # a missing library raises here: no fallback
+    return radio
+
+
+def rel_l2(a, b):
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b)) / (nb if nb > 0 else 1.0)
+
+
+def gpu_deposit(radio, spec, chunks, precision="fp64"):
+    import torch
+    det = radio.Detector.from_spec(spec, precision=precision)
+    if not isinstance(chunks, (list, tuple)):
+        chunks = [chunks]
+    for ch in chunks:
+        det.deposit(radio.Chunk.from_numpy(ch))
+    E, B = det.read()
+    torch.cuda.synchronize()
+    st = det.stats()
+    det.close()
+    return E.cpu().numpy(), B.cpu().numpy(), st
+
+
+def oracle_deposit(spec, chunk, cell_index=None):
+    cnt = np.zeros(2, dtype=np.int64)
+    D = oracle.deposit_workload(spec, chunk, cell_index=cell_index, counters=cnt)
+    E, B = oracle.read(D)
+    return E, B, cnt
+
+
+def check_parity(Eg, Bg, Eo, Bo, tol, what):
+    eE, eB = rel_l2(Eg, Eo), rel_l2(Bg, Bo)
+    print(f"[parity] {what}: relL2 E={eE:.3e} B={eB:.3e}", flush=True)
+    assert max(eE, eB) <= tol, (what, eE, eB)
+
+
+def _window(cells, chunk, n_t, pad=0.05):
+    t = chunk.state_times()
+    lo, hi = np.inf, -np.inf
+    for xc in cells:
+        d = xc[:, None, None] - chunk.x
+        tt = t[:, None] + np.sqrt((d * d).sum(axis=0))
+        lo, hi = min(lo, tt.min()), max(hi, tt.max())
+    w = hi - lo
+    t0 = lo - pad * w
+    return t0, (hi + pad * w - t0) / n_t
+
+
+def test_arrival_times_bit_exact(radio, oracle_mod):
+    import torch
+    rng = np.random.Generator(np.random.PCG64(1))
+    n = 3000
+    scale = 10.0 ** rng.uniform(-1, 5, size=n)
+    cells = rng.normal(size=(n, 3)) * scale[:, None]
+    pts = rng.normal(size=(n, 3)) * rng.uniform(0, 100, size=(n, 1))
+    t = rng.uniform(-50, 500, size=n)
+    for c in (1.0, 0.7):
+        out = radio.arrival_times(torch.from_numpy(cells).cuda(), torch.from_numpy(pts).cuda(),
+                                  torch.from_numpy(t).cuda(), c=c).cpu().numpy()
+        ref = np.array([oracle_mod.arrival(cells[i], pts[i], t[i], c) for i in range(n)])
+        bad = np.flatnonzero(out != ref)
+        assert bad.size == 0, (c, bad[:5], out[bad[:5]] - ref[bad[:5]])
+
+
+@PRECISIONS
+def test_parity_circular_orbit(radio, precision):
+    wl = W.circular_workload()
+    Eg, Bg, st = gpu_deposit(radio, wl.detector, wl.chunk, precision)
+    Eo, Bo, cnt = oracle_deposit(wl.detector, wl.chunk)
+    check_parity(Eg, Bg, Eo, Bo, TOLS[precision], f"{wl.name} {precision}")
+    assert st["interactions"] == wl.interactions
+    assert st["clipped"] == cnt[0] and st["nonmonotone"] == cnt[1]
+
+
+@pytest.mark.parametrize("seed,n_p,n_s,n_side,n_t,clip", [
+    (1, 37, 77, (20, 15), 333, False),
+    (2, 1, 1, (3, 1), 5, False),
+    (3, 17, 33, (16, 16), 64, True),
+    (4, 50, 64, (1, 1), 1, True),
+    (5, 33, 95, (17, 31), 200, True),
+])
+@PRECISIONS
+def test_parity_random_ragged(radio, precision, seed, n_p, n_s, n_side, n_t, clip):
+    chunk = W.random_chunk(n_p, n_s, seed=seed, dt=0.07, gamma_max=30.0, t_first=0.3 * seed)
+    cells = W.plane_cells([1.0, -2.0, 30.0], [1, 0.2, 0], [0, 1, 0.1], n_side[0], n_side[1],
+                          12.0, 9.0)
+    t0, dtd = _window(cells, chunk, n_t)
+    if clip:  # cut both ends of the arrival interval
+        t0 += 0.2 * n_t * dtd
+        dtd *= 0.6
+    spec = W.DetectorSpec(cells=cells, t0=t0, dt_det=dtd, n_t=n_t)
+    Eg, Bg, st = gpu_deposit(radio, spec, chunk, precision)
+    Eo, Bo, cnt = oracle_deposit(spec, chunk)
+    check_parity(Eg, Bg, Eo, Bo, TOLS[precision], f"random seed={seed} {precision}")
+    assert st["clipped"] == cnt[0] and st["nonmonotone"] == cnt[1]
+    if clip:
+        assert cnt[0] > 0
+
+
+@PRECISIONS
+def test_parity_undulator_small(radio, precision):
+    wl = W.undulator_workload(n_particles=64, n_steps=600, n_side=24, n_t=512)
+    Eg, Bg, _ = gpu_deposit(radio, wl.detector, wl.chunk, precision)
+    Eo, Bo, _ = oracle_deposit(wl.detector, wl.chunk)
+    check_parity(Eg, Bg, Eo, Bo, TOLS[precision], f"{wl.name} {precision}")
+
+
+@PRECISIONS
+def test_parity_plasma_mirror_small(radio, precision):
+    wl = W.plasma_mirror_workload(n_particles=300, n_steps=250, n_side=16, n_t=1024)
+    Eg, Bg, _ = gpu_deposit(radio, wl.detector, wl.chunk, precision)
+    Eo, Bo, _ = oracle_deposit(wl.detector, wl.chunk)
+    check_parity(Eg, Bg, Eo, Bo, TOLS[precision], f"{wl.name} {precision}")
+
+
+def test_edge_cases(radio):
+    import torch
+    chunk = W.random_chunk(4, 20, seed=8, dt=0.05, gamma_max=5.0)
+    cells = W.plane_cells([0, 0, 20.0], [1, 0, 0], [0, 1, 0], 5, 4, 3.0, 3.0)
+    t0, dtd = _window(cells, chunk, 50)
+    spec = W.DetectorSpec(cells=cells, t0=t0, dt_det=dtd, n_t=50)
+    # every arrival before the window: nothing lands, everything counted clipped
+    late = W.DetectorSpec(cells=cells, t0=t0 + 1e3, dt_det=dtd, n_t=50)
+    Eg, Bg, st = gpu_deposit(radio, late, chunk)
+    assert np.abs(Eg).max() == 0.0 and np.abs(Bg).max() == 0.0
+    assert st["clipped"] == chunk.n_particles * chunk.n_steps * cells.shape[0]
+    # every arrival after the window
+    early = W.DetectorSpec(cells=cells, t0=t0 - 1e3, dt_det=dtd, n_t=50)
+    Eg, Bg, _ = gpu_deposit(radio, early, chunk)
+    Eo, Bo, _ = oracle_deposit(early, chunk)
+    check_parity(Eg, Bg, Eo, Bo, TOL_FP64, "window before arrivals")
+    # NULL charges mean electrons
+    det = radio.Detector.from_spec(spec)
+    det2 = radio.Detector.from_spec(spec)
+    c1 = radio.Chunk.from_numpy(chunk)
+    c_none = radio.Chunk(c1.x, c1.u, None, chunk.t_first, chunk.dt)
+    c_neg = radio.Chunk(c1.x, c1.u, torch.full((chunk.n_particles,), -1.0, dtype=torch.float64,
+                                               device="cuda"), chunk.t_first, chunk.dt)
+    det.deposit(c_none)
+    det2.deposit(c_neg)
+    E1, B1 = det.read()
+    E2, B2 = det2.read()
+    assert torch.equal(E1, E2) and torch.equal(B1, B2)
+    # empty chunks are valid no-ops
+    before = det.read()[0].clone()
+    empty = radio.Chunk(c1.x[:, :1, :].contiguous(), c1.u[:, :1, :].contiguous(), c1.q, 0.0,
+                        0.1)  # zero segments
+    det.deposit(empty)
+    nop = radio.Chunk(c1.x[:, :, :0].contiguous(), c1.u[:, :, :0].contiguous(), None, 0.0, 0.1)
+    det.deposit(nop)
+    assert torch.equal(det.read()[0], before)
+    # invalid chunks are rejected and change nothing
+    bad = radio.Chunk(c1.x, c1.u, c1.q, chunk.t_first, 0.0)
+    with pytest.raises(radio.RadioError) as ei:
+        det.deposit(bad)
+    assert ei.value.status == radio.EINVAL
+    bad = radio.Chunk(c1.x, c1.u, c1.q, float("nan"), 0.1)
+    with pytest.raises(radio.RadioError):
+        det.deposit(bad)
+    assert torch.equal(det.read()[0], before)
+    # reset
+    det.reset()
+    E0, B0 = det.read()
+    assert float(E0.abs().max()) == 0.0 and float(B0.abs().max()) == 0.0
+    assert det.stats()["interactions"] == 0
+    det.close()
+    det2.close()
+
+
+def test_chunk_split_and_superposition(radio):
+    chunk = W.random_chunk(23, 150, seed=12, dt=0.04, gamma_max=20.0)
+    cells = W.plane_cells([0, 3.0, 40.0], [1, 0, 0], [0, 1, 0], 13, 11, 8.0, 8.0)
+    t0, dtd = _window(cells, chunk, 300)
+    spec = W.DetectorSpec(cells=cells, t0=t0, dt_det=dtd, n_t=300)
+    parts = W.split_steps(chunk, [1, 40, 41, 99])
+    parts += [parts.pop(0)]  # out of order
+    Eg, Bg, st = gpu_deposit(radio, spec, parts)
+    assert st["chunks"] == len(parts)
+    D = np.zeros((cells.shape[0], 300, 6))
+    for part in parts:
+        oracle.deposit_workload(spec, part, D=D)
+    Eo, Bo = oracle.read(D)
+    check_parity(Eg, Bg, Eo, Bo, TOL_FP64, "chunk split vs oracle of the same parts")
+    # against the unsplit chunk: each part recomputes its state times from its own
+    # t_first, which may move an arrival time by an ulp (~1e-7 of a slot here)
+    Eu, Bu, _ = oracle_deposit(spec, chunk)
+    check_parity(Eg, Bg, Eu, Bu, 1e-10, "chunk split vs unsplit")
+    halves = [chunk.slice_particles(0, 10), chunk.slice_particles(10, 23)]
+    Eg, Bg, _ = gpu_deposit(radio, spec, halves)
+    check_parity(Eg, Bg, Eu, Bu, TOL_FP64, "particle split")
+
+
+def test_generated_geometries_match_generators(radio):
+    p = radio.Detector.plane([1.0, 2.0, 300.0], [1, 0, 0], [0, 2, 0], 7, 5, 40.0, 30.0,
+                             t0=0.0, dt_det=1.0, n_t=4)
+    np.testing.assert_allclose(p.cells(), W.plane_cells([1.0, 2.0, 300.0], [1, 0, 0], [0, 2, 0],
+                                                         7, 5, 40.0, 30.0), rtol=1e-14, atol=1e-12)
+    s = radio.Detector.sphere(1e5, [-1, 1, 0], [1, 1, 0.3], 6, 9, 0.1, 0.05,
+                              t0=0.0, dt_det=1.0, n_t=4)
+    np.testing.assert_allclose(s.cells(), W.sphere_cap_cells(1e5, [-1, 1, 0], [1, 1, 0.3], 6, 9,
+                                                             0.1, 0.05), rtol=1e-13, atol=1e-8)
+    p.close()
+    s.close()
+
+
+@PRECISIONS
+def test_full_size_undulator_sampled_cells(radio, precision):
+    """The benchmark workload at full size, in the launch configuration the benchmark
+    times, compared on sampled cells (corners, centre, and a seeded random set)."""
+    import torch
+    wl = _undulator_full()
+    det = radio.Detector.from_spec(wl.detector, precision=precision)
+    ch = radio.Chunk.from_numpy(wl.chunk)
+    det.deposit(ch)
+    E, B = det.read()
+    torch.cuda.synchronize()
+    n1, n2 = wl.detector.grid
+    rng = np.random.Generator(np.random.PCG64(99))
+    idx = sorted(set(W.grid_corner_cells(n1, n2)) | set(rng.choice(n1 * n2, 11, replace=False).tolist()))
+    Eg = E[idx].cpu().numpy()
+    Bg = B[idx].cpu().numpy()
+    del E, B, ch
+    det.close()
+    Eo, Bo, _ = _undulator_oracle(tuple(idx))
+    check_parity(Eg, Bg, Eo, Bo, TOLS[precision], f"{wl.name} sampled {precision}")
+
+
+_CACHE = {}
+
+
+def _undulator_full():
+    if "wl" not in _CACHE:
+        _CACHE["wl"] = W.undulator_workload()
+    return _CACHE["wl"]
+
+
+def _undulator_oracle(idx):
+    key = ("oracle", idx)
+    if key not in _CACHE:
+        wl = _undulator_full()
+        _CACHE[key] = oracle_deposit(wl.detector, wl.chunk, cell_index=list(idx))
+    return _CACHE[key]
