@@ -24,7 +24,7 @@ if ROOT not in sys.path:
 # two flops and a sqrt or divide as one: arrival time 16, n - beta and kappa 9,
 # cross products 18, 1/kappa^3 and the two coefficients 7, E 9, B 9, one slot 16
 FLOPS_PER_INTERACTION = 84
-PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}  # MI355X vector FP64 / FP32 (published)
+PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3, "mixed_twosum": 157.3}  # MI355X vector FP64 / FP32
 
 
 def parse():
@@ -32,9 +32,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--precision", choices=["mixed", "fp64", "mixed_twosum"], default="mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the double-precision leg")
+    ap.add_argument("--twosum", action="store_true",
+                    help="also time the compensated single-precision accumulation")
     ap.add_argument("--cpu-cells", type=int, default=0,
                     help="cells in the oracle sample (default: two per host thread)")
     return ap.parse_args()
@@ -56,9 +58,10 @@ def time_precision(radio, wl, chunk_dev, precision, steps, warmup):
             ev[1].record(stream)
         det.read(E, B, stream)
 
-    for _ in range(warmup):
+    for i in range(warmup):
         step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        print(f"[bench] {precision} warmup {i + 1}/{warmup} done", file=sys.stderr, flush=True)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(steps)]
     torch.cuda.synchronize()
@@ -116,6 +119,8 @@ def main():
 
     legs = {}
     order = [args.precision] + ([] if args.no_fp64 or args.precision == "fp64" else ["fp64"])
+    if args.twosum and args.precision != "mixed_twosum":
+        order.append("mixed_twosum")
     for prec in order:
         ms, kms = time_precision(radio, wl, chunk_dev, prec, args.steps, args.warmup)
         flops = inter * FLOPS_PER_INTERACTION
@@ -141,7 +146,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "n_particles": wl.chunk.n_particles,
                    "n_steps": wl.chunk.n_steps, "n_cells": wl.detector.n_cells,
@@ -152,6 +157,8 @@ def main():
     if "fp64" in legs and args.precision != "fp64":
         out["fp64"] = legs["fp64"]
         out["mixed_vs_fp64_speedup"] = legs["fp64"]["ms_per_step"] / main_leg["ms_per_step"]
+    if "mixed_twosum" in legs and args.precision != "mixed_twosum":
+        out["mixed_twosum"] = legs["mixed_twosum"]
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, args.cpu_cells)
         out["cpu_baseline"] = cb

@@ -50,10 +50,14 @@ extern "C" {
 #define RADIO_ESTATE (-4)  /* object in the wrong state (e.g. wrong device) */
 
 /* arithmetic of the deposit */
-#define RADIO_FP64 0  /* every step in IEEE double */
-#define RADIO_MIXED 1 /* arrival time, bin index, n - beta and kappa in double; the
-                         field, weights and slot accumulation in single, merged into
-                         a double accumulator */
+#define RADIO_FP64 0         /* every step in IEEE double */
+#define RADIO_MIXED 1        /* arrival time, slot coordinate, n - beta and kappa in
+                                double; the rest of the field and the slot weights in
+                                single; slot accumulation in double */
+#define RADIO_MIXED_TWOSUM 2 /* as RADIO_MIXED, but slots accumulate in single precision
+                                with compensation: each slot holds a (hi, lo) pair and
+                                every add carries its exact rounding error (two-sum)
+                                into lo */
 
 /* detector cell geometry (Sec. 3.1: spherical grids centred at the origin and
    cartesian planes) */
@@ -71,7 +75,7 @@ typedef struct radio_detector radio_detector; /* opaque, owned by the library */
 
 typedef struct radio_detector_desc {
     int32_t geometry;     /* RADIO_GEOM_* */
-    int32_t precision;    /* RADIO_FP64 or RADIO_MIXED */
+    int32_t precision;    /* RADIO_FP64, RADIO_MIXED or RADIO_MIXED_TWOSUM */
     int64_t n_cells;      /* EXPLICIT only: number of cells */
     const double* cells;  /* EXPLICIT only: HOST pointer to [n_cells][3] positions; copied */
     double origin[3];     /* PLANE: grid centre */
@@ -111,7 +115,9 @@ typedef struct radio_stats {
     int64_t clipped;      /* of those, pairs with some part outside the time array */
     int64_t nonmonotone;  /* of those, pairs whose arrival time decreases (|dx| > c dt) */
     int64_t chunks;       /* deposit calls accepted */
-    int64_t bytes;        /* device bytes held by the detector */
+    int64_t bytes;        /* device bytes held by the detector (with its workspace) */
+    int64_t bypassed;     /* slot updates that missed the on-chip slot window and went
+                             straight to device memory (a performance counter) */
 } radio_stats;
 
 /*

@@ -19,9 +19,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libradio.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4
-FP64, MIXED = 0, 1
+FP64, MIXED, MIXED_TWOSUM = 0, 1, 2
 GEOM_EXPLICIT, GEOM_PLANE, GEOM_SPHERE = 0, 1, 2
-_PRECISIONS = {"fp64": FP64, "mixed": MIXED}
+_PRECISIONS = {"fp64": FP64, "mixed": MIXED, "mixed_twosum": MIXED_TWOSUM}
 
 # every function the C header declares
 EXPORTS = (
@@ -62,7 +62,7 @@ class _Chunk(ctypes.Structure):
 
 class _Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
-                ("interactions", "clipped", "nonmonotone", "chunks", "bytes")]
+                ("interactions", "clipped", "nonmonotone", "chunks", "bytes", "bypassed")]
 
 
 _LIB = None

@@ -6,40 +6,79 @@
 
 namespace radio {
 
+// One trajectory state as the deposit reads it (96 B, 16-B aligned): position,
+// beta, betadot = (beta_s - beta_{s-1})/dt (zero for the first state of a
+// chunk, which carries no segment), 1/gamma^2, and single-precision copies of
+// betadot and 1/gamma^2 for the mixed field.
+struct StateRec {
+    double x[3];
+    double b[3];
+    double bd[3];
+    double g2i;
+    float bdf[3];
+    float g2if;
+};
+static_assert(sizeof(StateRec) == 96, "StateRec layout");
+
+// arithmetic of a deposit: field in double, accumulation in double; field in
+// single, accumulation in double; field in single, accumulation in compensated
+// single pairs
+constexpr int kModeF64 = 0;
+constexpr int kModeMix = 1;
+constexpr int kModeMixTwoSum = 2;
+
+// workgroup shape of the deposit
+constexpr int kTileCells = 16;                          // cells per workgroup
+constexpr int kGroups = 16;                             // particle lanes per cell
+constexpr int kDepositThreads = kTileCells * kGroups;   // 256
+constexpr int kRunL = 16;                               // segments per run
+constexpr int kRingMargin = 2;                          // ring slots kept below a batch's start
+
+// slots per cell in the LDS ring (a power of two): 48 B per slot for both
+// paths (6 doubles, or 6 compensated single pairs), 24.6 KB per workgroup
+template <typename T>
+struct RingSlots;
+template <>
+struct RingSlots<double> {
+    static constexpr int value = 32;
+};
+template <>
+struct RingSlots<float> {
+    static constexpr int value = 32;
+};
+
 // One (detector, chunk) deposit as the kernels see it.  Sizes are 64-bit; the
 // host runtime has validated every pointer and size before filling this in.
 struct DepositJob {
-    const double* cells;            // [n_c][3]
+    const double* cells;            // [n_c][3], internal (tile-ordered) rows
     double* acc;                    // [n_c][n_t][6] doubles, or [n_c][n_t][12] floats (hi, lo)
-    unsigned long long* counters;   // [2]: clipped, nonmonotone
+                                    // for the compensated single mode
+    unsigned long long* counters;   // [3]: clipped, nonmonotone, ring bypasses
     const double* x;                // [3][n_s+1][n_p]
     const double* u;                // [3][n_s+1][n_p]
     const double* q;                // [n_p] or nullptr (all -1)
+    StateRec* recs;                 // workspace [n_p][n_s+1]
+    int32_t* perm;                  // workspace [n_tiles][n_p]
     int64_t n_c, n_t, n_p, n_s;
     double t_first, dt;             // state s at t_first + s*dt
     double t0, inv_dt_det;          // slot coordinate (t_det - t0) * inv_dt_det
     double inv_c, c;
     // work decomposition, filled by plan_job()
-    int64_t n_pb;                   // particle blocks of kTileP
-    int64_t n_tiles;                // runs * particle blocks
-    int64_t tiles_per_split;        // tiles per workgroup along grid.y
-    int64_t n_splits;
-    int64_t cell_blocks;            // workgroups along the cells
+    int64_t n_tiles;                // tiles of kTileCells cells
+    int64_t n_runs;                 // runs of kRunL segments
+    int64_t runs_per_split;         // runs per workgroup
+    int64_t n_splits;               // workgroups per tile
 };
-
-// tile shape of the deposit kernels
-constexpr int kCellsPerBlock = 256;  // one cell per lane, 4 waves
-constexpr int kTileP = 16;           // particles staged per tile
-constexpr int kRunL = 32;            // segments per run (states kRunL + 1)
 
 void plan_job(DepositJob& job, int target_blocks);
 
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
-hipError_t launch_deposit_fp64(const DepositJob& job, hipStream_t s);
-hipError_t launch_deposit_mixed(const DepositJob& job, hipStream_t s);
-hipError_t launch_readout(const double* acc, int64_t n_c, int64_t n_t, bool mixed, double* E,
-                          double* B, hipStream_t s);
+hipError_t launch_kinematics(const DepositJob& job, hipStream_t s);
+hipError_t launch_order(const DepositJob& job, hipStream_t s);
+hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s);
+hipError_t launch_readout(const double* acc, int64_t n_c, int64_t n_t, const int64_t* user_index,
+                          bool pairs, double* E, double* B, hipStream_t s);
 hipError_t launch_arrival(const double* cells, const double* pts, const double* t, int64_t n,
                           double inv_c, double* out, hipStream_t s);
 

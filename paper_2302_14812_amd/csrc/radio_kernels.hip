@@ -4,30 +4,37 @@
 // Lienard-Wiechert field (Eq. 1) of the segment's current state and the
 // arrival times of its two end states (Eq. 2), and adds the field held
 // between those arrival times to the detector slots with the integrator
-// weights of Sec. 3.2 / Alg. 2.
+// weights of Sec. 3.2 / Alg. 2.  Three kernels run per deposit:
+//
+// 1. kinematics_kernel (Alg. 1, velocity and acceleration lines): one thread
+//    per trajectory state turns (x, u) into a 96-byte record with x, beta,
+//    betadot and 1/gamma^2, laid out particle-major so that the states of one
+//    particle's run are contiguous.
+//
+// 2. order_kernel: for every tile of kTileCells detector cells, a counting
+//    sort of the particles by their light-travel time to the tile's centre at
+//    the chunk's middle state.  Processing particles in that order makes the
+//    arrival slots a tile's cells see advance nearly monotonically.
+//
+// 3. deposit_kernel: one workgroup per (tile, range of runs).  Lane
+//    (cell, group) = (lane / kGroups, lane % kGroups): the kTileCells cells of
+//    the tile each get kGroups lanes, and the lanes of one group walk the
+//    same particle.  Trajectories are cut into runs of kRunL segments; a batch
+//    of kGroups particles (consecutive in the tile's order) x (kRunL + 1)
+//    states is staged in LDS and each lane walks its particle's run against
+//    its cell.  The lane integrates the held field over its current slot with
+//    the exact slot-unit overlaps of Alg. 2 and emits slot-value differences
+//    only when its arrivals move on; emissions go to a per-cell ring of slots
+//    in LDS that slides forward as the sorted batches advance, and only slots
+//    leaving the ring (or emissions that fall outside it) reach the detector
+//    in HBM, through atomic adds.
 //
 // Slot-difference accumulator.  The detector stores, per cell and slot, the
 // difference between consecutive slot values; the readout turns differences
-// back into slot values with a prefix sum along the slots.  A lane walks one
-// particle's segments in order and integrates the held field over its current
-// slot with the exact slot-unit overlaps of Alg. 2; it emits a difference only
-// when the particle's arrivals move to a later slot.  A segment spanning many
-// slots therefore costs two emissions (its value is constant in between), and
-// consecutive segments landing in the same slot are summed in registers
-// before any memory traffic.
-//
-// Work decomposition.  One lane owns one detector cell (256 cells per
-// workgroup, 4 wavefronts).  Trajectories are cut into runs of kRunL
-// segments; a tile of kTileP particles x (kRunL + 1) states is staged in LDS
-// (coalesced SoA loads, kinematics computed once per state) and every lane
-// walks the tile's states in order against its own cell, so the state data
-// is a wave-uniform LDS broadcast.  Runs are independent: a run of kRunL
-// segments needs its kRunL + 1 end states, so the state two runs share is
-// staged (and its arrival time evaluated) by both, and each segment belongs
-// to exactly one run.  Workgroups along the second grid dimension take
-// contiguous ranges of (run, particle block) tiles, so the same cells receive
-// deposits from several workgroups and the detector is updated with atomic
-// adds.
+// back into slot values with a prefix sum along the slots.  A segment
+// spanning many slots therefore costs two emissions (its value is constant
+// in between), and all emissions are additive, so the ring, its fallback and
+// the order of the particles only change rounding.
 #include "radio_internal.h"
 
 #include <type_traits>
@@ -35,6 +42,10 @@
 namespace radio {
 
 namespace {
+
+// pointers into LDS keep their address space, so ring updates compile to ds_*
+// instructions rather than generic (flat) ones
+#define RADIO_LDS __attribute__((address_space(3)))
 
 // ---------------------------------------------------------------------------
 // Quantities that cancel catastrophically.  Both this library and any
@@ -102,35 +113,22 @@ __device__ __forceinline__ void canon_kinematics(double u0, double u1, double u2
     *inv_g2 = 1.0 / g;
 }
 
+// betadot = (beta_s - beta_{s-1}) / dt
+__device__ __forceinline__ double canon_betadot(double b, double bp, double dt)
+{
+#pragma clang fp contract(off)
+    return (b - bp) / dt;
+}
+
+// ---------------------------------------------------------------------------
+// detector updates
 // ---------------------------------------------------------------------------
 
-struct StateRec {           // one staged trajectory state (96 B, 16-B aligned)
-    double x[3];
-    double b[3];
-    double bd[3];
-    double g2i;
-    float bdf[3];           // betadot and 1/gamma^2 rounded to single for the mixed field
-    float g2if;
-};
-
-// Where a lane's finished slot differences go.  Double path: one atomic add per
-// component.  Mixed path: a compensated single-precision pair (hi, lo) per
-// component; the atomic add on hi returns the old value, so the lane knows the
-// exact sum the hardware rounded (old + v) and adds that rounding error
+// Where a lane's finished slot differences go in HBM.  Double path: one atomic
+// add per component.  Mixed path: a compensated single-precision pair (hi, lo)
+// per component; the atomic add on hi returns the old value, so the lane knows
+// the exact sum the hardware rounded (old + v) and adds that rounding error
 // (two-sum) to lo.
-struct RowF64 {
-    double* p;  // [n_t][6]
-    __device__ __forceinline__ void flush(int n_t, int j, const double a[6]) const
-    {
-        if (j >= 0 && j < n_t) {
-            double* q = p + (int64_t)j * 6;
-#pragma unroll
-            for (int k = 0; k < 6; ++k)
-                unsafeAtomicAdd(q + k, a[k]);
-        }
-    }
-};
-
 __device__ __forceinline__ float two_sum_err(float a, float b, float s)
 {
 #pragma clang fp contract(off)
@@ -138,26 +136,120 @@ __device__ __forceinline__ float two_sum_err(float a, float b, float s)
     return (a - (s - bv)) + (b - bv);
 }
 
-struct RowMixed {
-    float* p;  // [n_t][12]: hi[6] then lo[6]
-    __device__ __forceinline__ void flush(int n_t, int j, const float a[6]) const
-    {
-        if (j >= 0 && j < n_t) {
-            float* q = p + (int64_t)j * 12;
+__device__ __forceinline__ void global_add(double* row, int j, const double a[6])
+{
+    double* q = row + (int64_t)j * 6;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                const float old = atomicAdd(q + k, a[k]);
-                unsafeAtomicAdd(q + 6 + k, two_sum_err(old, a[k], old + a[k]));
-            }
+    for (int k = 0; k < 6; ++k)
+        unsafeAtomicAdd(q + k, a[k]);
+}
+
+__device__ __forceinline__ void global_add(float* row, int j, const float a[6])
+{
+    float* q = row + (int64_t)j * 12;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        if (a[k] != 0.0f) {
+            const float old = atomicAdd(q + k, a[k]);
+            unsafeAtomicAdd(q + 6 + k, two_sum_err(old, a[k], old + a[k]));
+        }
+    }
+}
+
+// a compensated pair (hi, lo) into the HBM pair
+__device__ __forceinline__ void global_add_pair(float* row, int j, const float hi[6],
+                                                const float lo[6])
+{
+    float* q = row + (int64_t)j * 12;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        if (hi[k] != 0.0f || lo[k] != 0.0f) {
+            const float old = atomicAdd(q + k, hi[k]);
+            unsafeAtomicAdd(q + 6 + k, two_sum_err(old, hi[k], old + hi[k]) + lo[k]);
+        }
+    }
+}
+
+// One cell's ring of slots in LDS, covering slots [base, base + R); slot j lives
+// at position j mod R.  Emissions inside go to the ring (LDS atomic add: the
+// kGroups lanes of a cell share it), anything else straight to HBM.
+//
+// Double accumulation (Acc = double): 6 values per slot; the emission (double
+// or single) is widened and added.  Compensated single accumulation (Acc =
+// float): the pair hi[6], lo[6] per slot, updated like the HBM pair -- the LDS
+// atomic returns the old hi and the lane adds the rounding error of its own
+// add (two-sum) to lo.
+template <typename Acc>
+struct CellSink;
+
+template <>
+struct CellSink<double> {
+    static constexpr int R = RingSlots<double>::value;
+    static constexpr int W = 6;  // values per ring slot
+    RADIO_LDS double* ring;
+    double* row;
+    int base;
+    int n_t;
+    unsigned* n_bypass;
+    template <typename F>
+    __device__ __forceinline__ void flush(int, int j, const F a[6]) const
+    {
+        if (j < 0 || j >= n_t)
+            return;
+        double v[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            v[k] = (double)a[k];
+        if ((unsigned)(j - base) < (unsigned)R) {
+            RADIO_LDS double* q = ring + (j & (R - 1)) * W;
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                __hip_atomic_fetch_add(q + k, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+            *n_bypass += 1u;
+            global_add(row, j, v);
         }
     }
 };
 
-// A lane's open slot.  For the run being processed the lane integrates the
-// held field over its current slot J (V) and remembers the previous slot's
-// value (Vp); when the run leaves slot J the difference V - Vp is final and
-// goes to the detector, so every emitted number is a slot value difference,
-// with the same exact slot-unit overlaps as the integrator definition.
+template <>
+struct CellSink<float> {
+    static constexpr int R = RingSlots<float>::value;
+    static constexpr int W = 12;  // hi[6], lo[6]
+    RADIO_LDS float* ring;
+    float* row;
+    int base;
+    int n_t;
+    unsigned* n_bypass;
+    __device__ __forceinline__ void flush(int, int j, const float a[6]) const
+    {
+        if (j < 0 || j >= n_t)
+            return;
+        if ((unsigned)(j - base) < (unsigned)R) {
+            RADIO_LDS float* q = ring + (j & (R - 1)) * W;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const float old = __hip_atomic_fetch_add(q + k, a[k], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(q + 6 + k, two_sum_err(old, a[k], old + a[k]),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        } else {
+            *n_bypass += 1u;
+            global_add(row, j, a);
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// the lane's open slot
+// ---------------------------------------------------------------------------
+
+// For the run being processed the lane integrates the held field over its
+// current slot J (V) and remembers the previous slot's value (Vp); when the
+// run leaves slot J the difference V - Vp is final and is emitted, so every
+// emitted number is a slot value difference computed with the same exact
+// slot-unit overlaps as the integrator definition.
 template <typename T>
 struct Carry {
     int J;                  // current slot, -1 when nothing is open
@@ -177,8 +269,8 @@ __device__ __forceinline__ void carry_init(Carry<T>& C)
 }
 
 // Finish the open slot: its value difference, then the drop to zero after it.
-template <typename T, typename Row>
-__device__ __forceinline__ void carry_close(Carry<T>& C, const Row& row, int n_t)
+template <typename T, typename Sink>
+__device__ __forceinline__ void carry_close(Carry<T>& C, const Sink& sink, int n_t)
 {
     if (C.J >= 0) {
         T d[6], m[6];
@@ -187,8 +279,8 @@ __device__ __forceinline__ void carry_close(Carry<T>& C, const Row& row, int n_t
             d[k] = C.V[k] - C.Vp[k];
             m[k] = -C.V[k];
         }
-        row.flush(n_t, C.J, d);
-        row.flush(n_t, C.J + 1, m);
+        sink.flush(n_t, C.J, d);
+        sink.flush(n_t, C.J + 1, m);
     }
     carry_init(C);
 }
@@ -198,8 +290,8 @@ __device__ __forceinline__ void carry_close(Carry<T>& C, const Row& row, int n_t
 // outside [0, n_t) are dropped).  Segments normally continue where the last
 // one ended; any other start (a reversed or out-of-order segment) closes the
 // open slot and opens a new one, which is exact because deposits add.
-template <typename T, typename Row>
-__device__ __forceinline__ void add_segment(Carry<T>& C, const Row& row, int n_t, double a,
+template <typename T, typename Sink>
+__device__ __forceinline__ void add_segment(Carry<T>& C, const Sink& sink, int n_t, double a,
                                             double b, const T F[6])
 {
     const double ntd = (double)n_t;
@@ -210,7 +302,7 @@ __device__ __forceinline__ void add_segment(Carry<T>& C, const Row& row, int n_t
     const int jl = (int)floor(lo);  // lo < n_t
     const int jh = (int)floor(hi);  // <= n_t; n_t only when hi reaches the end
     if (jl != C.J) {
-        carry_close(C, row, n_t);
+        carry_close(C, sink, n_t);
         C.J = jl;
     }
     if (jh == C.J) {
@@ -228,14 +320,14 @@ __device__ __forceinline__ void add_segment(Carry<T>& C, const Row& row, int n_t
         d[k] = C.V[k] - C.Vp[k];
         C.Vp[k] = C.V[k];
     }
-    row.flush(n_t, C.J, d);
+    sink.flush(n_t, C.J, d);
     if (jh > C.J + 1) {  // whole slots in between hold F
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             d[k] = F[k] - C.Vp[k];
             C.Vp[k] = F[k];
         }
-        row.flush(n_t, C.J + 1, d);
+        sink.flush(n_t, C.J + 1, d);
     }
     const T wb = T(hi - (double)jh);
 #pragma unroll
@@ -243,6 +335,10 @@ __device__ __forceinline__ void add_segment(Carry<T>& C, const Row& row, int n_t
         C.V[k] = F[k] * wb;
     C.J = jh;
 }
+
+// ---------------------------------------------------------------------------
+// field evaluation
+// ---------------------------------------------------------------------------
 
 struct Consts {
     double t0, inv_dt_det, inv_c;
@@ -342,8 +438,7 @@ __device__ __forceinline__ double slot_coord_fp64(const double xc[3], const Stat
 {
     double d[3] = {xc[0] - st.x[0], xc[1] - st.x[1], xc[2] - st.x[2]};
     double R = __builtin_sqrt(canon_norm2(d[0], d[1], d[2]));
-    double tau = canon_arrival(t_s, R, K.inv_c);
-    return canon_slot(tau, K.t0, K.inv_dt_det);
+    return canon_slot(canon_arrival(t_s, R, K.inv_c), K.t0, K.inv_dt_det);
 }
 
 __device__ __forceinline__ double slot_coord_mixed(const double xc[3], const StateRec& st,
@@ -355,132 +450,290 @@ __device__ __forceinline__ double slot_coord_mixed(const double xc[3], const Sta
     return canon_slot(t_s + R * K.inv_c, K.t0, K.inv_dt_det);
 }
 
-// Stage the states s_a .. s_a+len of particles p0 .. p0+np-1 into LDS.
-__device__ __forceinline__ void stage_tile(const DepositJob& J, StateRec (*rec)[kRunL + 1],
-                                           double* sq, int64_t s_a, int len, int64_t p0, int np)
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+// One thread per (particle, state): the state record, particle-major.
+__global__ __launch_bounds__(256) void kinematics_kernel(const double* __restrict__ x,
+                                                         const double* __restrict__ u,
+                                                         int64_t n_p, int64_t n_s, double dt,
+                                                         StateRec* __restrict__ recs)
 {
-    const int tid = threadIdx.x;
-    const int64_t stride = (J.n_s + 1) * J.n_p;
-    for (int i = tid; i < kTileP * (kRunL + 1); i += kCellsPerBlock) {
-        const int pp = i % kTileP;
-        const int k = i / kTileP;
-        if (pp < np && k <= len) {
-            const int64_t off = (s_a + k) * J.n_p + (p0 + pp);
-            StateRec& r = rec[pp][k];
-            r.x[0] = J.x[off];
-            r.x[1] = J.x[off + stride];
-            r.x[2] = J.x[off + 2 * stride];
-            canon_kinematics(J.u[off], J.u[off + stride], J.u[off + 2 * stride], r.b, &r.g2i);
-            r.g2if = (float)r.g2i;
-        }
-    }
-    if (tid < kTileP)
-        sq[tid] = (tid < np) ? (J.q ? J.q[p0 + tid] : -1.0) : 0.0;
-    __syncthreads();
-    for (int i = tid; i < kTileP * kRunL; i += kCellsPerBlock) {
-        const int pp = i % kTileP;
-        const int k = 1 + i / kTileP;
-        if (pp < np && k <= len) {
-            StateRec& r = rec[pp][k];
-            const StateRec& rp = rec[pp][k - 1];
+    const int64_t n_states = n_s + 1;
+    const int64_t total = n_p * n_states;
+    const int64_t stride = n_states * n_p;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = i / n_p;  // consecutive threads read consecutive particles
+        const int64_t p = i - s * n_p;
+        const int64_t off = s * n_p + p;
+        StateRec r;
+        r.x[0] = x[off];
+        r.x[1] = x[off + stride];
+        r.x[2] = x[off + 2 * stride];
+        canon_kinematics(u[off], u[off + stride], u[off + 2 * stride], r.b, &r.g2i);
+        if (s > 0) {
+            double bp[3], gp;
+            const int64_t o2 = off - n_p;
+            canon_kinematics(u[o2], u[o2 + stride], u[o2 + 2 * stride], bp, &gp);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                r.bd[c] = (r.b[c] - rp.b[c]) / J.dt;
-                r.bdf[c] = (float)r.bd[c];
-            }
+            for (int c = 0; c < 3; ++c)
+                r.bd[c] = canon_betadot(r.b[c], bp[c], dt);
+        } else {
+            r.bd[0] = r.bd[1] = r.bd[2] = 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            r.bdf[c] = (float)r.bd[c];
+        r.g2if = (float)r.g2i;
+        recs[p * n_states + s] = r;
+    }
+}
+
+// Counting sort of the particles of one chunk, per tile, by the light-travel
+// distance from the tile's centre to each particle at state s_key, in bins of
+// one slot (widened if the spread needs more than kOrderBins).  perm[tile][i]
+// is the i-th particle in that order.
+constexpr int kOrderBins = 4096;
+
+__global__ __launch_bounds__(256) void order_kernel(const double* __restrict__ x, int64_t n_p,
+                                                    int64_t n_s, int64_t s_key,
+                                                    const double* __restrict__ cells, int64_t n_c,
+                                                    double inv_c, double inv_dt_det,
+                                                    int32_t* __restrict__ perm)
+{
+    __shared__ unsigned hist[kOrderBins];
+    __shared__ double red_lo[256], red_hi[256];
+    __shared__ double ctr[3];
+    const int tid = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const int64_t c0 = tile * kTileCells;
+    const int64_t c1 = min(c0 + (int64_t)kTileCells, n_c);
+    if (tid < 3) {
+        double s = 0.0;
+        for (int64_t c = c0; c < c1; ++c)
+            s += cells[3 * c + tid];
+        ctr[tid] = s / (double)(c1 - c0);
+    }
+    for (int i = tid; i < kOrderBins; i += 256)
+        hist[i] = 0u;
+    __syncthreads();
+    const int64_t stride = (n_s + 1) * n_p;
+    const int64_t base = s_key * n_p;
+    const double cx = ctr[0], cy = ctr[1], cz = ctr[2];
+    auto key = [&](int64_t p) {
+        const double d0 = cx - x[base + p];
+        const double d1 = cy - x[base + p + stride];
+        const double d2 = cz - x[base + p + 2 * stride];
+        return __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2) * (inv_c * inv_dt_det);
+    };
+    double lo = 1e300, hi = -1e300;
+    for (int64_t p = tid; p < n_p; p += 256) {
+        const double k = key(p);
+        if (k == k) {
+            lo = fmin(lo, k);
+            hi = fmax(hi, k);
+        }
+    }
+    red_lo[tid] = lo;
+    red_hi[tid] = hi;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            red_lo[tid] = fmin(red_lo[tid], red_lo[tid + s]);
+            red_hi[tid] = fmax(red_hi[tid], red_hi[tid + s]);
+        }
+        __syncthreads();
+    }
+    lo = red_lo[0];
+    hi = red_hi[0];
+    const double span = hi > lo ? hi - lo : 0.0;
+    const double width = span < (double)(kOrderBins - 1) ? 1.0 : span / (double)(kOrderBins - 1);
+    auto bin_of = [&](int64_t p) {
+        const double k = key(p);
+        double b = (k - lo) / width;
+        b = (b == b) ? fmin(fmax(b, 0.0), (double)(kOrderBins - 1)) : (double)(kOrderBins - 1);
+        return (int)b;
+    };
+    for (int64_t p = tid; p < n_p; p += 256)
+        atomicAdd(&hist[bin_of(p)], 1u);
+    __syncthreads();
+    if (tid == 0) {  // exclusive scan (4096 entries, once per tile)
+        unsigned run = 0;
+        for (int i = 0; i < kOrderBins; ++i) {
+            const unsigned h = hist[i];
+            hist[i] = run;
+            run += h;
         }
     }
     __syncthreads();
-}
-
-// One particle's run against one cell: the fields of states 1..len, each held
-// between the arrival times of its segment's two end states.
-template <bool MIX>
-__device__ __forceinline__ void run_particle(const double xc[3], const StateRec* st, int len,
-                                             int64_t s_a, double q, const DepositJob& J,
-                                             const Consts& K, double* acc_row, int n_t,
-                                             unsigned& n_clip, unsigned& n_back)
-{
-    using T = typename std::conditional<MIX, float, double>::type;
-    using Row = typename std::conditional<MIX, RowMixed, RowF64>::type;
-    Row row{reinterpret_cast<T*>(acc_row)};
-    Carry<T> C;
-    carry_init(C);
-    const double t_a = canon_state_time(J.t_first, s_a, J.dt);
-    double u_prev = MIX ? slot_coord_mixed(xc, st[0], t_a, K) : slot_coord_fp64(xc, st[0], t_a, K);
-    for (int k = 1; k <= len; ++k) {
-        T F[6];
-        const double t_s = canon_state_time(J.t_first, s_a + k, J.dt);
-        double uk;
-        if constexpr (MIX)
-            uk = field_mixed(xc, st[k], t_s, (float)q, K, F);
-        else
-            uk = field_fp64(xc, st[k], t_s, q, K, F);
-        const bool back = uk < u_prev;
-        n_back += back ? 1u : 0u;
-        n_clip += (fmin(uk, u_prev) < 0.0 || fmax(uk, u_prev) > (double)n_t) ? 1u : 0u;
-        add_segment(C, row, n_t, u_prev, uk, F);
-        u_prev = uk;
+    int32_t* out = perm + tile * n_p;
+    for (int64_t p = tid; p < n_p; p += 256) {
+        const unsigned pos = atomicAdd(&hist[bin_of(p)], 1u);
+        out[pos] = (int32_t)p;
     }
-    carry_close(C, row, n_t);
 }
 
-template <bool MIX>
-__global__ __launch_bounds__(kCellsPerBlock) void deposit_kernel(DepositJob J)
+// M: arithmetic of the deposit (field in double or single; accumulation in
+// double or compensated single pairs)
+template <int M>
+__global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
 {
-    __shared__ StateRec rec[kTileP][kRunL + 1];
-    __shared__ double sq[kTileP];
-    __shared__ unsigned long long s_cnt[2];
+    constexpr bool MIX = (M != kModeF64);
+    using T = typename std::conditional<MIX, float, double>::type;  // field and lane carry
+    using Acc = typename std::conditional<M == kModeMixTwoSum, float, double>::type;
+    using Sink = CellSink<Acc>;
+    constexpr int R = Sink::R;
+    constexpr int RW = Sink::W;
+    __shared__ __align__(16) StateRec rec[kGroups][kRunL + 1];
+    __shared__ double sq[kGroups];
+    __shared__ Acc ring[kTileCells][R][RW];
+    __shared__ unsigned long long s_cnt[3];
 
     const int tid = threadIdx.x;
-    const int64_t cb = blockIdx.x % J.cell_blocks;
-    const int64_t split = blockIdx.x / J.cell_blocks;
-    const int64_t cell = cb * kCellsPerBlock + tid;
-    const bool active = cell < J.n_c;
+    const int cl = tid / kGroups;  // cell within the tile
+    const int g = tid % kGroups;   // particle group
+    const int64_t tile = blockIdx.x % J.n_tiles;
+    const int64_t split = blockIdx.x / J.n_tiles;
+    const int64_t row_i = tile * kTileCells + cl;  // internal (tile-ordered) cell row
+    const bool active = row_i < J.n_c;
     const int n_t = (int)J.n_t;
     const Consts K{J.t0, J.inv_dt_det, J.inv_c, (float)J.inv_c};
     double xc[3] = {0.0, 0.0, 0.0};
-    double* row = nullptr;
+    Acc* row = nullptr;
     if (active) {
-        xc[0] = J.cells[3 * cell];
-        xc[1] = J.cells[3 * cell + 1];
-        xc[2] = J.cells[3 * cell + 2];
-        row = J.acc + cell * J.n_t * 6;  // 6 doubles or 12 floats per slot
+        xc[0] = J.cells[3 * row_i];
+        xc[1] = J.cells[3 * row_i + 1];
+        xc[2] = J.cells[3 * row_i + 2];
+        row = reinterpret_cast<Acc*>(J.acc + row_i * J.n_t * 6);
     }
-    if (tid < 2)
+    RADIO_LDS Acc* my_ring = (RADIO_LDS Acc*)&ring[cl][0][0];
+    for (int i = g; i < R * RW; i += kGroups)
+        my_ring[i] = Acc(0);
+    if (tid < 3)
         s_cnt[tid] = 0;
-    unsigned n_clip = 0, n_back = 0;
+    int base = -1;  // ring covers [base, base + R); -1 until the first batch
+    unsigned n_clip = 0, n_back = 0, n_bypass = 0;
+    const int32_t* order = J.perm + tile * J.n_p;
+    const int64_t n_states = J.n_s + 1;
+    const int64_t n_batches = (J.n_p + kGroups - 1) / kGroups;
 
-    const int64_t tile_begin = split * J.tiles_per_split;
-    const int64_t tile_end = min(tile_begin + J.tiles_per_split, J.n_tiles);
-    for (int64_t tile = tile_begin; tile < tile_end; ++tile) {
-        const int64_t run = tile / J.n_pb;
-        const int64_t pb = tile - run * J.n_pb;
-        const int64_t s_a = run * kRunL;
+    // Move the ring to start at new_base: slots leaving it go to HBM.  Only the
+    // cell's own kGroups lanes (one wavefront) touch its ring.
+    auto move_ring = [&](int new_base) {
+        if (base >= 0 && active) {
+            int lo = base, hi = base + R;  // slots to flush
+            if (new_base > base && new_base < base + R)
+                hi = new_base;
+            for (int j = lo + g; j < hi; j += kGroups) {
+                RADIO_LDS Acc* q = my_ring + (j & (R - 1)) * RW;
+                Acc a[RW];
+                bool nz = false;
+#pragma unroll
+                for (int k = 0; k < RW; ++k) {
+                    a[k] = q[k];
+                    q[k] = Acc(0);
+                    nz |= (a[k] != Acc(0));
+                }
+                if (nz && j < n_t) {
+                    if constexpr (M == kModeMixTwoSum)
+                        global_add_pair(row, j, a, a + 6);
+                    else
+                        global_add(row, j, a);
+                }
+            }
+        }
+        base = new_base;
+    };
+
+    const int64_t rb_begin = split * J.runs_per_split;
+    const int64_t rb_end = min(rb_begin + J.runs_per_split, J.n_runs);
+    for (int64_t rb = rb_begin; rb < rb_end; ++rb) {
+        const int64_t s_a = rb * kRunL;
         const int len = (int)min((int64_t)kRunL, J.n_s - s_a);
-        const int64_t p0 = pb * kTileP;
-        const int np = (int)min((int64_t)kTileP, J.n_p - p0);
-        __syncthreads();  // the previous tile's readers are done with the LDS
-        stage_tile(J, rec, sq, s_a, len, p0, np);
-        if (active) {
-            for (int pp = 0; pp < np; ++pp)
-                run_particle<MIX>(xc, rec[pp], len, s_a, sq[pp], J, K, row, n_t, n_clip, n_back);
+        const double t_a = canon_state_time(J.t_first, s_a, J.dt);
+        for (int64_t bt = 0; bt < n_batches; ++bt) {
+            const int64_t i0 = bt * kGroups;
+            const int np = (int)min((int64_t)kGroups, J.n_p - i0);
+            __syncthreads();  // the previous batch's readers are done with the LDS
+            // stage: particle order[i0 + gg], states s_a .. s_a + len (contiguous)
+            {
+                constexpr int kChunks = (int)(sizeof(StateRec) / 16);  // 16-byte pieces
+                const int per = (len + 1) * kChunks;
+                for (int i = tid; i < kGroups * per; i += kDepositThreads) {
+                    const int gg = i / per;
+                    const int r = i - gg * per;
+                    if (gg < np) {
+                        const int64_t p = order[i0 + gg];
+                        const int4* src =
+                            reinterpret_cast<const int4*>(J.recs + p * n_states + s_a) + r;
+                        reinterpret_cast<int4*>(&rec[gg][0])[r] = *src;
+                    }
+                }
+                if (tid < kGroups)
+                    sq[tid] = (tid < np) ? (J.q ? J.q[order[i0 + tid]] : -1.0) : 0.0;
+            }
+            __syncthreads();
+            const bool mine = active && g < np;
+            double u_prev = 1e300;
+            if (mine)
+                u_prev = MIX ? slot_coord_mixed(xc, rec[g][0], t_a, K)
+                             : slot_coord_fp64(xc, rec[g][0], t_a, K);
+            // ring start for this batch: the earliest start among the cell's lanes
+            double m = u_prev;
+#pragma unroll
+            for (int off = kGroups / 2; off > 0; off >>= 1)
+                m = fmin(m, __shfl_xor(m, off, kGroups));
+            if (m < 1e299) {
+                const double mc = fmin(fmax(floor(m) - (double)kRingMargin, 0.0),
+                                       fmax((double)(n_t - R), 0.0));
+                const int nb = (int)mc;
+                if (nb != base)
+                    move_ring(nb);
+            }
+            if (mine) {
+                Sink sink{my_ring, row, base, n_t, &n_bypass};
+                Carry<T> C;
+                carry_init(C);
+                const double q = sq[g];
+                for (int k = 1; k <= len; ++k) {
+                    T F[6];
+                    const double t_s = canon_state_time(J.t_first, s_a + k, J.dt);
+                    double uk;
+                    if constexpr (MIX)
+                        uk = field_mixed(xc, rec[g][k], t_s, (float)q, K, F);
+                    else
+                        uk = field_fp64(xc, rec[g][k], t_s, q, K, F);
+                    const bool back = uk < u_prev;
+                    n_back += back ? 1u : 0u;
+                    n_clip += (fmin(uk, u_prev) < 0.0 || fmax(uk, u_prev) > (double)n_t) ? 1u : 0u;
+                    add_segment(C, sink, n_t, u_prev, uk, F);
+                    u_prev = uk;
+                }
+                carry_close(C, sink, n_t);
+            }
         }
     }
+    move_ring(-1);  // flush what the ring still holds
     if (n_clip)
         atomicAdd(&s_cnt[0], (unsigned long long)n_clip);
     if (n_back)
         atomicAdd(&s_cnt[1], (unsigned long long)n_back);
+    if (n_bypass)
+        atomicAdd(&s_cnt[2], (unsigned long long)n_bypass);
     __syncthreads();
-    if (tid < 2 && s_cnt[tid])
+    if (tid < 3 && s_cnt[tid])
         atomicAdd(&J.counters[tid], s_cnt[tid]);
 }
 
 // Prefix sum of the slot differences along the slots of each cell; writes
-// E[c][j][0..2] and B[c][j][0..2].  One workgroup per cell.  The mixed
-// accumulator holds (hi, lo) single pairs, folded to double before the sum.
-template <bool MIX>
+// E[c][j][0..2] and B[c][j][0..2] for the caller's cell index c of internal
+// row r.  One workgroup per cell.  The mixed accumulator holds (hi, lo)
+// single pairs, folded to double before the sum.
+template <bool PAIRS>
 __global__ __launch_bounds__(256) void readout_kernel(const double* __restrict__ acc, int64_t n_t,
+                                                      const int64_t* __restrict__ user_index,
                                                       double* __restrict__ E,
                                                       double* __restrict__ B)
 {
@@ -488,17 +741,18 @@ __global__ __launch_bounds__(256) void readout_kernel(const double* __restrict__
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int64_t cell = blockIdx.x;
-    const double* rowp = acc + cell * n_t * 6;
+    const int64_t r = blockIdx.x;
+    const int64_t cell = user_index[r];
+    const double* rowp = acc + r * n_t * 6;
     const float* rowf = reinterpret_cast<const float*>(rowp);
     double carry[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t base = 0; base < n_t; base += 256) {
-        const int64_t j = base + tid;
+    for (int64_t b0 = 0; b0 < n_t; b0 += 256) {
+        const int64_t j = b0 + tid;
         double v[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             if (j < n_t)
-                v[k] = MIX ? (double)rowf[j * 12 + k] + (double)rowf[j * 12 + 6 + k]
+                v[k] = PAIRS ? (double)rowf[j * 12 + k] + (double)rowf[j * 12 + 6 + k]
                            : rowp[j * 6 + k];
             else
                 v[k] = 0.0;
@@ -577,17 +831,15 @@ __global__ void arrival_kernel(const double* cells, const double* pts, const dou
 
 void plan_job(DepositJob& job, int target_blocks)
 {
-    const int64_t n_runs = (job.n_s + kRunL - 1) / kRunL;
-    job.n_pb = (job.n_p + kTileP - 1) / kTileP;
-    job.n_tiles = n_runs * job.n_pb;
-    job.cell_blocks = (job.n_c + kCellsPerBlock - 1) / kCellsPerBlock;
-    int64_t splits = (target_blocks + job.cell_blocks - 1) / job.cell_blocks;
+    job.n_runs = (job.n_s + kRunL - 1) / kRunL;
+    job.n_tiles = (job.n_c + kTileCells - 1) / kTileCells;
+    int64_t splits = (target_blocks + job.n_tiles - 1) / job.n_tiles;
     if (splits < 1)
         splits = 1;
-    if (splits > job.n_tiles)
-        splits = job.n_tiles;
-    job.tiles_per_split = (job.n_tiles + splits - 1) / splits;
-    job.n_splits = (job.n_tiles + job.tiles_per_split - 1) / job.tiles_per_split;
+    if (splits > job.n_runs)
+        splits = job.n_runs;
+    job.runs_per_split = (job.n_runs + splits - 1) / splits;
+    job.n_splits = (job.n_runs + job.runs_per_split - 1) / job.runs_per_split;
 }
 
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s)
@@ -609,37 +861,51 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_deposit_fp64(const DepositJob& job, hipStream_t s)
+hipError_t launch_kinematics(const DepositJob& job, hipStream_t s)
 {
-    const int64_t blocks = job.cell_blocks * job.n_splits;
-    if (blocks <= 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(deposit_kernel<false>, dim3((unsigned)blocks), dim3(kCellsPerBlock), 0, s,
-                       job);
+    const int64_t total = job.n_p * (job.n_s + 1);
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536)
+        blocks = 65536;
+    hipLaunchKernelGGL(kinematics_kernel, dim3((unsigned)blocks), dim3(256), 0, s, job.x, job.u,
+                       job.n_p, job.n_s, job.dt, job.recs);
     return hipGetLastError();
 }
 
-hipError_t launch_deposit_mixed(const DepositJob& job, hipStream_t s)
+hipError_t launch_order(const DepositJob& job, hipStream_t s)
 {
-    const int64_t blocks = job.cell_blocks * job.n_splits;
-    if (blocks <= 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(deposit_kernel<true>, dim3((unsigned)blocks), dim3(kCellsPerBlock), 0, s,
-                       job);
+    hipLaunchKernelGGL(order_kernel, dim3((unsigned)job.n_tiles), dim3(256), 0, s, job.x, job.n_p,
+                       job.n_s, job.n_s / 2, job.cells, job.n_c, job.inv_c, job.inv_dt_det,
+                       job.perm);
     return hipGetLastError();
 }
 
-hipError_t launch_readout(const double* acc, int64_t n_c, int64_t n_t, bool mixed, double* E,
-                          double* B, hipStream_t s)
+hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s)
+{
+    const int64_t blocks = job.n_tiles * job.n_splits;
+    if (blocks <= 0)
+        return hipSuccess;
+    const dim3 grid((unsigned)blocks), block(kDepositThreads);
+    if (mode == kModeMix)
+        hipLaunchKernelGGL(deposit_kernel<kModeMix>, grid, block, 0, s, job);
+    else if (mode == kModeMixTwoSum)
+        hipLaunchKernelGGL(deposit_kernel<kModeMixTwoSum>, grid, block, 0, s, job);
+    else
+        hipLaunchKernelGGL(deposit_kernel<kModeF64>, grid, block, 0, s, job);
+    return hipGetLastError();
+}
+
+hipError_t launch_readout(const double* acc, int64_t n_c, int64_t n_t, const int64_t* user_index,
+                          bool pairs, double* E, double* B, hipStream_t s)
 {
     if (n_c <= 0)
         return hipSuccess;
-    if (mixed)
-        hipLaunchKernelGGL(readout_kernel<true>, dim3((unsigned)n_c), dim3(256), 0, s, acc, n_t, E,
-                           B);
+    if (pairs)
+        hipLaunchKernelGGL(readout_kernel<true>, dim3((unsigned)n_c), dim3(256), 0, s, acc, n_t,
+                           user_index, E, B);
     else
-        hipLaunchKernelGGL(readout_kernel<false>, dim3((unsigned)n_c), dim3(256), 0, s, acc, n_t, E,
-                           B);
+        hipLaunchKernelGGL(readout_kernel<false>, dim3((unsigned)n_c), dim3(256), 0, s, acc, n_t,
+                           user_index, E, B);
     return hipGetLastError();
 }
 

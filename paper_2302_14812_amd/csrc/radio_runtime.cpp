@@ -6,9 +6,11 @@
 // kernels on the caller's stream.
 #include "radio.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <numeric>
 #include <vector>
 
 #include "radio_internal.h"
@@ -21,13 +23,22 @@ struct radio_detector {
     double t0 = 0.0;
     double dt_det = 1.0;
     double c = 1.0;
-    double* d_cells = nullptr;
+    double* d_cells = nullptr;        // internal (tile-ordered) rows
+    int64_t* d_user_index = nullptr;  // internal row -> caller's cell index
     double* d_acc = nullptr;
-    unsigned long long* d_counters = nullptr;  // [2] clipped, nonmonotone
+    unsigned long long* d_counters = nullptr;  // [3] clipped, nonmonotone, ring bypasses
+    radio::StateRec* d_recs = nullptr;         // workspace, grown on demand
+    size_t recs_cap = 0;                       // in records
+    int32_t* d_perm = nullptr;                 // workspace, grown on demand
+    size_t perm_cap = 0;                       // in entries
     int64_t interactions = 0;
     int64_t chunks = 0;
-    std::vector<double> h_cells;
+    std::vector<double> h_cells;               // caller's order
 };
+
+static_assert(RADIO_FP64 == radio::kModeF64 && RADIO_MIXED == radio::kModeMix &&
+                  RADIO_MIXED_TWOSUM == radio::kModeMixTwoSum,
+              "precision codes double as kernel modes");
 
 namespace {
 
@@ -111,6 +122,77 @@ int build_cells(const radio_detector_desc& d, std::vector<double>& out)
     return RADIO_EINVAL;
 }
 
+// Order the cells so that tiles of consecutive rows are compact in direction
+// (as seen from the origin, where the radiating particles are expected): a
+// Morton code of each cell's direction projected on the plane normal to the
+// mean direction.  Cells with similar directions see similar arrival-time
+// offsets between particles, which is what the deposit's slot rings rely on.
+std::vector<int64_t> order_cells(const std::vector<double>& cells)
+{
+    const int64_t n = (int64_t)(cells.size() / 3);
+    std::vector<double> dir(3 * n, 0.0);
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i) {
+        const double* c = &cells[3 * i];
+        const double l = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        if (l > 0.0)
+            for (int k = 0; k < 3; ++k) {
+                dir[3 * i + k] = c[k] / l;
+                m[k] += c[k] / l;
+            }
+    }
+    double lm = norm3(m);
+    if (!(lm > 1e-12 * (double)n)) {
+        m[0] = 0.0;
+        m[1] = 0.0;
+        m[2] = 1.0;
+        lm = 1.0;
+    }
+    for (double& v : m)
+        v /= lm;
+    // e1 orthogonal to m, e2 = m x e1
+    double t[3] = {1.0, 0.0, 0.0};
+    if (std::fabs(m[0]) > 0.9) {
+        t[0] = 0.0;
+        t[1] = 1.0;
+    }
+    const double pr = t[0] * m[0] + t[1] * m[1] + t[2] * m[2];
+    double e1[3] = {t[0] - pr * m[0], t[1] - pr * m[1], t[2] - pr * m[2]};
+    const double l1 = norm3(e1);
+    for (double& v : e1)
+        v /= l1;
+    const double e2[3] = {m[1] * e1[2] - m[2] * e1[1], m[2] * e1[0] - m[0] * e1[2],
+                          m[0] * e1[1] - m[1] * e1[0]};
+    std::vector<double> a(n), b(n);
+    double amin = 1e300, amax = -1e300, bmin = 1e300, bmax = -1e300;
+    for (int64_t i = 0; i < n; ++i) {
+        const double* d = &dir[3 * i];
+        a[i] = d[0] * e1[0] + d[1] * e1[1] + d[2] * e1[2];
+        b[i] = d[0] * e2[0] + d[1] * e2[1] + d[2] * e2[2];
+        amin = std::min(amin, a[i]);
+        amax = std::max(amax, a[i]);
+        bmin = std::min(bmin, b[i]);
+        bmax = std::max(bmax, b[i]);
+    }
+    const double sa = amax > amin ? 65535.0 / (amax - amin) : 0.0;
+    const double sb = bmax > bmin ? 65535.0 / (bmax - bmin) : 0.0;
+    std::vector<uint64_t> code(n);
+    for (int64_t i = 0; i < n; ++i) {
+        const uint32_t qa = (uint32_t)std::lround((a[i] - amin) * sa);
+        const uint32_t qb = (uint32_t)std::lround((b[i] - bmin) * sb);
+        uint64_t c = 0;
+        for (int bit = 0; bit < 16; ++bit)
+            c |= ((uint64_t)((qa >> bit) & 1u) << (2 * bit)) |
+                 ((uint64_t)((qb >> bit) & 1u) << (2 * bit + 1));
+        code[i] = c;
+    }
+    std::vector<int64_t> idx(n);
+    std::iota(idx.begin(), idx.end(), (int64_t)0);
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](int64_t x, int64_t y) { return code[x] < code[y]; });
+    return idx;
+}
+
 // Make det's device current for the duration of a call, restoring the caller's.
 class DeviceGuard {
   public:
@@ -179,6 +261,51 @@ radio::DepositJob make_job(radio_detector* det, const radio_chunk* k)
     return J;
 }
 
+// Grow a device workspace to hold at least `need` elements (the device is
+// synchronised before an old buffer is released).
+template <typename T>
+int grow(T** p, size_t* cap, size_t need)
+{
+    if (need <= *cap)
+        return RADIO_OK;
+    if (*p) {
+        if (hipDeviceSynchronize() != hipSuccess)
+            return RADIO_EDEVICE;
+        (void)hipFree(*p);
+        *p = nullptr;
+        *cap = 0;
+    }
+    if (hipMalloc((void**)p, need * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return RADIO_ENOMEM;
+    }
+    *cap = need;
+    return RADIO_OK;
+}
+
+int enqueue_deposit(radio_detector* det, const radio_chunk* k, hipStream_t s)
+{
+    if (k->n_particles == 0 || k->n_steps == 0)
+        return RADIO_OK;
+    if (k->n_particles > INT32_MAX)
+        return RADIO_EINVAL;
+    radio::DepositJob J = make_job(det, k);
+    int rc = grow(&det->d_recs, &det->recs_cap, (size_t)(J.n_p * (J.n_s + 1)));
+    if (rc != RADIO_OK)
+        return rc;
+    rc = grow(&det->d_perm, &det->perm_cap, (size_t)(J.n_tiles * J.n_p));
+    if (rc != RADIO_OK)
+        return rc;
+    J.recs = det->d_recs;
+    J.perm = det->d_perm;
+    if (radio::launch_kinematics(J, s) != hipSuccess || radio::launch_order(J, s) != hipSuccess ||
+        radio::launch_deposit(J, det->precision, s) != hipSuccess)
+        return RADIO_EDEVICE;
+    det->interactions += k->n_particles * k->n_steps * det->n_c;
+    return RADIO_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -205,7 +332,8 @@ int radio_detector_create(const radio_detector_desc* desc, void* stream, radio_d
 {
     if (!desc || !out)
         return RADIO_EINVAL;
-    if (desc->precision != RADIO_FP64 && desc->precision != RADIO_MIXED)
+    if (desc->precision != RADIO_FP64 && desc->precision != RADIO_MIXED &&
+        desc->precision != RADIO_MIXED_TWOSUM)
         return RADIO_EINVAL;
     if (!std::isfinite(desc->t0) || !std::isfinite(desc->dt_det) || !(desc->dt_det > 0.0) ||
         !std::isfinite(1.0 / desc->dt_det))
@@ -237,6 +365,11 @@ int radio_detector_create(const radio_detector_desc* desc, void* stream, radio_d
     det->c = desc->c;
     det->h_cells.swap(cells);
     hipStream_t s = (hipStream_t)stream;
+    const std::vector<int64_t> user = order_cells(det->h_cells);
+    std::vector<double> internal((size_t)(3 * n_c));
+    for (int64_t r = 0; r < n_c; ++r)
+        for (int k = 0; k < 3; ++k)
+            internal[(size_t)(3 * r + k)] = det->h_cells[(size_t)(3 * user[(size_t)r] + k)];
     const size_t acc_bytes = (size_t)n_c * (size_t)det->n_t * 6 * sizeof(double);
     if (hipMalloc((void**)&det->d_acc, acc_bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -244,16 +377,19 @@ int radio_detector_create(const radio_detector_desc* desc, void* stream, radio_d
         return RADIO_ENOMEM;
     }
     if (hipMalloc((void**)&det->d_cells, (size_t)n_c * 3 * sizeof(double)) != hipSuccess ||
-        hipMalloc((void**)&det->d_counters, 2 * sizeof(unsigned long long)) != hipSuccess) {
+        hipMalloc((void**)&det->d_user_index, (size_t)n_c * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc((void**)&det->d_counters, 3 * sizeof(unsigned long long)) != hipSuccess) {
         (void)hipGetLastError();
         radio_detector_destroy(det);
         return RADIO_ENOMEM;
     }
-    if (hipMemcpyAsync(det->d_cells, det->h_cells.data(), (size_t)n_c * 3 * sizeof(double),
+    if (hipMemcpyAsync(det->d_cells, internal.data(), (size_t)n_c * 3 * sizeof(double),
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(det->d_user_index, user.data(), (size_t)n_c * sizeof(int64_t),
                        hipMemcpyHostToDevice, s) != hipSuccess ||
         radio::launch_zero(det->d_acc, n_c * det->n_t * 6, s) != hipSuccess ||
-        radio::launch_zero_u64(det->d_counters, 2, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {  // h_cells is pageable: finish the copy
+        radio::launch_zero_u64(det->d_counters, 3, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {  // the host vectors are pageable: finish
         radio_detector_destroy(det);
         return RADIO_EDEVICE;
     }
@@ -276,8 +412,14 @@ int radio_detector_destroy(radio_detector* det)
             (void)hipFree(det->d_acc);
         if (det->d_cells)
             (void)hipFree(det->d_cells);
+        if (det->d_user_index)
+            (void)hipFree(det->d_user_index);
         if (det->d_counters)
             (void)hipFree(det->d_counters);
+        if (det->d_recs)
+            (void)hipFree(det->d_recs);
+        if (det->d_perm)
+            (void)hipFree(det->d_perm);
     }
     delete det;
     return rc;
@@ -292,23 +434,10 @@ int radio_detector_reset(radio_detector* det, void* stream)
         return RADIO_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
     if (radio::launch_zero(det->d_acc, det->n_c * det->n_t * 6, s) != hipSuccess ||
-        radio::launch_zero_u64(det->d_counters, 2, s) != hipSuccess)
+        radio::launch_zero_u64(det->d_counters, 3, s) != hipSuccess)
         return RADIO_EDEVICE;
     det->interactions = 0;
     det->chunks = 0;
-    return RADIO_OK;
-}
-
-static int enqueue_deposit(radio_detector* det, const radio_chunk* k, hipStream_t s)
-{
-    if (k->n_particles == 0 || k->n_steps == 0)
-        return RADIO_OK;
-    radio::DepositJob J = make_job(det, k);
-    hipError_t e = det->precision == RADIO_MIXED ? radio::launch_deposit_mixed(J, s)
-                                                 : radio::launch_deposit_fp64(J, s);
-    if (e != hipSuccess)
-        return RADIO_EDEVICE;
-    det->interactions += k->n_particles * k->n_steps * det->n_c;
     return RADIO_OK;
 }
 
@@ -366,7 +495,8 @@ int radio_read_detector(const radio_detector* det, double* E, double* B, void* s
     DeviceGuard g(det->device);
     if (!g.ok())
         return RADIO_EDEVICE;
-    if (radio::launch_readout(det->d_acc, det->n_c, det->n_t, det->precision == RADIO_MIXED, E, B,
+    if (radio::launch_readout(det->d_acc, det->n_c, det->n_t, det->d_user_index,
+                              det->precision == RADIO_MIXED_TWOSUM, E, B,
                               (hipStream_t)stream) != hipSuccess)
         return RADIO_EDEVICE;
     return RADIO_OK;
@@ -379,17 +509,21 @@ int radio_detector_stats(const radio_detector* det, radio_stats* out)
     DeviceGuard g(det->device);
     if (!g.ok())
         return RADIO_EDEVICE;
-    unsigned long long cnt[2] = {0, 0};
+    unsigned long long cnt[3] = {0, 0, 0};
     if (hipDeviceSynchronize() != hipSuccess ||
         hipMemcpy(cnt, det->d_counters, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess)
         return RADIO_EDEVICE;
     out->interactions = det->interactions;
     out->clipped = (int64_t)cnt[0];
     out->nonmonotone = (int64_t)cnt[1];
+    out->bypassed = (int64_t)cnt[2];
     out->chunks = det->chunks;
     out->bytes = (int64_t)(det->n_c * det->n_t * 6 * (int64_t)sizeof(double) +
                            det->n_c * 3 * (int64_t)sizeof(double) +
-                           2 * (int64_t)sizeof(unsigned long long));
+                           det->n_c * (int64_t)sizeof(int64_t) +
+                           3 * (int64_t)sizeof(unsigned long long) +
+                           (int64_t)(det->recs_cap * sizeof(radio::StateRec)) +
+                           (int64_t)(det->perm_cap * sizeof(int32_t)));
     return RADIO_OK;
 }
 

@@ -18,8 +18,8 @@ pytestmark = pytest.mark.gpu
 
 TOL_FP64 = 1e-12
 TOL_MIXED = 1e-5
-TOLS = {"fp64": TOL_FP64, "mixed": TOL_MIXED}
-PRECISIONS = pytest.mark.parametrize("precision", ["fp64", "mixed"])
+TOLS = {"fp64": TOL_FP64, "mixed": TOL_MIXED, "mixed_twosum": TOL_MIXED}
+PRECISIONS = pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_twosum"])
 
 
 @pytest.fixture(scope="module")
