@@ -39,6 +39,9 @@ def parse():
                     help="also time the compensated single-precision accumulation")
     ap.add_argument("--cpu-cells", type=int, default=0,
                     help="cells in the oracle sample (default: two per host thread)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device-to-device copy (reference for "
+                         "the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -116,6 +119,16 @@ def main():
     chunk_dev = radio.Chunk.from_numpy(wl.chunk)
     torch.cuda.synchronize()
     inter = wl.interactions
+
+    if args.calibrate_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] copied 1 GiB device to device (counter calibration)", file=sys.stderr,
+              flush=True)
+        del src, dst
 
     legs = {}
     order = [args.precision] + ([] if args.no_fp64 or args.precision == "fp64" else ["fp64"])

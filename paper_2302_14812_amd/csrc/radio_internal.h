@@ -35,16 +35,19 @@ constexpr int kRunL = 16;                               // segments per run
 constexpr int kRingMargin = 2;                          // ring slots kept below a batch's start
 
 // slots per cell in the LDS ring (a power of two): 48 B per slot for both
-// paths (6 doubles, or 6 compensated single pairs), 24.6 KB per workgroup
+// paths (6 doubles, or 6 compensated single pairs)
+#ifndef RADIO_RING_SLOTS
+#define RADIO_RING_SLOTS 16
+#endif
 template <typename T>
 struct RingSlots;
 template <>
 struct RingSlots<double> {
-    static constexpr int value = 32;
+    static constexpr int value = RADIO_RING_SLOTS;
 };
 template <>
 struct RingSlots<float> {
-    static constexpr int value = 32;
+    static constexpr int value = RADIO_RING_SLOTS;
 };
 
 // One (detector, chunk) deposit as the kernels see it.  Sizes are 64-bit; the

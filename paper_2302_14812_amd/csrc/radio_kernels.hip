@@ -60,7 +60,7 @@ __device__ __forceinline__ double canon_norm2(double a, double b, double c)
     return (a * a + b * b) + c * c;
 }
 
-__device__ __forceinline__ double canon_state_time(double t_first, int64_t s, double dt)
+__device__ __forceinline__ double canon_state_time(double t_first, int s, double dt)
 {
 #pragma clang fp contract(off)
     return t_first + (double)s * dt;
@@ -345,6 +345,17 @@ struct Consts {
     float inv_cf;
 };
 
+// 1/x from the hardware reciprocal refined by two Newton steps (within an ulp
+// or two; used where Eq. 1 needs no particular rounding)
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // Lienard-Wiechert E, B (Eq. 1) at a cell from one staged state, all in double;
 // returns the state's slot coordinate.  Everything after the canonical part may
 // use FMAs.
@@ -359,7 +370,7 @@ __device__ __forceinline__ double field_fp64(const double xc[3], const StateRec&
     double n[3], w[3];
     canon_direction(d, rinv, st.b, n, w);
     double kap = canon_kappa(w, st.g2i);
-    double k3inv = 1.0 / (kap * kap * kap);
+    double k3inv = recip(kap * kap * kap);
     double ca = q * k3inv * rinv * K.inv_c;        // (q/c) / (kappa^3 R)
     double cv = q * st.g2i * k3inv * rinv * rinv;  // q / (gamma^2 kappa^3 R^2)
     // w x betadot, then n x (w x betadot)
@@ -652,7 +663,7 @@ __global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
     for (int64_t rb = rb_begin; rb < rb_end; ++rb) {
         const int64_t s_a = rb * kRunL;
         const int len = (int)min((int64_t)kRunL, J.n_s - s_a);
-        const double t_a = canon_state_time(J.t_first, s_a, J.dt);
+        const double t_a = canon_state_time(J.t_first, (int)s_a, J.dt);
         for (int64_t bt = 0; bt < n_batches; ++bt) {
             const int64_t i0 = bt * kGroups;
             const int np = (int)min((int64_t)kGroups, J.n_p - i0);
@@ -699,7 +710,7 @@ __global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
                 const double q = sq[g];
                 for (int k = 1; k <= len; ++k) {
                     T F[6];
-                    const double t_s = canon_state_time(J.t_first, s_a + k, J.dt);
+                    const double t_s = canon_state_time(J.t_first, (int)s_a + k, J.dt);
                     double uk;
                     if constexpr (MIX)
                         uk = field_mixed(xc, rec[g][k], t_s, (float)q, K, F);

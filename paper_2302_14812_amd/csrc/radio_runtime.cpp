@@ -288,7 +288,7 @@ int enqueue_deposit(radio_detector* det, const radio_chunk* k, hipStream_t s)
 {
     if (k->n_particles == 0 || k->n_steps == 0)
         return RADIO_OK;
-    if (k->n_particles > INT32_MAX)
+    if (k->n_particles > INT32_MAX || k->n_steps > INT32_MAX - 1)
         return RADIO_EINVAL;
     radio::DepositJob J = make_job(det, k);
     int rc = grow(&det->d_recs, &det->recs_cap, (size_t)(J.n_p * (J.n_s + 1)));
