@@ -79,6 +79,25 @@ def time_precision(radio, wl, chunk_dev, precision, steps, warmup):
     return wall / steps * 1e3, kernel_ms
 
 
+def measured_traffic(precision, workload):
+    """HBM bytes per deposit launch from the committed rocprofv3 counter summary, or None
+    when it was taken on another workload or on a different kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "deposit_traffic_undulator_10000e_4096steps.json")
+    src = os.path.join(ROOT, "paper_2302_14812_amd", "csrc", "radio_kernels.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if rec.get("kernel_source_sha256_16") != sha or rec.get("workload") != workload:
+        return None
+    leg = rec.get("per_launch", {}).get(precision)
+    return None if leg is None else leg["hbm_bytes"]
+
+
 def cpu_baseline(wl, n_cells):
     import numpy as np
 
@@ -142,7 +161,7 @@ def main():
             "roofline": {"bound": "alu", "achieved": flops / (kms * 1e-3) / 1e12,
                          "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
                          "frac": flops / (kms * 1e-3) / 1e12 / PEAK_TFLOPS[prec],
-                         "traffic": None},
+                         "traffic": measured_traffic(prec, wl.name)},
         }
         print(f"[bench] {prec}: {ms:.1f} ms/step, deposit kernel {kms:.1f} ms, "
               f"{legs[prec]['value']:.3e} interactions/s", file=sys.stderr, flush=True)
