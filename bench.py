@@ -39,6 +39,9 @@ def parse():
                     help="also time the compensated single-precision accumulation")
     ap.add_argument("--cpu-cells", type=int, default=0,
                     help="cells in the oracle sample (default: two per host thread)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-launch leg (64 uneven sets, one persistent launch "
+                         "vs 64 separate launches)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -77,6 +80,60 @@ def time_precision(radio, wl, chunk_dev, precision, steps, warmup):
     det.close()
     del E, B
     return wall / steps * 1e3, kernel_ms
+
+
+def batch_leg(radio, W, precision, steps, warmup):
+    """64 independent uneven sets: one persistent batched launch vs 64 launches."""
+    import torch
+
+    from paper_2302_14812_amd import autotune
+    sets = W.batched_sets(n_sets=64, scale=0.02, sides=(32, 64, 128),
+                          n_t_choices=(256, 512, 1024, 2048))
+    chunks = [radio.Chunk.from_numpy(wl.chunk) for wl in sets]
+    dets = [radio.Detector.from_spec(wl.detector, precision=precision) for wl in sets]
+    total = sum(wl.interactions for wl in sets)
+    tuned = autotune.apply_batch([wl.detector for wl in sets], chunks)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(warmup):
+            for d in dets:
+                d.reset(stream)
+            fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(steps):
+            for d in dets:
+                d.reset(stream)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return sum(ms) / len(ms)
+
+    ms_batch = timed(lambda: radio.deposit_batch(dets, chunks, stream))
+    print(f"[bench] batch ({precision}): one launch {ms_batch:.1f} ms", file=sys.stderr, flush=True)
+
+    def separate():
+        for d, c in zip(dets, chunks):
+            d.deposit(c, stream)
+
+    ms_sep = timed(separate)
+    print(f"[bench] batch ({precision}): 64 launches {ms_sep:.1f} ms", file=sys.stderr, flush=True)
+    sizes = [wl.interactions for wl in sets]
+    for d in dets:
+        d.close()
+    return {"workload": "64 uneven sets (batched-launch recipe, particle counts x 0.02, sides "
+                        "32-128, 256-2048 slots)",
+            "interactions": total, "precision": precision,
+            "smallest_set": min(sizes), "largest_set": max(sizes),
+            "one_launch_ms": ms_batch, "separate_launches_ms": ms_sep,
+            "one_launch_value": total / (ms_batch * 1e-3),
+            "separate_value": total / (ms_sep * 1e-3),
+            "speedup": ms_sep / ms_batch, "autotuned": tuned}
 
 
 def measured_traffic(precision, workload):
@@ -167,6 +224,8 @@ def main():
               f"{legs[prec]['value']:.3e} interactions/s", file=sys.stderr, flush=True)
 
     main_leg = legs[args.precision]
+    del chunk_dev
+    batch = None if args.no_batch else batch_leg(radio, W, args.precision, args.steps, args.warmup)
     out = {
         "metric": "LW interactions/s (particle-step x cell)",
         "value": main_leg["value"],
@@ -191,6 +250,8 @@ def main():
         out["mixed_vs_fp64_speedup"] = legs["fp64"]["ms_per_step"] / main_leg["ms_per_step"]
     if "mixed_twosum" in legs and args.precision != "mixed_twosum":
         out["mixed_twosum"] = legs["mixed_twosum"]
+    if batch is not None:
+        out["batch"] = batch
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, args.cpu_cells)
         out["cpu_baseline"] = cb

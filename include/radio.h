@@ -144,14 +144,33 @@ RADIO_API int radio_detector_reset(radio_detector* det, void* stream);
 RADIO_API int radio_deposit_trajectory_chunk(radio_detector* det, const radio_chunk* chunk, void* stream);
 
 /*
- * Deposit n independent (detector, chunk) pairs in one persistent launch.
- * The result equals n separate radio_deposit_trajectory_chunk calls (up to
- * the order of floating-point additions).  All detectors must live on the
- * current device; a detector may appear more than once.  On any invalid pair
- * nothing is enqueued.
+ * Deposit n independent (detector, chunk) pairs in one persistent launch per
+ * precision present: the pairs' work is cut into items (a tile of cells x a
+ * range of runs), ordered longest first, and taken by resident workgroups
+ * from a device counter.  The result equals n separate
+ * radio_deposit_trajectory_chunk calls (up to the order of floating-point
+ * additions).  All detectors must live on the current device; a detector may
+ * appear more than once.  On any invalid pair nothing is enqueued.  The
+ * batch's workspace is shared by the device's batches: a call waits for the
+ * previous batch on that device to finish before reusing it.
  */
 RADIO_API int radio_deposit_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
                         void* stream);
+
+/*
+ * Launch tunables, process wide (the autotuner sets them):
+ *   target_blocks        workgroups aimed at by a single deposit (the runs of a
+ *                        chunk are split until tiles x splits reaches it)
+ *   items_per_workgroup  work items per resident workgroup in a batched deposit
+ *                        (finer items balance uneven jobs, coarser ones cost less)
+ */
+typedef struct radio_tuning {
+    int32_t target_blocks;
+    int32_t items_per_workgroup;
+} radio_tuning;
+
+RADIO_API int radio_set_tuning(const radio_tuning* t);
+RADIO_API int radio_get_tuning(radio_tuning* t);
 
 /*
  * Write the detector fields: E and B as DEVICE arrays [n_cells][n_t][3]

@@ -28,7 +28,7 @@ EXPORTS = (
     "radio_detector_create", "radio_detector_destroy", "radio_detector_reset",
     "radio_deposit_trajectory_chunk", "radio_deposit_batch", "radio_read_detector",
     "radio_detector_stats", "radio_detector_shape", "radio_detector_cells",
-    "radio_arrival_times", "radio_status_string",
+    "radio_arrival_times", "radio_status_string", "radio_set_tuning", "radio_get_tuning",
 )
 
 
@@ -58,6 +58,10 @@ class _Chunk(ctypes.Structure):
         ("t_first", ctypes.c_double), ("dt", ctypes.c_double),
         ("x", ctypes.c_void_p), ("u", ctypes.c_void_p), ("q", ctypes.c_void_p),
     ]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("target_blocks", ctypes.c_int32), ("items_per_workgroup", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -93,6 +97,8 @@ def _lib():
                                              ctypes.POINTER(ctypes.c_int32)]
         lib.radio_detector_cells.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         lib.radio_arrival_times.argtypes = [vp, vp, vp, i64, ctypes.c_double, vp, vp]
+        lib.radio_set_tuning.argtypes = [ctypes.POINTER(_Tuning)]
+        lib.radio_get_tuning.argtypes = [ctypes.POINTER(_Tuning)]
         for name in EXPORTS:
             if name != "radio_status_string":
                 getattr(lib, name).restype = ctypes.c_int
@@ -290,6 +296,20 @@ def deposit_batch(detectors: Sequence[Detector], chunks: Sequence[Chunk], stream
     hs = (ctypes.c_void_p * max(n, 1))(*[d.handle for d in detectors])
     cs = (_Chunk * max(n, 1))(*[c._c() for c in chunks])
     _check(_lib().radio_deposit_batch(hs, cs, n, _stream(stream)), "radio_deposit_batch")
+
+
+def get_tuning() -> dict:
+    t = _Tuning()
+    _check(_lib().radio_get_tuning(ctypes.byref(t)), "radio_get_tuning")
+    return {"target_blocks": int(t.target_blocks), "items_per_workgroup": int(t.items_per_workgroup)}
+
+
+def set_tuning(target_blocks: Optional[int] = None, items_per_workgroup: Optional[int] = None) -> None:
+    cur = get_tuning()
+    t = _Tuning(int(target_blocks if target_blocks is not None else cur["target_blocks"]),
+                int(items_per_workgroup if items_per_workgroup is not None
+                    else cur["items_per_workgroup"]))
+    _check(_lib().radio_set_tuning(ctypes.byref(t)), "radio_set_tuning")
 
 
 def arrival_times(cells, points, t, c: float = 1.0, stream=None):

@@ -28,11 +28,20 @@ constexpr int kModeMix = 1;
 constexpr int kModeMixTwoSum = 2;
 
 // workgroup shape of the deposit
-constexpr int kTileCells = 16;                          // cells per workgroup
-constexpr int kGroups = 16;                             // particle lanes per cell
-constexpr int kDepositThreads = kTileCells * kGroups;   // 256
-constexpr int kRunL = 16;                               // segments per run
+#ifndef RADIO_TILE_CELLS
+#define RADIO_TILE_CELLS 16
+#endif
+#ifndef RADIO_RUN_L
+#define RADIO_RUN_L 16
+#endif
+constexpr int kTileCells = RADIO_TILE_CELLS;            // cells per workgroup
+constexpr int kDepositThreads = 256;
+constexpr int kGroups = kDepositThreads / kTileCells;   // particle lanes per cell
+constexpr int kRunL = RADIO_RUN_L;                      // segments per run
+static_assert(kGroups * kTileCells == kDepositThreads && (kGroups & (kGroups - 1)) == 0,
+              "tile shape");
 constexpr int kRingMargin = 2;                          // ring slots kept below a batch's start
+constexpr int kXcds = 8;                                // accelerator dies sharing one L2 each
 
 // slots per cell in the LDS ring (a power of two): 48 B per slot for both
 // paths (6 doubles, or 6 compensated single pairs)
@@ -73,6 +82,14 @@ struct DepositJob {
     int64_t n_splits;               // workgroups per tile
 };
 
+// One unit of a batched deposit: a tile of cells against a range of runs of one job.
+struct WorkItem {
+    int32_t job;
+    int32_t tile;
+    int32_t split;
+    int32_t pad;
+};
+
 void plan_job(DepositJob& job, int target_blocks);
 
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
@@ -80,6 +97,9 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
 hipError_t launch_kinematics(const DepositJob& job, hipStream_t s);
 hipError_t launch_order(const DepositJob& job, hipStream_t s);
 hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s);
+hipError_t launch_deposit_batch(const DepositJob* jobs, const WorkItem* items, int64_t n_items,
+                                unsigned long long* next, int mode, int n_blocks, hipStream_t s);
+int persistent_blocks_per_cu(int mode);
 hipError_t launch_readout(const double* acc, int64_t n_c, int64_t n_t, const int64_t* user_index,
                           bool pairs, double* E, double* B, hipStream_t s);
 hipError_t launch_arrival(const double* cells, const double* pts, const double* t, int64_t n,

@@ -46,6 +46,17 @@ namespace {
 // pointers into LDS keep their address space, so ring updates compile to ds_*
 // instructions rather than generic (flat) ones
 #define RADIO_LDS __attribute__((address_space(3)))
+// likewise for device memory reached through pointers that were loaded from
+// memory (the job descriptors of the persistent kernel)
+#define RADIO_GLOBAL __attribute__((address_space(1)))
+
+typedef long long v2i64 __attribute__((ext_vector_type(2)));  // a 16-byte piece
+
+template <typename P>
+__device__ __forceinline__ RADIO_GLOBAL P* gptr(P* p)
+{
+    return (RADIO_GLOBAL P*)p;
+}
 
 // ---------------------------------------------------------------------------
 // Quantities that cancel catastrophically.  Both this library and any
@@ -136,36 +147,40 @@ __device__ __forceinline__ float two_sum_err(float a, float b, float s)
     return (a - (s - bv)) + (b - bv);
 }
 
-__device__ __forceinline__ void global_add(double* row, int j, const double a[6])
+__device__ __forceinline__ void global_add(RADIO_GLOBAL double* row, int j, const double a[6])
 {
-    double* q = row + (int64_t)j * 6;
+    RADIO_GLOBAL double* q = row + (int64_t)j * 6;
 #pragma unroll
     for (int k = 0; k < 6; ++k)
-        unsafeAtomicAdd(q + k, a[k]);
+        __hip_atomic_fetch_add(q + k, a[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void global_add(float* row, int j, const float a[6])
+__device__ __forceinline__ void global_add(RADIO_GLOBAL float* row, int j, const float a[6])
 {
-    float* q = row + (int64_t)j * 12;
+    RADIO_GLOBAL float* q = row + (int64_t)j * 12;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         if (a[k] != 0.0f) {
-            const float old = atomicAdd(q + k, a[k]);
-            unsafeAtomicAdd(q + 6 + k, two_sum_err(old, a[k], old + a[k]));
+            const float old =
+                __hip_atomic_fetch_add(q + k, a[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(q + 6 + k, two_sum_err(old, a[k], old + a[k]), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
 
 // a compensated pair (hi, lo) into the HBM pair
-__device__ __forceinline__ void global_add_pair(float* row, int j, const float hi[6],
+__device__ __forceinline__ void global_add_pair(RADIO_GLOBAL float* row, int j, const float hi[6],
                                                 const float lo[6])
 {
-    float* q = row + (int64_t)j * 12;
+    RADIO_GLOBAL float* q = row + (int64_t)j * 12;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         if (hi[k] != 0.0f || lo[k] != 0.0f) {
-            const float old = atomicAdd(q + k, hi[k]);
-            unsafeAtomicAdd(q + 6 + k, two_sum_err(old, hi[k], old + hi[k]) + lo[k]);
+            const float old =
+                __hip_atomic_fetch_add(q + k, hi[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(q + 6 + k, two_sum_err(old, hi[k], old + hi[k]) + lo[k],
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -187,7 +202,7 @@ struct CellSink<double> {
     static constexpr int R = RingSlots<double>::value;
     static constexpr int W = 6;  // values per ring slot
     RADIO_LDS double* ring;
-    double* row;
+    RADIO_GLOBAL double* row;
     int base;
     int n_t;
     unsigned* n_bypass;
@@ -217,7 +232,7 @@ struct CellSink<float> {
     static constexpr int R = RingSlots<float>::value;
     static constexpr int W = 12;  // hi[6], lo[6]
     RADIO_LDS float* ring;
-    float* row;
+    RADIO_GLOBAL float* row;
     int base;
     int n_t;
     unsigned* n_bypass;
@@ -589,44 +604,62 @@ __global__ __launch_bounds__(256) void order_kernel(const double* __restrict__ x
 // M: arithmetic of the deposit (field in double or single; accumulation in
 // double or compensated single pairs)
 template <int M>
-__global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
-{
-    constexpr bool MIX = (M != kModeF64);
+struct ModeTypes {
+    static constexpr bool MIX = (M != kModeF64);
     using T = typename std::conditional<MIX, float, double>::type;  // field and lane carry
     using Acc = typename std::conditional<M == kModeMixTwoSum, float, double>::type;
     using Sink = CellSink<Acc>;
+};
+
+// LDS of one deposit workgroup
+template <int M>
+struct DepositShared {
+    using Acc = typename ModeTypes<M>::Acc;
+    StateRec rec[kGroups][kRunL + 1];   // staged batch: one run per particle group
+    double sq[kGroups];                 // its charges
+    Acc ring[kTileCells][CellSink<Acc>::R][CellSink<Acc>::W];  // per-cell slot rings
+    unsigned long long cnt[3];          // clipped, nonmonotone, bypassed
+};
+
+// One work item: a tile of kTileCells cells against the runs
+// [split * runs_per_split, ...) of every particle of job J, in the tile's
+// particle order.  Called by all kDepositThreads threads of a workgroup.
+template <int M>
+__device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, int64_t split,
+                                             DepositShared<M>& sh)
+{
+    constexpr bool MIX = ModeTypes<M>::MIX;
+    using T = typename ModeTypes<M>::T;
+    using Acc = typename ModeTypes<M>::Acc;
+    using Sink = typename ModeTypes<M>::Sink;
     constexpr int R = Sink::R;
     constexpr int RW = Sink::W;
-    __shared__ __align__(16) StateRec rec[kGroups][kRunL + 1];
-    __shared__ double sq[kGroups];
-    __shared__ Acc ring[kTileCells][R][RW];
-    __shared__ unsigned long long s_cnt[3];
 
     const int tid = threadIdx.x;
     const int cl = tid / kGroups;  // cell within the tile
     const int g = tid % kGroups;   // particle group
-    const int64_t tile = blockIdx.x % J.n_tiles;
-    const int64_t split = blockIdx.x / J.n_tiles;
     const int64_t row_i = tile * kTileCells + cl;  // internal (tile-ordered) cell row
     const bool active = row_i < J.n_c;
     const int n_t = (int)J.n_t;
     const Consts K{J.t0, J.inv_dt_det, J.inv_c, (float)J.inv_c};
     double xc[3] = {0.0, 0.0, 0.0};
-    Acc* row = nullptr;
+    RADIO_GLOBAL Acc* row = nullptr;
     if (active) {
-        xc[0] = J.cells[3 * row_i];
-        xc[1] = J.cells[3 * row_i + 1];
-        xc[2] = J.cells[3 * row_i + 2];
-        row = reinterpret_cast<Acc*>(J.acc + row_i * J.n_t * 6);
+        const RADIO_GLOBAL double* cells = gptr(J.cells);
+        xc[0] = cells[3 * row_i];
+        xc[1] = cells[3 * row_i + 1];
+        xc[2] = cells[3 * row_i + 2];
+        row = gptr(reinterpret_cast<Acc*>(J.acc + row_i * J.n_t * 6));
     }
-    RADIO_LDS Acc* my_ring = (RADIO_LDS Acc*)&ring[cl][0][0];
+    RADIO_LDS Acc* my_ring = (RADIO_LDS Acc*)&sh.ring[cl][0][0];
     for (int i = g; i < R * RW; i += kGroups)
         my_ring[i] = Acc(0);
     if (tid < 3)
-        s_cnt[tid] = 0;
+        sh.cnt[tid] = 0;
     int base = -1;  // ring covers [base, base + R); -1 until the first batch
     unsigned n_clip = 0, n_back = 0, n_bypass = 0;
-    const int32_t* order = J.perm + tile * J.n_p;
+    const RADIO_GLOBAL int32_t* order = gptr(J.perm + tile * J.n_p);
+    const RADIO_GLOBAL double* charges = J.q ? gptr(J.q) : nullptr;
     const int64_t n_states = J.n_s + 1;
     const int64_t n_batches = (J.n_p + kGroups - 1) / kGroups;
 
@@ -677,20 +710,20 @@ __global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
                     const int r = i - gg * per;
                     if (gg < np) {
                         const int64_t p = order[i0 + gg];
-                        const int4* src =
-                            reinterpret_cast<const int4*>(J.recs + p * n_states + s_a) + r;
-                        reinterpret_cast<int4*>(&rec[gg][0])[r] = *src;
+                        const RADIO_GLOBAL v2i64* src =
+                            gptr(reinterpret_cast<const v2i64*>(J.recs + p * n_states + s_a)) + r;
+                        reinterpret_cast<v2i64*>(&sh.rec[gg][0])[r] = *src;
                     }
                 }
                 if (tid < kGroups)
-                    sq[tid] = (tid < np) ? (J.q ? J.q[order[i0 + tid]] : -1.0) : 0.0;
+                    sh.sq[tid] = (tid < np) ? (charges ? charges[order[i0 + tid]] : -1.0) : 0.0;
             }
             __syncthreads();
             const bool mine = active && g < np;
             double u_prev = 1e300;
             if (mine)
-                u_prev = MIX ? slot_coord_mixed(xc, rec[g][0], t_a, K)
-                             : slot_coord_fp64(xc, rec[g][0], t_a, K);
+                u_prev = MIX ? slot_coord_mixed(xc, sh.rec[g][0], t_a, K)
+                             : slot_coord_fp64(xc, sh.rec[g][0], t_a, K);
             // ring start for this batch: the earliest start among the cell's lanes
             double m = u_prev;
 #pragma unroll
@@ -707,15 +740,15 @@ __global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
                 Sink sink{my_ring, row, base, n_t, &n_bypass};
                 Carry<T> C;
                 carry_init(C);
-                const double q = sq[g];
+                const double q = sh.sq[g];
                 for (int k = 1; k <= len; ++k) {
                     T F[6];
                     const double t_s = canon_state_time(J.t_first, (int)s_a + k, J.dt);
                     double uk;
                     if constexpr (MIX)
-                        uk = field_mixed(xc, rec[g][k], t_s, (float)q, K, F);
+                        uk = field_mixed(xc, sh.rec[g][k], t_s, (float)q, K, F);
                     else
-                        uk = field_fp64(xc, rec[g][k], t_s, q, K, F);
+                        uk = field_fp64(xc, sh.rec[g][k], t_s, q, K, F);
                     const bool back = uk < u_prev;
                     n_back += back ? 1u : 0u;
                     n_clip += (fmin(uk, u_prev) < 0.0 || fmax(uk, u_prev) > (double)n_t) ? 1u : 0u;
@@ -728,14 +761,55 @@ __global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
     }
     move_ring(-1);  // flush what the ring still holds
     if (n_clip)
-        atomicAdd(&s_cnt[0], (unsigned long long)n_clip);
+        atomicAdd(&sh.cnt[0], (unsigned long long)n_clip);
     if (n_back)
-        atomicAdd(&s_cnt[1], (unsigned long long)n_back);
+        atomicAdd(&sh.cnt[1], (unsigned long long)n_back);
     if (n_bypass)
-        atomicAdd(&s_cnt[2], (unsigned long long)n_bypass);
+        atomicAdd(&sh.cnt[2], (unsigned long long)n_bypass);
     __syncthreads();
-    if (tid < 3 && s_cnt[tid])
-        atomicAdd(&J.counters[tid], s_cnt[tid]);
+    if (tid < 3 && sh.cnt[tid])
+        __hip_atomic_fetch_add(gptr(J.counters) + tid, sh.cnt[tid], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One workgroup per work item of a single deposit.
+template <int M>
+__global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
+{
+    __shared__ __align__(16) DepositShared<M> sh;
+    // Workgroups are dealt round-robin over the XCDs; give each XCD a contiguous
+    // range of (split, tile) indices so that neighbouring tiles, whose particle
+    // orders and record batches are alike, share that XCD's L2.
+    const int64_t per_xcd = (int64_t)gridDim.x / kXcds;
+    const int64_t logical = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+    if (logical >= J.n_tiles * J.n_splits)
+        return;
+    deposit_item<M>(J, logical % J.n_tiles, logical / J.n_tiles, sh);
+}
+
+// Persistent workgroups for many independent deposits: each takes the next work
+// item (largest first, as ordered by the host) from a device counter until
+// the list is exhausted, so uneven jobs share one launch without a tail of idle
+// workgroups.  Every workgroup leaves once the counter passes n_items.
+template <int M>
+__global__ __launch_bounds__(kDepositThreads) void deposit_persistent_kernel(
+    const DepositJob* __restrict__ jobs, const WorkItem* __restrict__ items, int64_t n_items,
+    unsigned long long* __restrict__ next)
+{
+    __shared__ __align__(16) DepositShared<M> sh;
+    __shared__ int64_t cur;
+    for (;;) {
+        __syncthreads();  // everyone has read the previous `cur`
+        if (threadIdx.x == 0)
+            cur = (int64_t)atomicAdd(next, 1ull);
+        __syncthreads();
+        const int64_t it = cur;
+        if (it >= n_items)
+            break;
+        const WorkItem w = items[it];
+        const DepositJob J = jobs[w.job];
+        deposit_item<M>(J, w.tile, w.split, sh);
+    }
 }
 
 // Prefix sum of the slot differences along the slots of each cell; writes
@@ -893,9 +967,10 @@ hipError_t launch_order(const DepositJob& job, hipStream_t s)
 
 hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s)
 {
-    const int64_t blocks = job.n_tiles * job.n_splits;
+    int64_t blocks = job.n_tiles * job.n_splits;
     if (blocks <= 0)
         return hipSuccess;
+    blocks = (blocks + kXcds - 1) / kXcds * kXcds;  // a multiple of the XCD count
     const dim3 grid((unsigned)blocks), block(kDepositThreads);
     if (mode == kModeMix)
         hipLaunchKernelGGL(deposit_kernel<kModeMix>, grid, block, 0, s, job);
@@ -904,6 +979,44 @@ hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s)
     else
         hipLaunchKernelGGL(deposit_kernel<kModeF64>, grid, block, 0, s, job);
     return hipGetLastError();
+}
+
+hipError_t launch_deposit_batch(const DepositJob* jobs, const WorkItem* items, int64_t n_items,
+                                unsigned long long* next, int mode, int n_blocks, hipStream_t s)
+{
+    if (n_items <= 0)
+        return hipSuccess;
+    hipError_t e = launch_zero_u64(next, 1, s);
+    if (e != hipSuccess)
+        return e;
+    const dim3 grid((unsigned)n_blocks), block(kDepositThreads);
+    if (mode == kModeMix)
+        hipLaunchKernelGGL(deposit_persistent_kernel<kModeMix>, grid, block, 0, s, jobs, items,
+                           n_items, next);
+    else if (mode == kModeMixTwoSum)
+        hipLaunchKernelGGL(deposit_persistent_kernel<kModeMixTwoSum>, grid, block, 0, s, jobs, items,
+                           n_items, next);
+    else
+        hipLaunchKernelGGL(deposit_persistent_kernel<kModeF64>, grid, block, 0, s, jobs, items,
+                           n_items, next);
+    return hipGetLastError();
+}
+
+int persistent_blocks_per_cu(int mode)
+{
+    int n = 0;
+    hipError_t e;
+    if (mode == kModeMix)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, reinterpret_cast<const void*>(deposit_persistent_kernel<kModeMix>), kDepositThreads, 0);
+    else if (mode == kModeMixTwoSum)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, reinterpret_cast<const void*>(deposit_persistent_kernel<kModeMixTwoSum>),
+            kDepositThreads, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, reinterpret_cast<const void*>(deposit_persistent_kernel<kModeF64>), kDepositThreads, 0);
+    return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 hipError_t launch_readout(const double* acc, int64_t n_c, int64_t n_t, const int64_t* user_index,

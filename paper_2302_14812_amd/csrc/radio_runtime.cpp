@@ -9,6 +9,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -42,7 +44,15 @@ static_assert(RADIO_FP64 == radio::kModeF64 && RADIO_MIXED == radio::kModeMix &&
 
 namespace {
 
-constexpr int kTargetBlocks = 3072;  // workgroups per deposit launch (256 CUs, ~3 resident each)
+// launch tunables (radio_set_tuning)
+std::mutex g_tuning_mu;
+radio_tuning g_tuning = {3072, 4};
+
+radio_tuning current_tuning()
+{
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    return g_tuning;
+}
 
 bool finite3(const double v[3])
 {
@@ -257,7 +267,7 @@ radio::DepositJob make_job(radio_detector* det, const radio_chunk* k)
     J.inv_dt_det = 1.0 / det->dt_det;
     J.inv_c = 1.0 / det->c;
     J.c = det->c;
-    radio::plan_job(J, kTargetBlocks);
+    radio::plan_job(J, current_tuning().target_blocks);
     return J;
 }
 
@@ -303,6 +313,156 @@ int enqueue_deposit(radio_detector* det, const radio_chunk* k, hipStream_t s)
         radio::launch_deposit(J, det->precision, s) != hipSuccess)
         return RADIO_EDEVICE;
     det->interactions += k->n_particles * k->n_steps * det->n_c;
+    return RADIO_OK;
+}
+
+// Workspaces of batched deposits, per device: every pair of a batch needs its
+// own state records and particle orders until the persistent launch has run, so
+// they come from one arena; before the arena is reused the previous batch's
+// event is waited for.
+struct BatchArena {
+    radio::DepositJob* d_jobs = nullptr;
+    size_t jobs_cap = 0;
+    radio::WorkItem* d_items = nullptr;
+    size_t items_cap = 0;
+    unsigned long long* d_next = nullptr;  // one counter per precision mode
+    radio::StateRec* d_recs = nullptr;
+    size_t recs_cap = 0;
+    int32_t* d_perm = nullptr;
+    size_t perm_cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+    std::vector<radio::DepositJob> h_jobs;
+    std::vector<radio::WorkItem> h_items;
+    int n_cus = 0;
+};
+
+std::mutex g_arena_mu;
+std::map<int, BatchArena*> g_arenas;
+
+int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n, hipStream_t s,
+                  int dev)
+{
+    std::lock_guard<std::mutex> lk(g_arena_mu);
+    BatchArena*& A = g_arenas[dev];
+    if (!A) {
+        A = new (std::nothrow) BatchArena();
+        if (!A)
+            return RADIO_ENOMEM;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+            hipEventCreateWithFlags(&A->done, hipEventDisableTiming) != hipSuccess ||
+            hipMalloc((void**)&A->d_next, 3 * sizeof(unsigned long long)) != hipSuccess) {
+            (void)hipGetLastError();
+            return RADIO_EDEVICE;
+        }
+        A->n_cus = prop.multiProcessorCount;
+    }
+    if (A->pending) {
+        if (hipEventSynchronize(A->done) != hipSuccess)
+            return RADIO_EDEVICE;
+        A->pending = false;
+    }
+    // plan every nonempty pair
+    const radio_tuning tun = current_tuning();
+    std::vector<int> idx;
+    size_t recs_need = 0, perm_need = 0;
+    A->h_jobs.clear();
+    for (int i = 0; i < n; ++i) {
+        const radio_chunk* k = &chunks[i];
+        if (k->n_particles == 0 || k->n_steps == 0)
+            continue;
+        radio::DepositJob J = make_job(dets[i], k);
+        recs_need += (size_t)(J.n_p * (J.n_s + 1));
+        perm_need += (size_t)(J.n_tiles * J.n_p);
+        A->h_jobs.push_back(J);
+        idx.push_back(i);
+    }
+    if (idx.empty()) {
+        for (int i = 0; i < n; ++i)
+            dets[i]->chunks += 1;
+        return RADIO_OK;
+    }
+    int rc = grow(&A->d_recs, &A->recs_cap, recs_need);
+    if (rc == RADIO_OK)
+        rc = grow(&A->d_perm, &A->perm_cap, perm_need);
+    if (rc == RADIO_OK)
+        rc = grow(&A->d_jobs, &A->jobs_cap, A->h_jobs.size());
+    if (rc != RADIO_OK)
+        return rc;
+    // work items: a per-pair split chosen so that items carry similar work, longest first
+    double total = 0.0;
+    for (const auto& J : A->h_jobs)
+        total += (double)J.n_c * (double)J.n_p * (double)J.n_s;
+    const int n_modes = 3;
+    int bpc[n_modes];
+    for (int m = 0; m < n_modes; ++m)
+        bpc[m] = radio::persistent_blocks_per_cu(m);
+    const double resident = (double)A->n_cus * (double)bpc[0];
+    const double item_work = std::max(total / (resident * (double)tun.items_per_workgroup), 1.0);
+    struct Item {
+        radio::WorkItem w;
+        double cost;
+        int mode;
+    };
+    std::vector<Item> items;
+    size_t ro = 0, po = 0;
+    for (size_t j = 0; j < A->h_jobs.size(); ++j) {
+        radio::DepositJob& J = A->h_jobs[j];
+        J.recs = A->d_recs + ro;
+        J.perm = A->d_perm + po;
+        ro += (size_t)(J.n_p * (J.n_s + 1));
+        po += (size_t)(J.n_tiles * J.n_p);
+        const double run_work = (double)radio::kTileCells * (double)J.n_p * (double)radio::kRunL;
+        int64_t rps = (int64_t)std::ceil(item_work / run_work);
+        rps = std::max<int64_t>(1, std::min<int64_t>(rps, J.n_runs));
+        J.runs_per_split = rps;
+        J.n_splits = (J.n_runs + rps - 1) / rps;
+        const int mode = dets[idx[j]]->precision;
+        for (int64_t sp = 0; sp < J.n_splits; ++sp) {
+            const int64_t runs = std::min<int64_t>(rps, J.n_runs - sp * rps);
+            for (int64_t t = 0; t < J.n_tiles; ++t)
+                items.push_back({{(int32_t)j, (int32_t)t, (int32_t)sp, 0},
+                                 (double)runs * run_work, mode});
+        }
+        if (radio::launch_kinematics(J, s) != hipSuccess || radio::launch_order(J, s) != hipSuccess)
+            return RADIO_EDEVICE;
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+        return a.mode != b.mode ? a.mode < b.mode : a.cost > b.cost;
+    });
+    A->h_items.resize(items.size());
+    for (size_t i = 0; i < items.size(); ++i)
+        A->h_items[i] = items[i].w;
+    rc = grow(&A->d_items, &A->items_cap, A->h_items.size());
+    if (rc != RADIO_OK)
+        return rc;
+    if (hipMemcpyAsync(A->d_jobs, A->h_jobs.data(), A->h_jobs.size() * sizeof(radio::DepositJob),
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(A->d_items, A->h_items.data(), A->h_items.size() * sizeof(radio::WorkItem),
+                       hipMemcpyHostToDevice, s) != hipSuccess)
+        return RADIO_EDEVICE;
+    size_t b = 0;
+    while (b < items.size()) {
+        const int mode = items[b].mode;
+        size_t e = b;
+        while (e < items.size() && items[e].mode == mode)
+            ++e;
+        const int blocks = A->n_cus * bpc[mode];
+        if (radio::launch_deposit_batch(A->d_jobs, A->d_items + b, (int64_t)(e - b),
+                                        A->d_next + mode, mode, blocks, s) != hipSuccess)
+            return RADIO_EDEVICE;
+        b = e;
+    }
+    if (hipEventRecord(A->done, s) != hipSuccess)
+        return RADIO_EDEVICE;
+    A->pending = true;
+    for (size_t j = 0; j < idx.size(); ++j) {
+        const radio_chunk* k = &chunks[idx[j]];
+        dets[idx[j]]->interactions += k->n_particles * k->n_steps * dets[idx[j]]->n_c;
+    }
+    for (int i = 0; i < n; ++i)
+        dets[i]->chunks += 1;
     return RADIO_OK;
 }
 
@@ -475,14 +635,27 @@ int radio_deposit_batch(radio_detector* const* dets, const radio_chunk* chunks, 
         int rc = validate_chunk(&chunks[i]);
         if (rc != RADIO_OK)
             return rc;
+        if (chunks[i].n_particles > INT32_MAX || chunks[i].n_steps > INT32_MAX - 1)
+            return RADIO_EINVAL;
     }
-    hipStream_t s = (hipStream_t)stream;
-    for (int i = 0; i < n; ++i) {
-        int rc = enqueue_deposit(dets[i], &chunks[i], s);
-        if (rc != RADIO_OK)
-            return rc;
-        dets[i]->chunks += 1;
-    }
+    return enqueue_batch(dets, chunks, n, (hipStream_t)stream, dev);
+}
+
+int radio_set_tuning(const radio_tuning* t)
+{
+    if (!t || t->target_blocks < 1 || t->target_blocks > (1 << 24) || t->items_per_workgroup < 1 ||
+        t->items_per_workgroup > 4096)
+        return RADIO_EINVAL;
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    g_tuning = *t;
+    return RADIO_OK;
+}
+
+int radio_get_tuning(radio_tuning* t)
+{
+    if (!t)
+        return RADIO_EINVAL;
+    *t = current_tuning();
     return RADIO_OK;
 }
 

@@ -1,0 +1,148 @@
+"""Batched deposits: many (detector, chunk) pairs of uneven size in one persistent launch.
+
+Each detector's result must equal its separate deposit (up to the order of
+floating-point additions) and the CPU oracle on sampled cells.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_14812_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def radio():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2302_14812_amd as radio
+    radio._lib()
+    return radio
+
+
+def rel_l2(a, b):
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b)) / (nb if nb > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def sets():
+    # the batched workload's recipe at reduced sizes: 12 uneven sets
+    return W.batched_sets(n_sets=12, max_particles=400, max_steps=700, sides=(8, 16, 24),
+                          n_t_choices=(64, 128, 256))
+
+
+def _read(det):
+    import torch
+    E, B = det.read()
+    torch.cuda.synchronize()
+    return E.cpu().numpy(), B.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_equals_separate_and_oracle(radio, sets, precision):
+    tol_sep = 1e-13 if precision == "fp64" else 1e-6
+    tol_or = 1e-12 if precision == "fp64" else 1e-5
+    chunks = [radio.Chunk.from_numpy(wl.chunk) for wl in sets]
+    dets_b = [radio.Detector.from_spec(wl.detector, precision=precision) for wl in sets]
+    radio.deposit_batch(dets_b, chunks)
+    sizes = [wl.interactions for wl in sets]
+    assert max(sizes) / max(1, min(sizes)) > 20  # uneven on purpose
+    rng = np.random.Generator(np.random.PCG64(4))
+    for wl, ch, db in zip(sets, chunks, dets_b):
+        ds = radio.Detector.from_spec(wl.detector, precision=precision)
+        ds.deposit(ch)
+        Eb, Bb = _read(db)
+        Es, Bs = _read(ds)
+        e = max(rel_l2(Eb, Es), rel_l2(Bb, Bs))
+        print(f"[batch] {wl.name} {precision}: batch vs alone relL2 {e:.3e}", flush=True)
+        assert e <= tol_sep, (wl.name, e)
+        assert db.stats()["interactions"] == wl.interactions
+        idx = sorted(rng.choice(wl.detector.n_cells, size=min(6, wl.detector.n_cells),
+                                replace=False).tolist())
+        D = oracle.deposit_workload(wl.detector, wl.chunk, cell_index=idx)
+        Eo, Bo = oracle.read(D)
+        eo = max(rel_l2(Eb[idx], Eo), rel_l2(Bb[idx], Bo))
+        print(f"[batch] {wl.name} {precision}: batch vs oracle relL2 {eo:.3e}", flush=True)
+        assert eo <= tol_or, (wl.name, eo)
+        ds.close()
+        db.close()
+
+
+def test_batch_mixed_modes_duplicates_and_empty(radio, sets):
+    import torch
+    wl = sets[0]
+    halves = W.split_steps(wl.chunk, [wl.chunk.n_steps // 2])
+    c_full = radio.Chunk.from_numpy(wl.chunk)
+    c_h = [radio.Chunk.from_numpy(h) for h in halves]
+    det64 = radio.Detector.from_spec(wl.detector, precision="fp64")
+    detmx = radio.Detector.from_spec(wl.detector, precision="mixed")
+    det2s = radio.Detector.from_spec(wl.detector, precision="mixed_twosum")
+    empty = radio.Chunk(c_full.x[:, :, :0].contiguous(), c_full.u[:, :, :0].contiguous(), None,
+                        0.0, 0.1)
+    # one call: every precision, the fp64 detector twice (two halves), an empty chunk
+    radio.deposit_batch([det64, detmx, det64, det2s, detmx],
+                        [c_h[0], c_full, c_h[1], c_full, empty])
+    ref = radio.Detector.from_spec(wl.detector, precision="fp64")
+    ref.deposit(c_full)
+    Er, Br = _read(ref)
+    E64, B64 = _read(det64)
+    # the halves recompute state times from their own t_first (ulp-level shifts)
+    assert max(rel_l2(E64, Er), rel_l2(B64, Br)) <= 1e-11
+    for d in (detmx, det2s):
+        Em, Bm = _read(d)
+        assert max(rel_l2(Em, Er), rel_l2(Bm, Br)) <= 1e-5
+    assert det64.stats()["chunks"] == 2 and detmx.stats()["chunks"] == 2
+    for d in (det64, detmx, det2s, ref):
+        d.close()
+
+
+def test_batch_rejects_invalid_pairs_without_work(radio, sets):
+    wl = sets[1]
+    det = radio.Detector.from_spec(wl.detector)
+    good = radio.Chunk.from_numpy(wl.chunk)
+    bad = radio.Chunk(good.x, good.u, good.q, 0.0, -1.0)
+    with pytest.raises(radio.RadioError):
+        radio.deposit_batch([det, det], [good, bad])
+    E, B = _read(det)
+    assert np.abs(E).max() == 0.0 and det.stats()["chunks"] == 0
+    det.close()
+
+
+def test_tuning_roundtrip(radio):
+    cur = radio.get_tuning()
+    radio.set_tuning(target_blocks=1024, items_per_workgroup=2)
+    assert radio.get_tuning() == {"target_blocks": 1024, "items_per_workgroup": 2}
+    with pytest.raises(radio.RadioError):
+        radio.set_tuning(target_blocks=0)
+    radio.set_tuning(**cur)
+    assert radio.get_tuning() == cur
+
+
+def test_autotuner_picks_a_candidate_and_caches(radio, sets, tmp_path):
+    from paper_2302_14812_amd import autotune
+    specs = [wl.detector for wl in sets[:6]]
+    chunks = [radio.Chunk.from_numpy(wl.chunk) for wl in sets[:6]]
+    cache = {}
+    before = radio.get_tuning()
+    rb = autotune.tune_batch(specs, chunks, precision="fp64", candidates=(1, 4), repeats=1,
+                             cache=cache)
+    assert rb["items_per_workgroup"] in (1, 4) and len(rb["timings_ms"]) == 2
+    rs = autotune.tune_single(specs[0], chunks[0], precision="fp64", candidates=(256, 1024),
+                              repeats=1, cache=cache)
+    assert rs["target_blocks"] in (256, 1024)
+    assert radio.get_tuning() == before  # tuning restores the caller's settings
+    path = str(tmp_path / "tune.json")
+    autotune.save_cache(cache, path)
+    loaded = autotune.load_cache(path)
+    assert loaded == json_roundtrip(cache)
+    assert autotune.apply_batch(specs, chunks, cache=loaded)
+    assert radio.get_tuning()["items_per_workgroup"] == rb["items_per_workgroup"]
+    radio.set_tuning(**before)
+
+
+def json_roundtrip(obj):
+    import json
+    return json.loads(json.dumps(obj))
