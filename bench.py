@@ -12,6 +12,7 @@ is timed on a bounded sample of cells on the host cores (cpu_baseline).
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -42,6 +43,11 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-launch leg (64 uneven sets, one persistent launch "
                          "vs 64 separate launches)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the streaming-service leg")
+    ap.add_argument("--serve-chunks", type=int, default=40,
+                    help="timed chunks of the streaming leg (after a fifth as many warm-up)")
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="offered load as a fraction of the measured single-chunk throughput")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -134,6 +140,80 @@ def batch_leg(radio, W, precision, steps, warmup):
             "one_launch_value": total / (ms_batch * 1e-3),
             "separate_value": total / (ms_sep * 1e-3),
             "speedup": ms_sep / ms_batch, "autotuned": tuned}
+
+
+def serve_leg(radio, W, precisions, n_chunks, load):
+    """Streaming service: 8 plasma-mirror detectors (256 x 256 cells, 4096 slots each)
+    resident in HBM, fed by a Poisson stream of chunks of 1-64 steps x 10^3-10^5
+    fresh particles.  The arrival rate is load x X / E[work], where X is the
+    throughput measured on chunks deposited one at a time; p50/p99 latency is
+    device completion minus host arrival, over the chunks after the warm-up."""
+    import torch
+
+    from paper_2302_14812_amd.serving import DepositServer, poisson_arrivals, replay
+    n_det, side, n_t = 8, 256, 4096
+    specs = {d: W.plasma_mirror_detector(n_side=side, n_t=n_t, seed=W.BASE_SEED + 3 + d)
+             for d in range(n_det)}
+    n_warm = max(1, n_chunks // 5)
+    n_all = n_warm + n_chunks
+    rows = list(W.stream_schedule(n_all, n_det, seed=W.BASE_SEED + 500, min_steps=1,
+                                  max_steps=64, min_log_particles=3.0, max_log_particles=5.0))
+    t = time.perf_counter()
+    host = [(d, W.plasma_mirror_chunk(n, s0, st, seed=W.BASE_SEED + 1000 + k))
+            for k, (d, s0, st, n) in enumerate(rows)]
+    items = [(d, radio.Chunk.from_numpy(c)) for d, c in host]
+    torch.cuda.synchronize()
+    del host
+    print(f"[bench] serve: {n_all} chunks generated in {time.perf_counter() - t:.1f} s",
+          file=sys.stderr, flush=True)
+    cells = side * side
+    # E[work] of the recipe: E[S] = 32.5 steps, E[n] = (1e5 - 1e3) / ln(100) particles
+    mean_work = 32.5 * (1e5 - 1e3) / math.log(100.0) * cells
+    out = {}
+    for prec in precisions:
+        # X: chunks deposited one at a time on one resident detector
+        det = radio.Detector.from_spec(specs[0], precision=prec)
+        probe = [c for _, c in items[:6]]
+        det.deposit(probe[0])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for c in probe:
+            det.deposit(c)
+        torch.cuda.synchronize()
+        x_rate = sum(c.n_particles * c.n_steps * cells for c in probe) / (time.perf_counter() - t)
+        det.close()
+        rate = load * x_rate / mean_work
+        # keep the stream to about a minute: fewer chunks when the device is slow
+        n_use = int(min(n_all, max(10, rate * 60.0)))
+        n_skip = max(1, n_use * n_warm // n_all)
+        offsets = poisson_arrivals(rate, n_use, seed=W.BASE_SEED + 501)
+        print(f"[bench] serve ({prec}): X = {x_rate:.3e} I/s, {rate:.2f} chunks/s, "
+              f"{n_use} chunks", file=sys.stderr, flush=True)
+
+        def progress(k):
+            if (k + 1) % 10 == 0:
+                print(f"[bench] serve ({prec}): {k + 1} chunks submitted", file=sys.stderr,
+                      flush=True)
+
+        t = time.perf_counter()
+        with DepositServer(specs, precision=prec) as srv:
+            replay(srv, items[:n_use], offsets, progress=progress)
+            srv.drain(timeout=600)
+            st = srv.summary(skip=n_skip)
+            for d in specs:
+                srv.finish(d, read="none")
+        print(f"[bench] serve ({prec}): {time.perf_counter() - t:.1f} s, p50 {st['p50_ms']:.0f} ms"
+              f", p99 {st['p99_ms']:.0f} ms, {st['interactions_per_s']:.3e} I/s",
+              file=sys.stderr, flush=True)
+        st["single_chunk_rate"] = x_rate
+        st["offered_chunks_per_s"] = rate
+        st["warmup_chunks"] = n_skip
+        out[prec] = st
+    del items
+    torch.cuda.synchronize()
+    return {"workload": f"{n_det} plasma-mirror detectors of {side}x{side} cells x {n_t} slots; "
+                        f"Poisson chunks of 1-64 steps x 10^3-10^5 particles",
+            "load": load, **out}
 
 
 def measured_traffic(precision, workload):
@@ -252,6 +332,9 @@ def main():
         out["mixed_twosum"] = legs["mixed_twosum"]
     if batch is not None:
         out["batch"] = batch
+    if not args.no_serve:
+        precs = [args.precision] + (["fp64"] if args.precision != "fp64" and not args.no_fp64 else [])
+        out["serve"] = serve_leg(radio, W, precs, args.serve_chunks, args.serve_load)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, args.cpu_cells)
         out["cpu_baseline"] = cb

@@ -150,9 +150,10 @@ RADIO_API int radio_deposit_trajectory_chunk(radio_detector* det, const radio_ch
  * from a device counter.  The result equals n separate
  * radio_deposit_trajectory_chunk calls (up to the order of floating-point
  * additions).  All detectors must live on the current device; a detector may
- * appear more than once.  On any invalid pair nothing is enqueued.  The
- * batch's workspace is shared by the device's batches: a call waits for the
- * previous batch on that device to finish before reusing it.
+ * appear more than once.  On any invalid pair nothing is enqueued.  Batch
+ * workspaces are shared by the device's batches, two in turn: a call waits
+ * (on the host) for the batch enqueued two calls earlier on that device to
+ * finish, so one batch can run while the next is prepared.
  */
 RADIO_API int radio_deposit_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
                         void* stream);

@@ -337,14 +337,21 @@ struct BatchArena {
     int n_cus = 0;
 };
 
+// Two arenas per device, used in turn: a batch can be prepared and enqueued
+// while the previous one still runs, and only the batch before that must have
+// finished.
+constexpr int kArenas = 2;
 std::mutex g_arena_mu;
-std::map<int, BatchArena*> g_arenas;
+std::map<int, BatchArena*> g_arenas[kArenas];
+std::map<int, int> g_arena_next;
 
 int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n, hipStream_t s,
                   int dev)
 {
     std::lock_guard<std::mutex> lk(g_arena_mu);
-    BatchArena*& A = g_arenas[dev];
+    const int which = g_arena_next[dev];
+    g_arena_next[dev] = (which + 1) % kArenas;
+    BatchArena*& A = g_arenas[which][dev];
     if (!A) {
         A = new (std::nothrow) BatchArena();
         if (!A)

@@ -471,3 +471,59 @@ def stream_schedule(n_chunks: int, n_detectors: int, seed: int, min_steps: int =
             cursor[d] = 0
         yield d, cursor[d], s, n
         cursor[d] += s
+
+
+def plasma_mirror_chunk(n_particles: int, s_begin: int, n_steps: int, seed: int,
+                        steps_total: int = 1000, periods: float = 10.0, gamma_peak: float = 10.0,
+                        half_width_wavelengths: float = 10.0, incidence: float = math.pi / 4,
+                        jitter: float = 0.01, q: float = -1.0) -> Chunk:
+    """A chunk of the plasma-mirror sheet as a running simulation would emit it.
+
+    Fresh particles drawn like plasma_mirror_sheet, states s_begin ..
+    s_begin + n_steps of a run of steps_total steps over `periods` laser
+    periods.  The position at s_begin follows the unjittered motion in closed
+    form (x = A (sin(t - k_y y0) + sin(k_y y0))); within the chunk positions
+    integrate the jittered beta with the trapezoid rule, so every step moves
+    less than c dt.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lam = 2.0 * math.pi
+    hw = half_width_wavelengths * lam
+    y0 = rng.uniform(-hw, hw, size=n_particles)
+    z0 = rng.uniform(-hw, hw, size=n_particles)
+    A = math.sqrt(1.0 - 1.0 / (gamma_peak * gamma_peak))
+    u_peak = gamma_peak * A
+    du = rng.normal(0.0, jitter * u_peak, size=(3, n_particles))
+    ky = math.sin(incidence)
+    dt = periods * lam / steps_total
+    t = (s_begin + np.arange(n_steps + 1, dtype=np.float64)) * dt
+    phase0 = ky * y0
+    x = np.empty((3, n_steps + 1, n_particles))
+    u = np.empty((3, n_steps + 1, n_particles))
+    pos = np.stack([A * (np.sin(t[0] - phase0) + np.sin(phase0)), y0, z0])
+    beta_prev = None
+    for s in range(n_steps + 1):
+        bx = A * np.cos(t[s] - phase0)
+        us = du.copy()
+        us[0] += bx / np.sqrt(1.0 - bx * bx)
+        u[:, s, :] = us
+        beta = us / np.sqrt(1.0 + (us * us).sum(axis=0))[None, :]
+        if beta_prev is not None:
+            pos = pos + 0.5 * dt * (beta_prev + beta)
+        x[:, s, :] = pos
+        beta_prev = beta
+    return Chunk(x=x, u=u, q=np.full(n_particles, q), t_first=float(t[0]), dt=dt)
+
+
+def plasma_mirror_detector(n_side: int = 256, n_t: int = 4096, seed: int = BASE_SEED + 3,
+                           sample_particles: int = 64) -> DetectorSpec:
+    """The plasma-mirror detector (cap about the specular direction at 1e5, +-0.1 rad)
+    with its window chosen from a sample of the whole 1000-step run."""
+    inc = math.pi / 4
+    axis = [-math.cos(inc), math.sin(inc), 0.0]
+    cells = sphere_cap_cells(1.0e5, axis, [math.sin(inc), math.cos(inc), 0.0], n_side, n_side,
+                             0.1, 0.1)
+    sample = plasma_mirror_sheet(sample_particles, 1000, periods=10.0, seed=seed)
+    t0, dtd = arrival_window(cells, sample, n_t, cell_index=grid_corner_cells(n_side, n_side),
+                             seed=seed)
+    return DetectorSpec(cells=cells, t0=t0, dt_det=dtd, n_t=n_t, grid=(n_side, n_side))
