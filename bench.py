@@ -44,7 +44,7 @@ def parse():
                     help="skip the batched-launch leg (64 uneven sets, one persistent launch "
                          "vs 64 separate launches)")
     ap.add_argument("--no-serve", action="store_true", help="skip the streaming-service leg")
-    ap.add_argument("--serve-chunks", type=int, default=40,
+    ap.add_argument("--serve-chunks", type=int, default=30,
                     help="timed chunks of the streaming leg (after a fifth as many warm-up)")
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="offered load as a fraction of the measured single-chunk throughput")

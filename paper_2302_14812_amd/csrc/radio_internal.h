@@ -43,21 +43,20 @@ static_assert(kGroups * kTileCells == kDepositThreads && (kGroups & (kGroups - 1
 constexpr int kRingMargin = 2;                          // ring slots kept below a batch's start
 constexpr int kXcds = 8;                                // accelerator dies sharing one L2 each
 
-// slots per cell in the LDS ring (a power of two): 48 B per slot for both
-// paths (6 doubles, or 6 compensated single pairs)
-#ifndef RADIO_RING_SLOTS
-#define RADIO_RING_SLOTS 16
+// Slots per cell in the LDS ring (powers of two), 48 B per slot in every mode
+// (6 doubles, or 6 compensated single pairs).  Each tile takes the small ring
+// when the slots a batch touches fit it (four workgroups per CU), else the
+// large one (two per CU): slowly advancing arrivals, where many segments
+// share a slot, fit the small ring; arrivals that cross a slot every segment
+// or two need the large one.
+#ifndef RADIO_RING_SMALL
+#define RADIO_RING_SMALL 16
 #endif
-template <typename T>
-struct RingSlots;
-template <>
-struct RingSlots<double> {
-    static constexpr int value = RADIO_RING_SLOTS;
-};
-template <>
-struct RingSlots<float> {
-    static constexpr int value = RADIO_RING_SLOTS;
-};
+#ifndef RADIO_RING_LARGE
+#define RADIO_RING_LARGE 64
+#endif
+constexpr int kRingSmall = RADIO_RING_SMALL;
+constexpr int kRingLarge = RADIO_RING_LARGE;
 
 // One (detector, chunk) deposit as the kernels see it.  Sizes are 64-bit; the
 // host runtime has validated every pointer and size before filling this in.
@@ -71,6 +70,7 @@ struct DepositJob {
     const double* q;                // [n_p] or nullptr (all -1)
     StateRec* recs;                 // workspace [n_p][n_s+1]
     int32_t* perm;                  // workspace [n_tiles][n_p]
+    uint8_t* ring_sel;              // workspace [n_tiles]: 1 where a tile takes the large ring
     int64_t n_c, n_t, n_p, n_s;
     double t_first, dt;             // state s at t_first + s*dt
     double t0, inv_dt_det;          // slot coordinate (t_det - t0) * inv_dt_det
@@ -96,10 +96,13 @@ hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
 hipError_t launch_kinematics(const DepositJob& job, hipStream_t s);
 hipError_t launch_order(const DepositJob& job, hipStream_t s);
+hipError_t launch_ring_choice(const DepositJob& job, hipStream_t s);
 hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s);
+// next: two work counters (small-ring and large-ring workgroups)
 hipError_t launch_deposit_batch(const DepositJob* jobs, const WorkItem* items, int64_t n_items,
-                                unsigned long long* next, int mode, int n_blocks, hipStream_t s);
-int persistent_blocks_per_cu(int mode);
+                                unsigned long long* next, int mode, int blocks_small,
+                                int blocks_large, hipStream_t s);
+int persistent_blocks_per_cu(int mode, bool large_ring);
 hipError_t launch_readout(const double* acc, int64_t n_c, int64_t n_t, const int64_t* user_index,
                           bool pairs, double* E, double* B, hipStream_t s);
 hipError_t launch_arrival(const double* cells, const double* pts, const double* t, int64_t n,

@@ -4,7 +4,7 @@
 // Lienard-Wiechert field (Eq. 1) of the segment's current state and the
 // arrival times of its two end states (Eq. 2), and adds the field held
 // between those arrival times to the detector slots with the integrator
-// weights of Sec. 3.2 / Alg. 2.  Three kernels run per deposit:
+// weights of Sec. 3.2 / Alg. 2.  Four kernels run per deposit:
 //
 // 1. kinematics_kernel (Alg. 1, velocity and acceleration lines): one thread
 //    per trajectory state turns (x, u) into a 96-byte record with x, beta,
@@ -16,18 +16,23 @@
 //    the chunk's middle state.  Processing particles in that order makes the
 //    arrival slots a tile's cells see advance nearly monotonically.
 //
-// 3. deposit_kernel: one workgroup per (tile, range of runs).  Lane
-//    (cell, group) = (lane / kGroups, lane % kGroups): the kTileCells cells of
-//    the tile each get kGroups lanes, and the lanes of one group walk the
-//    same particle.  Trajectories are cut into runs of kRunL segments; a batch
-//    of kGroups particles (consecutive in the tile's order) x (kRunL + 1)
-//    states is staged in LDS and each lane walks its particle's run against
-//    its cell.  The lane integrates the held field over its current slot with
-//    the exact slot-unit overlaps of Alg. 2 and emits slot-value differences
-//    only when its arrivals move on; emissions go to a per-cell ring of slots
-//    in LDS that slides forward as the sorted batches advance, and only slots
-//    leaving the ring (or emissions that fall outside it) reach the detector
-//    in HBM, through atomic adds.
+// 3. ring_choice_kernel: per tile, whether the arrivals a batch touches fit
+//    the small LDS ring (slow advance, many segments per slot) or need the
+//    large one (a slot crossed every segment or two); it samples batches.
+//
+// 4. deposit_kernel: one workgroup per (tile, range of runs), launched once
+//    per ring size; tiles of the other size leave at once.  Lane
+//    (cell, group) = (lane % kTileCells, lane / kTileCells): the kTileCells
+//    cells of the tile each get kGroups lanes, and the lanes of one group walk
+//    the same particle.  Trajectories are cut into runs of kRunL segments; a
+//    batch of kGroups particles (consecutive in the tile's order) x
+//    (kRunL + 1) states is staged in LDS and each lane walks its particle's
+//    run against its cell.  The lane integrates the held field over its
+//    current slot with the exact slot-unit overlaps of Alg. 2 and emits
+//    slot-value differences only when its arrivals move on; emissions go to a
+//    per-cell ring of slots in LDS that slides forward as the sorted batches
+//    advance, and only slots leaving the ring (or emissions that fall outside
+//    it) reach the detector in HBM, through atomic adds.
 //
 // Slot-difference accumulator.  The detector stores, per cell and slot, the
 // difference between consecutive slot values; the readout turns differences
@@ -37,6 +42,7 @@
 // the order of the particles only change rounding.
 #include "radio_internal.h"
 
+#include <climits>
 #include <type_traits>
 
 namespace radio {
@@ -194,12 +200,11 @@ __device__ __forceinline__ void global_add_pair(RADIO_GLOBAL float* row, int j, 
 // float): the pair hi[6], lo[6] per slot, updated like the HBM pair -- the LDS
 // atomic returns the old hi and the lane adds the rounding error of its own
 // add (two-sum) to lo.
-template <typename Acc>
+template <typename Acc, int R>
 struct CellSink;
 
-template <>
-struct CellSink<double> {
-    static constexpr int R = RingSlots<double>::value;
+template <int R>
+struct CellSink<double, R> {
     static constexpr int W = 6;  // values per ring slot
     RADIO_LDS double* ring;
     RADIO_GLOBAL double* row;
@@ -227,9 +232,8 @@ struct CellSink<double> {
     }
 };
 
-template <>
-struct CellSink<float> {
-    static constexpr int R = RingSlots<float>::value;
+template <int R>
+struct CellSink<float, R> {
     static constexpr int W = 12;  // hi[6], lo[6]
     RADIO_LDS float* ring;
     RADIO_GLOBAL float* row;
@@ -601,6 +605,78 @@ __global__ __launch_bounds__(256) void order_kernel(const double* __restrict__ x
     }
 }
 
+// For every tile, whether its batches need the large slot ring.  Samples
+// batches of the first and the middle run in the tile's particle order and
+// takes the largest spread of their slot coordinates at the tile's centre over
+// kGroups particles x (kRunL + 1) states; a tile whose spread, with the ring's
+// margin, exceeds the small ring takes the large one.  Only speed depends on
+// this choice: emissions outside a ring go to HBM directly.
+constexpr int kChoiceBatches = 8;  // sampled batches per sampled run
+
+__global__ __launch_bounds__(256) void ring_choice_kernel(const StateRec* __restrict__ recs,
+                                                          const int32_t* __restrict__ perm,
+                                                          const double* __restrict__ cells,
+                                                          int64_t n_c, int64_t n_p, int64_t n_s,
+                                                          int64_t n_runs, double t_first,
+                                                          double dt, double t0, double inv_dt_det,
+                                                          double inv_c, int64_t n_t,
+                                                          uint8_t* __restrict__ sel)
+{
+    constexpr int kSamples = 2 * kChoiceBatches;
+    constexpr int kPer = kGroups * (kRunL + 1);
+    __shared__ int lo[kSamples], hi[kSamples];
+    __shared__ double ctr[3];
+    const int tid = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const int64_t c0 = tile * kTileCells;
+    const int64_t c1 = min(c0 + (int64_t)kTileCells, n_c);
+    if (tid < 3) {
+        double sum = 0.0;
+        for (int64_t c = c0; c < c1; ++c)
+            sum += cells[3 * c + tid];
+        ctr[tid] = sum / (double)(c1 - c0);
+    }
+    if (tid < kSamples) {
+        lo[tid] = INT_MAX;
+        hi[tid] = INT_MIN;
+    }
+    __syncthreads();
+    const int64_t n_states = n_s + 1;
+    const int64_t n_batches = (n_p + kGroups - 1) / kGroups;
+    const double lim = (double)n_t + 1.0;
+    for (int i = tid; i < kSamples * kPer; i += 256) {
+        const int smp = i / kPer;
+        const int rem = i - smp * kPer;
+        const int gg = rem / (kRunL + 1);
+        const int k = rem - gg * (kRunL + 1);
+        const int64_t run = (smp < kChoiceBatches) ? 0 : n_runs / 2;
+        const int64_t bt = (2 * (int64_t)(smp % kChoiceBatches) + 1) * n_batches / (2 * kChoiceBatches);
+        const int64_t st = run * kRunL + k;
+        const int64_t pi = bt * kGroups + gg;
+        if (st > n_s || pi >= n_p)
+            continue;
+        const int64_t p = perm[tile * n_p + pi];
+        const StateRec& r = recs[p * n_states + st];
+        const double d0 = ctr[0] - r.x[0], d1 = ctr[1] - r.x[1], d2 = ctr[2] - r.x[2];
+        const double tau = (t_first + (double)st * dt) + __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2) * inv_c;
+        double u = (tau - t0) * inv_dt_det;
+        if (!(u == u))
+            continue;
+        u = fmin(fmax(u, -1.0), lim);
+        const int f = (int)floor(u);
+        atomicMin(&lo[smp], f);
+        atomicMax(&hi[smp], f);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int span = 0;
+        for (int i = 0; i < kSamples; ++i)
+            if (hi[i] >= lo[i])
+                span = max(span, hi[i] - lo[i]);
+        sel[tile] = (span + kRingMargin + 2 > kRingSmall) ? 1 : 0;
+    }
+}
+
 // M: arithmetic of the deposit (field in double or single; accumulation in
 // double or compensated single pairs)
 template <int M>
@@ -608,36 +684,42 @@ struct ModeTypes {
     static constexpr bool MIX = (M != kModeF64);
     using T = typename std::conditional<MIX, float, double>::type;  // field and lane carry
     using Acc = typename std::conditional<M == kModeMixTwoSum, float, double>::type;
-    using Sink = CellSink<Acc>;
 };
 
-// LDS of one deposit workgroup
-template <int M>
+// LDS of one deposit workgroup with rings of R slots
+template <int M, int R>
 struct DepositShared {
     using Acc = typename ModeTypes<M>::Acc;
+    // one cell's ring, padded by one word so that the rings of the kTileCells
+    // cells, which one instruction updates together, start in different banks
+    static constexpr int kStride = R * CellSink<Acc, R>::W + 1;
     StateRec rec[kGroups][kRunL + 1];   // staged batch: one run per particle group
     double sq[kGroups];                 // its charges
-    Acc ring[kTileCells][CellSink<Acc>::R][CellSink<Acc>::W];  // per-cell slot rings
+    Acc ring[kTileCells * kStride];     // per-cell slot rings
+    int nb[2][kTileCells];              // per cell: lowest start slot of a coming batch
     unsigned long long cnt[3];          // clipped, nonmonotone, bypassed
 };
 
 // One work item: a tile of kTileCells cells against the runs
 // [split * runs_per_split, ...) of every particle of job J, in the tile's
 // particle order.  Called by all kDepositThreads threads of a workgroup.
-template <int M>
+// Lane (cell, group) = (lane % kTileCells, lane / kTileCells): the sixteen
+// lanes of a wavefront's row hold different cells, so one ring update
+// instruction touches different rings, and the four groups of a wavefront
+// read their particles' records as LDS broadcasts.
+template <int M, int R>
 __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, int64_t split,
-                                             DepositShared<M>& sh)
+                                             DepositShared<M, R>& sh)
 {
     constexpr bool MIX = ModeTypes<M>::MIX;
     using T = typename ModeTypes<M>::T;
     using Acc = typename ModeTypes<M>::Acc;
-    using Sink = typename ModeTypes<M>::Sink;
-    constexpr int R = Sink::R;
+    using Sink = CellSink<Acc, R>;
     constexpr int RW = Sink::W;
 
     const int tid = threadIdx.x;
-    const int cl = tid / kGroups;  // cell within the tile
-    const int g = tid % kGroups;   // particle group
+    const int cl = tid % kTileCells;  // cell within the tile
+    const int g = tid / kTileCells;   // particle group
     const int64_t row_i = tile * kTileCells + cl;  // internal (tile-ordered) cell row
     const bool active = row_i < J.n_c;
     const int n_t = (int)J.n_t;
@@ -651,20 +733,46 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         xc[2] = cells[3 * row_i + 2];
         row = gptr(reinterpret_cast<Acc*>(J.acc + row_i * J.n_t * 6));
     }
-    RADIO_LDS Acc* my_ring = (RADIO_LDS Acc*)&sh.ring[cl][0][0];
+    RADIO_LDS Acc* my_ring = (RADIO_LDS Acc*)&sh.ring[cl * DepositShared<M, R>::kStride];
+    RADIO_LDS int* nb = (RADIO_LDS int*)&sh.nb[0][0];
     for (int i = g; i < R * RW; i += kGroups)
         my_ring[i] = Acc(0);
     if (tid < 3)
         sh.cnt[tid] = 0;
+    if (tid < 2 * kTileCells)
+        nb[tid] = INT_MAX;
     int base = -1;  // ring covers [base, base + R); -1 until the first batch
     unsigned n_clip = 0, n_back = 0, n_bypass = 0;
     const RADIO_GLOBAL int32_t* order = gptr(J.perm + tile * J.n_p);
     const RADIO_GLOBAL double* charges = J.q ? gptr(J.q) : nullptr;
     const int64_t n_states = J.n_s + 1;
     const int64_t n_batches = (J.n_p + kGroups - 1) / kGroups;
+    const int64_t rb_begin = split * J.runs_per_split;
+    const int64_t rb_end = min(rb_begin + J.runs_per_split, J.n_runs);
+    const int64_t n_it = (rb_end - rb_begin) * n_batches;  // batches of this item, run-major
 
-    // Move the ring to start at new_base: slots leaving it go to HBM.  Only the
-    // cell's own kGroups lanes (one wavefront) touch its ring.
+    // Lowest slot where the lane's particle of batch `it` starts, into nb[buf][cell]
+    // (from the record in HBM, so a batch's ring position is known before it is staged).
+    auto scout = [&](int64_t it, int buf) {
+        const int64_t i = (it % n_batches) * kGroups + g;
+        if (!active || i >= J.n_p)
+            return;
+        const int64_t s_a = (rb_begin + it / n_batches) * kRunL;
+        const RADIO_GLOBAL double* xr =
+            gptr(reinterpret_cast<const double*>(J.recs + order[i] * n_states + s_a));
+        const double d0 = xc[0] - xr[0], d1 = xc[1] - xr[1], d2 = xc[2] - xr[2];
+        const double tau = canon_state_time(J.t_first, (int)s_a, J.dt) +
+                           __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2) * K.inv_c;
+        const double u = (tau - K.t0) * K.inv_dt_det;
+        if (u == u) {
+            const int f = (int)floor(fmin(fmax(u, -1.0), (double)n_t + 1.0));
+            __hip_atomic_fetch_min(nb + buf * kTileCells + cl, f, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    };
+
+    // Move the ring to start at new_base: slots leaving it go to HBM.  The
+    // cell's kGroups lanes share the work.
     auto move_ring = [&](int new_base) {
         if (base >= 0 && active) {
             int lo = base, hi = base + R;  // slots to flush
@@ -691,73 +799,75 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         base = new_base;
     };
 
-    const int64_t rb_begin = split * J.runs_per_split;
-    const int64_t rb_end = min(rb_begin + J.runs_per_split, J.n_runs);
-    for (int64_t rb = rb_begin; rb < rb_end; ++rb) {
+    __syncthreads();  // rings and start slots cleared
+    if (n_it > 0)
+        scout(0, 0);
+    __syncthreads();
+    for (int64_t it = 0; it < n_it; ++it) {
+        const int buf = (int)(it & 1);
+        const int64_t rb = rb_begin + it / n_batches;
+        const int64_t bt = it % n_batches;
         const int64_t s_a = rb * kRunL;
         const int len = (int)min((int64_t)kRunL, J.n_s - s_a);
         const double t_a = canon_state_time(J.t_first, (int)s_a, J.dt);
-        for (int64_t bt = 0; bt < n_batches; ++bt) {
-            const int64_t i0 = bt * kGroups;
-            const int np = (int)min((int64_t)kGroups, J.n_p - i0);
-            __syncthreads();  // the previous batch's readers are done with the LDS
-            // stage: particle order[i0 + gg], states s_a .. s_a + len (contiguous)
-            {
-                constexpr int kChunks = (int)(sizeof(StateRec) / 16);  // 16-byte pieces
-                const int per = (len + 1) * kChunks;
-                for (int i = tid; i < kGroups * per; i += kDepositThreads) {
-                    const int gg = i / per;
-                    const int r = i - gg * per;
-                    if (gg < np) {
-                        const int64_t p = order[i0 + gg];
-                        const RADIO_GLOBAL v2i64* src =
-                            gptr(reinterpret_cast<const v2i64*>(J.recs + p * n_states + s_a)) + r;
-                        reinterpret_cast<v2i64*>(&sh.rec[gg][0])[r] = *src;
-                    }
-                }
-                if (tid < kGroups)
-                    sh.sq[tid] = (tid < np) ? (charges ? charges[order[i0 + tid]] : -1.0) : 0.0;
-            }
-            __syncthreads();
-            const bool mine = active && g < np;
-            double u_prev = 1e300;
-            if (mine)
-                u_prev = MIX ? slot_coord_mixed(xc, sh.rec[g][0], t_a, K)
-                             : slot_coord_fp64(xc, sh.rec[g][0], t_a, K);
-            // ring start for this batch: the earliest start among the cell's lanes
-            double m = u_prev;
-#pragma unroll
-            for (int off = kGroups / 2; off > 0; off >>= 1)
-                m = fmin(m, __shfl_xor(m, off, kGroups));
-            if (m < 1e299) {
-                const double mc = fmin(fmax(floor(m) - (double)kRingMargin, 0.0),
-                                       fmax((double)(n_t - R), 0.0));
-                const int nb = (int)mc;
-                if (nb != base)
-                    move_ring(nb);
-            }
-            if (mine) {
-                Sink sink{my_ring, row, base, n_t, &n_bypass};
-                Carry<T> C;
-                carry_init(C);
-                const double q = sh.sq[g];
-                for (int k = 1; k <= len; ++k) {
-                    T F[6];
-                    const double t_s = canon_state_time(J.t_first, (int)s_a + k, J.dt);
-                    double uk;
-                    if constexpr (MIX)
-                        uk = field_mixed(xc, sh.rec[g][k], t_s, (float)q, K, F);
-                    else
-                        uk = field_fp64(xc, sh.rec[g][k], t_s, q, K, F);
-                    const bool back = uk < u_prev;
-                    n_back += back ? 1u : 0u;
-                    n_clip += (fmin(uk, u_prev) < 0.0 || fmax(uk, u_prev) > (double)n_t) ? 1u : 0u;
-                    add_segment(C, sink, n_t, u_prev, uk, F);
-                    u_prev = uk;
-                }
-                carry_close(C, sink, n_t);
-            }
+        const int64_t i0 = bt * kGroups;
+        const int np = (int)min((int64_t)kGroups, J.n_p - i0);
+        // slide the ring to this batch's earliest start (every lane of the
+        // previous batch is past the barrier that ended it)
+        const int lo_slot = nb[buf * kTileCells + cl];
+        if (lo_slot != INT_MAX) {
+            const double mc = fmin(fmax((double)lo_slot - (double)kRingMargin, 0.0),
+                                   fmax((double)(n_t - R), 0.0));
+            const int nbase = (int)mc;
+            if (nbase != base)
+                move_ring(nbase);
         }
+        // stage: particle order[i0 + gg], states s_a .. s_a + len (contiguous)
+        {
+            constexpr int kChunks = (int)(sizeof(StateRec) / 16);  // 16-byte pieces
+            const int per = (len + 1) * kChunks;
+            for (int i = tid; i < kGroups * per; i += kDepositThreads) {
+                const int gg = i / per;
+                const int r = i - gg * per;
+                if (gg < np) {
+                    const int64_t p = order[i0 + gg];
+                    const RADIO_GLOBAL v2i64* src =
+                        gptr(reinterpret_cast<const v2i64*>(J.recs + p * n_states + s_a)) + r;
+                    reinterpret_cast<v2i64*>(&sh.rec[gg][0])[r] = *src;
+                }
+            }
+            if (tid < kGroups)
+                sh.sq[tid] = (tid < np) ? (charges ? charges[order[i0 + tid]] : -1.0) : 0.0;
+        }
+        if (it + 1 < n_it)
+            scout(it + 1, buf ^ 1);
+        __syncthreads();
+        if (tid < kTileCells)  // read by every lane before the barrier; next used two batches on
+            nb[buf * kTileCells + tid] = INT_MAX;
+        if (active && g < np) {
+            Sink sink{my_ring, row, base, n_t, &n_bypass};
+            Carry<T> C;
+            carry_init(C);
+            const double q = sh.sq[g];
+            double u_prev = MIX ? slot_coord_mixed(xc, sh.rec[g][0], t_a, K)
+                                : slot_coord_fp64(xc, sh.rec[g][0], t_a, K);
+            for (int k = 1; k <= len; ++k) {
+                T F[6];
+                const double t_s = canon_state_time(J.t_first, (int)s_a + k, J.dt);
+                double uk;
+                if constexpr (MIX)
+                    uk = field_mixed(xc, sh.rec[g][k], t_s, (float)q, K, F);
+                else
+                    uk = field_fp64(xc, sh.rec[g][k], t_s, q, K, F);
+                const bool back = uk < u_prev;
+                n_back += back ? 1u : 0u;
+                n_clip += (fmin(uk, u_prev) < 0.0 || fmax(uk, u_prev) > (double)n_t) ? 1u : 0u;
+                add_segment(C, sink, n_t, u_prev, uk, F);
+                u_prev = uk;
+            }
+            carry_close(C, sink, n_t);
+        }
+        __syncthreads();  // records and rings are free for the next batch
     }
     move_ring(-1);  // flush what the ring still holds
     if (n_clip)
@@ -772,11 +882,12 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
                                __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One workgroup per work item of a single deposit.
-template <int M>
+// One workgroup per work item of a single deposit; the tiles that take the
+// other ring size leave at once.
+template <int M, int R>
 __global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
 {
-    __shared__ __align__(16) DepositShared<M> sh;
+    __shared__ __align__(16) DepositShared<M, R> sh;
     // Workgroups are dealt round-robin over the XCDs; give each XCD a contiguous
     // range of (split, tile) indices so that neighbouring tiles, whose particle
     // orders and record batches are alike, share that XCD's L2.
@@ -784,19 +895,23 @@ __global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
     const int64_t logical = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
     if (logical >= J.n_tiles * J.n_splits)
         return;
-    deposit_item<M>(J, logical % J.n_tiles, logical / J.n_tiles, sh);
+    const int64_t tile = logical % J.n_tiles;
+    if (gptr(J.ring_sel)[tile] != (R == kRingLarge ? 1 : 0))
+        return;
+    deposit_item<M, R>(J, tile, logical / J.n_tiles, sh);
 }
 
 // Persistent workgroups for many independent deposits: each takes the next work
 // item (largest first, as ordered by the host) from a device counter until
 // the list is exhausted, so uneven jobs share one launch without a tail of idle
-// workgroups.  Every workgroup leaves once the counter passes n_items.
-template <int M>
+// workgroups; items whose tile takes the other ring size are skipped.  Every
+// workgroup leaves once the counter passes n_items.
+template <int M, int R>
 __global__ __launch_bounds__(kDepositThreads) void deposit_persistent_kernel(
     const DepositJob* __restrict__ jobs, const WorkItem* __restrict__ items, int64_t n_items,
     unsigned long long* __restrict__ next)
 {
-    __shared__ __align__(16) DepositShared<M> sh;
+    __shared__ __align__(16) DepositShared<M, R> sh;
     __shared__ int64_t cur;
     for (;;) {
         __syncthreads();  // everyone has read the previous `cur`
@@ -808,7 +923,9 @@ __global__ __launch_bounds__(kDepositThreads) void deposit_persistent_kernel(
             break;
         const WorkItem w = items[it];
         const DepositJob J = jobs[w.job];
-        deposit_item<M>(J, w.tile, w.split, sh);
+        if (gptr(J.ring_sel)[w.tile] != (R == kRingLarge ? 1 : 0))
+            continue;
+        deposit_item<M, R>(J, w.tile, w.split, sh);
     }
 }
 
@@ -965,58 +1082,87 @@ hipError_t launch_order(const DepositJob& job, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_ring_choice(const DepositJob& job, hipStream_t s)
+{
+    if (job.n_tiles <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(ring_choice_kernel, dim3((unsigned)job.n_tiles), dim3(256), 0, s, job.recs,
+                       job.perm, job.cells, job.n_c, job.n_p, job.n_s, job.n_runs, job.t_first,
+                       job.dt, job.t0, job.inv_dt_det, job.inv_c, job.n_t, job.ring_sel);
+    return hipGetLastError();
+}
+
+template <int M>
+static void launch_deposit_mode(const DepositJob& job, dim3 grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((deposit_kernel<M, kRingSmall>), grid, dim3(kDepositThreads), 0, s, job);
+    hipLaunchKernelGGL((deposit_kernel<M, kRingLarge>), grid, dim3(kDepositThreads), 0, s, job);
+}
+
 hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s)
 {
     int64_t blocks = job.n_tiles * job.n_splits;
     if (blocks <= 0)
         return hipSuccess;
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;  // a multiple of the XCD count
-    const dim3 grid((unsigned)blocks), block(kDepositThreads);
+    const dim3 grid((unsigned)blocks);
     if (mode == kModeMix)
-        hipLaunchKernelGGL(deposit_kernel<kModeMix>, grid, block, 0, s, job);
+        launch_deposit_mode<kModeMix>(job, grid, s);
     else if (mode == kModeMixTwoSum)
-        hipLaunchKernelGGL(deposit_kernel<kModeMixTwoSum>, grid, block, 0, s, job);
+        launch_deposit_mode<kModeMixTwoSum>(job, grid, s);
     else
-        hipLaunchKernelGGL(deposit_kernel<kModeF64>, grid, block, 0, s, job);
+        launch_deposit_mode<kModeF64>(job, grid, s);
     return hipGetLastError();
+}
+
+template <int M>
+static void launch_persistent_mode(const DepositJob* jobs, const WorkItem* items, int64_t n_items,
+                                   unsigned long long* next, int blocks_small, int blocks_large,
+                                   hipStream_t s)
+{
+    hipLaunchKernelGGL((deposit_persistent_kernel<M, kRingSmall>), dim3((unsigned)blocks_small),
+                       dim3(kDepositThreads), 0, s, jobs, items, n_items, next);
+    hipLaunchKernelGGL((deposit_persistent_kernel<M, kRingLarge>), dim3((unsigned)blocks_large),
+                       dim3(kDepositThreads), 0, s, jobs, items, n_items, next + 1);
 }
 
 hipError_t launch_deposit_batch(const DepositJob* jobs, const WorkItem* items, int64_t n_items,
-                                unsigned long long* next, int mode, int n_blocks, hipStream_t s)
+                                unsigned long long* next, int mode, int blocks_small,
+                                int blocks_large, hipStream_t s)
 {
     if (n_items <= 0)
         return hipSuccess;
-    hipError_t e = launch_zero_u64(next, 1, s);
+    hipError_t e = launch_zero_u64(next, 2, s);
     if (e != hipSuccess)
         return e;
-    const dim3 grid((unsigned)n_blocks), block(kDepositThreads);
     if (mode == kModeMix)
-        hipLaunchKernelGGL(deposit_persistent_kernel<kModeMix>, grid, block, 0, s, jobs, items,
-                           n_items, next);
+        launch_persistent_mode<kModeMix>(jobs, items, n_items, next, blocks_small, blocks_large, s);
     else if (mode == kModeMixTwoSum)
-        hipLaunchKernelGGL(deposit_persistent_kernel<kModeMixTwoSum>, grid, block, 0, s, jobs, items,
-                           n_items, next);
+        launch_persistent_mode<kModeMixTwoSum>(jobs, items, n_items, next, blocks_small,
+                                               blocks_large, s);
     else
-        hipLaunchKernelGGL(deposit_persistent_kernel<kModeF64>, grid, block, 0, s, jobs, items,
-                           n_items, next);
+        launch_persistent_mode<kModeF64>(jobs, items, n_items, next, blocks_small, blocks_large, s);
     return hipGetLastError();
 }
 
-int persistent_blocks_per_cu(int mode)
+template <int M>
+static int blocks_per_cu(bool large_ring)
 {
     int n = 0;
-    hipError_t e;
-    if (mode == kModeMix)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, reinterpret_cast<const void*>(deposit_persistent_kernel<kModeMix>), kDepositThreads, 0);
-    else if (mode == kModeMixTwoSum)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, reinterpret_cast<const void*>(deposit_persistent_kernel<kModeMixTwoSum>),
-            kDepositThreads, 0);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, reinterpret_cast<const void*>(deposit_persistent_kernel<kModeF64>), kDepositThreads, 0);
+    const void* f = large_ring
+                        ? reinterpret_cast<const void*>(deposit_persistent_kernel<M, kRingLarge>)
+                        : reinterpret_cast<const void*>(deposit_persistent_kernel<M, kRingSmall>);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kDepositThreads, 0);
     return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+int persistent_blocks_per_cu(int mode, bool large_ring)
+{
+    if (mode == kModeMix)
+        return blocks_per_cu<kModeMix>(large_ring);
+    if (mode == kModeMixTwoSum)
+        return blocks_per_cu<kModeMixTwoSum>(large_ring);
+    return blocks_per_cu<kModeF64>(large_ring);
 }
 
 hipError_t launch_readout(const double* acc, int64_t n_c, int64_t n_t, const int64_t* user_index,

@@ -33,6 +33,8 @@ struct radio_detector {
     size_t recs_cap = 0;                       // in records
     int32_t* d_perm = nullptr;                 // workspace, grown on demand
     size_t perm_cap = 0;                       // in entries
+    uint8_t* d_sel = nullptr;                  // workspace: ring size per tile
+    size_t sel_cap = 0;
     int64_t interactions = 0;
     int64_t chunks = 0;
     std::vector<double> h_cells;               // caller's order
@@ -305,11 +307,15 @@ int enqueue_deposit(radio_detector* det, const radio_chunk* k, hipStream_t s)
     if (rc != RADIO_OK)
         return rc;
     rc = grow(&det->d_perm, &det->perm_cap, (size_t)(J.n_tiles * J.n_p));
+    if (rc == RADIO_OK)
+        rc = grow(&det->d_sel, &det->sel_cap, (size_t)J.n_tiles);
     if (rc != RADIO_OK)
         return rc;
     J.recs = det->d_recs;
     J.perm = det->d_perm;
+    J.ring_sel = det->d_sel;
     if (radio::launch_kinematics(J, s) != hipSuccess || radio::launch_order(J, s) != hipSuccess ||
+        radio::launch_ring_choice(J, s) != hipSuccess ||
         radio::launch_deposit(J, det->precision, s) != hipSuccess)
         return RADIO_EDEVICE;
     det->interactions += k->n_particles * k->n_steps * det->n_c;
@@ -325,11 +331,13 @@ struct BatchArena {
     size_t jobs_cap = 0;
     radio::WorkItem* d_items = nullptr;
     size_t items_cap = 0;
-    unsigned long long* d_next = nullptr;  // one counter per precision mode
+    unsigned long long* d_next = nullptr;  // two counters (ring sizes) per precision mode
     radio::StateRec* d_recs = nullptr;
     size_t recs_cap = 0;
     int32_t* d_perm = nullptr;
     size_t perm_cap = 0;
+    uint8_t* d_sel = nullptr;
+    size_t sel_cap = 0;
     hipEvent_t done = nullptr;
     bool pending = false;
     std::vector<radio::DepositJob> h_jobs;
@@ -359,7 +367,7 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, dev) != hipSuccess ||
             hipEventCreateWithFlags(&A->done, hipEventDisableTiming) != hipSuccess ||
-            hipMalloc((void**)&A->d_next, 3 * sizeof(unsigned long long)) != hipSuccess) {
+            hipMalloc((void**)&A->d_next, 6 * sizeof(unsigned long long)) != hipSuccess) {
             (void)hipGetLastError();
             return RADIO_EDEVICE;
         }
@@ -373,7 +381,7 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
     // plan every nonempty pair
     const radio_tuning tun = current_tuning();
     std::vector<int> idx;
-    size_t recs_need = 0, perm_need = 0;
+    size_t recs_need = 0, perm_need = 0, sel_need = 0;
     A->h_jobs.clear();
     for (int i = 0; i < n; ++i) {
         const radio_chunk* k = &chunks[i];
@@ -382,6 +390,7 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
         radio::DepositJob J = make_job(dets[i], k);
         recs_need += (size_t)(J.n_p * (J.n_s + 1));
         perm_need += (size_t)(J.n_tiles * J.n_p);
+        sel_need += (size_t)J.n_tiles;
         A->h_jobs.push_back(J);
         idx.push_back(i);
     }
@@ -394,6 +403,8 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
     if (rc == RADIO_OK)
         rc = grow(&A->d_perm, &A->perm_cap, perm_need);
     if (rc == RADIO_OK)
+        rc = grow(&A->d_sel, &A->sel_cap, sel_need);
+    if (rc == RADIO_OK)
         rc = grow(&A->d_jobs, &A->jobs_cap, A->h_jobs.size());
     if (rc != RADIO_OK)
         return rc;
@@ -402,10 +413,11 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
     for (const auto& J : A->h_jobs)
         total += (double)J.n_c * (double)J.n_p * (double)J.n_s;
     const int n_modes = 3;
-    int bpc[n_modes];
+    int bpc[n_modes][2];  // resident workgroups per CU: [mode][large ring]
     for (int m = 0; m < n_modes; ++m)
-        bpc[m] = radio::persistent_blocks_per_cu(m);
-    const double resident = (double)A->n_cus * (double)bpc[0];
+        for (int r = 0; r < 2; ++r)
+            bpc[m][r] = radio::persistent_blocks_per_cu(m, r == 1);
+    const double resident = (double)A->n_cus * (double)bpc[0][0];
     const double item_work = std::max(total / (resident * (double)tun.items_per_workgroup), 1.0);
     struct Item {
         radio::WorkItem w;
@@ -413,13 +425,15 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
         int mode;
     };
     std::vector<Item> items;
-    size_t ro = 0, po = 0;
+    size_t ro = 0, po = 0, so = 0;
     for (size_t j = 0; j < A->h_jobs.size(); ++j) {
         radio::DepositJob& J = A->h_jobs[j];
         J.recs = A->d_recs + ro;
         J.perm = A->d_perm + po;
+        J.ring_sel = A->d_sel + so;
         ro += (size_t)(J.n_p * (J.n_s + 1));
         po += (size_t)(J.n_tiles * J.n_p);
+        so += (size_t)J.n_tiles;
         const double run_work = (double)radio::kTileCells * (double)J.n_p * (double)radio::kRunL;
         int64_t rps = (int64_t)std::ceil(item_work / run_work);
         rps = std::max<int64_t>(1, std::min<int64_t>(rps, J.n_runs));
@@ -432,7 +446,8 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
                 items.push_back({{(int32_t)j, (int32_t)t, (int32_t)sp, 0},
                                  (double)runs * run_work, mode});
         }
-        if (radio::launch_kinematics(J, s) != hipSuccess || radio::launch_order(J, s) != hipSuccess)
+        if (radio::launch_kinematics(J, s) != hipSuccess || radio::launch_order(J, s) != hipSuccess ||
+            radio::launch_ring_choice(J, s) != hipSuccess)
             return RADIO_EDEVICE;
     }
     std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
@@ -455,9 +470,9 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
         size_t e = b;
         while (e < items.size() && items[e].mode == mode)
             ++e;
-        const int blocks = A->n_cus * bpc[mode];
         if (radio::launch_deposit_batch(A->d_jobs, A->d_items + b, (int64_t)(e - b),
-                                        A->d_next + mode, mode, blocks, s) != hipSuccess)
+                                        A->d_next + 2 * mode, mode, A->n_cus * bpc[mode][0],
+                                        A->n_cus * bpc[mode][1], s) != hipSuccess)
             return RADIO_EDEVICE;
         b = e;
     }
@@ -587,6 +602,8 @@ int radio_detector_destroy(radio_detector* det)
             (void)hipFree(det->d_recs);
         if (det->d_perm)
             (void)hipFree(det->d_perm);
+        if (det->d_sel)
+            (void)hipFree(det->d_sel);
     }
     delete det;
     return rc;
@@ -703,7 +720,7 @@ int radio_detector_stats(const radio_detector* det, radio_stats* out)
                            det->n_c * (int64_t)sizeof(int64_t) +
                            3 * (int64_t)sizeof(unsigned long long) +
                            (int64_t)(det->recs_cap * sizeof(radio::StateRec)) +
-                           (int64_t)(det->perm_cap * sizeof(int32_t)));
+                           (int64_t)(det->perm_cap * sizeof(int32_t)) + (int64_t)det->sel_cap);
     return RADIO_OK;
 }
 
