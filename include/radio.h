@@ -92,8 +92,11 @@ typedef struct radio_detector_desc {
 } radio_detector_desc;
 
 /*
- * A chunk of trajectory: n_steps + 1 states of n_particles particles, state s
- * at time t_first + s*dt.  Segment s (1..n_steps) joins states s-1 and s and
+ * A chunk of trajectory: n_steps + 1 states of n_particles particles.  State s
+ * of the chunk is state first_step + s of its run, at time
+ * t_first + (first_step + s)*dt (time step n of a run sits at n*dt, Sec. 3.1),
+ * so a chunk cut out of a longer one keeps the exact state times of the
+ * whole.  Segment s (1..n_steps) joins states s-1 and s and
  * carries the field of state s (beta_s, betadot_s = (beta_s - beta_{s-1})/dt),
  * as Alg. 1 passes the current step's E(n, beta, betadot) to the deposit.
  * Streaming: consecutive chunks share one state (state 0 of a chunk is the
@@ -103,8 +106,10 @@ typedef struct radio_detector_desc {
 typedef struct radio_chunk {
     int64_t n_particles;  /* >= 0 (0 deposits nothing) */
     int64_t n_steps;      /* segments, >= 0 (0 deposits nothing) */
-    double t_first;       /* time of state 0 */
+    double t_first;       /* time of the run's state 0 */
     double dt;            /* time between states, > 0 */
+    int64_t first_step;   /* index in its run of the chunk's state 0, >= 0;
+                             first_step + n_steps < 2^53 */
     const double* x;      /* DEVICE [3][n_steps+1][n_particles] positions (SoA) */
     const double* u;      /* DEVICE [3][n_steps+1][n_particles] momenta p/(m c) */
     const double* q;      /* DEVICE [n_particles] signed charges, or NULL for all -1 */

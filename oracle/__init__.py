@@ -60,7 +60,7 @@ def _load():
                                            ctypes.c_double, dp, dp]
         lib.radio_oracle_field.restype = None
         lib.radio_oracle_deposit.argtypes = [dp, i64, ctypes.c_double, ctypes.c_double, i64,
-                                             ctypes.c_double, i64, i64, ctypes.c_double,
+                                             ctypes.c_double, i64, i64, ctypes.c_double, i64,
                                              ctypes.c_double, dp, dp, dp, dp,
                                              ctypes.POINTER(i64), ctypes.c_int]
         lib.radio_oracle_deposit.restype = ctypes.c_int
@@ -103,8 +103,11 @@ def field(x_cell, x_part, beta, inv_gamma2: float, betadot, q: float = -1.0,
 
 def deposit(cells, t0: float, dt_det: float, n_t: int, x, u, q, t_first: float, dt: float,
             c: float = 1.0, D: Optional[np.ndarray] = None, n_threads: Optional[int] = None,
-            counters: Optional[np.ndarray] = None) -> np.ndarray:
-    """Accumulate one chunk into D[n_cells, n_t, 6] (created zeroed if None)."""
+            counters: Optional[np.ndarray] = None, first_step: int = 0) -> np.ndarray:
+    """Accumulate one chunk into D[n_cells, n_t, 6] (created zeroed if None).
+
+    State s of the chunk is state first_step + s of the run, at time
+    t_first + (first_step + s) * dt."""
     cells = _f64(cells).reshape(-1, 3)
     x = _f64(x)
     u = _f64(u)
@@ -125,7 +128,7 @@ def deposit(cells, t0: float, dt_det: float, n_t: int, x, u, q, t_first: float, 
         n_threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     rc = _load().radio_oracle_deposit(
         _dptr(cells), n_c, float(t0), float(dt_det), int(n_t), float(c), n_p, n_states - 1,
-        float(t_first), float(dt), _dptr(x), _dptr(u), _dptr(qa), _dptr(D),
+        float(t_first), int(first_step), float(dt), _dptr(x), _dptr(u), _dptr(qa), _dptr(D),
         counters.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(n_threads))
     if rc != 0:
         raise ValueError(f"oracle deposit rejected its arguments (rc={rc})")
@@ -137,7 +140,7 @@ def deposit_workload(detector, chunk, cell_index=None, D=None, n_threads=None, c
     cells = detector.cells if cell_index is None else detector.cells[np.asarray(cell_index)]
     return deposit(cells, detector.t0, detector.dt_det, detector.n_t, chunk.x, chunk.u, chunk.q,
                    chunk.t_first, chunk.dt, c=detector.c, D=D, n_threads=n_threads,
-                   counters=counters)
+                   counters=counters, first_step=getattr(chunk, "first_step", 0))
 
 
 def read(D: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:

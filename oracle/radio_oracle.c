@@ -16,7 +16,8 @@
  *       g      = |u_s|^2 + 1,   beta_s = u_s / sqrt(g),   1/gamma_s^2 = 1/g
  *       betadot_s = (beta_s - beta_{s-1}) / dt
  *   arrival time (Eq. 2, Alg. 1):  tau_s = t_s + |x_c - x_{p,s}| / c,
- *       t_s = t_first + s*dt
+ *       t_s = t_first + (first_step + s)*dt   (state s of a chunk is the run's
+ *       state first_step + s; time step n of the run sits at n*dt, Sec. 3.1)
  *   Lienard-Wiechert field of the segment (Eq. 1), with the current state's
  *   quantities (Alg. 1 passes E(n, beta, betadot) of the current step):
  *       n = (x_c - x_{p,s}) / R   (from the particle towards the cell, Sec. 2)
@@ -36,7 +37,7 @@
  * implementations must round them the same way; every other line may be
  * evaluated in any order):
  *   |v|^2 = (v0*v0 + v1*v1) + v2*v2 ;  g = |u|^2 + 1 ;  beta_k = u_k / sqrt(g)
- *   t_s  = t_first + (double)s * dt ;  R = sqrt(|x_c - x_s|^2)
+ *   t_s  = t_first + (double)(first_step + s) * dt ;  R = sqrt(|x_c - x_s|^2)
  *   tau  = t_s + R * (1/c)          ;  n_k = d_k * (1/R)
  *   slot coordinate (tau - t0) * (1/dt_det): the time in units of slots, whose
  *   integer part is the slot of Alg. 2 (a segment much shorter than a slot
@@ -146,10 +147,12 @@ static void load_state(const double* a, int64_t n_states, int64_t n_p, int64_t s
  */
 EXPORT int radio_oracle_deposit(const double* cells, int64_t n_cells, double t0, double dt_det,
                                 int64_t n_t, double c, int64_t n_p, int64_t n_steps,
-                                double t_first, double dt, const double* x, const double* u,
-                                const double* q, double* D, int64_t* counters, int n_threads)
+                                double t_first, int64_t first_step, double dt, const double* x,
+                                const double* u, const double* q, double* D, int64_t* counters,
+                                int n_threads)
 {
-    if (n_cells < 0 || n_t < 1 || n_p < 0 || n_steps < 0 || !(dt_det > 0.0) || !(c > 0.0))
+    if (n_cells < 0 || n_t < 1 || n_p < 0 || n_steps < 0 || first_step < 0 ||
+        !(dt_det > 0.0) || !(c > 0.0))
         return -1;
     if (n_cells == 0 || n_p == 0 || n_steps == 0)
         return 0;
@@ -178,8 +181,8 @@ EXPORT int radio_oracle_deposit(const double* cells, int64_t n_cells, double t0,
                 double betadot[3];
                 for (int k = 0; k < 3; ++k)
                     betadot[k] = (beta[k] - beta_prev[k]) / dt;
-                double t_prev = t_first + (double)(s - 1) * dt;
-                double t_cur = t_first + (double)s * dt;
+                double t_prev = t_first + (double)(first_step + s - 1) * dt;
+                double t_cur = t_first + (double)(first_step + s) * dt;
                 double tau_prev = radio_oracle_arrival(xc, x_prev, t_prev, c);
                 double tau = radio_oracle_arrival(xc, x_cur, t_cur, c);
                 double F[6];

@@ -55,7 +55,7 @@ class _Desc(ctypes.Structure):
 class _Chunk(ctypes.Structure):
     _fields_ = [
         ("n_particles", ctypes.c_int64), ("n_steps", ctypes.c_int64),
-        ("t_first", ctypes.c_double), ("dt", ctypes.c_double),
+        ("t_first", ctypes.c_double), ("dt", ctypes.c_double), ("first_step", ctypes.c_int64),
         ("x", ctypes.c_void_p), ("u", ctypes.c_void_p), ("q", ctypes.c_void_p),
     ]
 
@@ -134,9 +134,12 @@ def _dev_f64(t, shape, name):
 
 
 class Chunk:
-    """Device-resident trajectory chunk: x, u of shape (3, S+1, Np), q of shape (Np,)."""
+    """Device-resident trajectory chunk: x, u of shape (3, S+1, Np), q of shape (Np,).
 
-    def __init__(self, x, u, q=None, t_first: float = 0.0, dt: float = 1.0):
+    State s of the chunk is state first_step + s of its run, at time
+    t_first + (first_step + s) * dt."""
+
+    def __init__(self, x, u, q=None, t_first: float = 0.0, dt: float = 1.0, first_step: int = 0):
         import torch
         if not isinstance(x, torch.Tensor) or x.dim() != 3 or x.shape[0] != 3:
             raise ValueError("x must be a (3, S+1, Np) tensor")
@@ -145,6 +148,7 @@ class Chunk:
         self.q = None if q is None else _dev_f64(q, (x.shape[2],), "q")
         self.t_first = float(t_first)
         self.dt = float(dt)
+        self.first_step = int(first_step)
 
     @classmethod
     def from_numpy(cls, chunk, device="cuda") -> "Chunk":
@@ -153,7 +157,26 @@ class Chunk:
         return cls(torch.from_numpy(np.ascontiguousarray(chunk.x)).to(device),
                    torch.from_numpy(np.ascontiguousarray(chunk.u)).to(device),
                    torch.from_numpy(np.ascontiguousarray(chunk.q)).to(device),
-                   chunk.t_first, chunk.dt)
+                   chunk.t_first, chunk.dt, getattr(chunk, "first_step", 0))
+
+    def slice(self, s_begin: int, s_end: int, p_begin: int = 0,
+              p_end: Optional[int] = None) -> "Chunk":
+        """States s_begin..s_end inclusive of particles p_begin..p_end-1 as a new chunk
+        (a device copy) with the same state times; its deposit adds those particles'
+        segments s_begin+1..s_end."""
+        p_end = self.n_particles if p_end is None else p_end
+        if not (0 <= s_begin <= s_end <= self.n_steps and 0 <= p_begin <= p_end <= self.n_particles):
+            raise ValueError("slice out of bounds")
+        return Chunk(self.x[:, s_begin:s_end + 1, p_begin:p_end].contiguous(),
+                     self.u[:, s_begin:s_end + 1, p_begin:p_end].contiguous(),
+                     None if self.q is None else self.q[p_begin:p_end].contiguous(),
+                     self.t_first, self.dt, self.first_step + s_begin)
+
+    def slice_steps(self, s_begin: int, s_end: int) -> "Chunk":
+        return self.slice(s_begin, s_end)
+
+    def slice_particles(self, p_begin: int, p_end: int) -> "Chunk":
+        return self.slice(0, self.n_steps, p_begin, p_end)
 
     @property
     def n_particles(self) -> int:
@@ -164,7 +187,7 @@ class Chunk:
         return int(self.x.shape[1]) - 1
 
     def _c(self) -> _Chunk:
-        return _Chunk(self.n_particles, self.n_steps, self.t_first, self.dt,
+        return _Chunk(self.n_particles, self.n_steps, self.t_first, self.dt, self.first_step,
                       self.x.data_ptr(), self.u.data_ptr(),
                       None if self.q is None else self.q.data_ptr())
 

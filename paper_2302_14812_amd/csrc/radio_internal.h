@@ -72,7 +72,8 @@ struct DepositJob {
     int32_t* perm;                  // workspace [n_tiles][n_p]
     uint8_t* ring_sel;              // workspace [n_tiles]: 1 where a tile takes the large ring
     int64_t n_c, n_t, n_p, n_s;
-    double t_first, dt;             // state s at t_first + s*dt
+    double t_first, dt;             // state s at t_first + (s0 + s)*dt
+    int64_t s0;                     // the chunk's first state within its run
     double t0, inv_dt_det;          // slot coordinate (t_det - t0) * inv_dt_det
     double inv_c, c;
     // work decomposition, filled by plan_job()

@@ -77,7 +77,8 @@ __device__ __forceinline__ double canon_norm2(double a, double b, double c)
     return (a * a + b * b) + c * c;
 }
 
-__device__ __forceinline__ double canon_state_time(double t_first, int s, double dt)
+// time of the run's state s (s < 2^53, so exact as a double)
+__device__ __forceinline__ double canon_state_time(double t_first, int64_t s, double dt)
 {
 #pragma clang fp contract(off)
     return t_first + (double)s * dt;
@@ -618,7 +619,8 @@ __global__ __launch_bounds__(256) void ring_choice_kernel(const StateRec* __rest
                                                           const double* __restrict__ cells,
                                                           int64_t n_c, int64_t n_p, int64_t n_s,
                                                           int64_t n_runs, double t_first,
-                                                          double dt, double t0, double inv_dt_det,
+                                                          int64_t s0, double dt, double t0,
+                                                          double inv_dt_det,
                                                           double inv_c, int64_t n_t,
                                                           uint8_t* __restrict__ sel)
 {
@@ -658,7 +660,8 @@ __global__ __launch_bounds__(256) void ring_choice_kernel(const StateRec* __rest
         const int64_t p = perm[tile * n_p + pi];
         const StateRec& r = recs[p * n_states + st];
         const double d0 = ctr[0] - r.x[0], d1 = ctr[1] - r.x[1], d2 = ctr[2] - r.x[2];
-        const double tau = (t_first + (double)st * dt) + __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2) * inv_c;
+        const double tau = (t_first + (double)(s0 + st) * dt) +
+                           __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2) * inv_c;
         double u = (tau - t0) * inv_dt_det;
         if (!(u == u))
             continue;
@@ -761,7 +764,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         const RADIO_GLOBAL double* xr =
             gptr(reinterpret_cast<const double*>(J.recs + order[i] * n_states + s_a));
         const double d0 = xc[0] - xr[0], d1 = xc[1] - xr[1], d2 = xc[2] - xr[2];
-        const double tau = canon_state_time(J.t_first, (int)s_a, J.dt) +
+        const double tau = canon_state_time(J.t_first, J.s0 + s_a, J.dt) +
                            __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2) * K.inv_c;
         const double u = (tau - K.t0) * K.inv_dt_det;
         if (u == u) {
@@ -809,7 +812,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         const int64_t bt = it % n_batches;
         const int64_t s_a = rb * kRunL;
         const int len = (int)min((int64_t)kRunL, J.n_s - s_a);
-        const double t_a = canon_state_time(J.t_first, (int)s_a, J.dt);
+        const double t_a = canon_state_time(J.t_first, J.s0 + s_a, J.dt);
         const int64_t i0 = bt * kGroups;
         const int np = (int)min((int64_t)kGroups, J.n_p - i0);
         // slide the ring to this batch's earliest start (every lane of the
@@ -853,7 +856,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
                                 : slot_coord_fp64(xc, sh.rec[g][0], t_a, K);
             for (int k = 1; k <= len; ++k) {
                 T F[6];
-                const double t_s = canon_state_time(J.t_first, (int)s_a + k, J.dt);
+                const double t_s = canon_state_time(J.t_first, J.s0 + s_a + k, J.dt);
                 double uk;
                 if constexpr (MIX)
                     uk = field_mixed(xc, sh.rec[g][k], t_s, (float)q, K, F);
@@ -1088,7 +1091,7 @@ hipError_t launch_ring_choice(const DepositJob& job, hipStream_t s)
         return hipSuccess;
     hipLaunchKernelGGL(ring_choice_kernel, dim3((unsigned)job.n_tiles), dim3(256), 0, s, job.recs,
                        job.perm, job.cells, job.n_c, job.n_p, job.n_s, job.n_runs, job.t_first,
-                       job.dt, job.t0, job.inv_dt_det, job.inv_c, job.n_t, job.ring_sel);
+                       job.s0, job.dt, job.t0, job.inv_dt_det, job.inv_c, job.n_t, job.ring_sel);
     return hipGetLastError();
 }
 

@@ -237,6 +237,8 @@ int validate_chunk(const radio_chunk* k)
         return RADIO_EINVAL;
     if (k->n_particles < 0 || k->n_steps < 0)
         return RADIO_EINVAL;
+    if (k->first_step < 0 || k->first_step > (INT64_C(1) << 53) - 1 - k->n_steps)
+        return RADIO_EINVAL;
     if (!std::isfinite(k->t_first) || !std::isfinite(k->dt) || !(k->dt > 0.0))
         return RADIO_EINVAL;
     if (k->n_particles == 0 || k->n_steps == 0)
@@ -264,6 +266,7 @@ radio::DepositJob make_job(radio_detector* det, const radio_chunk* k)
     J.n_p = k->n_particles;
     J.n_s = k->n_steps;
     J.t_first = k->t_first;
+    J.s0 = k->first_step;
     J.dt = k->dt;
     J.t0 = det->t0;
     J.inv_dt_det = 1.0 / det->dt_det;

@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import math
 import threading
 import time
 from typing import Callable, Deque, Dict, List, Optional, Sequence, Tuple
@@ -36,8 +37,11 @@ class Request:
     payload: object = None            # the device chunk (DepositServer) or anything (tests)
     work: int = 0                     # interactions: n_particles * n_steps * n_cells
     ready: object = None              # event on the producer's stream after the chunk was written
-    batch: int = -1                   # index of the batch that carried it
-    launched: Optional[float] = None
+    pieces: Optional[List[Tuple[object, int]]] = None  # (payload, work) parts, in order
+    next_piece: int = 0               # parts handed to batches so far
+    open_pieces: int = 0              # parts handed out and not yet finished
+    batch: int = -1                   # index of the batch that carried its last part
+    launched: Optional[float] = None  # when its first part was launched
     completion: Optional[float] = None
 
     @property
@@ -45,15 +49,42 @@ class Request:
         return None if self.completion is None else self.completion - self.arrival
 
 
-class Scheduler:
-    """Admission by memory and batch formation, FIFO over arrivals.
+def plan_pieces(n_particles: int, n_steps: int, n_cells: int, piece_work: float,
+                min_steps: int = 16) -> List[Tuple[int, int, int, int]]:
+    """Cut a chunk into parts of at most about piece_work interactions.
 
-    A detector becomes resident when the first request for it reaches the head
-    of the queue and its bytes fit the budget next to the resident detectors;
-    requests for detectors that do not fit wait (and do not block requests for
-    resident detectors behind them).  A batch takes pending requests of
-    resident detectors in arrival order until max_batch_work interactions
-    (a single larger request goes alone).
+    Parts are (s_begin, s_end, p_begin, p_end): states s_begin..s_end (sharing
+    one state with the neighbouring part, so the parts add up to the whole) of
+    particles p_begin..p_end-1.  Steps are cut first, into ranges of at least
+    min_steps (one pass of the deposit over the particle order covers that
+    many); particles are cut after that.
+    """
+    work = n_particles * n_steps * n_cells
+    if work <= piece_work or n_particles == 0 or n_steps == 0:
+        return [(0, n_steps, 0, n_particles)]
+    n_s = int(min(math.ceil(work / piece_work), max(1, n_steps // min_steps)))
+    sb = np.linspace(0, n_steps, n_s + 1).round().astype(int)
+    parts = []
+    for a, b in zip(sb[:-1], sb[1:]):
+        w = n_particles * (b - a) * n_cells
+        n_p = int(min(math.ceil(w / piece_work), n_particles))
+        pb = np.linspace(0, n_particles, n_p + 1).round().astype(int)
+        parts.extend((int(a), int(b), int(p0), int(p1)) for p0, p1 in zip(pb[:-1], pb[1:]))
+    return parts
+
+
+class Scheduler:
+    """Admission by memory and batch formation over the parts of the requests.
+
+    A detector becomes resident when a pending request for it is considered
+    and its bytes fit the budget next to the resident detectors; requests for
+    detectors that do not fit wait (and do not block requests for resident
+    detectors behind them).  A batch visits the pending requests of resident
+    detectors in arrival order and takes the next part of each, round after
+    round, until max_batch_work interactions (a batch takes at least one
+    part): a request cut into many parts advances by a part per round and
+    never holds back the requests that arrived after it for longer than a
+    batch.
     """
 
     def __init__(self, detector_bytes: Dict[int, int], cells: Dict[int, int], budget: int,
@@ -79,6 +110,8 @@ class Scheduler:
             raise ValueError(f"detector {req.det_id} needs {self.detector_bytes[req.det_id]} bytes,"
                              f" more than the budget of {self.budget}")
         req.work = req.n_particles * req.n_steps * self.cells[req.det_id]
+        if req.pieces is None:
+            req.pieces = [(req.payload, req.work)]
         self.pending.append(req)
         return req
 
@@ -108,27 +141,36 @@ class Scheduler:
         return any(r.det_id in self.resident or self.detector_bytes[r.det_id] <= free
                    for r in self.pending)
 
-    def next_batch(self) -> List[Request]:
-        batch: List[Request] = []
-        work = 0
-        keep: Deque[Request] = collections.deque()
-        while self.pending:
-            req = self.pending.popleft()
-            if req.det_id not in self.resident:
-                keep.append(req)
-                continue
-            if batch and work + req.work > self.max_batch_work:
-                keep.append(req)
-                keep.extend(self.pending)
-                self.pending.clear()
-                break
-            req.batch = self.n_batches
-            batch.append(req)
-            work += req.work
-        self.pending = keep
+    def next_batch(self) -> List[Tuple[Request, int]]:
+        """The next batch as (request, part index) pairs."""
+        batch: List[Tuple[Request, int]] = []
+        work = 0.0
+        progress = True
+        while progress:
+            progress = False
+            for req in list(self.pending):
+                if req.det_id not in self.resident:
+                    continue
+                k = req.next_piece
+                w = req.pieces[k][1]
+                if batch and work + w > self.max_batch_work:
+                    continue
+                batch.append((req, k))
+                work += w
+                req.next_piece += 1
+                req.open_pieces += 1
+                req.batch = self.n_batches
+                progress = True
+                if req.next_piece == len(req.pieces):
+                    self.pending.remove(req)
         if batch:
             self.n_batches += 1
         return batch
+
+    def piece_done(self, req: Request) -> bool:
+        """Record that one handed-out part of req finished; True when req is complete."""
+        req.open_pieces -= 1
+        return req.open_pieces == 0 and req.next_piece == len(req.pieces)
 
     def release(self, det_id: int) -> None:
         self.resident.pop(det_id, None)
@@ -146,8 +188,9 @@ class DepositServer:
     """
 
     def __init__(self, specs: Dict[int, object], precision: str = "mixed",
-                 memory_budget: Optional[int] = None, max_batch_work: float = 2e11,
-                 max_inflight: int = 2, clock: Callable[[], float] = time.perf_counter):
+                 memory_budget: Optional[int] = None, max_batch_work: float = 4e10,
+                 piece_work: Optional[float] = None, max_inflight: int = 2,
+                 clock: Callable[[], float] = time.perf_counter):
         import torch
 
         import paper_2302_14812_amd as radio
@@ -164,11 +207,12 @@ class DepositServer:
                                {d: s.n_cells for d, s in self.specs.items()},
                                memory_budget, max_batch_work)
         self.max_inflight = int(max_inflight)
+        self.piece_work = float(max_batch_work / 2 if piece_work is None else piece_work)
         self.detectors: Dict[int, object] = {}
         self.stream = torch.cuda.Stream()  # default priority
         self.requests: List[Request] = []
         self._lock = threading.Condition()
-        self._inflight: Deque[Tuple[object, List[Request]]] = collections.deque()
+        self._inflight: Deque[Tuple[object, List[Tuple[Request, int]]]] = collections.deque()
         self._running = True
         self._error: Optional[BaseException] = None
         self._outstanding: Dict[int, int] = collections.defaultdict(int)
@@ -185,9 +229,20 @@ class DepositServer:
         service orders its stream after the work the caller's current stream
         has enqueued so far (the writes of the chunk)."""
         torch = self._torch
+        arrival = self.clock()
+        if det_id not in self.specs:
+            raise KeyError(f"unknown detector {det_id}")
+        plan = plan_pieces(chunk.n_particles, chunk.n_steps, self.specs[det_id].n_cells,
+                           self.piece_work)
+        if len(plan) == 1:
+            pieces = [chunk]
+        else:  # device copies, ordered on the caller's stream before the event below
+            pieces = [chunk.slice(a, b, p0, p1) for a, b, p0, p1 in plan]
+        n_c = self.specs[det_id].n_cells
         ev = torch.cuda.Event()
         ev.record(torch.cuda.current_stream())
-        req = Request(det_id, chunk.n_particles, chunk.n_steps, self.clock(), chunk, ready=ev)
+        req = Request(det_id, chunk.n_particles, chunk.n_steps, arrival, chunk, ready=ev,
+                      pieces=[(c, c.n_particles * c.n_steps * n_c) for c in pieces])
         with self._lock:
             self._raise_if_failed()
             self.sched.add(req)
@@ -290,14 +345,15 @@ class DepositServer:
                         self.detectors[d] = radio.Detector.from_spec(
                             self.specs[d], precision=self.precision, stream=self.stream)
                     batch = self.sched.next_batch()
-                    dets = [self.detectors[r.det_id] for r in batch]
+                    dets = [self.detectors[r.det_id] for r, _ in batch]
                 if not batch:
                     continue
                 t = self.clock()
-                for r in batch:
-                    r.launched = t
-                    self.stream.wait_event(r.ready)
-                radio.deposit_batch(dets, [r.payload for r in batch], self.stream)
+                for r, k in batch:
+                    if k == 0:
+                        r.launched = t
+                        self.stream.wait_event(r.ready)
+                radio.deposit_batch(dets, [r.pieces[k][0] for r, k in batch], self.stream)
                 ev = torch.cuda.Event()
                 ev.record(self.stream)
                 with self._lock:
@@ -321,11 +377,13 @@ class DepositServer:
                 t = self.clock()
                 with self._lock:
                     self._inflight.popleft()
-                    for r in batch:
-                        r.completion = t
-                        r.payload = None  # the chunk's memory may go
-                        r.ready = None
-                        self._outstanding[r.det_id] -= 1
+                    for r, k in batch:
+                        r.pieces[k] = (None, r.pieces[k][1])  # the part's memory may go
+                        if self.sched.piece_done(r):
+                            r.completion = t
+                            r.payload = None
+                            r.ready = None
+                            self._outstanding[r.det_id] -= 1
                     self._lock.notify_all()
         except BaseException as e:
             with self._lock:
@@ -356,30 +414,36 @@ def summarize(requests: Sequence[Request], skip: int = 0, sched: Optional[Schedu
            "interactions_per_s": work / (t1 - t0) if t1 > t0 else float("nan"),
            "batches": len({r.batch for r in done})}
     if sched is not None:
+        out["batches"] = sched.n_batches
         out["peak_resident"] = sched.peak_resident
         out["peak_bytes"] = sched.peak_used
     return out
 
 
 def simulate(sched: Scheduler, requests: Sequence[Request],
-             service_time: Callable[[List[Request]], float], max_inflight: int = 2
-             ) -> List[Request]:
+             service_time: Callable[[List[float]], float], max_inflight: int = 2,
+             piece_work: Optional[float] = None) -> List[Request]:
     """Run the service's policy against a model of the device, on a virtual clock.
 
-    requests carry their arrival times; service_time(batch) gives the device
-    time of a batch.  The policy is the server's: whenever fewer than
+    requests carry their arrival times (and sizes); service_time(part works)
+    gives the device time of a batch.  The policy is the server's: requests
+    are cut into parts of at most piece_work interactions; whenever fewer than
     max_inflight batches are on the device and a pending request can run,
-    admit what fits and launch a batch of everything pending (up to the work
-    bound); batches run one after another in launch order.  Returns the
-    requests with launch and completion times filled in.  Detectors are never
-    finished here, so requests of detectors that never fit stay pending.
+    admit what fits and launch the next batch; batches run one after another
+    in launch order.  Returns the requests with launch and completion times
+    filled in.  Detectors are never finished here, so requests of detectors
+    that never fit stay pending.
     """
     arrivals = sorted(requests, key=lambda r: r.arrival)
+    for r in arrivals:
+        if piece_work is not None and r.pieces is None:
+            n_c = sched.cells[r.det_id]
+            r.pieces = [(None, (p1 - p0) * (b - a) * n_c)
+                        for a, b, p0, p1 in plan_pieces(r.n_particles, r.n_steps, n_c, piece_work)]
     i = 0
     now = 0.0
     device_free = 0.0
-    inflight: List[float] = []          # completion times, in order
-    done_batches: List[Tuple[float, List[Request]]] = []
+    inflight: List[float] = []          # completion times
     while True:
         while i < len(arrivals) and arrivals[i].arrival <= now:
             sched.add(arrivals[i])
@@ -390,13 +454,14 @@ def simulate(sched: Scheduler, requests: Sequence[Request],
             batch = sched.next_batch()
             if batch:
                 start = max(now, device_free)
-                end = start + float(service_time(batch))
+                end = start + float(service_time([r.pieces[k][1] for r, k in batch]))
                 device_free = end
                 inflight.append(end)
-                for r in batch:
-                    r.launched = now
-                    r.completion = end
-                done_batches.append((end, batch))
+                for r, k in batch:
+                    if k == 0:
+                        r.launched = now
+                    if sched.piece_done(r):
+                        r.completion = end
                 continue
         nxt = [t for t in inflight if t > now]
         if i < len(arrivals):

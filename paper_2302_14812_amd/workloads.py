@@ -14,7 +14,8 @@ Array layout handed to both sides (structure of arrays, float64):
     x[k, s, p]  position component k of particle p at trajectory state s
     u[k, s, p]  momentum component k (units of m c)
     q[p]        signed charge
-State s sits at time t_first + s*dt; S segments join S+1 states.
+State s of a chunk sits at time t_first + (first_step + s)*dt; S segments join
+S+1 states.
 """
 from __future__ import annotations
 
@@ -29,13 +30,17 @@ BASE_SEED = 230214812
 
 @dataclasses.dataclass
 class Chunk:
-    """A block of trajectory states: S+1 states of n_particles particles."""
+    """A block of trajectory states: S+1 states of n_particles particles.
+
+    State s of the block is state first_step + s of its run, at time
+    t_first + (first_step + s) * dt."""
 
     x: np.ndarray  # (3, S+1, Np) float64
     u: np.ndarray  # (3, S+1, Np) float64
     q: np.ndarray  # (Np,) float64
     t_first: float
     dt: float
+    first_step: int = 0
 
     @property
     def n_particles(self) -> int:
@@ -46,16 +51,18 @@ class Chunk:
         return int(self.x.shape[1]) - 1
 
     def state_times(self) -> np.ndarray:
-        return self.t_first + np.arange(self.n_steps + 1, dtype=np.float64) * self.dt
+        steps = self.first_step + np.arange(self.n_steps + 1, dtype=np.int64)
+        return self.t_first + steps.astype(np.float64) * self.dt
 
     def slice_steps(self, s_begin: int, s_end: int) -> "Chunk":
-        """States s_begin..s_end inclusive (segments s_begin+1..s_end)."""
+        """States s_begin..s_end inclusive (segments s_begin+1..s_end), at the same times."""
         return Chunk(
             x=np.ascontiguousarray(self.x[:, s_begin:s_end + 1, :]),
             u=np.ascontiguousarray(self.u[:, s_begin:s_end + 1, :]),
             q=self.q,
-            t_first=self.t_first + s_begin * self.dt,
+            t_first=self.t_first,
             dt=self.dt,
+            first_step=self.first_step + s_begin,
         )
 
     def slice_particles(self, p_begin: int, p_end: int) -> "Chunk":
@@ -65,6 +72,7 @@ class Chunk:
             q=np.ascontiguousarray(self.q[p_begin:p_end]),
             t_first=self.t_first,
             dt=self.dt,
+            first_step=self.first_step,
         )
 
 
@@ -512,7 +520,7 @@ def plasma_mirror_chunk(n_particles: int, s_begin: int, n_steps: int, seed: int,
             pos = pos + 0.5 * dt * (beta_prev + beta)
         x[:, s, :] = pos
         beta_prev = beta
-    return Chunk(x=x, u=u, q=np.full(n_particles, q), t_first=float(t[0]), dt=dt)
+    return Chunk(x=x, u=u, q=np.full(n_particles, q), t_first=0.0, dt=dt, first_step=s_begin)
 
 
 def plasma_mirror_detector(n_side: int = 256, n_t: int = 4096, seed: int = BASE_SEED + 3,

@@ -23,6 +23,29 @@ def test_header_declares_the_binding_exports():
     assert _declared() == sorted(radio.EXPORTS)
 
 
+def _struct_fields(name):
+    """Field names of `typedef struct name {...} name;` in the header, in order."""
+    src = open(HEADER).read()
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), src, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = []
+    for decl in body.split(";"):
+        if not decl.strip():
+            continue
+        # "type a, b" declares a and b; drop array extents and pointer stars
+        first, *rest = decl.split(",")
+        for d in [first.split()[-1]] + [r.strip() for r in rest]:
+            names.append(re.sub(r"\[.*\]", "", d).lstrip("*"))
+    return names
+
+
+@pytest.mark.parametrize("cname,pyname", [("radio_chunk", "_Chunk"), ("radio_detector_desc", "_Desc"),
+                                          ("radio_stats", "_Stats"), ("radio_tuning", "_Tuning")])
+def test_binding_structs_follow_the_header(cname, pyname):
+    import paper_2302_14812_amd as radio
+    assert [f for f, _ in getattr(radio, pyname)._fields_] == _struct_fields(cname)
+
+
 def test_library_exports_every_declared_symbol():
     import paper_2302_14812_amd as radio
     lib = radio._lib()
@@ -73,7 +96,7 @@ def test_invalid_arguments_rejected_before_any_device_work():
     d.cells = ctypes.POINTER(ctypes.c_double)()  # NULL
     assert lib.radio_detector_create(ctypes.byref(d), None, ctypes.byref(h)) == radio.EINVAL
     assert lib.radio_detector_create(None, None, ctypes.byref(h)) == radio.EINVAL
-    ch = radio._Chunk(1, 1, 0.0, 0.1, None, None, None)
+    ch = radio._Chunk(1, 1, 0.0, 0.1, 0, None, None, None)
     assert lib.radio_deposit_trajectory_chunk(None, ctypes.byref(ch), None) == radio.EINVAL
     assert lib.radio_read_detector(None, None, None, None) == radio.EINVAL
     assert lib.radio_detector_reset(None, None) == radio.EINVAL

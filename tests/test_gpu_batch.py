@@ -89,8 +89,8 @@ def test_batch_mixed_modes_duplicates_and_empty(radio, sets):
     ref.deposit(c_full)
     Er, Br = _read(ref)
     E64, B64 = _read(det64)
-    # the halves recompute state times from their own t_first (ulp-level shifts)
-    assert max(rel_l2(E64, Er), rel_l2(B64, Br)) <= 1e-11
+    # the halves keep the state times of the whole; only the order of additions differs
+    assert max(rel_l2(E64, Er), rel_l2(B64, Br)) <= 1e-13
     for d in (detmx, det2s):
         Em, Bm = _read(d)
         assert max(rel_l2(Em, Er), rel_l2(Bm, Br)) <= 1e-5

@@ -211,10 +211,20 @@ def test_chunk_split_and_superposition(radio):
         oracle.deposit_workload(spec, part, D=D)
     Eo, Bo = oracle.read(D)
     check_parity(Eg, Bg, Eo, Bo, TOL_FP64, "chunk split vs oracle of the same parts")
-    # against the unsplit chunk: each part recomputes its state times from its own
-    # t_first, which may move an arrival time by an ulp (~1e-7 of a slot here)
+    # against the unsplit chunk: the parts keep the state times of the whole
+    # (first_step), so only the order of the additions differs
     Eu, Bu, _ = oracle_deposit(spec, chunk)
-    check_parity(Eg, Bg, Eu, Bu, 1e-10, "chunk split vs unsplit")
+    check_parity(Eg, Bg, Eu, Bu, TOL_FP64, "chunk split vs unsplit")
+    # device-side slicing of a device chunk gives the same parts
+    dev = radio.Chunk.from_numpy(chunk)
+    dparts = [dev.slice_steps(0, 40), dev.slice_steps(40, 99), dev.slice_steps(99, 150)]
+    assert [p.first_step for p in dparts] == [0, 40, 99]
+    det = radio.Detector.from_spec(spec, precision="fp64")
+    for p in dparts[::-1]:
+        det.deposit(p)
+    E2, B2 = det.read()
+    check_parity(E2.cpu().numpy(), B2.cpu().numpy(), Eu, Bu, TOL_FP64, "device step slices")
+    det.close()
     halves = [chunk.slice_particles(0, 10), chunk.slice_particles(10, 23)]
     Eg, Bg, _ = gpu_deposit(radio, spec, halves)
     check_parity(Eg, Bg, Eu, Bu, TOL_FP64, "particle split")

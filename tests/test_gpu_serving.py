@@ -35,7 +35,7 @@ def stream():
     """Five uneven plasma-mirror detectors and a 40-chunk stream over them."""
     specs = {d: W.plasma_mirror_detector(n_side=side, n_t=nt, sample_particles=16)
              for d, (side, nt) in enumerate([(6, 128), (10, 256), (16, 192), (4, 512), (12, 64)])}
-    rows = list(W.stream_schedule(40, len(specs), seed=W.BASE_SEED + 50, max_steps=24,
+    rows = list(W.stream_schedule(40, len(specs), seed=W.BASE_SEED + 50, max_steps=48,
                                   min_log_particles=1.5, max_log_particles=3.0))
     host = [(d, W.plasma_mirror_chunk(n, s0, st, seed=W.BASE_SEED + 100 + k))
             for k, (d, s0, st, n) in enumerate(rows)]
@@ -60,13 +60,16 @@ def test_served_mix_equals_alone_and_oracle(radio, stream, precision):
     specs, host = stream
     dev = [(d, radio.Chunk.from_numpy(c)) for d, c in host]
     offsets = poisson_arrivals(400.0, len(dev), seed=7)
-    with DepositServer(specs, precision=precision, max_batch_work=2e8) as srv:
-        replay(srv, dev, offsets)
+    # parts of at most 1e6 interactions: the larger chunks are cut by steps and
+    # particles and their parts interleave with other chunks across batches
+    with DepositServer(specs, precision=precision, max_batch_work=4e6, piece_work=1e6) as srv:
+        reqs = replay(srv, dev, offsets)
         srv.drain(timeout=60)
         got = {d: srv.finish(d, timeout=60) for d in specs}
         st = srv.summary()
     print(f"[serve] {precision}: {st}", flush=True)
     assert st["chunks"] == len(dev)
+    assert max(len(r.pieces) for r in reqs) > 3 and st["batches"] > 5
     rng = np.random.Generator(np.random.PCG64(11))
     tol_alone = 1e-13 if precision == "fp64" else 1e-6
     for d, spec in specs.items():

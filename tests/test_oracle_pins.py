@@ -376,14 +376,36 @@ def test_superposition_and_chunk_split(oracle_mod):
     acc = np.zeros_like(full)
     for part in reversed(parts):
         oracle_mod.deposit(cells, x=part.x, u=part.u, q=part.q, t_first=part.t_first, dt=part.dt,
-                           D=acc, **args)
-    # each part recomputes its state times from its own t_first, which may round the
-    # arrival times differently by an ulp: a relative slot shift of ulp(tau)/dt_det
-    np.testing.assert_allclose(acc, full, rtol=0, atol=1e-12 * scale)
+                           D=acc, first_step=part.first_step, **args)
+    # the parts keep the state times of the whole (first_step), so every segment
+    # contributes the same numbers; only the order of the additions differs
+    np.testing.assert_allclose(acc, full, rtol=0, atol=1e-13 * scale)
+    # parts rebased to their own first state (t_first + s*dt rounded once more)
+    # may move an arrival time by an ulp: a slot shift of ulp(tau)/dt_det
+    acc2 = np.zeros_like(full)
+    for part in parts:
+        oracle_mod.deposit(cells, x=part.x, u=part.u, q=part.q,
+                           t_first=part.t_first + part.first_step * part.dt, dt=part.dt, D=acc2,
+                           **args)
+    np.testing.assert_allclose(acc2, full, rtol=0, atol=1e-12 * scale)
     # the charge enters linearly; opposite charges on one trajectory cancel
     neg = oracle_mod.deposit(cells, x=chunk.x, u=chunk.u, q=-2.0 * chunk.q,
                              t_first=chunk.t_first, dt=chunk.dt, **args)
     np.testing.assert_allclose(neg, -2.0 * full, rtol=0, atol=1e-14 * scale)
+
+
+def test_first_step_places_states_in_the_run(oracle_mod):
+    """State s of a chunk with first_step k sits at t_first + (k + s) dt: with a
+    step that is a power of two both forms of the state times are exact."""
+    chunk = W.random_chunk(3, 20, seed=4, dt=0.25, gamma_max=4.0)
+    cells = np.array([[8.0, -2.0, 5.0], [1.0, 9.0, -4.0]])
+    t0, dt_det, n_t = _window_for(cells, chunk, n_t=64, pad=20.0)
+    k = 12
+    a = oracle_mod.deposit(cells, t0, dt_det, n_t, chunk.x, chunk.u, chunk.q, 0.0, 0.25,
+                           first_step=k)
+    b = oracle_mod.deposit(cells, t0, dt_det, n_t, chunk.x, chunk.u, chunk.q, k * 0.25, 0.25)
+    assert np.abs(a).max() > 0.0
+    assert np.array_equal(a, b)
 
 
 def test_time_shift_moves_slots(oracle_mod):

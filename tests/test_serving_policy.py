@@ -2,8 +2,8 @@
 import numpy as np
 import pytest
 
-from paper_2302_14812_amd.serving import (Request, Scheduler, detector_bytes, poisson_arrivals,
-                                          simulate, summarize)
+from paper_2302_14812_amd.serving import (Request, Scheduler, detector_bytes, plan_pieces,
+                                          poisson_arrivals, simulate, summarize)
 from paper_2302_14812_amd import workloads as W
 
 
@@ -20,13 +20,13 @@ def test_admission_respects_budget_and_does_not_block_residents():
     assert s.used() == 300 and s.peak_resident == 3
     b = s.next_batch()
     # every request of a resident detector, in arrival order; 3 and 4 wait
-    assert [r.det_id for r in b] == [0, 1, 2, 0, 1]
+    assert [r.det_id for r, _ in b] == [0, 1, 2, 0, 1]
     assert [r.det_id for r in s.pending] == [3, 4]
     assert not s.runnable()
     assert s.next_batch() == []
     s.release(1)
     assert s.runnable() and s.admit() == [3]
-    assert [r.det_id for r in s.next_batch()] == [3]
+    assert [r.det_id for r, _ in s.next_batch()] == [3]
     assert s.admission_order == [0, 1, 2, 3]
     with pytest.raises(ValueError):
         s.add(Request(1, 1, 1, 9.0))  # finished detectors take no more chunks
@@ -49,11 +49,51 @@ def test_batches_are_fifo_and_bounded_in_work():
     s.admit()
     sizes = []
     while s.pending:
-        sizes.append([r.work for r in s.next_batch()])
-    # the bound cuts a batch before the request that would cross it; a request
-    # larger than the bound runs alone; order is arrival order throughout
-    assert sizes == [[30, 30, 30], [30], [500], [10]]
-    assert s.n_batches == 4
+        sizes.append([r.work for r, _ in s.next_batch()])
+    # a batch takes what fits in arrival order, skipping a request that would
+    # cross the bound (it goes first in a later batch); a request larger than
+    # the bound runs alone
+    assert sizes == [[30, 30, 30, 10], [30], [500]]
+    assert s.n_batches == 3
+
+
+def test_round_robin_over_parts():
+    s = make_sched(n_det=2, cells=1, max_work=40)
+    big = s.add(Request(0, 10, 1, 0.0, pieces=[(None, 10)] * 8))   # 80 in parts of 10
+    small = s.add(Request(1, 10, 1, 1.0, pieces=[(None, 10)]))
+    s.admit()
+    b1 = s.next_batch()
+    # the big request's first part, the small request, then more parts of the big one
+    assert [(r is big, k) for r, k in b1] == [(True, 0), (False, 0), (True, 1), (True, 2)]
+    assert s.piece_done(small)          # the small request completes with the first batch
+    assert not s.piece_done(big)
+    rest = []
+    while s.pending:
+        rest.append([k for r, k in s.next_batch()])
+    assert rest == [[3, 4, 5, 6], [7]]
+    for _ in range(2 + 5):
+        done = s.piece_done(big)
+    assert done
+
+
+@pytest.mark.parametrize("n_p,n_s,n_c,limit", [(1000, 64, 4096, 1e8), (100000, 64, 65536, 2e10),
+                                               (5, 3, 7, 1.0), (1000, 10, 100, 1e12)])
+def test_plan_pieces_cover_the_chunk(n_p, n_s, n_c, limit):
+    parts = plan_pieces(n_p, n_s, n_c, limit)
+    # every (particle, segment) pair exactly once
+    seen = np.zeros((n_p, n_s), dtype=int)
+    for a, b, p0, p1 in parts:
+        assert 0 <= a < b <= n_s and 0 <= p0 < p1 <= n_p
+        seen[p0:p1, a:b] += 1
+    assert (seen == 1).all()
+    works = [(p1 - p0) * (b - a) * n_c for a, b, p0, p1 in parts]
+    if n_p * n_s * n_c <= limit:
+        assert len(parts) == 1
+    else:
+        # steps are cut no finer than 16 (or the chunk's own length); parts stay
+        # within the limit unless one particle-run alone exceeds it
+        assert min(b - a for a, b, _, _ in parts) >= min(16, n_s)
+        assert max(works) <= max(limit, n_c * 2 * 16) * 1.01
 
 
 def test_work_counts_interactions():
@@ -77,7 +117,7 @@ def test_light_load_latency_is_the_service_time():
     # one chunk at a time: each waits for nothing and takes its own service time
     s = make_sched(n_det=4, cells=256)
     reqs = [Request(k % 4, 100, 4, 10.0 * k) for k in range(20)]
-    simulate(s, reqs, lambda b: 1e-3 + sum(r.work for r in b) / 1e9)
+    simulate(s, reqs, lambda ws: 1e-3 + sum(ws) / 1e9)
     for r in reqs:
         assert r.launched == r.arrival
         assert r.latency == pytest.approx(1e-3 + 100 * 4 * 256 / 1e9)
@@ -91,7 +131,7 @@ def test_heavy_load_forms_larger_batches_and_keeps_up():
     span = max(r.arrival for r in reqs)
     overhead = 2e-3
     s = make_sched(n_det=4, cells=256)
-    simulate(s, reqs, lambda b: overhead + sum(r.work for r in b) / rate_cap)
+    simulate(s, reqs, lambda ws: overhead + sum(ws) / rate_cap)
     st = summarize(reqs, sched=s)
     assert st["chunks"] == 400
     # offered load above what one-chunk batches could carry, yet the service
@@ -106,10 +146,34 @@ def test_heavy_load_forms_larger_batches_and_keeps_up():
         assert r.arrival <= r.launched <= r.completion
 
 
+def test_parts_bound_the_wait_behind_a_giant_chunk():
+    """A giant chunk followed by small ones: cut into parts, it no longer delays them."""
+    def stream():
+        reqs = [Request(0, 100000, 64, 0.0)]  # 4.2e11 interactions at 65536 cells
+        reqs += [Request(1 + k % 3, 1000, 8, 0.01 + 0.05 * k) for k in range(20)]
+        return reqs
+
+    def run(piece_work):
+        s = make_sched(n_det=4, cells=65536, max_work=4e10)
+        reqs = stream()
+        simulate(s, reqs, lambda ws: 1e-3 + sum(ws) / 1e11, piece_work=piece_work)
+        return reqs
+
+    whole = run(None)
+    cut = run(2e10)
+    small_whole = max(r.latency for r in whole[1:])
+    small_cut = max(r.latency for r in cut[1:])
+    assert small_whole > 3.0           # stuck behind 4.2 s of work
+    # at most the batches already on the device (two) and its own: 3 x 0.4 s
+    assert small_cut < 3 * (1e-3 + 4e10 / 1e11) + 1e-6
+    # the giant one finishes about when it would have
+    assert cut[0].completion < 1.2 * whole[0].completion
+
+
 def test_inflight_bound_holds():
     s = make_sched(n_det=2, cells=1)
     reqs = [Request(k % 2, 1, 1, 0.001 * k) for k in range(50)]
-    simulate(s, reqs, lambda b: 0.01, max_inflight=2)
+    simulate(s, reqs, lambda ws: 0.01, max_inflight=2)
     # at any launch time, at most two batches are unfinished
     launches = sorted({(r.batch, r.launched, r.completion) for r in reqs})
     for b, t, _ in launches:
@@ -137,7 +201,8 @@ def test_plasma_mirror_chunk_shape_and_speed():
     again = W.plasma_mirror_chunk(50, 40, 20, seed=3)
     assert np.array_equal(a.x, again.x) and np.array_equal(a.u, again.u)
     assert a.x.shape == (3, 21, 50) and a.q.shape == (50,)
-    assert a.t_first == pytest.approx(40 * a.dt)
+    assert a.first_step == 40 and a.t_first == 0.0
+    assert a.state_times()[0] == 40 * a.dt
     # every step is slower than light, and the sheet oscillates about x = 0
     step = np.linalg.norm(np.diff(a.x, axis=1), axis=0)
     assert step.max() < a.dt
