@@ -29,17 +29,16 @@
 //    (kRunL + 1) states is staged in LDS and each lane walks its particle's
 //    run against its cell.  The lane integrates the held field over its
 //    current slot with the exact slot-unit overlaps of Alg. 2 and emits
-//    slot-value differences only when its arrivals move on; emissions go to a
+//    a slot's value only when its arrivals move on; emissions go to a
 //    per-cell ring of slots in LDS that slides forward as the sorted batches
 //    advance, and only slots leaving the ring (or emissions that fall outside
 //    it) reach the detector in HBM, through atomic adds.
 //
-// Slot-difference accumulator.  The detector stores, per cell and slot, the
-// difference between consecutive slot values; the readout turns differences
-// back into slot values with a prefix sum along the slots.  A segment
-// spanning many slots therefore costs two emissions (its value is constant
-// in between), and all emissions are additive, so the ring, its fallback and
-// the order of the particles only change rounding.
+// Slot accumulator.  The detector holds, per cell and slot, the sum over
+// segments of the held E and B times the segment's overlap with the slot in
+// units of dt_det (Alg. 2): the slot's time average, read out as it is.  All
+// updates are additive, so the ring, its fallback and the order of the
+// particles only change rounding.
 #include "radio_internal.h"
 
 #include <climits>
@@ -77,11 +76,11 @@ __device__ __forceinline__ double canon_norm2(double a, double b, double c)
     return (a * a + b * b) + c * c;
 }
 
-// time of the run's state s (s < 2^53, so exact as a double)
-__device__ __forceinline__ double canon_state_time(double t_first, int64_t s, double dt)
+// time of the run's state s (s < 2^53, an integer held exactly as a double)
+__device__ __forceinline__ double canon_state_time(double t_first, double s, double dt)
 {
 #pragma clang fp contract(off)
-    return t_first + (double)s * dt;
+    return t_first + s * dt;
 }
 
 __device__ __forceinline__ double canon_arrival(double t, double R, double inv_c)
@@ -142,7 +141,7 @@ __device__ __forceinline__ double canon_betadot(double b, double bp, double dt)
 // detector updates
 // ---------------------------------------------------------------------------
 
-// Where a lane's finished slot differences go in HBM.  Double path: one atomic
+// Where a lane's finished slot values go in HBM.  Double path: one atomic
 // add per component.  Mixed path: a compensated single-precision pair (hi, lo)
 // per component; the atomic add on hi returns the old value, so the lane knows
 // the exact sum the hardware rounded (old + v) and adds that rounding error
@@ -213,7 +212,7 @@ struct CellSink<double, R> {
     int n_t;
     unsigned* n_bypass;
     template <typename F>
-    __device__ __forceinline__ void flush(int, int j, const F a[6]) const
+    __device__ __forceinline__ void flush(int j, const F a[6]) const
     {
         if (j < 0 || j >= n_t)
             return;
@@ -241,7 +240,7 @@ struct CellSink<float, R> {
     int base;
     int n_t;
     unsigned* n_bypass;
-    __device__ __forceinline__ void flush(int, int j, const float a[6]) const
+    __device__ __forceinline__ void flush(int j, const float a[6]) const
     {
         if (j < 0 || j >= n_t)
             return;
@@ -266,53 +265,32 @@ struct CellSink<float, R> {
 // ---------------------------------------------------------------------------
 
 // For the run being processed the lane integrates the held field over its
-// current slot J (V) and remembers the previous slot's value (Vp); when the
-// run leaves slot J the difference V - Vp is final and is emitted, so every
-// emitted number is a slot value difference computed with the same exact
-// slot-unit overlaps as the integrator definition.
+// current slot J (V); when the run leaves slot J, V is final and is emitted.
+// Every overlap is the exact slot-unit overlap of the integrator definition
+// (Alg. 2), so each segment contributes the same numbers the definition
+// gives; only the order of the additions differs.  Slots outside [0, n_t)
+// are dropped by the sink, which is how the window clips (Alg. 1).
 template <typename T>
 struct Carry {
-    int J;                  // current slot, -1 when nothing is open
-    T V[6];                 // integral of the held field over slot J so far
-    T Vp[6];                // this run's value in slot J - 1
+    int J;     // open slot; may be -1 or n_t (outside the window: dropped on emission)
+    T V[6];    // integral of the held field over slot J so far
 };
 
 template <typename T>
-__device__ __forceinline__ void carry_init(Carry<T>& C)
+__device__ __forceinline__ void carry_open(Carry<T>& C, int J)
 {
-    C.J = -1;
+    C.J = J;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < 6; ++k)
         C.V[k] = T(0);
-        C.Vp[k] = T(0);
-    }
 }
 
-// Finish the open slot: its value difference, then the drop to zero after it.
+// General case: hold F over the slot-coordinate interval between a and b,
+// clipped to [0, n_t]; any order, any length.  A segment that does not start
+// in the open slot closes it first, which is exact because deposits add.
 template <typename T, typename Sink>
-__device__ __forceinline__ void carry_close(Carry<T>& C, const Sink& sink, int n_t)
-{
-    if (C.J >= 0) {
-        T d[6], m[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            d[k] = C.V[k] - C.Vp[k];
-            m[k] = -C.V[k];
-        }
-        sink.flush(n_t, C.J, d);
-        sink.flush(n_t, C.J + 1, m);
-    }
-    carry_init(C);
-}
-
-// Hold F over the slot-coordinate interval between a and b (Alg. 2: each slot
-// receives F times its overlap with the interval, in units of dt_det; parts
-// outside [0, n_t) are dropped).  Segments normally continue where the last
-// one ended; any other start (a reversed or out-of-order segment) closes the
-// open slot and opens a new one, which is exact because deposits add.
-template <typename T, typename Sink>
-__device__ __forceinline__ void add_segment(Carry<T>& C, const Sink& sink, int n_t, double a,
-                                            double b, const T F[6])
+__device__ __forceinline__ void add_segment_general(Carry<T>& C, const Sink& sink, int n_t, double a,
+                                                 double b, const T F[6])
 {
     const double ntd = (double)n_t;
     const double lo = fmin(fmax(fmin(a, b), 0.0), ntd);
@@ -322,38 +300,65 @@ __device__ __forceinline__ void add_segment(Carry<T>& C, const Sink& sink, int n
     const int jl = (int)floor(lo);  // lo < n_t
     const int jh = (int)floor(hi);  // <= n_t; n_t only when hi reaches the end
     if (jl != C.J) {
-        carry_close(C, sink, n_t);
-        C.J = jl;
+        sink.flush(C.J, C.V);
+        carry_open(C, jl);
     }
-    if (jh == C.J) {
+    if (jh == jl) {
         const T w = T(hi - lo);
 #pragma unroll
         for (int k = 0; k < 6; ++k)
             C.V[k] += F[k] * w;
         return;
     }
-    T d[6];
-    const T wa = T((double)(C.J + 1) - lo);
+    const T wa = T((double)(jl + 1) - lo);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < 6; ++k)
         C.V[k] += F[k] * wa;
-        d[k] = C.V[k] - C.Vp[k];
-        C.Vp[k] = C.V[k];
-    }
-    sink.flush(n_t, C.J, d);
-    if (jh > C.J + 1) {  // whole slots in between hold F
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            d[k] = F[k] - C.Vp[k];
-            C.Vp[k] = F[k];
-        }
-        sink.flush(n_t, C.J + 1, d);
-    }
+    sink.flush(jl, C.V);
+    for (int j = jl + 1; j < jh; ++j)  // whole slots hold F
+        sink.flush(j, F);
     const T wb = T(hi - (double)jh);
 #pragma unroll
     for (int k = 0; k < 6; ++k)
         C.V[k] = F[k] * wb;
     C.J = jh;
+}
+
+// One segment [a, b] of a lane's run.  Fast path, taken when the segment
+// runs forward from inside the open slot J (J in [-1, n_t]) and ends at most
+// kFastSlots slots further: the overlaps are b - a (same slot) or J + 1 - a,
+// whole slots, and b - floor(b) -- those of the definition -- and the
+// emissions are guarded by the crossing count only.  Everything else goes
+// through add_segment_general.
+constexpr double kFastSlots = 6.0;
+
+template <typename T, typename Sink>
+__device__ __forceinline__ void add_segment(Carry<T>& C, const Sink& sink, int n_t, double a,
+                                            double b, const T F[6])
+{
+    const double Jd = (double)C.J;
+    const bool fast = (b >= a) & (a >= Jd) & (b < Jd + (kFastSlots + 1.0)) & (Jd >= -1.0) &
+                      (b < (double)n_t + 1.0);
+    if (fast) {
+        const double fb = floor(b);
+        const int n = (int)(fb - Jd);  // slots crossed, at most kFastSlots
+        const T w0 = T((n == 0 ? b : Jd + 1.0) - a);
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            C.V[k] += F[k] * w0;
+        if (n >= 1) {
+            sink.flush(C.J, C.V);
+            for (int i = 1; i < n; ++i)  // whole slots hold F
+                sink.flush(C.J + i, F);
+            const T wb = T(b - fb);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                C.V[k] = F[k] * wb;
+            C.J += n;
+        }
+    } else {
+        add_segment_general(C, sink, n_t, a, b, F);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -764,7 +769,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         const RADIO_GLOBAL double* xr =
             gptr(reinterpret_cast<const double*>(J.recs + order[i] * n_states + s_a));
         const double d0 = xc[0] - xr[0], d1 = xc[1] - xr[1], d2 = xc[2] - xr[2];
-        const double tau = canon_state_time(J.t_first, J.s0 + s_a, J.dt) +
+        const double tau = canon_state_time(J.t_first, (double)(J.s0 + s_a), J.dt) +
                            __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2) * K.inv_c;
         const double u = (tau - K.t0) * K.inv_dt_det;
         if (u == u) {
@@ -812,7 +817,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         const int64_t bt = it % n_batches;
         const int64_t s_a = rb * kRunL;
         const int len = (int)min((int64_t)kRunL, J.n_s - s_a);
-        const double t_a = canon_state_time(J.t_first, J.s0 + s_a, J.dt);
+        const double t_a = canon_state_time(J.t_first, (double)(J.s0 + s_a), J.dt);
         const int64_t i0 = bt * kGroups;
         const int np = (int)min((int64_t)kGroups, J.n_p - i0);
         // slide the ring to this batch's earliest start (every lane of the
@@ -849,14 +854,19 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
             nb[buf * kTileCells + tid] = INT_MAX;
         if (active && g < np) {
             Sink sink{my_ring, row, base, n_t, &n_bypass};
-            Carry<T> C;
-            carry_init(C);
             const double q = sh.sq[g];
             double u_prev = MIX ? slot_coord_mixed(xc, sh.rec[g][0], t_a, K)
                                 : slot_coord_fp64(xc, sh.rec[g][0], t_a, K);
+            Carry<T> C;
+            // open the slot where the run starts (a start far outside the window
+            // leaves the first segment to the general path)
+            carry_open(C, (u_prev >= -1.0 && u_prev < (double)n_t + 1.0) ? (int)floor(u_prev)
+                                                                           : INT_MIN / 2);
+            double sk = (double)(J.s0 + s_a);  // state index, exact below 2^53
             for (int k = 1; k <= len; ++k) {
                 T F[6];
-                const double t_s = canon_state_time(J.t_first, J.s0 + s_a + k, J.dt);
+                sk += 1.0;
+                const double t_s = canon_state_time(J.t_first, sk, J.dt);
                 double uk;
                 if constexpr (MIX)
                     uk = field_mixed(xc, sh.rec[g][k], t_s, (float)q, K, F);
@@ -868,7 +878,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
                 add_segment(C, sink, n_t, u_prev, uk, F);
                 u_prev = uk;
             }
-            carry_close(C, sink, n_t);
+            sink.flush(C.J, C.V);
         }
         __syncthreads();  // records and rings are free for the next batch
     }
@@ -932,77 +942,43 @@ __global__ __launch_bounds__(kDepositThreads) void deposit_persistent_kernel(
     }
 }
 
-// Prefix sum of the slot differences along the slots of each cell; writes
-// E[c][j][0..2] and B[c][j][0..2] for the caller's cell index c of internal
-// row r.  One workgroup per cell.  The mixed accumulator holds (hi, lo)
-// single pairs, folded to double before the sum.
+// E and B from the slot accumulator: E[c][j][0..2] and B[c][j][0..2] for the
+// caller's cell index c of internal row r.  The compensated single
+// accumulator holds (hi, lo) pairs, folded to double.  One thread per slot.
 template <bool PAIRS>
-__global__ __launch_bounds__(256) void readout_kernel(const double* __restrict__ acc, int64_t n_t,
+__global__ __launch_bounds__(256) void readout_kernel(const double* __restrict__ acc, int64_t n_c,
+                                                      int64_t n_t,
                                                       const int64_t* __restrict__ user_index,
                                                       double* __restrict__ E,
                                                       double* __restrict__ B)
 {
-    __shared__ double wsum[4][6];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int64_t r = blockIdx.x;
-    const int64_t cell = user_index[r];
-    const double* rowp = acc + r * n_t * 6;
-    const float* rowf = reinterpret_cast<const float*>(rowp);
-    double carry[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t b0 = 0; b0 < n_t; b0 += 256) {
-        const int64_t j = b0 + tid;
+    const int64_t total = n_c * n_t;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / n_t;
+        const int64_t j = i - r * n_t;
         double v[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            if (j < n_t)
-                v[k] = PAIRS ? (double)rowf[j * 12 + k] + (double)rowf[j * 12 + 6 + k]
-                           : rowp[j * 6 + k];
-            else
-                v[k] = 0.0;
-        }
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                double t = __shfl_up(v[k], off, 64);
-                if (lane >= off)
-                    v[k] += t;
-            }
-        }
-        if (lane == 63) {
+        if (PAIRS) {
+            const float* q = reinterpret_cast<const float*>(acc) + i * 12;
 #pragma unroll
             for (int k = 0; k < 6; ++k)
-                wsum[wave][k] = v[k];
-        }
-        __syncthreads();
-        double tot[6];
+                v[k] = (double)q[k] + (double)q[6 + k];
+        } else {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            double pre = carry[k];
-            for (int w = 0; w < wave; ++w)
-                pre += wsum[w][k];
-            v[k] += pre;
-            tot[k] = carry[k] + ((wsum[0][k] + wsum[1][k]) + (wsum[2][k] + wsum[3][k]));
+            for (int k = 0; k < 6; ++k)
+                v[k] = acc[i * 6 + k];
         }
-        if (j < n_t) {
-            const int64_t o = (cell * n_t + j) * 3;
-            if (E) {
-                E[o] = v[0];
-                E[o + 1] = v[1];
-                E[o + 2] = v[2];
-            }
-            if (B) {
-                B[o] = v[3];
-                B[o + 1] = v[4];
-                B[o + 2] = v[5];
-            }
+        const int64_t o = (user_index[r] * n_t + j) * 3;
+        if (E) {
+            E[o] = v[0];
+            E[o + 1] = v[1];
+            E[o + 2] = v[2];
         }
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-            carry[k] = tot[k];
-        __syncthreads();
+        if (B) {
+            B[o] = v[3];
+            B[o + 1] = v[4];
+            B[o + 2] = v[5];
+        }
     }
 }
 
@@ -1173,12 +1149,15 @@ hipError_t launch_readout(const double* acc, int64_t n_c, int64_t n_t, const int
 {
     if (n_c <= 0)
         return hipSuccess;
+    int64_t blocks = (n_c * n_t + 255) / 256;
+    if (blocks > 65536)
+        blocks = 65536;
     if (pairs)
-        hipLaunchKernelGGL(readout_kernel<true>, dim3((unsigned)n_c), dim3(256), 0, s, acc, n_t,
-                           user_index, E, B);
+        hipLaunchKernelGGL(readout_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, acc, n_c,
+                           n_t, user_index, E, B);
     else
-        hipLaunchKernelGGL(readout_kernel<false>, dim3((unsigned)n_c), dim3(256), 0, s, acc, n_t,
-                           user_index, E, B);
+        hipLaunchKernelGGL(readout_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, acc, n_c,
+                           n_t, user_index, E, B);
     return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
 // Host runtime of libradio: the C interface declared in include/radio.h.
 //
-// Owns the detector objects (cell positions and the slot-difference
-// accumulator resident in device memory), validates every call on the host
+// Owns the detector objects (cell positions and the slot accumulator
+// resident in device memory), validates every call on the host
 // before anything is enqueued, plans the work decomposition and launches the
 // kernels on the caller's stream.
 #include "radio.h"
