@@ -9,7 +9,9 @@ marshals numpy arrays into it.
 Functions and the passages they follow:
   kinematics(u)            Alg. 1: beta = p / sqrt(|p|^2 + 1), 1/gamma^2
   arrival(x_cell, x, t, c) Eq. 2: t_det = t + |x_part - x_cell| / c
-  field(...)               Eq. 1: Lienard-Wiechert E and B = n x E
+                           (far=True: Eq. 3, t + R_cell/c - x_part . n_cell / c)
+  field(...)               Eq. 1: Lienard-Wiechert E and B = n x E (options:
+                           FAR_FIELD geometry, ACCEL_ONLY second term)
   deposit(...)             Alg. 1 + Alg. 2 with the integrator-detector
                            definition of Sec. 3.2 (slot value = integral of
                            the piecewise-constant field over the slot / dt_det)
@@ -28,6 +30,9 @@ _SRC = os.path.join(_HERE, "radio_oracle.c")
 _LIB = os.path.join(_HERE, "libradio_oracle.so")
 
 _lib = None
+
+FAR_FIELD = 1   # Eq. 3 arrival time and the cell's direction and distance in Eq. 1
+ACCEL_ONLY = 2  # only the acceleration term of Eq. 1
 
 
 def build(force: bool = True) -> str:
@@ -56,12 +61,14 @@ def _load():
         lib.radio_oracle_kinematics.restype = None
         lib.radio_oracle_arrival.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double]
         lib.radio_oracle_arrival.restype = ctypes.c_double
-        lib.radio_oracle_field.argtypes = [dp, dp, dp, ctypes.c_double, dp, ctypes.c_double,
-                                           ctypes.c_double, dp, dp]
-        lib.radio_oracle_field.restype = None
+        lib.radio_oracle_arrival_far.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double]
+        lib.radio_oracle_arrival_far.restype = ctypes.c_double
+        lib.radio_oracle_field_opts.argtypes = [dp, dp, dp, ctypes.c_double, dp, ctypes.c_double,
+                                                ctypes.c_double, ctypes.c_int, dp, dp]
+        lib.radio_oracle_field_opts.restype = None
         lib.radio_oracle_deposit.argtypes = [dp, i64, ctypes.c_double, ctypes.c_double, i64,
                                              ctypes.c_double, i64, i64, ctypes.c_double, i64,
-                                             ctypes.c_double, dp, dp, dp, dp,
+                                             ctypes.c_double, dp, dp, dp, ctypes.c_int, dp,
                                              ctypes.POINTER(i64), ctypes.c_int]
         lib.radio_oracle_deposit.restype = ctypes.c_int
         _lib = lib
@@ -86,24 +93,25 @@ def kinematics(u) -> Tuple[np.ndarray, float]:
     return beta, g2.value
 
 
-def arrival(x_cell, x_part, t: float, c: float = 1.0) -> float:
-    return _load().radio_oracle_arrival(_dptr(_f64(x_cell)), _dptr(_f64(x_part)), float(t),
-                                        float(c))
+def arrival(x_cell, x_part, t: float, c: float = 1.0, far: bool = False) -> float:
+    f = _load().radio_oracle_arrival_far if far else _load().radio_oracle_arrival
+    return f(_dptr(_f64(x_cell)), _dptr(_f64(x_part)), float(t), float(c))
 
 
 def field(x_cell, x_part, beta, inv_gamma2: float, betadot, q: float = -1.0,
-          c: float = 1.0) -> Tuple[np.ndarray, np.ndarray]:
+          c: float = 1.0, options: int = 0) -> Tuple[np.ndarray, np.ndarray]:
     E = np.empty(3)
     B = np.empty(3)
-    _load().radio_oracle_field(_dptr(_f64(x_cell)), _dptr(_f64(x_part)), _dptr(_f64(beta)),
-                               float(inv_gamma2), _dptr(_f64(betadot)), float(q), float(c),
-                               _dptr(E), _dptr(B))
+    _load().radio_oracle_field_opts(_dptr(_f64(x_cell)), _dptr(_f64(x_part)), _dptr(_f64(beta)),
+                                    float(inv_gamma2), _dptr(_f64(betadot)), float(q), float(c),
+                                    int(options), _dptr(E), _dptr(B))
     return E, B
 
 
 def deposit(cells, t0: float, dt_det: float, n_t: int, x, u, q, t_first: float, dt: float,
             c: float = 1.0, D: Optional[np.ndarray] = None, n_threads: Optional[int] = None,
-            counters: Optional[np.ndarray] = None, first_step: int = 0) -> np.ndarray:
+            counters: Optional[np.ndarray] = None, first_step: int = 0,
+            options: int = 0) -> np.ndarray:
     """Accumulate one chunk into D[n_cells, n_t, 6] (created zeroed if None).
 
     State s of the chunk is state first_step + s of the run, at time
@@ -128,19 +136,24 @@ def deposit(cells, t0: float, dt_det: float, n_t: int, x, u, q, t_first: float, 
         n_threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     rc = _load().radio_oracle_deposit(
         _dptr(cells), n_c, float(t0), float(dt_det), int(n_t), float(c), n_p, n_states - 1,
-        float(t_first), int(first_step), float(dt), _dptr(x), _dptr(u), _dptr(qa), _dptr(D),
+        float(t_first), int(first_step), float(dt), _dptr(x), _dptr(u), _dptr(qa), int(options),
+        _dptr(D),
         counters.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(n_threads))
     if rc != 0:
         raise ValueError(f"oracle deposit rejected its arguments (rc={rc})")
     return D
 
 
-def deposit_workload(detector, chunk, cell_index=None, D=None, n_threads=None, counters=None):
-    """Convenience: deposit a workloads.Chunk on (a subset of) a DetectorSpec's cells."""
+def deposit_workload(detector, chunk, cell_index=None, D=None, n_threads=None, counters=None,
+                     options=None):
+    """Convenience: deposit a workloads.Chunk on (a subset of) a DetectorSpec's cells
+    (options default to the spec's own, if it has any)."""
+    if options is None:
+        options = getattr(detector, "options", 0)
     cells = detector.cells if cell_index is None else detector.cells[np.asarray(cell_index)]
     return deposit(cells, detector.t0, detector.dt_det, detector.n_t, chunk.x, chunk.u, chunk.q,
                    chunk.t_first, chunk.dt, c=detector.c, D=D, n_threads=n_threads,
-                   counters=counters, first_step=getattr(chunk, "first_step", 0))
+                   counters=counters, first_step=getattr(chunk, "first_step", 0), options=options)
 
 
 def read(D: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:

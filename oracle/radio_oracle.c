@@ -46,6 +46,17 @@
  *   unit n (|n - beta|^2 = 1 - 2 n.beta + |beta|^2 and 1 - |beta|^2 = 1/g)
  *   but has no cancellation as beta -> 1.
  *
+ * Detector options (bit flags, may be combined):
+ *   FAR_FIELD (1): the far-field arrival time of Eq. 3,
+ *       tau_s = t_s + (R_cell - x_{p,s} . n_cell) / c,
+ *       R_cell = |x_c|, n_cell = x_c / R_cell (the cell's distance and
+ *       direction from the origin), and the field of Eq. 1 with the same
+ *       far-field geometry: n = n_cell and R = R_cell.
+ *       Canonical order: R_cell = sqrt(|x_c|^2), n_cell_k = x_c_k * (1/R_cell),
+ *       dot = (x0*n0 + x1*n1) + x2*n2, tau = t_s + (R_cell - dot) * (1/c).
+ *   ACCEL_ONLY (2): only the second (acceleration) term of Eq. 1, which the
+ *       paper keeps when R gamma^2 |betadot| / c >> 1 (Sec. 2).
+ *
  * Conventions: Gaussian units, c given (1 in normalised units), signed
  * charge q per particle (a NULL charge array means q = -1, electrons).
  * Positions and momenta are structure-of-arrays float64
@@ -58,6 +69,9 @@
 #include <stdint.h>
 
 #define EXPORT __attribute__((visibility("default")))
+
+#define ORACLE_FAR_FIELD 1
+#define ORACLE_ACCEL_ONLY 2
 
 /* beta and 1/gamma^2 from the momentum u = gamma beta (Alg. 1). */
 EXPORT void radio_oracle_kinematics(const double u[3], double beta[3], double* inv_gamma2)
@@ -81,6 +95,30 @@ EXPORT double radio_oracle_arrival(const double x_cell[3], const double x_part[3
     return t + R * (1.0 / c);
 }
 
+/* The cell's distance from the origin and its direction (the far-field
+   geometry of Eq. 3). */
+static void far_geometry(const double x_cell[3], double n[3], double* R, double* R2)
+{
+    double Rc2 = (x_cell[0] * x_cell[0] + x_cell[1] * x_cell[1]) + x_cell[2] * x_cell[2];
+    double Rc = sqrt(Rc2);
+    double ri = 1.0 / Rc;
+    n[0] = x_cell[0] * ri;
+    n[1] = x_cell[1] * ri;
+    n[2] = x_cell[2] * ri;
+    *R = Rc;
+    *R2 = Rc2;
+}
+
+/* Far-field arrival time (Eq. 3): t + R_cell/c - x_part . n_cell / c. */
+EXPORT double radio_oracle_arrival_far(const double x_cell[3], const double x_part[3], double t,
+                                       double c)
+{
+    double n[3], Rc, Rc2;
+    far_geometry(x_cell, n, &Rc, &Rc2);
+    double dot = (x_part[0] * n[0] + x_part[1] * n[1]) + x_part[2] * n[2];
+    return t + (Rc - dot) * (1.0 / c);
+}
+
 static void cross(const double a[3], const double b[3], double out[3])
 {
     out[0] = a[1] * b[2] - a[2] * b[1];
@@ -88,21 +126,16 @@ static void cross(const double a[3], const double b[3], double out[3])
     out[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-/* Lienard-Wiechert E and B at x_cell from a charge q at x_part (Eq. 1). */
-EXPORT void radio_oracle_field(const double x_cell[3], const double x_part[3],
-                               const double beta[3], double inv_gamma2, const double betadot[3],
-                               double q, double c, double E[3], double B[3])
+/* Eq. 1 for a given direction n (unit, towards the cell), distance R and R2 = R^2. */
+static void lw_field(const double n[3], double R, double R2, const double beta[3],
+                     double inv_gamma2, const double betadot[3], double q, double c,
+                     int accel_only, double E[3], double B[3])
 {
-    double d[3] = {x_cell[0] - x_part[0], x_cell[1] - x_part[1], x_cell[2] - x_part[2]};
-    double R2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-    double R = sqrt(R2);
-    double rinv = 1.0 / R;
-    double n[3] = {d[0] * rinv, d[1] * rinv, d[2] * rinv};
     double w[3] = {n[0] - beta[0], n[1] - beta[1], n[2] - beta[2]};
     double kappa = 0.5 * (((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]) + inv_gamma2);
     double k3 = kappa * kappa * kappa;
     /* velocity field: q (n - beta) / (gamma^2 kappa^3 R^2) */
-    double cv = q * inv_gamma2 / (k3 * R2);
+    double cv = accel_only ? 0.0 : q * inv_gamma2 / (k3 * R2);
     /* acceleration field: (q/c) n x ((n - beta) x betadot) / (kappa^3 R) */
     double ca = q / (c * k3 * R);
     double wxb[3], nxwxb[3];
@@ -111,6 +144,37 @@ EXPORT void radio_oracle_field(const double x_cell[3], const double x_part[3],
     for (int k = 0; k < 3; ++k)
         E[k] = cv * w[k] + ca * nxwxb[k];
     cross(n, E, B);
+}
+
+/* Lienard-Wiechert E and B at x_cell from a charge q at x_part (Eq. 1), with
+   the detector options above. */
+EXPORT void radio_oracle_field_opts(const double x_cell[3], const double x_part[3],
+                                    const double beta[3], double inv_gamma2,
+                                    const double betadot[3], double q, double c, int options,
+                                    double E[3], double B[3])
+{
+    double n[3], R, R2;
+    if (options & ORACLE_FAR_FIELD) {
+        far_geometry(x_cell, n, &R, &R2);
+    } else {
+        double d[3] = {x_cell[0] - x_part[0], x_cell[1] - x_part[1], x_cell[2] - x_part[2]};
+        R2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+        R = sqrt(R2);
+        double rinv = 1.0 / R;
+        n[0] = d[0] * rinv;
+        n[1] = d[1] * rinv;
+        n[2] = d[2] * rinv;
+    }
+    lw_field(n, R, R2, beta, inv_gamma2, betadot, q, c, (options & ORACLE_ACCEL_ONLY) != 0, E,
+             B);
+}
+
+/* The exact field (no options). */
+EXPORT void radio_oracle_field(const double x_cell[3], const double x_part[3],
+                               const double beta[3], double inv_gamma2, const double betadot[3],
+                               double q, double c, double E[3], double B[3])
+{
+    radio_oracle_field_opts(x_cell, x_part, beta, inv_gamma2, betadot, q, c, 0, E, B);
 }
 
 /* Add F * overlap of the slot-unit interval [lo, hi] with each slot. */
@@ -148,8 +212,8 @@ static void load_state(const double* a, int64_t n_states, int64_t n_p, int64_t s
 EXPORT int radio_oracle_deposit(const double* cells, int64_t n_cells, double t0, double dt_det,
                                 int64_t n_t, double c, int64_t n_p, int64_t n_steps,
                                 double t_first, int64_t first_step, double dt, const double* x,
-                                const double* u, const double* q, double* D, int64_t* counters,
-                                int n_threads)
+                                const double* u, const double* q, int options, double* D,
+                                int64_t* counters, int n_threads)
 {
     if (n_cells < 0 || n_t < 1 || n_p < 0 || n_steps < 0 || first_step < 0 ||
         !(dt_det > 0.0) || !(c > 0.0))
@@ -183,10 +247,16 @@ EXPORT int radio_oracle_deposit(const double* cells, int64_t n_cells, double t0,
                     betadot[k] = (beta[k] - beta_prev[k]) / dt;
                 double t_prev = t_first + (double)(first_step + s - 1) * dt;
                 double t_cur = t_first + (double)(first_step + s) * dt;
-                double tau_prev = radio_oracle_arrival(xc, x_prev, t_prev, c);
-                double tau = radio_oracle_arrival(xc, x_cur, t_cur, c);
+                double tau_prev, tau;
+                if (options & ORACLE_FAR_FIELD) {
+                    tau_prev = radio_oracle_arrival_far(xc, x_prev, t_prev, c);
+                    tau = radio_oracle_arrival_far(xc, x_cur, t_cur, c);
+                } else {
+                    tau_prev = radio_oracle_arrival(xc, x_prev, t_prev, c);
+                    tau = radio_oracle_arrival(xc, x_cur, t_cur, c);
+                }
                 double F[6];
-                radio_oracle_field(xc, x_cur, beta, g2, betadot, qp, c, F, F + 3);
+                radio_oracle_field_opts(xc, x_cur, beta, g2, betadot, qp, c, options, F, F + 3);
                 double a = (tau_prev - t0) * inv_dt_det;
                 double b = (tau - t0) * inv_dt_det;
                 double lo = a < b ? a : b;

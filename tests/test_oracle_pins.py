@@ -562,3 +562,105 @@ def test_coherent_vs_incoherent_emitters(oracle_mod):
     ei = (inc[:, sl, :3] ** 2).sum()
     assert abs(eN / e1 / N ** 2 - 1) < 1e-12
     assert 0.7 < ei / e1 / N < 1.3, ei / e1 / N
+
+
+# ---------------------------------------------------------------- detector options (far field, acceleration only)
+
+def _unit(v):
+    v = np.asarray(v, dtype=np.float64)
+    return v / np.linalg.norm(v)
+
+
+def test_far_field_arrival_is_the_expansion_of_eq2(oracle_mod):
+    """Eq. 3 drops the second-order term of |R_cell n - r| = R - n.r + (r^2 - (n.r)^2)/(2R) + ..."""
+    rng = np.random.Generator(np.random.PCG64(31))
+    for R in (2e2, 1e3, 5e3):
+        for _ in range(20):
+            n = _unit(rng.normal(size=3))
+            r = rng.normal(size=3)
+            xc = R * n
+            t = rng.uniform(-5, 5)
+            exact = oracle_mod.arrival(xc, r, t)
+            far = oracle_mod.arrival(xc, r, t, far=True)
+            second = (r @ r - (r @ n) ** 2) / (2 * R)
+            rr = np.linalg.norm(r)
+            # third-order remainder bounded by |r|^3 / R^2, plus rounding at the size of R
+            assert abs((exact - far) - second) <= rr ** 3 / R ** 2 + 1e-13 * R
+    # the far-field form is linear in the particle position
+    xc = np.array([3.0, -4.0, 1e4])
+    a = oracle_mod.arrival(xc, [1.0, 2.0, 3.0], 0.0, far=True)
+    b = oracle_mod.arrival(xc, [2.0, 4.0, 6.0], 0.0, far=True)
+    z = oracle_mod.arrival(xc, [0.0, 0.0, 0.0], 0.0, far=True)
+    assert abs((b - z) - 2 * (a - z)) <= 1e-11
+
+
+def test_acceleration_only_field_closed_forms(oracle_mod):
+    q = -1.5
+    xc = np.array([40.0, -25.0, 60.0])
+    xp = np.array([1.0, 2.0, -3.0])
+    d = xc - xp
+    R = np.linalg.norm(d)
+    n = d / R
+    bd = np.array([0.03, -0.07, 0.02])
+    ACC = oracle_mod.ACCEL_ONLY
+    # a charge at rest or in uniform motion radiates nothing
+    for beta in ([0.0, 0.0, 0.0], [0.3, -0.4, 0.5]):
+        g2 = 1.0 - float(np.dot(beta, beta))
+        E, B = oracle_mod.field(xc, xp, beta, g2, [0.0, 0.0, 0.0], q=q, options=ACC)
+        assert np.abs(E).max() == 0.0 and np.abs(B).max() == 0.0
+    # instantaneously at rest, accelerating: the dipole radiation field
+    # (q/(c R)) n x (n x a) = (q/(c R)) (n (n.a) - a), kappa = 1
+    c = 1.0
+    E, B = oracle_mod.field(xc, xp, [0.0, 0.0, 0.0], 1.0, bd, q=q, c=c, options=ACC)
+    ref = q / (c * R) * (n * (n @ bd) - bd)
+    np.testing.assert_allclose(E, ref, rtol=1e-13, atol=1e-18)
+    np.testing.assert_allclose(B, np.cross(n, ref), rtol=1e-13, atol=1e-18)
+    # the full field adds the Coulomb field of the charge at rest
+    Ef, _ = oracle_mod.field(xc, xp, [0.0, 0.0, 0.0], 1.0, bd, q=q, c=c)
+    np.testing.assert_allclose(Ef - E, q * n / R ** 2, rtol=1e-12, atol=1e-18)
+
+
+def test_far_field_geometry_uses_the_cell_direction(oracle_mod):
+    """FAR_FIELD: n and R are the cell's direction and distance from the origin,
+    wherever the particle is (at rest and accelerating: the dipole field at n_cell)."""
+    q = 2.0
+    xc = np.array([-300.0, 500.0, 2000.0])
+    Rc = np.linalg.norm(xc)
+    nc = xc / Rc
+    bd = np.array([0.01, 0.02, -0.05])
+    FAR, ACC = oracle_mod.FAR_FIELD, oracle_mod.ACCEL_ONLY
+    for xp in ([0.0, 0.0, 0.0], [5.0, -7.0, 3.0]):
+        E, B = oracle_mod.field(xc, xp, [0.0, 0.0, 0.0], 1.0, bd, q=q, options=FAR | ACC)
+        ref = q / Rc * (nc * (nc @ bd) - bd)
+        np.testing.assert_allclose(E, ref, rtol=1e-13, atol=1e-18)
+        # with the velocity term: Coulomb at the cell's distance, along n_cell
+        Ev, _ = oracle_mod.field(xc, xp, [0.0, 0.0, 0.0], 1.0, [0.0, 0.0, 0.0], q=q, options=FAR)
+        np.testing.assert_allclose(Ev, q * nc / Rc ** 2, rtol=1e-13, atol=1e-20)
+    # and it approaches the exact field as the cell recedes: error O(|r|/R)
+    xp = np.array([2.0, -1.0, 0.5])
+    beta, g2 = [0.2, 0.1, 0.6], 1.0 - 0.41
+    errs = []
+    for R in (1e3, 1e4, 1e5):
+        xcR = _unit([0.2, -0.3, 1.0]) * R
+        Ee, _ = oracle_mod.field(xcR, xp, beta, g2, bd, q=q)
+        Ea, _ = oracle_mod.field(xcR, xp, beta, g2, bd, q=q, options=FAR)
+        errs.append(np.linalg.norm(Ea - Ee) / np.linalg.norm(Ee))
+    assert 5 < errs[0] / errs[1] < 20 and 5 < errs[1] / errs[2] < 20
+
+
+def test_far_field_deposit_equals_exact_for_a_charge_at_the_origin(oracle_mod):
+    """A charge sitting at the origin is where both geometries coincide: the
+    far-field deposit must then equal the exact one bit for bit."""
+    S = 40
+    x = np.zeros((3, S + 1, 1))
+    t = np.arange(S + 1) * 0.05
+    u = np.zeros((3, S + 1, 1))
+    u[0, :, 0] = 0.8 * np.sin(3.0 * t)       # an oscillating velocity at a fixed point
+    u[2, :, 0] = 0.3 * np.cos(2.0 * t)
+    cells = np.array([[0.0, 0.0, 500.0], [120.0, -40.0, 480.0], [-30.0, 200.0, -400.0]])
+    t0, dt_det, n_t = 399.0, 0.05, 2100
+    exact = oracle_mod.deposit(cells, t0, dt_det, n_t, x, u, None, 0.0, 0.05)
+    far = oracle_mod.deposit(cells, t0, dt_det, n_t, x, u, None, 0.0, 0.05,
+                             options=oracle_mod.FAR_FIELD)
+    assert np.abs(exact).max() > 0.0
+    assert np.array_equal(exact, far)
