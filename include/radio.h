@@ -59,6 +59,16 @@ extern "C" {
                                 every add carries its exact rounding error (two-sum)
                                 into lo */
 
+/* detector options (bit flags in radio_detector_desc.options) */
+#define RADIO_FAR_FIELD 1  /* far-field arrival time, Eq. 3: t + R_cell/c - x_part . n_cell/c
+                              with R_cell = |x_cell| and n_cell = x_cell / R_cell (distance
+                              and direction from the origin), and the same geometry in
+                              Eq. 1 (n = n_cell, R = R_cell): no square root per
+                              interaction.  Valid when the particles stay near the origin
+                              compared with R_cell */
+#define RADIO_ACCEL_ONLY 2 /* only the acceleration (second) term of Eq. 1, enough when
+                              R gamma^2 |betadot| / c >> 1 (Sec. 2) */
+
 /* detector cell geometry (Sec. 3.1: spherical grids centred at the origin and
    cartesian planes) */
 #define RADIO_GEOM_EXPLICIT 0 /* cells[n_cells][3] given by the caller */
@@ -89,6 +99,7 @@ typedef struct radio_detector_desc {
     double dt_det;        /* slot width, > 0 */
     int64_t n_t;          /* number of slots, >= 1 */
     double c;             /* speed of light, > 0 (1 in normalised units) */
+    int32_t options;      /* RADIO_FAR_FIELD | RADIO_ACCEL_ONLY, or 0 (Eq. 2 and all of Eq. 1) */
 } radio_detector_desc;
 
 /*

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libradio.so")
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4
 FP64, MIXED, MIXED_TWOSUM = 0, 1, 2
 GEOM_EXPLICIT, GEOM_PLANE, GEOM_SPHERE = 0, 1, 2
+FAR_FIELD, ACCEL_ONLY = 1, 2  # detector options (bit flags)
 _PRECISIONS = {"fp64": FP64, "mixed": MIXED, "mixed_twosum": MIXED_TWOSUM}
 
 # every function the C header declares
@@ -48,7 +49,7 @@ class _Desc(ctypes.Structure):
         ("radius", ctypes.c_double), ("n1", ctypes.c_int64), ("n2", ctypes.c_int64),
         ("half1", ctypes.c_double), ("half2", ctypes.c_double),
         ("t0", ctypes.c_double), ("dt_det", ctypes.c_double), ("n_t", ctypes.c_int64),
-        ("c", ctypes.c_double),
+        ("c", ctypes.c_double), ("options", ctypes.c_int32),
     ]
 
 
@@ -197,11 +198,14 @@ class Detector:
 
     Create it from explicit cell positions (`cells`, an (Nc, 3) array) or
     with Detector.plane / Detector.sphere.  Slot j covers
-    [t0 + j dt_det, t0 + (j+1) dt_det), j < n_t.
+    [t0 + j dt_det, t0 + (j+1) dt_det), j < n_t.  options: FAR_FIELD (Eq. 3
+    arrival time, cell direction and distance in Eq. 1) and/or ACCEL_ONLY (the
+    acceleration term of Eq. 1 alone).
     """
 
     def __init__(self, cells=None, *, t0: float, dt_det: float, n_t: int, c: float = 1.0,
-                 precision: str = "fp64", stream=None, _desc: Optional[_Desc] = None):
+                 precision: str = "fp64", options: int = 0, stream=None,
+                 _desc: Optional[_Desc] = None):
         lib = _lib()
         d = _desc if _desc is not None else _Desc()
         keep = None
@@ -215,12 +219,14 @@ class Detector:
             raise ValueError(f"precision must be one of {sorted(_PRECISIONS)}")
         d.precision = _PRECISIONS[precision]
         d.t0, d.dt_det, d.n_t, d.c = float(t0), float(dt_det), int(n_t), float(c)
+        d.options = int(options)
         h = ctypes.c_void_p()
         _check(lib.radio_detector_create(ctypes.byref(d), _stream(stream), ctypes.byref(h)),
                "radio_detector_create")
         del keep
         self._h = h
         self.precision = precision
+        self.options = int(options)
         n_c, nt, prec = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
         _check(lib.radio_detector_shape(h, ctypes.byref(n_c), ctypes.byref(nt), ctypes.byref(prec)),
                "radio_detector_shape")
@@ -248,10 +254,13 @@ class Detector:
         return cls(_desc=d, **kw)
 
     @classmethod
-    def from_spec(cls, spec, precision: str = "fp64", stream=None) -> "Detector":
-        """From a workloads.DetectorSpec."""
+    def from_spec(cls, spec, precision: str = "fp64", stream=None,
+                  options: Optional[int] = None) -> "Detector":
+        """From a workloads.DetectorSpec (options default to the spec's)."""
+        if options is None:
+            options = getattr(spec, "options", 0)
         return cls(spec.cells, t0=spec.t0, dt_det=spec.dt_det, n_t=spec.n_t, c=spec.c,
-                   precision=precision, stream=stream)
+                   precision=precision, options=options, stream=stream)
 
     @property
     def handle(self) -> ctypes.c_void_p:

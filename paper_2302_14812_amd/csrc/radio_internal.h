@@ -71,6 +71,8 @@ struct DepositJob {
     StateRec* recs;                 // workspace [n_p][n_s+1]
     int32_t* perm;                  // workspace [n_tiles][n_p]
     uint8_t* ring_sel;              // workspace [n_tiles]: 1 where a tile takes the large ring
+    const double* far;              // far-field detector: [n_c][4] n_cell, R_cell; else nullptr
+    double vscale;                  // 1, or 0 for an acceleration-only detector
     int64_t n_c, n_t, n_p, n_s;
     double t_first, dt;             // state s at t_first + (s0 + s)*dt
     int64_t s0;                     // the chunk's first state within its run
@@ -101,9 +103,9 @@ hipError_t launch_ring_choice(const DepositJob& job, hipStream_t s);
 hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s);
 // next: two work counters (small-ring and large-ring workgroups)
 hipError_t launch_deposit_batch(const DepositJob* jobs, const WorkItem* items, int64_t n_items,
-                                unsigned long long* next, int mode, int blocks_small,
+                                unsigned long long* next, int mode, bool far, int blocks_small,
                                 int blocks_large, hipStream_t s);
-int persistent_blocks_per_cu(int mode, bool large_ring);
+int persistent_blocks_per_cu(int mode, bool far, bool large_ring);
 hipError_t launch_readout(const double* acc, int64_t n_c, int64_t n_t, const int64_t* user_index,
                           bool pairs, double* E, double* B, hipStream_t s);
 hipError_t launch_arrival(const double* cells, const double* pts, const double* t, int64_t n,

@@ -368,6 +368,8 @@ __device__ __forceinline__ void add_segment(Carry<T>& C, const Sink& sink, int n
 struct Consts {
     double t0, inv_dt_det, inv_c;
     float inv_cf;
+    double vs;   // weight of the velocity term: 1, or 0 for an acceleration-only detector
+    float vsf;
 };
 
 // 1/x from the hardware reciprocal refined by two Newton steps (within an ulp
@@ -396,8 +398,8 @@ __device__ __forceinline__ double field_fp64(const double xc[3], const StateRec&
     canon_direction(d, rinv, st.b, n, w);
     double kap = canon_kappa(w, st.g2i);
     double k3inv = recip(kap * kap * kap);
-    double ca = q * k3inv * rinv * K.inv_c;        // (q/c) / (kappa^3 R)
-    double cv = q * st.g2i * k3inv * rinv * rinv;  // q / (gamma^2 kappa^3 R^2)
+    double ca = q * k3inv * rinv * K.inv_c;               // (q/c) / (kappa^3 R)
+    double cv = K.vs * q * st.g2i * k3inv * rinv * rinv;  // q / (gamma^2 kappa^3 R^2)
     // w x betadot, then n x (w x betadot)
     double a0 = w[1] * st.bd[2] - w[2] * st.bd[1];
     double a1 = w[2] * st.bd[0] - w[0] * st.bd[2];
@@ -450,7 +452,101 @@ __device__ __forceinline__ double field_mixed(const double xc[3], const StateRec
     const float k3inv = kinv * kinv * kinv;
     const float rinvf = (float)rinv;
     const float ca = q * k3inv * rinvf * K.inv_cf;
-    const float cv = q * st.g2if * k3inv * rinvf * rinvf;
+    const float cv = K.vsf * q * st.g2if * k3inv * rinvf * rinvf;
+    const float a0 = w[1] * st.bdf[2] - w[2] * st.bdf[1];
+    const float a1 = w[2] * st.bdf[0] - w[0] * st.bdf[2];
+    const float a2 = w[0] * st.bdf[1] - w[1] * st.bdf[0];
+    const float m0 = n[1] * a2 - n[2] * a1;
+    const float m1 = n[2] * a0 - n[0] * a2;
+    const float m2 = n[0] * a1 - n[1] * a0;
+    const float E0 = cv * w[0] + ca * m0;
+    const float E1 = cv * w[1] + ca * m1;
+    const float E2 = cv * w[2] + ca * m2;
+    F[0] = E0;
+    F[1] = E1;
+    F[2] = E2;
+    F[3] = n[1] * E2 - n[2] * E1;
+    F[4] = n[2] * E0 - n[0] * E2;
+    F[5] = n[0] * E1 - n[1] * E0;
+    return u;
+}
+
+// Far-field geometry (Eq. 3): the cell's direction and distance from the
+// origin, fc = {n0, n1, n2, R_cell}; arrival t + (R_cell - x.n) (1/c), the
+// dot product in a fixed order without FMA.
+__device__ __forceinline__ double canon_far_arrival(double t, const double fc[4],
+                                                    const double x[3], double inv_c)
+{
+#pragma clang fp contract(off)
+    const double dot = (x[0] * fc[0] + x[1] * fc[1]) + x[2] * fc[2];
+    return t + (fc[3] - dot) * inv_c;
+}
+
+// w = n - beta with the cell's direction
+__device__ __forceinline__ void canon_far_w(const double fc[4], const double b[3], double w[3])
+{
+#pragma clang fp contract(off)
+    w[0] = fc[0] - b[0];
+    w[1] = fc[1] - b[1];
+    w[2] = fc[2] - b[2];
+}
+
+__device__ __forceinline__ double slot_far_mixed(const double fc[4], const double x[3], double t_s,
+                                                 const Consts& K)
+{
+    return canon_slot(t_s + (fc[3] - (x[0] * fc[0] + x[1] * fc[1] + x[2] * fc[2])) * K.inv_c,
+                      K.t0, K.inv_dt_det);
+}
+
+__device__ __forceinline__ double slot_far_fp64(const double fc[4], const double x[3], double t_s,
+                                                const Consts& K)
+{
+    return canon_slot(canon_far_arrival(t_s, fc, x, K.inv_c), K.t0, K.inv_dt_det);
+}
+
+// Eq. 1 with the far-field geometry n = n_cell, R = R_cell; Rinv = 1/R_cell
+__device__ __forceinline__ double field_far_fp64(const double fc[4], double Rinv,
+                                                 const StateRec& st, double t_s, double q,
+                                                 const Consts& K, double F[6])
+{
+    double w[3];
+    canon_far_w(fc, st.b, w);
+    const double kap = canon_kappa(w, st.g2i);
+    const double k3inv = recip(kap * kap * kap);
+    const double ca = q * k3inv * Rinv * K.inv_c;
+    const double cv = K.vs * q * st.g2i * k3inv * Rinv * Rinv;
+    const double a0 = w[1] * st.bd[2] - w[2] * st.bd[1];
+    const double a1 = w[2] * st.bd[0] - w[0] * st.bd[2];
+    const double a2 = w[0] * st.bd[1] - w[1] * st.bd[0];
+    const double m0 = fc[1] * a2 - fc[2] * a1;
+    const double m1 = fc[2] * a0 - fc[0] * a2;
+    const double m2 = fc[0] * a1 - fc[1] * a0;
+    const double E0 = cv * w[0] + ca * m0;
+    const double E1 = cv * w[1] + ca * m1;
+    const double E2 = cv * w[2] + ca * m2;
+    F[0] = E0;
+    F[1] = E1;
+    F[2] = E2;
+    F[3] = fc[1] * E2 - fc[2] * E1;
+    F[4] = fc[2] * E0 - fc[0] * E2;
+    F[5] = fc[0] * E1 - fc[1] * E0;
+    return slot_far_fp64(fc, st.x, t_s, K);
+}
+
+__device__ __forceinline__ double field_far_mixed(const double fc[4], double Rinv,
+                                                  const StateRec& st, double t_s, float q,
+                                                  const Consts& K, float F[6])
+{
+    const double u = slot_far_mixed(fc, st.x, t_s, K);
+    const double wd[3] = {fc[0] - st.b[0], fc[1] - st.b[1], fc[2] - st.b[2]};
+    const double kap = 0.5 * ((wd[0] * wd[0] + wd[1] * wd[1] + wd[2] * wd[2]) + st.g2i);
+    const float n[3] = {(float)fc[0], (float)fc[1], (float)fc[2]};
+    const float w[3] = {(float)wd[0], (float)wd[1], (float)wd[2]};
+    const float kinv = __builtin_amdgcn_rcpf((float)kap);
+    const float k3inv = kinv * kinv * kinv;
+    const float rinvf = (float)Rinv;
+    const float ca = q * k3inv * rinvf * K.inv_cf;
+    const float cv = K.vsf * q * st.g2if * k3inv * rinvf * rinvf;
     const float a0 = w[1] * st.bdf[2] - w[2] * st.bdf[1];
     const float a1 = w[2] * st.bdf[0] - w[0] * st.bdf[2];
     const float a2 = w[0] * st.bdf[1] - w[1] * st.bdf[0];
@@ -622,6 +718,7 @@ constexpr int kChoiceBatches = 8;  // sampled batches per sampled run
 __global__ __launch_bounds__(256) void ring_choice_kernel(const StateRec* __restrict__ recs,
                                                           const int32_t* __restrict__ perm,
                                                           const double* __restrict__ cells,
+                                                          const double* __restrict__ far,
                                                           int64_t n_c, int64_t n_p, int64_t n_s,
                                                           int64_t n_runs, double t_first,
                                                           int64_t s0, double dt, double t0,
@@ -664,9 +761,15 @@ __global__ __launch_bounds__(256) void ring_choice_kernel(const StateRec* __rest
             continue;
         const int64_t p = perm[tile * n_p + pi];
         const StateRec& r = recs[p * n_states + st];
-        const double d0 = ctr[0] - r.x[0], d1 = ctr[1] - r.x[1], d2 = ctr[2] - r.x[2];
-        const double tau = (t_first + (double)(s0 + st) * dt) +
-                           __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2) * inv_c;
+        double dist;
+        if (far) {  // far field: the tile's first cell's direction and distance
+            const double* f = far + 4 * c0;
+            dist = f[3] - (r.x[0] * f[0] + r.x[1] * f[1] + r.x[2] * f[2]);
+        } else {
+            const double d0 = ctr[0] - r.x[0], d1 = ctr[1] - r.x[1], d2 = ctr[2] - r.x[2];
+            dist = __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        }
+        const double tau = (t_first + (double)(s0 + st) * dt) + dist * inv_c;
         double u = (tau - t0) * inv_dt_det;
         if (!(u == u))
             continue;
@@ -715,7 +818,7 @@ struct DepositShared {
 // lanes of a wavefront's row hold different cells, so one ring update
 // instruction touches different rings, and the four groups of a wavefront
 // read their particles' records as LDS broadcasts.
-template <int M, int R>
+template <int M, int R, bool FAR>
 __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, int64_t split,
                                              DepositShared<M, R>& sh)
 {
@@ -731,16 +834,32 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
     const int64_t row_i = tile * kTileCells + cl;  // internal (tile-ordered) cell row
     const bool active = row_i < J.n_c;
     const int n_t = (int)J.n_t;
-    const Consts K{J.t0, J.inv_dt_det, J.inv_c, (float)J.inv_c};
+    const Consts K{J.t0, J.inv_dt_det, J.inv_c, (float)J.inv_c, J.vscale, (float)J.vscale};
     double xc[3] = {0.0, 0.0, 0.0};
+    double fc[4] = {0.0, 0.0, 0.0, 1.0};  // far field: the cell's direction and distance
     RADIO_GLOBAL Acc* row = nullptr;
     if (active) {
         const RADIO_GLOBAL double* cells = gptr(J.cells);
         xc[0] = cells[3 * row_i];
         xc[1] = cells[3 * row_i + 1];
         xc[2] = cells[3 * row_i + 2];
+        if constexpr (FAR) {
+            const RADIO_GLOBAL double* f = gptr(J.far) + 4 * row_i;
+            fc[0] = f[0];
+            fc[1] = f[1];
+            fc[2] = f[2];
+            fc[3] = f[3];
+        }
         row = gptr(reinterpret_cast<Acc*>(J.acc + row_i * J.n_t * 6));
     }
+    const double Rinv = 1.0 / fc[3];
+    // slot coordinate of a state, the same expression the field functions use
+    auto slot_of = [&](const StateRec& st, double t_s) {
+        if constexpr (FAR)
+            return MIX ? slot_far_mixed(fc, st.x, t_s, K) : slot_far_fp64(fc, st.x, t_s, K);
+        else
+            return MIX ? slot_coord_mixed(xc, st, t_s, K) : slot_coord_fp64(xc, st, t_s, K);
+    };
     RADIO_LDS Acc* my_ring = (RADIO_LDS Acc*)&sh.ring[cl * DepositShared<M, R>::kStride];
     RADIO_LDS int* nb = (RADIO_LDS int*)&sh.nb[0][0];
     for (int i = g; i < R * RW; i += kGroups)
@@ -768,10 +887,15 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         const int64_t s_a = (rb_begin + it / n_batches) * kRunL;
         const RADIO_GLOBAL double* xr =
             gptr(reinterpret_cast<const double*>(J.recs + order[i] * n_states + s_a));
-        const double d0 = xc[0] - xr[0], d1 = xc[1] - xr[1], d2 = xc[2] - xr[2];
-        const double tau = canon_state_time(J.t_first, (double)(J.s0 + s_a), J.dt) +
-                           __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2) * K.inv_c;
-        const double u = (tau - K.t0) * K.inv_dt_det;
+        const double t = canon_state_time(J.t_first, (double)(J.s0 + s_a), J.dt);
+        double u;
+        if constexpr (FAR) {
+            u = (t + (fc[3] - (xr[0] * fc[0] + xr[1] * fc[1] + xr[2] * fc[2])) * K.inv_c - K.t0) *
+                K.inv_dt_det;
+        } else {
+            const double d0 = xc[0] - xr[0], d1 = xc[1] - xr[1], d2 = xc[2] - xr[2];
+            u = (t + __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2) * K.inv_c - K.t0) * K.inv_dt_det;
+        }
         if (u == u) {
             const int f = (int)floor(fmin(fmax(u, -1.0), (double)n_t + 1.0));
             __hip_atomic_fetch_min(nb + buf * kTileCells + cl, f, __ATOMIC_RELAXED,
@@ -855,8 +979,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         if (active && g < np) {
             Sink sink{my_ring, row, base, n_t, &n_bypass};
             const double q = sh.sq[g];
-            double u_prev = MIX ? slot_coord_mixed(xc, sh.rec[g][0], t_a, K)
-                                : slot_coord_fp64(xc, sh.rec[g][0], t_a, K);
+            double u_prev = slot_of(sh.rec[g][0], t_a);
             Carry<T> C;
             // open the slot where the run starts (a start far outside the window
             // leaves the first segment to the general path)
@@ -868,10 +991,17 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
                 sk += 1.0;
                 const double t_s = canon_state_time(J.t_first, sk, J.dt);
                 double uk;
-                if constexpr (MIX)
-                    uk = field_mixed(xc, sh.rec[g][k], t_s, (float)q, K, F);
-                else
-                    uk = field_fp64(xc, sh.rec[g][k], t_s, q, K, F);
+                if constexpr (FAR) {
+                    if constexpr (MIX)
+                        uk = field_far_mixed(fc, Rinv, sh.rec[g][k], t_s, (float)q, K, F);
+                    else
+                        uk = field_far_fp64(fc, Rinv, sh.rec[g][k], t_s, q, K, F);
+                } else {
+                    if constexpr (MIX)
+                        uk = field_mixed(xc, sh.rec[g][k], t_s, (float)q, K, F);
+                    else
+                        uk = field_fp64(xc, sh.rec[g][k], t_s, q, K, F);
+                }
                 const bool back = uk < u_prev;
                 n_back += back ? 1u : 0u;
                 n_clip += (fmin(uk, u_prev) < 0.0 || fmax(uk, u_prev) > (double)n_t) ? 1u : 0u;
@@ -897,7 +1027,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
 
 // One workgroup per work item of a single deposit; the tiles that take the
 // other ring size leave at once.
-template <int M, int R>
+template <int M, int R, bool FAR>
 __global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
 {
     __shared__ __align__(16) DepositShared<M, R> sh;
@@ -911,7 +1041,7 @@ __global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
     const int64_t tile = logical % J.n_tiles;
     if (gptr(J.ring_sel)[tile] != (R == kRingLarge ? 1 : 0))
         return;
-    deposit_item<M, R>(J, tile, logical / J.n_tiles, sh);
+    deposit_item<M, R, FAR>(J, tile, logical / J.n_tiles, sh);
 }
 
 // Persistent workgroups for many independent deposits: each takes the next work
@@ -919,7 +1049,7 @@ __global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
 // the list is exhausted, so uneven jobs share one launch without a tail of idle
 // workgroups; items whose tile takes the other ring size are skipped.  Every
 // workgroup leaves once the counter passes n_items.
-template <int M, int R>
+template <int M, int R, bool FAR>
 __global__ __launch_bounds__(kDepositThreads) void deposit_persistent_kernel(
     const DepositJob* __restrict__ jobs, const WorkItem* __restrict__ items, int64_t n_items,
     unsigned long long* __restrict__ next)
@@ -938,7 +1068,7 @@ __global__ __launch_bounds__(kDepositThreads) void deposit_persistent_kernel(
         const DepositJob J = jobs[w.job];
         if (gptr(J.ring_sel)[w.tile] != (R == kRingLarge ? 1 : 0))
             continue;
-        deposit_item<M, R>(J, w.tile, w.split, sh);
+        deposit_item<M, R, FAR>(J, w.tile, w.split, sh);
     }
 }
 
@@ -1066,16 +1196,30 @@ hipError_t launch_ring_choice(const DepositJob& job, hipStream_t s)
     if (job.n_tiles <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(ring_choice_kernel, dim3((unsigned)job.n_tiles), dim3(256), 0, s, job.recs,
-                       job.perm, job.cells, job.n_c, job.n_p, job.n_s, job.n_runs, job.t_first,
+                       job.perm, job.cells, job.far, job.n_c, job.n_p, job.n_s, job.n_runs,
+                       job.t_first,
                        job.s0, job.dt, job.t0, job.inv_dt_det, job.inv_c, job.n_t, job.ring_sel);
     return hipGetLastError();
 }
 
-template <int M>
+template <int M, bool FAR>
 static void launch_deposit_mode(const DepositJob& job, dim3 grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((deposit_kernel<M, kRingSmall>), grid, dim3(kDepositThreads), 0, s, job);
-    hipLaunchKernelGGL((deposit_kernel<M, kRingLarge>), grid, dim3(kDepositThreads), 0, s, job);
+    hipLaunchKernelGGL((deposit_kernel<M, kRingSmall, FAR>), grid, dim3(kDepositThreads), 0, s,
+                       job);
+    hipLaunchKernelGGL((deposit_kernel<M, kRingLarge, FAR>), grid, dim3(kDepositThreads), 0, s,
+                       job);
+}
+
+template <bool FAR>
+static void launch_deposit_far(const DepositJob& job, int mode, dim3 grid, hipStream_t s)
+{
+    if (mode == kModeMix)
+        launch_deposit_mode<kModeMix, FAR>(job, grid, s);
+    else if (mode == kModeMixTwoSum)
+        launch_deposit_mode<kModeMixTwoSum, FAR>(job, grid, s);
+    else
+        launch_deposit_mode<kModeF64, FAR>(job, grid, s);
 }
 
 hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s)
@@ -1085,28 +1229,44 @@ hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s)
         return hipSuccess;
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;  // a multiple of the XCD count
     const dim3 grid((unsigned)blocks);
-    if (mode == kModeMix)
-        launch_deposit_mode<kModeMix>(job, grid, s);
-    else if (mode == kModeMixTwoSum)
-        launch_deposit_mode<kModeMixTwoSum>(job, grid, s);
+    if (job.far)
+        launch_deposit_far<true>(job, mode, grid, s);
     else
-        launch_deposit_mode<kModeF64>(job, grid, s);
+        launch_deposit_far<false>(job, mode, grid, s);
     return hipGetLastError();
 }
 
-template <int M>
+template <int M, bool FAR>
 static void launch_persistent_mode(const DepositJob* jobs, const WorkItem* items, int64_t n_items,
                                    unsigned long long* next, int blocks_small, int blocks_large,
                                    hipStream_t s)
 {
-    hipLaunchKernelGGL((deposit_persistent_kernel<M, kRingSmall>), dim3((unsigned)blocks_small),
-                       dim3(kDepositThreads), 0, s, jobs, items, n_items, next);
-    hipLaunchKernelGGL((deposit_persistent_kernel<M, kRingLarge>), dim3((unsigned)blocks_large),
-                       dim3(kDepositThreads), 0, s, jobs, items, n_items, next + 1);
+    hipLaunchKernelGGL((deposit_persistent_kernel<M, kRingSmall, FAR>),
+                       dim3((unsigned)blocks_small), dim3(kDepositThreads), 0, s, jobs, items,
+                       n_items, next);
+    hipLaunchKernelGGL((deposit_persistent_kernel<M, kRingLarge, FAR>),
+                       dim3((unsigned)blocks_large), dim3(kDepositThreads), 0, s, jobs, items,
+                       n_items, next + 1);
+}
+
+template <bool FAR>
+static void launch_persistent_far(const DepositJob* jobs, const WorkItem* items, int64_t n_items,
+                                  unsigned long long* next, int mode, int blocks_small,
+                                  int blocks_large, hipStream_t s)
+{
+    if (mode == kModeMix)
+        launch_persistent_mode<kModeMix, FAR>(jobs, items, n_items, next, blocks_small,
+                                              blocks_large, s);
+    else if (mode == kModeMixTwoSum)
+        launch_persistent_mode<kModeMixTwoSum, FAR>(jobs, items, n_items, next, blocks_small,
+                                                    blocks_large, s);
+    else
+        launch_persistent_mode<kModeF64, FAR>(jobs, items, n_items, next, blocks_small,
+                                              blocks_large, s);
 }
 
 hipError_t launch_deposit_batch(const DepositJob* jobs, const WorkItem* items, int64_t n_items,
-                                unsigned long long* next, int mode, int blocks_small,
+                                unsigned long long* next, int mode, bool far, int blocks_small,
                                 int blocks_large, hipStream_t s)
 {
     if (n_items <= 0)
@@ -1114,34 +1274,39 @@ hipError_t launch_deposit_batch(const DepositJob* jobs, const WorkItem* items, i
     hipError_t e = launch_zero_u64(next, 2, s);
     if (e != hipSuccess)
         return e;
-    if (mode == kModeMix)
-        launch_persistent_mode<kModeMix>(jobs, items, n_items, next, blocks_small, blocks_large, s);
-    else if (mode == kModeMixTwoSum)
-        launch_persistent_mode<kModeMixTwoSum>(jobs, items, n_items, next, blocks_small,
-                                               blocks_large, s);
+    if (far)
+        launch_persistent_far<true>(jobs, items, n_items, next, mode, blocks_small, blocks_large,
+                                    s);
     else
-        launch_persistent_mode<kModeF64>(jobs, items, n_items, next, blocks_small, blocks_large, s);
+        launch_persistent_far<false>(jobs, items, n_items, next, mode, blocks_small, blocks_large,
+                                     s);
     return hipGetLastError();
 }
 
-template <int M>
+template <int M, bool FAR>
 static int blocks_per_cu(bool large_ring)
 {
     int n = 0;
-    const void* f = large_ring
-                        ? reinterpret_cast<const void*>(deposit_persistent_kernel<M, kRingLarge>)
-                        : reinterpret_cast<const void*>(deposit_persistent_kernel<M, kRingSmall>);
+    const void* f =
+        large_ring ? reinterpret_cast<const void*>(deposit_persistent_kernel<M, kRingLarge, FAR>)
+                   : reinterpret_cast<const void*>(deposit_persistent_kernel<M, kRingSmall, FAR>);
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kDepositThreads, 0);
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 
-int persistent_blocks_per_cu(int mode, bool large_ring)
+template <bool FAR>
+static int blocks_per_cu_far(int mode, bool large_ring)
 {
     if (mode == kModeMix)
-        return blocks_per_cu<kModeMix>(large_ring);
+        return blocks_per_cu<kModeMix, FAR>(large_ring);
     if (mode == kModeMixTwoSum)
-        return blocks_per_cu<kModeMixTwoSum>(large_ring);
-    return blocks_per_cu<kModeF64>(large_ring);
+        return blocks_per_cu<kModeMixTwoSum, FAR>(large_ring);
+    return blocks_per_cu<kModeF64, FAR>(large_ring);
+}
+
+int persistent_blocks_per_cu(int mode, bool far, bool large_ring)
+{
+    return far ? blocks_per_cu_far<true>(mode, large_ring) : blocks_per_cu_far<false>(mode, large_ring);
 }
 
 hipError_t launch_readout(const double* acc, int64_t n_c, int64_t n_t, const int64_t* user_index,

@@ -35,6 +35,8 @@ struct radio_detector {
     size_t perm_cap = 0;                       // in entries
     uint8_t* d_sel = nullptr;                  // workspace: ring size per tile
     size_t sel_cap = 0;
+    int32_t options = 0;                       // RADIO_FAR_FIELD | RADIO_ACCEL_ONLY
+    double* d_far = nullptr;                   // FAR_FIELD: [n_c][4] n_cell, R_cell per row
     int64_t interactions = 0;
     int64_t chunks = 0;
     std::vector<double> h_cells;               // caller's order
@@ -252,6 +254,29 @@ int validate_chunk(const radio_chunk* k)
     return RADIO_OK;
 }
 
+// The far-field geometry of every cell (Eq. 3): its direction n = x * (1/R) and
+// distance R = sqrt(|x|^2) from the origin, as [n0, n1, n2, R] per row, one IEEE
+// operation at a time (these enter the arrival time).  False if a cell sits
+// at the origin.
+bool far_geometry(const std::vector<double>& cells, std::vector<double>& far)
+{
+#pragma clang fp contract(off)
+    const size_t n = cells.size() / 3;
+    far.resize(4 * n);
+    for (size_t r = 0; r < n; ++r) {
+        const double* x = &cells[3 * r];
+        const double R = std::sqrt((x[0] * x[0] + x[1] * x[1]) + x[2] * x[2]);
+        if (!(R > 0.0) || !std::isfinite(R))
+            return false;
+        const double ri = 1.0 / R;
+        far[4 * r] = x[0] * ri;
+        far[4 * r + 1] = x[1] * ri;
+        far[4 * r + 2] = x[2] * ri;
+        far[4 * r + 3] = R;
+    }
+    return true;
+}
+
 radio::DepositJob make_job(radio_detector* det, const radio_chunk* k)
 {
     radio::DepositJob J{};
@@ -267,6 +292,8 @@ radio::DepositJob make_job(radio_detector* det, const radio_chunk* k)
     J.n_s = k->n_steps;
     J.t_first = k->t_first;
     J.s0 = k->first_step;
+    J.far = det->d_far;
+    J.vscale = (det->options & RADIO_ACCEL_ONLY) ? 0.0 : 1.0;
     J.dt = k->dt;
     J.t0 = det->t0;
     J.inv_dt_det = 1.0 / det->dt_det;
@@ -334,7 +361,7 @@ struct BatchArena {
     size_t jobs_cap = 0;
     radio::WorkItem* d_items = nullptr;
     size_t items_cap = 0;
-    unsigned long long* d_next = nullptr;  // two counters (ring sizes) per precision mode
+    unsigned long long* d_next = nullptr;  // two counters (ring sizes) per kernel variant
     radio::StateRec* d_recs = nullptr;
     size_t recs_cap = 0;
     int32_t* d_perm = nullptr;
@@ -352,6 +379,7 @@ struct BatchArena {
 // while the previous one still runs, and only the batch before that must have
 // finished.
 constexpr int kArenas = 2;
+constexpr int kVariants = 6;  // precision modes x {exact, far-field}
 std::mutex g_arena_mu;
 std::map<int, BatchArena*> g_arenas[kArenas];
 std::map<int, int> g_arena_next;
@@ -370,7 +398,7 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, dev) != hipSuccess ||
             hipEventCreateWithFlags(&A->done, hipEventDisableTiming) != hipSuccess ||
-            hipMalloc((void**)&A->d_next, 6 * sizeof(unsigned long long)) != hipSuccess) {
+            hipMalloc((void**)&A->d_next, 2 * kVariants * sizeof(unsigned long long)) != hipSuccess) {
             (void)hipGetLastError();
             return RADIO_EDEVICE;
         }
@@ -415,11 +443,10 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
     double total = 0.0;
     for (const auto& J : A->h_jobs)
         total += (double)J.n_c * (double)J.n_p * (double)J.n_s;
-    const int n_modes = 3;
-    int bpc[n_modes][2];  // resident workgroups per CU: [mode][large ring]
-    for (int m = 0; m < n_modes; ++m)
+    int bpc[kVariants][2];  // resident workgroups per CU: [variant][large ring]
+    for (int v = 0; v < kVariants; ++v)
         for (int r = 0; r < 2; ++r)
-            bpc[m][r] = radio::persistent_blocks_per_cu(m, r == 1);
+            bpc[v][r] = radio::persistent_blocks_per_cu(v % 3, v >= 3, r == 1);
     const double resident = (double)A->n_cus * (double)bpc[0][0];
     const double item_work = std::max(total / (resident * (double)tun.items_per_workgroup), 1.0);
     struct Item {
@@ -442,7 +469,8 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
         rps = std::max<int64_t>(1, std::min<int64_t>(rps, J.n_runs));
         J.runs_per_split = rps;
         J.n_splits = (J.n_runs + rps - 1) / rps;
-        const int mode = dets[idx[j]]->precision;
+        // kernel variant: precision mode, plus 3 for a far-field detector
+        const int mode = dets[idx[j]]->precision + (J.far ? 3 : 0);
         for (int64_t sp = 0; sp < J.n_splits; ++sp) {
             const int64_t runs = std::min<int64_t>(rps, J.n_runs - sp * rps);
             for (int64_t t = 0; t < J.n_tiles; ++t)
@@ -474,8 +502,9 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
         while (e < items.size() && items[e].mode == mode)
             ++e;
         if (radio::launch_deposit_batch(A->d_jobs, A->d_items + b, (int64_t)(e - b),
-                                        A->d_next + 2 * mode, mode, A->n_cus * bpc[mode][0],
-                                        A->n_cus * bpc[mode][1], s) != hipSuccess)
+                                        A->d_next + 2 * mode, mode % 3, mode >= 3,
+                                        A->n_cus * bpc[mode][0], A->n_cus * bpc[mode][1],
+                                        s) != hipSuccess)
             return RADIO_EDEVICE;
         b = e;
     }
@@ -527,6 +556,8 @@ int radio_detector_create(const radio_detector_desc* desc, void* stream, radio_d
         return RADIO_EINVAL;
     if (!std::isfinite(desc->c) || !(desc->c > 0.0))
         return RADIO_EINVAL;
+    if ((desc->options & ~(RADIO_FAR_FIELD | RADIO_ACCEL_ONLY)) != 0)
+        return RADIO_EINVAL;
     std::vector<double> cells;
     int rc = build_cells(*desc, cells);
     if (rc != RADIO_OK)
@@ -543,6 +574,7 @@ int radio_detector_create(const radio_detector_desc* desc, void* stream, radio_d
         return RADIO_EDEVICE;
     }
     det->precision = desc->precision;
+    det->options = desc->options;
     det->n_c = n_c;
     det->n_t = desc->n_t;
     det->t0 = desc->t0;
@@ -567,6 +599,20 @@ int radio_detector_create(const radio_detector_desc* desc, void* stream, radio_d
         (void)hipGetLastError();
         radio_detector_destroy(det);
         return RADIO_ENOMEM;
+    }
+    std::vector<double> far;
+    if (det->options & RADIO_FAR_FIELD) {
+        if (!far_geometry(internal, far)) {  // a cell at the origin has no direction
+            radio_detector_destroy(det);
+            return RADIO_EINVAL;
+        }
+        if (hipMalloc((void**)&det->d_far, far.size() * sizeof(double)) != hipSuccess ||
+            hipMemcpyAsync(det->d_far, far.data(), far.size() * sizeof(double),
+                           hipMemcpyHostToDevice, s) != hipSuccess) {
+            (void)hipGetLastError();
+            radio_detector_destroy(det);
+            return RADIO_ENOMEM;
+        }
     }
     if (hipMemcpyAsync(det->d_cells, internal.data(), (size_t)n_c * 3 * sizeof(double),
                        hipMemcpyHostToDevice, s) != hipSuccess ||
@@ -607,6 +653,8 @@ int radio_detector_destroy(radio_detector* det)
             (void)hipFree(det->d_perm);
         if (det->d_sel)
             (void)hipFree(det->d_sel);
+        if (det->d_far)
+            (void)hipFree(det->d_far);
     }
     delete det;
     return rc;

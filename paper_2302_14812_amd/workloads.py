@@ -86,6 +86,7 @@ class DetectorSpec:
     n_t: int
     c: float = 1.0
     grid: Tuple[int, int] = (0, 0)  # (n1, n2) when the cells come from a 2-D grid
+    options: int = 0                # detector options: 1 far field (Eq. 3), 2 acceleration only
 
     @property
     def n_cells(self) -> int:

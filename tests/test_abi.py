@@ -89,6 +89,9 @@ def test_invalid_arguments_rejected_before_any_device_work():
     d.precision = 7
     assert lib.radio_detector_create(ctypes.byref(d), None, ctypes.byref(h)) == radio.EINVAL
     d.precision = 0
+    d.options = 4  # unknown option bit
+    assert lib.radio_detector_create(ctypes.byref(d), None, ctypes.byref(h)) == radio.EINVAL
+    d.options = radio.FAR_FIELD | radio.ACCEL_ONLY
     d.geometry = 9
     assert lib.radio_detector_create(ctypes.byref(d), None, ctypes.byref(h)) == radio.EINVAL
     d.geometry = radio.GEOM_EXPLICIT
