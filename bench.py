@@ -44,6 +44,7 @@ def parse():
                     help="skip the batched-launch leg (64 uneven sets, one persistent launch "
                          "vs 64 separate launches)")
     ap.add_argument("--no-serve", action="store_true", help="skip the streaming-service leg")
+    ap.add_argument("--no-far", action="store_true", help="skip the far-field option leg")
     ap.add_argument("--serve-chunks", type=int, default=30,
                     help="timed chunks of the streaming leg (after a fifth as many warm-up)")
     ap.add_argument("--serve-load", type=float, default=0.8,
@@ -54,9 +55,9 @@ def parse():
     return ap.parse_args()
 
 
-def time_precision(radio, wl, chunk_dev, precision, steps, warmup):
+def time_precision(radio, wl, chunk_dev, precision, steps, warmup, options=0, keep=False):
     import torch
-    det = radio.Detector.from_spec(wl.detector, precision=precision)
+    det = radio.Detector.from_spec(wl.detector, precision=precision, options=options)
     E = torch.empty((det.n_cells, det.n_t, 3), dtype=torch.float64, device="cuda")
     B = torch.empty_like(E)
     stream = torch.cuda.current_stream()
@@ -84,8 +85,38 @@ def time_precision(radio, wl, chunk_dev, precision, steps, warmup):
     wall = time.perf_counter() - t0
     kernel_ms = sum(a.elapsed_time(b) for a, b in evs) / steps
     det.close()
+    if keep:
+        return wall / steps * 1e3, kernel_ms, (E, B)
     del E, B
     return wall / steps * 1e3, kernel_ms
+
+
+def far_leg(radio, wl, chunk_dev, precision, steps, warmup):
+    """The far-field detector option (Eq. 3 arrival time, cell direction and distance in
+    Eq. 1) on the benchmark workload: throughput, and its departure from the exact
+    deposit (a property of the approximation, not of the kernel)."""
+    import torch
+    out = {"precision": precision}
+    fields = {}
+    for name, opt in (("exact", 0), ("far_field", radio.FAR_FIELD),
+                      ("far_field_accel_only", radio.FAR_FIELD | radio.ACCEL_ONLY)):
+        ms, kms, EB = time_precision(radio, wl, chunk_dev, precision, steps if opt else 1,
+                                     warmup if opt else 0, options=opt, keep=True)
+        fields[name] = EB
+        inter = wl.interactions
+        if opt:
+            out[name] = {"ms_per_step": ms, "deposit_kernel_ms": kms,
+                         "value": inter / (ms * 1e-3)}
+        print(f"[bench] {precision} options={opt}: {ms:.1f} ms/step, "
+              f"{inter / (ms * 1e-3):.3e} interactions/s", file=sys.stderr, flush=True)
+    Ee = fields["exact"][0]
+    for name in ("far_field", "far_field_accel_only"):
+        Ef = fields[name][0]
+        out[name]["rel_l2_vs_exact"] = float(torch.linalg.vector_norm(Ef - Ee) /
+                                             torch.linalg.vector_norm(Ee))
+    del fields, Ee, Ef
+    torch.cuda.synchronize()
+    return out
 
 
 def batch_leg(radio, W, precision, steps, warmup):
@@ -304,6 +335,8 @@ def main():
               f"{legs[prec]['value']:.3e} interactions/s", file=sys.stderr, flush=True)
 
     main_leg = legs[args.precision]
+    far = None if args.no_far else far_leg(radio, wl, chunk_dev, args.precision, args.steps,
+                                           args.warmup)
     del chunk_dev
     batch = None if args.no_batch else batch_leg(radio, W, args.precision, args.steps, args.warmup)
     out = {
@@ -330,6 +363,8 @@ def main():
         out["mixed_vs_fp64_speedup"] = legs["fp64"]["ms_per_step"] / main_leg["ms_per_step"]
     if "mixed_twosum" in legs and args.precision != "mixed_twosum":
         out["mixed_twosum"] = legs["mixed_twosum"]
+    if far is not None:
+        out["far_field"] = far
     if batch is not None:
         out["batch"] = batch
     if not args.no_serve:

@@ -707,13 +707,17 @@ __global__ __launch_bounds__(256) void order_kernel(const double* __restrict__ x
     }
 }
 
-// For every tile, whether its batches need the large slot ring.  Samples
-// batches of the first and the middle run in the tile's particle order and
-// takes the largest spread of their slot coordinates at the tile's centre over
-// kGroups particles x (kRunL + 1) states; a tile whose spread, with the ring's
-// margin, exceeds the small ring takes the large one.  Only speed depends on
-// this choice: emissions outside a ring go to HBM directly.
-constexpr int kChoiceBatches = 8;  // sampled batches per sampled run
+// For every tile, whether its batches take the large slot ring.  The small
+// ring keeps four workgroups on a CU, the large one two, so the large ring
+// pays only where the small one would send many emissions to HBM.  The
+// kernel replays sampled batches (the first and the middle run, at eight
+// places of the tile's particle order) at the tile's first cell: it places
+// a small ring the way the deposit does (below the batch's earliest start)
+// and counts the slots a lane would emit outside it.  Above kRingBypassLimit
+// such emissions per interaction the tile takes the large ring.  Only speed
+// depends on this choice: emissions outside a ring go to HBM directly.
+constexpr int kChoiceBatches = 8;           // sampled batches per sampled run
+constexpr double kRingBypassLimit = 0.05;   // emissions to HBM per interaction
 
 __global__ __launch_bounds__(256) void ring_choice_kernel(const StateRec* __restrict__ recs,
                                                           const int32_t* __restrict__ perm,
@@ -722,70 +726,73 @@ __global__ __launch_bounds__(256) void ring_choice_kernel(const StateRec* __rest
                                                           int64_t n_c, int64_t n_p, int64_t n_s,
                                                           int64_t n_runs, double t_first,
                                                           int64_t s0, double dt, double t0,
-                                                          double inv_dt_det,
-                                                          double inv_c, int64_t n_t,
-                                                          uint8_t* __restrict__ sel)
+                                                          double inv_dt_det, double inv_c,
+                                                          int64_t n_t, uint8_t* __restrict__ sel)
 {
     constexpr int kSamples = 2 * kChoiceBatches;
-    constexpr int kPer = kGroups * (kRunL + 1);
-    __shared__ int lo[kSamples], hi[kSamples];
-    __shared__ double ctr[3];
+    static_assert(kSamples * kGroups <= 256, "one thread per sampled particle");
+    __shared__ int start[kSamples];
+    __shared__ unsigned out_count, segs;
     const int tid = threadIdx.x;
     const int64_t tile = blockIdx.x;
     const int64_t c0 = tile * kTileCells;
-    const int64_t c1 = min(c0 + (int64_t)kTileCells, n_c);
-    if (tid < 3) {
-        double sum = 0.0;
-        for (int64_t c = c0; c < c1; ++c)
-            sum += cells[3 * c + tid];
-        ctr[tid] = sum / (double)(c1 - c0);
+    if (tid < kSamples)
+        start[tid] = INT_MAX;
+    if (tid == 0) {
+        out_count = 0u;
+        segs = 0u;
     }
-    if (tid < kSamples) {
-        lo[tid] = INT_MAX;
-        hi[tid] = INT_MIN;
-    }
-    __syncthreads();
+    const int smp = tid / kGroups;  // sampled batch
+    const int gg = tid % kGroups;   // particle within it
     const int64_t n_states = n_s + 1;
     const int64_t n_batches = (n_p + kGroups - 1) / kGroups;
-    const double lim = (double)n_t + 1.0;
-    for (int i = tid; i < kSamples * kPer; i += 256) {
-        const int smp = i / kPer;
-        const int rem = i - smp * kPer;
-        const int gg = rem / (kRunL + 1);
-        const int k = rem - gg * (kRunL + 1);
-        const int64_t run = (smp < kChoiceBatches) ? 0 : n_runs / 2;
-        const int64_t bt = (2 * (int64_t)(smp % kChoiceBatches) + 1) * n_batches / (2 * kChoiceBatches);
-        const int64_t st = run * kRunL + k;
-        const int64_t pi = bt * kGroups + gg;
-        if (st > n_s || pi >= n_p)
-            continue;
-        const int64_t p = perm[tile * n_p + pi];
-        const StateRec& r = recs[p * n_states + st];
+    const int64_t run = (smp < kChoiceBatches) ? 0 : n_runs / 2;
+    const int64_t bt = (2 * (int64_t)(smp % kChoiceBatches) + 1) * n_batches / (2 * kChoiceBatches);
+    const int64_t pi = bt * kGroups + gg;
+    const int64_t s_a = run * kRunL;
+    const int len = (int)min((int64_t)kRunL, n_s - s_a);
+    const bool on = smp < kSamples && pi < n_p && len > 0;
+    const double* xc = cells + 3 * c0;
+    const double* fc = far ? far + 4 * c0 : nullptr;
+    auto slot_of = [&](const StateRec& r, int64_t st) {
         double dist;
-        if (far) {  // far field: the tile's first cell's direction and distance
-            const double* f = far + 4 * c0;
-            dist = f[3] - (r.x[0] * f[0] + r.x[1] * f[1] + r.x[2] * f[2]);
+        if (fc) {
+            dist = fc[3] - (r.x[0] * fc[0] + r.x[1] * fc[1] + r.x[2] * fc[2]);
         } else {
-            const double d0 = ctr[0] - r.x[0], d1 = ctr[1] - r.x[1], d2 = ctr[2] - r.x[2];
+            const double d0 = xc[0] - r.x[0], d1 = xc[1] - r.x[1], d2 = xc[2] - r.x[2];
             dist = __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2);
         }
-        const double tau = (t_first + (double)(s0 + st) * dt) + dist * inv_c;
-        double u = (tau - t0) * inv_dt_det;
-        if (!(u == u))
-            continue;
-        u = fmin(fmax(u, -1.0), lim);
-        const int f = (int)floor(u);
-        atomicMin(&lo[smp], f);
-        atomicMax(&hi[smp], f);
+        const double u = ((t_first + (double)(s0 + st) * dt) + dist * inv_c - t0) * inv_dt_det;
+        return (u == u) ? fmin(fmax(u, -2.0), (double)n_t + 2.0) : -2.0;
+    };
+    const StateRec* pr = on ? recs + (int64_t)perm[tile * n_p + pi] * n_states + s_a : nullptr;
+    __syncthreads();
+    if (on)
+        atomicMin(&start[smp], (int)floor(slot_of(pr[0], s_a)));
+    __syncthreads();
+    if (on) {
+        // the small ring of this batch, placed as the deposit places it
+        const int base = (int)fmin(fmax((double)start[smp] - (double)kRingMargin, 0.0),
+                                   fmax((double)(n_t - kRingSmall), 0.0));
+        unsigned outside = 0u;
+        auto emit = [&](int j) {
+            if (j >= 0 && j < n_t && (j < base || j >= base + kRingSmall))
+                ++outside;
+        };
+        int J = (int)floor(slot_of(pr[0], s_a));
+        for (int k = 1; k <= len; ++k) {
+            const int jk = (int)floor(slot_of(pr[k], s_a + k));
+            for (int j = min(J, jk); j < max(J, jk); ++j)  // slots the lane leaves
+                emit(j);
+            J = jk;
+        }
+        emit(J);  // the run's last slot
+        atomicAdd(&out_count, outside);
+        atomicAdd(&segs, (unsigned)len);
     }
     __syncthreads();
-    if (tid == 0) {
-        int span = 0;
-        for (int i = 0; i < kSamples; ++i)
-            if (hi[i] >= lo[i])
-                span = max(span, hi[i] - lo[i]);
-        sel[tile] = (span + kRingMargin + 2 > kRingSmall) ? 1 : 0;
-    }
+    if (tid == 0)
+        sel[tile] = (segs > 0u && (double)out_count > kRingBypassLimit * (double)segs) ? 1 : 0;
 }
 
 // M: arithmetic of the deposit (field in double or single; accumulation in
