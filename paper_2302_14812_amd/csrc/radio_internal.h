@@ -6,19 +6,26 @@
 
 namespace radio {
 
-// One trajectory state as the deposit reads it (96 B, 16-B aligned): position,
-// beta, betadot = (beta_s - beta_{s-1})/dt (zero for the first state of a
-// chunk, which carries no segment), 1/gamma^2, and single-precision copies of
-// betadot and 1/gamma^2 for the mixed field.
-struct StateRec {
+// One trajectory state as the deposit reads it, laid out per arithmetic mode
+// (the states of one particle are contiguous): position, beta, 1/gamma^2 and
+// betadot = (beta_s - beta_{s-1})/dt (zero for the first state of a chunk,
+// which carries no segment).  The mixed modes keep betadot and a copy of
+// 1/gamma^2 in single precision.  Both records are 80 bytes.
+struct RecF64 {
     double x[3];
     double b[3];
     double bd[3];
     double g2i;
+};
+struct RecMix {
+    double x[3];
+    double b[3];
+    double g2i;
     float bdf[3];
     float g2if;
+    double pad;  // to 80 bytes: records stay 16-byte aligned, and so do their LDS reads
 };
-static_assert(sizeof(StateRec) == 96, "StateRec layout");
+static_assert(sizeof(RecF64) == 80 && sizeof(RecMix) == 80, "state record layouts");
 
 // arithmetic of a deposit: field in double, accumulation in double; field in
 // single, accumulation in double; field in single, accumulation in compensated
@@ -26,6 +33,11 @@ static_assert(sizeof(StateRec) == 96, "StateRec layout");
 constexpr int kModeF64 = 0;
 constexpr int kModeMix = 1;
 constexpr int kModeMixTwoSum = 2;
+
+inline size_t rec_bytes(int mode)
+{
+    return mode == kModeF64 ? sizeof(RecF64) : sizeof(RecMix);
+}
 
 // workgroup shape of the deposit
 #ifndef RADIO_TILE_CELLS
@@ -68,7 +80,7 @@ struct DepositJob {
     const double* x;                // [3][n_s+1][n_p]
     const double* u;                // [3][n_s+1][n_p]
     const double* q;                // [n_p] or nullptr (all -1)
-    StateRec* recs;                 // workspace [n_p][n_s+1]
+    void* recs;                     // workspace [n_p][n_s+1] records of the job's mode
     int32_t* perm;                  // workspace [n_tiles][n_p]
     uint8_t* ring_sel;              // workspace [n_tiles]: 1 where a tile takes the large ring
     const double* far;              // far-field detector: [n_c][4] n_cell, R_cell; else nullptr
@@ -97,9 +109,9 @@ void plan_job(DepositJob& job, int target_blocks);
 
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
-hipError_t launch_kinematics(const DepositJob& job, hipStream_t s);
+hipError_t launch_kinematics(const DepositJob& job, int mode, hipStream_t s);
 hipError_t launch_order(const DepositJob& job, hipStream_t s);
-hipError_t launch_ring_choice(const DepositJob& job, hipStream_t s);
+hipError_t launch_ring_choice(const DepositJob& job, int mode, hipStream_t s);
 hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s);
 // next: two work counters (small-ring and large-ring workgroups)
 hipError_t launch_deposit_batch(const DepositJob* jobs, const WorkItem* items, int64_t n_items,

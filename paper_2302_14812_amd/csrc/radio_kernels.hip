@@ -7,9 +7,10 @@
 // weights of Sec. 3.2 / Alg. 2.  Four kernels run per deposit:
 //
 // 1. kinematics_kernel (Alg. 1, velocity and acceleration lines): one thread
-//    per trajectory state turns (x, u) into a 96-byte record with x, beta,
-//    betadot and 1/gamma^2, laid out particle-major so that the states of one
-//    particle's run are contiguous.
+//    per trajectory state turns (x, u) into an 80-byte record with x, beta,
+//    betadot and 1/gamma^2 (betadot in single precision for the mixed modes),
+//    laid out particle-major so that the states of one particle's run are
+//    contiguous.
 //
 // 2. order_kernel: for every tile of kTileCells detector cells, a counting
 //    sort of the particles by their light-travel time to the tile's centre at
@@ -386,7 +387,7 @@ __device__ __forceinline__ double recip(double x)
 // Lienard-Wiechert E, B (Eq. 1) at a cell from one staged state, all in double;
 // returns the state's slot coordinate.  Everything after the canonical part may
 // use FMAs.
-__device__ __forceinline__ double field_fp64(const double xc[3], const StateRec& st, double t_s,
+__device__ __forceinline__ double field_fp64(const double xc[3], const RecF64& st, double t_s,
                                              double q, const Consts& K, double F[6])
 {
     double d[3] = {xc[0] - st.x[0], xc[1] - st.x[1], xc[2] - st.x[2]};
@@ -435,7 +436,7 @@ __device__ __forceinline__ void fast_norm(double R2, double* R, double* rinv)
 
 // The mixed-precision field: double for what cancels (arrival time, slot
 // coordinate, n - beta and kappa), single for the rest of Eq. 1.
-__device__ __forceinline__ double field_mixed(const double xc[3], const StateRec& st, double t_s,
+__device__ __forceinline__ double field_mixed(const double xc[3], const RecMix& st, double t_s,
                                               float q, const Consts& K, float F[6])
 {
     double d[3] = {xc[0] - st.x[0], xc[1] - st.x[1], xc[2] - st.x[2]};
@@ -506,7 +507,7 @@ __device__ __forceinline__ double slot_far_fp64(const double fc[4], const double
 
 // Eq. 1 with the far-field geometry n = n_cell, R = R_cell; Rinv = 1/R_cell
 __device__ __forceinline__ double field_far_fp64(const double fc[4], double Rinv,
-                                                 const StateRec& st, double t_s, double q,
+                                                 const RecF64& st, double t_s, double q,
                                                  const Consts& K, double F[6])
 {
     double w[3];
@@ -534,7 +535,7 @@ __device__ __forceinline__ double field_far_fp64(const double fc[4], double Rinv
 }
 
 __device__ __forceinline__ double field_far_mixed(const double fc[4], double Rinv,
-                                                  const StateRec& st, double t_s, float q,
+                                                  const RecMix& st, double t_s, float q,
                                                   const Consts& K, float F[6])
 {
     const double u = slot_far_mixed(fc, st.x, t_s, K);
@@ -565,18 +566,18 @@ __device__ __forceinline__ double field_far_mixed(const double fc[4], double Rin
     return u;
 }
 
-__device__ __forceinline__ double slot_coord_fp64(const double xc[3], const StateRec& st,
+__device__ __forceinline__ double slot_coord_fp64(const double xc[3], const double x[3],
                                                   double t_s, const Consts& K)
 {
-    double d[3] = {xc[0] - st.x[0], xc[1] - st.x[1], xc[2] - st.x[2]};
+    double d[3] = {xc[0] - x[0], xc[1] - x[1], xc[2] - x[2]};
     double R = __builtin_sqrt(canon_norm2(d[0], d[1], d[2]));
     return canon_slot(canon_arrival(t_s, R, K.inv_c), K.t0, K.inv_dt_det);
 }
 
-__device__ __forceinline__ double slot_coord_mixed(const double xc[3], const StateRec& st,
+__device__ __forceinline__ double slot_coord_mixed(const double xc[3], const double x[3],
                                                    double t_s, const Consts& K)
 {
-    double d[3] = {xc[0] - st.x[0], xc[1] - st.x[1], xc[2] - st.x[2]};
+    double d[3] = {xc[0] - x[0], xc[1] - x[1], xc[2] - x[2]};
     double R, rinv;
     fast_norm(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], &R, &rinv);
     return canon_slot(t_s + R * K.inv_c, K.t0, K.inv_dt_det);
@@ -586,12 +587,15 @@ __device__ __forceinline__ double slot_coord_mixed(const double xc[3], const Sta
 // kernels
 // ---------------------------------------------------------------------------
 
-// One thread per (particle, state): the state record, particle-major.
+// One thread per (particle, state): the state record of mode M, particle-major.
+template <int M>
 __global__ __launch_bounds__(256) void kinematics_kernel(const double* __restrict__ x,
                                                          const double* __restrict__ u,
                                                          int64_t n_p, int64_t n_s, double dt,
-                                                         StateRec* __restrict__ recs)
+                                                         void* __restrict__ recs_out)
 {
+    using Rec = typename std::conditional<M == kModeF64, RecF64, RecMix>::type;
+    Rec* recs = reinterpret_cast<Rec*>(recs_out);
     const int64_t n_states = n_s + 1;
     const int64_t total = n_p * n_states;
     const int64_t stride = n_states * n_p;
@@ -600,25 +604,30 @@ __global__ __launch_bounds__(256) void kinematics_kernel(const double* __restric
         const int64_t s = i / n_p;  // consecutive threads read consecutive particles
         const int64_t p = i - s * n_p;
         const int64_t off = s * n_p + p;
-        StateRec r;
+        Rec r;
         r.x[0] = x[off];
         r.x[1] = x[off + stride];
         r.x[2] = x[off + 2 * stride];
         canon_kinematics(u[off], u[off + stride], u[off + 2 * stride], r.b, &r.g2i);
+        double bd[3] = {0.0, 0.0, 0.0};
         if (s > 0) {
             double bp[3], gp;
             const int64_t o2 = off - n_p;
             canon_kinematics(u[o2], u[o2 + stride], u[o2 + 2 * stride], bp, &gp);
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                r.bd[c] = canon_betadot(r.b[c], bp[c], dt);
-        } else {
-            r.bd[0] = r.bd[1] = r.bd[2] = 0.0;
+                bd[c] = canon_betadot(r.b[c], bp[c], dt);
         }
+        if constexpr (M == kModeF64) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            r.bdf[c] = (float)r.bd[c];
-        r.g2if = (float)r.g2i;
+            for (int c = 0; c < 3; ++c)
+                r.bd[c] = bd[c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                r.bdf[c] = (float)bd[c];
+            r.g2if = (float)r.g2i;
+        }
         recs[p * n_states + s] = r;
     }
 }
@@ -719,7 +728,8 @@ __global__ __launch_bounds__(256) void order_kernel(const double* __restrict__ x
 constexpr int kChoiceBatches = 8;           // sampled batches per sampled run
 constexpr double kRingBypassLimit = 0.05;   // emissions to HBM per interaction
 
-__global__ __launch_bounds__(256) void ring_choice_kernel(const StateRec* __restrict__ recs,
+__global__ __launch_bounds__(256) void ring_choice_kernel(const char* __restrict__ recs,
+                                                          int64_t rec_size,
                                                           const int32_t* __restrict__ perm,
                                                           const double* __restrict__ cells,
                                                           const double* __restrict__ far,
@@ -754,21 +764,24 @@ __global__ __launch_bounds__(256) void ring_choice_kernel(const StateRec* __rest
     const bool on = smp < kSamples && pi < n_p && len > 0;
     const double* xc = cells + 3 * c0;
     const double* fc = far ? far + 4 * c0 : nullptr;
-    auto slot_of = [&](const StateRec& r, int64_t st) {
+    const char* pr =
+        on ? recs + ((int64_t)perm[tile * n_p + pi] * n_states + s_a) * rec_size : nullptr;
+    // position of state k of this lane's particle: the first three doubles of its record
+    auto pos = [&](int k) { return reinterpret_cast<const double*>(pr + (int64_t)k * rec_size); };
+    auto slot_of = [&](const double* x, int64_t st) {
         double dist;
         if (fc) {
-            dist = fc[3] - (r.x[0] * fc[0] + r.x[1] * fc[1] + r.x[2] * fc[2]);
+            dist = fc[3] - (x[0] * fc[0] + x[1] * fc[1] + x[2] * fc[2]);
         } else {
-            const double d0 = xc[0] - r.x[0], d1 = xc[1] - r.x[1], d2 = xc[2] - r.x[2];
+            const double d0 = xc[0] - x[0], d1 = xc[1] - x[1], d2 = xc[2] - x[2];
             dist = __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2);
         }
         const double u = ((t_first + (double)(s0 + st) * dt) + dist * inv_c - t0) * inv_dt_det;
         return (u == u) ? fmin(fmax(u, -2.0), (double)n_t + 2.0) : -2.0;
     };
-    const StateRec* pr = on ? recs + (int64_t)perm[tile * n_p + pi] * n_states + s_a : nullptr;
     __syncthreads();
     if (on)
-        atomicMin(&start[smp], (int)floor(slot_of(pr[0], s_a)));
+        atomicMin(&start[smp], (int)floor(slot_of(pos(0), s_a)));
     __syncthreads();
     if (on) {
         // the small ring of this batch, placed as the deposit places it
@@ -779,9 +792,9 @@ __global__ __launch_bounds__(256) void ring_choice_kernel(const StateRec* __rest
             if (j >= 0 && j < n_t && (j < base || j >= base + kRingSmall))
                 ++outside;
         };
-        int J = (int)floor(slot_of(pr[0], s_a));
+        int J = (int)floor(slot_of(pos(0), s_a));
         for (int k = 1; k <= len; ++k) {
-            const int jk = (int)floor(slot_of(pr[k], s_a + k));
+            const int jk = (int)floor(slot_of(pos(k), s_a + k));
             for (int j = min(J, jk); j < max(J, jk); ++j)  // slots the lane leaves
                 emit(j);
             J = jk;
@@ -802,6 +815,7 @@ struct ModeTypes {
     static constexpr bool MIX = (M != kModeF64);
     using T = typename std::conditional<MIX, float, double>::type;  // field and lane carry
     using Acc = typename std::conditional<M == kModeMixTwoSum, float, double>::type;
+    using Rec = typename std::conditional<MIX, RecMix, RecF64>::type;  // staged state record
 };
 
 // LDS of one deposit workgroup with rings of R slots
@@ -811,7 +825,7 @@ struct DepositShared {
     // one cell's ring, padded by one word so that the rings of the kTileCells
     // cells, which one instruction updates together, start in different banks
     static constexpr int kStride = R * CellSink<Acc, R>::W + 1;
-    StateRec rec[kGroups][kRunL + 1];   // staged batch: one run per particle group
+    typename ModeTypes<M>::Rec rec[kGroups][kRunL + 1];  // staged batch: a run per group
     double sq[kGroups];                 // its charges
     Acc ring[kTileCells * kStride];     // per-cell slot rings
     int nb[2][kTileCells];              // per cell: lowest start slot of a coming batch
@@ -833,7 +847,9 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
     using T = typename ModeTypes<M>::T;
     using Acc = typename ModeTypes<M>::Acc;
     using Sink = CellSink<Acc, R>;
+    using Rec = typename ModeTypes<M>::Rec;
     constexpr int RW = Sink::W;
+    const Rec* recs = reinterpret_cast<const Rec*>(J.recs);
 
     const int tid = threadIdx.x;
     const int cl = tid % kTileCells;  // cell within the tile
@@ -861,11 +877,11 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
     }
     const double Rinv = 1.0 / fc[3];
     // slot coordinate of a state, the same expression the field functions use
-    auto slot_of = [&](const StateRec& st, double t_s) {
+    auto slot_of = [&](const Rec& st, double t_s) {
         if constexpr (FAR)
             return MIX ? slot_far_mixed(fc, st.x, t_s, K) : slot_far_fp64(fc, st.x, t_s, K);
         else
-            return MIX ? slot_coord_mixed(xc, st, t_s, K) : slot_coord_fp64(xc, st, t_s, K);
+            return MIX ? slot_coord_mixed(xc, st.x, t_s, K) : slot_coord_fp64(xc, st.x, t_s, K);
     };
     RADIO_LDS Acc* my_ring = (RADIO_LDS Acc*)&sh.ring[cl * DepositShared<M, R>::kStride];
     RADIO_LDS int* nb = (RADIO_LDS int*)&sh.nb[0][0];
@@ -893,7 +909,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
             return;
         const int64_t s_a = (rb_begin + it / n_batches) * kRunL;
         const RADIO_GLOBAL double* xr =
-            gptr(reinterpret_cast<const double*>(J.recs + order[i] * n_states + s_a));
+            gptr(reinterpret_cast<const double*>(recs + order[i] * n_states + s_a));
         const double t = canon_state_time(J.t_first, (double)(J.s0 + s_a), J.dt);
         double u;
         if constexpr (FAR) {
@@ -963,16 +979,18 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         }
         // stage: particle order[i0 + gg], states s_a .. s_a + len (contiguous)
         {
-            constexpr int kChunks = (int)(sizeof(StateRec) / 16);  // 16-byte pieces
-            const int per = (len + 1) * kChunks;
+            // pieces of 16 bytes where the record size allows, else of 8
+            using Piece = typename std::conditional<sizeof(Rec) % 16 == 0, v2i64, long long>::type;
+            constexpr int kPieces = (int)(sizeof(Rec) / sizeof(Piece));
+            const int per = (len + 1) * kPieces;
             for (int i = tid; i < kGroups * per; i += kDepositThreads) {
                 const int gg = i / per;
                 const int r = i - gg * per;
                 if (gg < np) {
                     const int64_t p = order[i0 + gg];
-                    const RADIO_GLOBAL v2i64* src =
-                        gptr(reinterpret_cast<const v2i64*>(J.recs + p * n_states + s_a)) + r;
-                    reinterpret_cast<v2i64*>(&sh.rec[gg][0])[r] = *src;
+                    const RADIO_GLOBAL Piece* src =
+                        gptr(reinterpret_cast<const Piece*>(recs + p * n_states + s_a)) + r;
+                    reinterpret_cast<Piece*>(&sh.rec[gg][0])[r] = *src;
                 }
             }
             if (tid < kGroups)
@@ -1179,14 +1197,18 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_kinematics(const DepositJob& job, hipStream_t s)
+hipError_t launch_kinematics(const DepositJob& job, int mode, hipStream_t s)
 {
     const int64_t total = job.n_p * (job.n_s + 1);
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536)
         blocks = 65536;
-    hipLaunchKernelGGL(kinematics_kernel, dim3((unsigned)blocks), dim3(256), 0, s, job.x, job.u,
-                       job.n_p, job.n_s, job.dt, job.recs);
+    if (mode == kModeF64)
+        hipLaunchKernelGGL(kinematics_kernel<kModeF64>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           job.x, job.u, job.n_p, job.n_s, job.dt, job.recs);
+    else
+        hipLaunchKernelGGL(kinematics_kernel<kModeMix>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           job.x, job.u, job.n_p, job.n_s, job.dt, job.recs);
     return hipGetLastError();
 }
 
@@ -1198,11 +1220,12 @@ hipError_t launch_order(const DepositJob& job, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_ring_choice(const DepositJob& job, hipStream_t s)
+hipError_t launch_ring_choice(const DepositJob& job, int mode, hipStream_t s)
 {
     if (job.n_tiles <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(ring_choice_kernel, dim3((unsigned)job.n_tiles), dim3(256), 0, s, job.recs,
+    hipLaunchKernelGGL(ring_choice_kernel, dim3((unsigned)job.n_tiles), dim3(256), 0, s,
+                       reinterpret_cast<const char*>(job.recs), (int64_t)rec_bytes(mode),
                        job.perm, job.cells, job.far, job.n_c, job.n_p, job.n_s, job.n_runs,
                        job.t_first,
                        job.s0, job.dt, job.t0, job.inv_dt_det, job.inv_c, job.n_t, job.ring_sel);

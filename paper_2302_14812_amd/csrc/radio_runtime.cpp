@@ -29,8 +29,8 @@ struct radio_detector {
     int64_t* d_user_index = nullptr;  // internal row -> caller's cell index
     double* d_acc = nullptr;
     unsigned long long* d_counters = nullptr;  // [3] clipped, nonmonotone, ring bypasses
-    radio::StateRec* d_recs = nullptr;         // workspace, grown on demand
-    size_t recs_cap = 0;                       // in records
+    char* d_recs = nullptr;                    // workspace (state records), grown on demand
+    size_t recs_cap = 0;                       // in bytes
     int32_t* d_perm = nullptr;                 // workspace, grown on demand
     size_t perm_cap = 0;                       // in entries
     uint8_t* d_sel = nullptr;                  // workspace: ring size per tile
@@ -333,7 +333,8 @@ int enqueue_deposit(radio_detector* det, const radio_chunk* k, hipStream_t s)
     if (k->n_particles > INT32_MAX || k->n_steps > INT32_MAX - 1)
         return RADIO_EINVAL;
     radio::DepositJob J = make_job(det, k);
-    int rc = grow(&det->d_recs, &det->recs_cap, (size_t)(J.n_p * (J.n_s + 1)));
+    int rc = grow(&det->d_recs, &det->recs_cap,
+                  (size_t)(J.n_p * (J.n_s + 1)) * radio::rec_bytes(det->precision));
     if (rc != RADIO_OK)
         return rc;
     rc = grow(&det->d_perm, &det->perm_cap, (size_t)(J.n_tiles * J.n_p));
@@ -344,8 +345,9 @@ int enqueue_deposit(radio_detector* det, const radio_chunk* k, hipStream_t s)
     J.recs = det->d_recs;
     J.perm = det->d_perm;
     J.ring_sel = det->d_sel;
-    if (radio::launch_kinematics(J, s) != hipSuccess || radio::launch_order(J, s) != hipSuccess ||
-        radio::launch_ring_choice(J, s) != hipSuccess ||
+    if (radio::launch_kinematics(J, det->precision, s) != hipSuccess ||
+        radio::launch_order(J, s) != hipSuccess ||
+        radio::launch_ring_choice(J, det->precision, s) != hipSuccess ||
         radio::launch_deposit(J, det->precision, s) != hipSuccess)
         return RADIO_EDEVICE;
     det->interactions += k->n_particles * k->n_steps * det->n_c;
@@ -362,7 +364,7 @@ struct BatchArena {
     radio::WorkItem* d_items = nullptr;
     size_t items_cap = 0;
     unsigned long long* d_next = nullptr;  // two counters (ring sizes) per kernel variant
-    radio::StateRec* d_recs = nullptr;
+    char* d_recs = nullptr;  // state records of every pair, in bytes
     size_t recs_cap = 0;
     int32_t* d_perm = nullptr;
     size_t perm_cap = 0;
@@ -419,7 +421,7 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
         if (k->n_particles == 0 || k->n_steps == 0)
             continue;
         radio::DepositJob J = make_job(dets[i], k);
-        recs_need += (size_t)(J.n_p * (J.n_s + 1));
+        recs_need += (size_t)(J.n_p * (J.n_s + 1)) * radio::rec_bytes(dets[i]->precision);
         perm_need += (size_t)(J.n_tiles * J.n_p);
         sel_need += (size_t)J.n_tiles;
         A->h_jobs.push_back(J);
@@ -458,10 +460,11 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
     size_t ro = 0, po = 0, so = 0;
     for (size_t j = 0; j < A->h_jobs.size(); ++j) {
         radio::DepositJob& J = A->h_jobs[j];
+        const int prec = dets[idx[j]]->precision;
         J.recs = A->d_recs + ro;
         J.perm = A->d_perm + po;
         J.ring_sel = A->d_sel + so;
-        ro += (size_t)(J.n_p * (J.n_s + 1));
+        ro += (size_t)(J.n_p * (J.n_s + 1)) * radio::rec_bytes(prec);
         po += (size_t)(J.n_tiles * J.n_p);
         so += (size_t)J.n_tiles;
         const double run_work = (double)radio::kTileCells * (double)J.n_p * (double)radio::kRunL;
@@ -470,15 +473,16 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
         J.runs_per_split = rps;
         J.n_splits = (J.n_runs + rps - 1) / rps;
         // kernel variant: precision mode, plus 3 for a far-field detector
-        const int mode = dets[idx[j]]->precision + (J.far ? 3 : 0);
+        const int mode = prec + (J.far ? 3 : 0);
         for (int64_t sp = 0; sp < J.n_splits; ++sp) {
             const int64_t runs = std::min<int64_t>(rps, J.n_runs - sp * rps);
             for (int64_t t = 0; t < J.n_tiles; ++t)
                 items.push_back({{(int32_t)j, (int32_t)t, (int32_t)sp, 0},
                                  (double)runs * run_work, mode});
         }
-        if (radio::launch_kinematics(J, s) != hipSuccess || radio::launch_order(J, s) != hipSuccess ||
-            radio::launch_ring_choice(J, s) != hipSuccess)
+        if (radio::launch_kinematics(J, prec, s) != hipSuccess ||
+            radio::launch_order(J, s) != hipSuccess ||
+            radio::launch_ring_choice(J, prec, s) != hipSuccess)
             return RADIO_EDEVICE;
     }
     std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
@@ -770,7 +774,7 @@ int radio_detector_stats(const radio_detector* det, radio_stats* out)
                            det->n_c * 3 * (int64_t)sizeof(double) +
                            det->n_c * (int64_t)sizeof(int64_t) +
                            3 * (int64_t)sizeof(unsigned long long) +
-                           (int64_t)(det->recs_cap * sizeof(radio::StateRec)) +
+                           (int64_t)det->recs_cap +
                            (int64_t)(det->perm_cap * sizeof(int32_t)) + (int64_t)det->sel_cap);
     return RADIO_OK;
 }
