@@ -15,6 +15,8 @@ Functions and the passages they follow:
   deposit(...)             Alg. 1 + Alg. 2 with the integrator-detector
                            definition of Sec. 3.2 (slot value = integral of
                            the piecewise-constant field over the slot / dt_det)
+  spectrum(...)            Sec. 4: detector fields Fourier transformed in time,
+                           d2I/domega dOmega, dI/domega, dI/dOmega
 """
 from __future__ import annotations
 
@@ -159,3 +161,39 @@ def deposit_workload(detector, chunk, cell_index=None, D=None, n_threads=None, c
 def read(D: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
     """Split an oracle detector array into E[n_cells, n_t, 3] and B[n_cells, n_t, 3]."""
     return np.ascontiguousarray(D[..., :3]), np.ascontiguousarray(D[..., 3:])
+
+
+def spectrum(E, dt_det: float, cells, n_fft: Optional[int] = None, weights=None, c: float = 1.0
+             ) -> Tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
+    """Spectral intensity of detector fields E[n_cells, n_t, 3] (the detector data
+    Fourier transformed with respect to time, Sec. 4).
+
+    The slot value is the field held over its slot, so the transform of the
+    piecewise-constant signal at omega is
+        F(omega) = sum_j E_j exp(i omega j dt) * (exp(i omega dt) - 1) / (i omega),
+    and, with R the cell's distance from the origin,
+        d2I/domega dOmega = c R^2 / (4 pi^2) |F(omega)|^2            (per cell)
+        dI/domega         = sum_cells weight_c d2I/domega dOmega
+        dI/dOmega         = c R^2 / (4 pi) sum_j |E_j|^2 dt          (Parseval, per cell)
+    at omega_m = 2 pi m / (n_fft dt), m = 0 .. n_fft/2, with the signal zero
+    beyond its n_t slots (n_fft >= n_t; default the next power of two).
+    Returns (omega, d2I [n_cells, n_fft/2 + 1], dIdomega, dIdOmega).
+    """
+    E = np.asarray(E, dtype=np.float64)
+    n_c, n_t = E.shape[0], E.shape[1]
+    N = int(n_fft) if n_fft else 1 << max(0, int(n_t - 1).bit_length())
+    if N < n_t:
+        raise ValueError("n_fft must be at least n_t")
+    m = np.arange(N // 2 + 1)
+    omega = 2.0 * np.pi * m / (N * dt_det)
+    # |(exp(i w dt) - 1) / (i w)|^2 = (2 sin(w dt / 2) / w)^2, -> dt^2 as w -> 0
+    W2 = np.empty_like(omega)
+    W2[0] = dt_det * dt_det
+    W2[1:] = (2.0 * np.sin(0.5 * omega[1:] * dt_det) / omega[1:]) ** 2
+    Z = np.fft.fft(E, n=N, axis=1)[:, :N // 2 + 1, :]           # library DFT, sum_j E_j e^{-i w t_j}
+    R2 = (np.asarray(cells, dtype=np.float64) ** 2).sum(axis=1)
+    d2I = (c * R2 / (4.0 * np.pi ** 2))[:, None] * W2[None, :] * (np.abs(Z) ** 2).sum(axis=2)
+    w = np.ones(n_c) if weights is None else np.asarray(weights, dtype=np.float64)
+    dIdw = w @ d2I
+    dIdO = c * R2 / (4.0 * np.pi) * (E * E).sum(axis=(1, 2)) * dt_det
+    return omega, d2I, dIdw, dIdO

@@ -250,6 +250,44 @@ def planar_undulator(n_particles: int, n_steps: int, periods: float, gamma_mean:
     return Chunk(x=x, u=u, q=np.full(n_particles, q), t_first=0.0, dt=dt)
 
 
+def sinusoidal_orbit(n_steps: int, gamma: float = 50.0, r_beta: float = 2.0,
+                     k_beta: float = 0.1, dt: float = 0.01, q: float = -1.0,
+                     substeps: int = 8) -> Chunk:
+    """One electron moving along x with a sinusoidal excursion in y (the paper's
+    spectral benchmark: gamma 50, r_beta = 2, k_beta = 0.1, so K = gamma k_beta
+    r_beta = 10, dt = 0.01, in units where c = 1).
+
+    u_y = K cos(k_beta t), |u| constant; y = r_beta sin(k_beta t) exactly and x
+    integrates beta_x with a substepped Simpson rule.
+    """
+    K = gamma * k_beta * r_beta
+    t = np.arange(n_steps + 1, dtype=np.float64) * dt
+    x = np.zeros((3, n_steps + 1, 1))
+    u = np.zeros((3, n_steps + 1, 1))
+    uy = K * np.cos(k_beta * t)
+    u[1, :, 0] = uy
+    u[0, :, 0] = np.sqrt(gamma * gamma - 1.0 - uy * uy)
+    x[1, :, 0] = (K / (gamma * k_beta)) * np.sin(k_beta * t)
+    m = 2 * substeps
+    wts = np.ones(m + 1)
+    wts[1:m:2] = 4.0
+    wts[2:m:2] = 2.0
+    wts *= (dt / m) / 3.0
+    frac = np.arange(m + 1, dtype=np.float64) / m
+    xs = 0.0
+    for s in range(n_steps):
+        uys = K * np.cos(k_beta * (t[s] + frac * dt))
+        xs += wts @ (np.sqrt(gamma * gamma - 1.0 - uys * uys) / gamma)
+        x[0, s + 1, 0] = xs
+    return Chunk(x=x, u=u, q=np.full(1, q), t_first=0.0, dt=dt)
+
+
+def line_cells(radius: float, n: int, half: float) -> np.ndarray:
+    """A line of cells on a sphere about the origin in the z-x plane, at angles
+    -half..half from the x axis (bin middles), as the spectral benchmark's detector."""
+    return sphere_cap_cells(radius, [1.0, 0.0, 0.0], [0.0, 0.0, 1.0], n, 1, half, 0.0)
+
+
 def helical_undulator(n_particles: int, n_steps: int, periods: float, gamma_mean: float,
                       gamma_sigma: float, K: float, offset_sigma: float, seed: int,
                       omega_u: float = 1.0, q: float = -1.0) -> Chunk:
