@@ -207,6 +207,32 @@ RADIO_API int radio_detector_shape(const radio_detector* det, int64_t* n_cells, 
 RADIO_API int radio_detector_cells(const radio_detector* det, double* out);
 
 /*
+ * Spectral post-processing (Sec. 4: the detector data Fourier transformed with
+ * respect to time, the route by which the paper checks its deposit against the
+ * spectra of Eq. 7 and Eq. 8).  A slot holds the field averaged over the slot,
+ * so the transform of the piecewise-constant signal of cell c is
+ *     F_c(omega) = sum_j E_cj e^{-i omega j dt_det} (e^{-i omega dt_det} - 1)/(-i omega)
+ * and, with R_c = |x_c| the cell's distance from the origin,
+ *     d2I[c][m] = c R_c^2 / (4 pi^2) |F_c(omega_m)|^2     (d2I/domega dOmega)
+ *     dIdw[m]   = sum_c weight_c d2I[c][m]                 (dI/domega)
+ *     dIdO[c]   = c R_c^2 / (4 pi) sum_j |E_cj|^2 dt_det   (dI/dOmega, Parseval)
+ * at omega_m = 2 pi m / (n_fft dt_det), m = 0 .. n_fft/2, the signal zero
+ * beyond its n_t slots.  In double precision for every detector precision.
+ *   n_fft   a power of two >= n_t, <= 2^30; 0 picks the smallest one
+ *   weights HOST [n_cells] per-cell weights of dIdw in the caller's cell order
+ *           (e.g. solid angles), or NULL for 1
+ *   d2I     DEVICE [n_cells][n_fft/2 + 1] in the caller's cell order, or NULL
+ *   dIdw    DEVICE [n_fft/2 + 1], or NULL
+ *   dIdO    DEVICE [n_cells] in the caller's cell order, or NULL
+ * Work is enqueued on `stream`, after the deposits already there; the call
+ * allocates a workspace of at most ~1 GiB (two complex arrays per group of
+ * cells), waits for the stream and frees it before returning.  RADIO_EINVAL for
+ * a bad n_fft or no output, RADIO_ENOMEM if the workspace cannot be had.
+ */
+RADIO_API int radio_spectrum(const radio_detector* det, int64_t n_fft, const double* weights,
+                             double* d2I, double* dIdw, double* dIdO, void* stream);
+
+/*
  * Arrival times t + |x_cell - x|/c (Eq. 2) of n explicit (cell, point, time)
  * triples, evaluated on the device with exactly the rounding the deposit uses:
  * t_s = t_first + s*dt is the caller's job; here t is given.  DEVICE arrays:

@@ -30,6 +30,7 @@ EXPORTS = (
     "radio_deposit_trajectory_chunk", "radio_deposit_batch", "radio_read_detector",
     "radio_detector_stats", "radio_detector_shape", "radio_detector_cells",
     "radio_arrival_times", "radio_status_string", "radio_set_tuning", "radio_get_tuning",
+    "radio_spectrum",
 )
 
 
@@ -98,6 +99,7 @@ def _lib():
                                              ctypes.POINTER(ctypes.c_int32)]
         lib.radio_detector_cells.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         lib.radio_arrival_times.argtypes = [vp, vp, vp, i64, ctypes.c_double, vp, vp]
+        lib.radio_spectrum.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double), vp, vp, vp, vp]
         lib.radio_set_tuning.argtypes = [ctypes.POINTER(_Tuning)]
         lib.radio_get_tuning.argtypes = [ctypes.POINTER(_Tuning)]
         for name in EXPORTS:
@@ -286,6 +288,30 @@ class Detector:
         _check(_lib().radio_read_detector(self.handle, E.data_ptr(), B.data_ptr(), _stream(stream)),
                "radio_read_detector")
         return E, B
+
+    def spectrum(self, n_fft: int = 0, weights=None, stream=None, d2I: bool = True,
+                 dIdw: bool = True, dIdO: bool = True):
+        """Spectral intensity of the detector's fields (radio_spectrum): returns
+        (omega [n_f] host array, d2I [n_cells, n_f], dIdw [n_f], dIdO [n_cells]) with
+        device tensors (None for outputs not asked for); n_f = n_fft/2 + 1."""
+        import torch
+        N = int(n_fft) if n_fft else 1 << max(0, int(self.n_t - 1).bit_length())
+        n_f = N // 2 + 1
+        a = torch.empty((self.n_cells, n_f), dtype=torch.float64, device="cuda") if d2I else None
+        b = torch.empty((n_f,), dtype=torch.float64, device="cuda") if dIdw else None
+        c = torch.empty((self.n_cells,), dtype=torch.float64, device="cuda") if dIdO else None
+        w = None
+        if weights is not None:
+            w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+            if w.shape[0] != self.n_cells:
+                raise ValueError("one weight per cell")
+        ptr = (lambda t: None if t is None else t.data_ptr())
+        _check(_lib().radio_spectrum(self.handle, int(n_fft),
+                                     None if w is None else w.ctypes.data_as(
+                                         ctypes.POINTER(ctypes.c_double)),
+                                     ptr(a), ptr(b), ptr(c), _stream(stream)), "radio_spectrum")
+        omega = 2.0 * np.pi * np.arange(n_f) / (N * self.dt_det)
+        return omega, a, b, c
 
     def reset(self, stream=None) -> None:
         _check(_lib().radio_detector_reset(self.handle, _stream(stream)), "radio_detector_reset")

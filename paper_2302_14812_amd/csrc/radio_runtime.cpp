@@ -816,4 +816,69 @@ int radio_arrival_times(const double* cells, const double* points, const double*
     return RADIO_OK;
 }
 
+int radio_spectrum(const radio_detector* det, int64_t n_fft, const double* weights, double* d2I,
+                   double* dIdw, double* dIdO, void* stream)
+{
+    if (!det || (!d2I && !dIdw && !dIdO))
+        return RADIO_EINVAL;
+    int64_t N = n_fft;
+    if (N == 0) {
+        N = 1;
+        while (N < det->n_t)
+            N *= 2;
+    }
+    if (N < det->n_t || N > ((int64_t)1 << 30) || (N & (N - 1)) != 0)
+        return RADIO_EINVAL;
+    DeviceGuard g(det->device);
+    if (!g.ok())
+        return RADIO_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    const bool pairs = det->precision == RADIO_MIXED_TWOSUM;
+    // cells per group: two complex work arrays of 2 G N values within ~1 GiB
+    const int64_t per_cell = 2 * 2 * N * (int64_t)sizeof(double2);
+    const int64_t G = std::max<int64_t>(1, std::min<int64_t>(det->n_c, ((int64_t)1 << 30) / per_cell));
+    double2* w0 = nullptr;
+    double2* w1 = nullptr;
+    double* d_w = nullptr;
+    int rc = RADIO_OK;
+    if ((d2I || dIdw) &&
+        (hipMalloc((void**)&w0, (size_t)(2 * G * N) * sizeof(double2)) != hipSuccess ||
+         hipMalloc((void**)&w1, (size_t)(2 * G * N) * sizeof(double2)) != hipSuccess)) {
+        (void)hipGetLastError();
+        rc = RADIO_ENOMEM;
+    }
+    if (rc == RADIO_OK && weights && dIdw) {
+        if (hipMalloc((void**)&d_w, (size_t)det->n_c * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = RADIO_ENOMEM;
+        } else if (hipMemcpyAsync(d_w, weights, (size_t)det->n_c * sizeof(double),
+                                  hipMemcpyHostToDevice, s) != hipSuccess) {
+            rc = RADIO_EDEVICE;
+        }
+    }
+    if (rc == RADIO_OK && (d2I || dIdw)) {
+        for (int64_t r0 = 0; r0 < det->n_c && rc == RADIO_OK; r0 += G) {
+            const int64_t Gi = std::min(G, det->n_c - r0);
+            if (radio::launch_spectrum_group(det->d_acc, pairs, det->n_t, r0, Gi, N, det->d_cells,
+                                             det->d_user_index, d_w, det->dt_det, det->c, w0, w1,
+                                             d2I, dIdw, r0 == 0, s) != hipSuccess)
+                rc = RADIO_EDEVICE;
+        }
+    }
+    if (rc == RADIO_OK && dIdO &&
+        radio::launch_spectrum_parseval(det->d_acc, pairs, det->n_c, det->n_t, det->d_cells,
+                                        det->d_user_index, det->dt_det, det->c, dIdO,
+                                        s) != hipSuccess)
+        rc = RADIO_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess && rc == RADIO_OK)
+        rc = RADIO_EDEVICE;
+    if (w0)
+        (void)hipFree(w0);
+    if (w1)
+        (void)hipFree(w1);
+    if (d_w)
+        (void)hipFree(d_w);
+    return rc;
+}
+
 }  // extern "C"

@@ -1,0 +1,91 @@
+"""Spectral post-processing on the device (radio_spectrum) against the oracle's
+spectrum of the same detector fields, and the device's own deposit of the
+paper's spectral benchmark against Eq. 8."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_14812_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def radio():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2302_14812_amd as radio
+    radio._lib()
+    return radio
+
+
+def rel_l2(a, b):
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b)) / (nb if nb > 0 else 1.0)
+
+
+@pytest.mark.parametrize("n_t,n_fft,precision", [(256, 0, "fp64"), (300, 0, "fp64"),
+                                                 (300, 2048, "mixed"), (200, 0, "mixed_twosum")])
+def test_spectrum_matches_oracle(radio, n_t, n_fft, precision):
+    import torch
+    wl = W.undulator_workload(n_particles=30, n_steps=200, n_side=6, n_t=n_t)
+    det = radio.Detector.from_spec(wl.detector, precision=precision)
+    det.deposit(radio.Chunk.from_numpy(wl.chunk))
+    rng = np.random.Generator(np.random.PCG64(n_t))
+    weights = rng.uniform(0.5, 2.0, size=wl.detector.n_cells)
+    om, d2, dw, dO = det.spectrum(n_fft=n_fft, weights=weights)
+    E, _ = det.read()
+    torch.cuda.synchronize()
+    omo, d2o, dwo, dOo = oracle.spectrum(E.cpu().numpy(), wl.detector.dt_det, wl.detector.cells,
+                                         n_fft=n_fft or None, weights=weights)
+    np.testing.assert_allclose(om, omo, rtol=1e-15)
+    errs = (rel_l2(d2.cpu().numpy(), d2o), rel_l2(dw.cpu().numpy(), dwo),
+            rel_l2(dO.cpu().numpy(), dOo))
+    print(f"[spectrum] n_t={n_t} n_fft={n_fft} {precision}: relL2 d2I {errs[0]:.2e} "
+          f"dIdw {errs[1]:.2e} dIdO {errs[2]:.2e}", flush=True)
+    assert max(errs) <= 1e-12
+    # outputs are optional; the others must not change
+    _, a, b, c = det.spectrum(n_fft=n_fft, d2I=False, dIdO=False)
+    assert a is None and c is None
+    np.testing.assert_allclose(b.cpu().numpy(), d2.cpu().numpy().sum(axis=0), rtol=1e-12)
+    with pytest.raises(radio.RadioError):
+        det.spectrum(n_fft=3 * n_t)      # not a power of two
+    with pytest.raises(radio.RadioError):
+        det.spectrum(n_fft=64)           # shorter than the signal
+    det.close()
+
+
+def test_device_benchmark_spectrum_follows_eq8(radio):
+    """The paper's spectral benchmark end to end on the device: deposit, then
+    spectrum; the angle-integrated spectrum follows Eq. 8 and equals the
+    oracle's pipeline."""
+    from scipy.integrate import quad
+    from scipy.special import kv
+    gamma, K, wb = 50.0, 10.0, 0.1
+    wc = 1.5 * K * gamma ** 2 * wb
+    chunk = W.sinusoidal_orbit(25133)
+    cells = W.line_cells(1e5, 41, 0.1)
+    t0, dtd = W.arrival_window(cells, chunk, 65536, pad_frac=0.01)
+    det = radio.Detector(cells, t0=t0, dt_det=dtd, n_t=65536, precision="fp64")
+    det.deposit(radio.Chunk.from_numpy(chunk))
+    om, d2, dw, dO = det.spectrum()
+    dw = dw.cpu().numpy()
+    D = oracle.deposit(cells, t0, dtd, 65536, chunk.x, chunk.u, chunk.q, chunk.t_first, chunk.dt)
+    _, d2o, dwo, dOo = oracle.spectrum(oracle.read(D)[0], dtd, cells)
+    e = max(rel_l2(d2.cpu().numpy(), d2o), rel_l2(dw, dwo), rel_l2(dO.cpu().numpy(), dOo))
+    print(f"[spectrum] benchmark device vs oracle pipeline relL2 {e:.2e}", flush=True)
+    assert e <= 1e-12
+    bands = wc * np.array([0.05, 0.1, 0.2, 0.3, 0.5, 0.7, 1.0, 1.5, 2.0, 3.0])
+    xs = np.geomspace(1e-3, 20.0, 400)
+    tail = np.array([quad(lambda y: kv(5 / 3, y), x, np.inf, limit=200)[0] for x in xs])
+    th = math.sqrt(3) * gamma * np.exp(np.interp(np.log(np.maximum(om, 1e-9) / wc), np.log(xs),
+                                                 np.log(xs * tail)))
+    sim_b = np.array([dw[(om >= a) & (om < b)].mean() for a, b in zip(bands[:-1], bands[1:])])
+    th_b = np.array([th[(om >= a) & (om < b)].mean() for a, b in zip(bands[:-1], bands[1:])])
+    ratio = (sim_b / sim_b[2]) / (th_b / th_b[2])
+    print("[spectrum] device integrated / Eq. 8:", np.round(ratio, 3), flush=True)
+    assert np.abs(ratio - 1).max() < 0.06
+    det.close()
