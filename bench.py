@@ -45,6 +45,8 @@ def parse():
                          "vs 64 separate launches)")
     ap.add_argument("--no-serve", action="store_true", help="skip the streaming-service leg")
     ap.add_argument("--no-far", action="store_true", help="skip the far-field option leg")
+    ap.add_argument("--no-spectrum", action="store_true",
+                    help="skip the spectral post-processing leg")
     ap.add_argument("--serve-chunks", type=int, default=30,
                     help="timed chunks of the streaming leg (after a fifth as many warm-up)")
     ap.add_argument("--serve-load", type=float, default=0.8,
@@ -247,6 +249,50 @@ def serve_leg(radio, W, precisions, n_chunks, load):
             "load": load, **out}
 
 
+def spectrum_leg(radio, W, steps):
+    """The paper's spectral benchmark at its size: one electron on a sinusoidal orbit
+    (gamma 50, K 10, dt 0.01, six betatron periods) seen by a line of 512 cells at 1e5
+    spanning +-0.1 rad with 131072 slots; deposit, then the spectral post-processing
+    (per-cell transform in time, d2I/domega dOmega, dI/domega, dI/dOmega)."""
+    import torch
+    chunk = W.sinusoidal_orbit(37699)
+    n_c, n_t = 512, 131072
+    cells = W.line_cells(1e5, n_c, 0.1)
+    t0, dtd = W.arrival_window(cells, chunk, n_t, pad_frac=0.01)
+    dch = radio.Chunk.from_numpy(chunk)
+    det = radio.Detector(cells, t0=t0, dt_det=dtd, n_t=n_t, precision="fp64")
+    stream = torch.cuda.current_stream()
+    det.deposit(dch)
+    det.spectrum()  # warm: code objects, workspace path
+    torch.cuda.synchronize()
+    dep_ms, spec_ms = [], []
+    for _ in range(steps):
+        det.reset(stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        det.deposit(dch, stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        dep_ms.append(a.elapsed_time(b))
+        t = time.perf_counter()
+        det.spectrum(stream=stream)  # returns after its stream work has finished
+        spec_ms.append((time.perf_counter() - t) * 1e3)
+    det.close()
+    N = n_t
+    fft_bytes = 2 * 2 * n_c * N * 16 * (int(math.log2(N)) + 1)  # passes + load, read and write
+    alg_bytes = n_c * n_t * 24 + n_c * (N // 2 + 1) * 8       # E in, d2I out
+    sms = min(spec_ms)
+    print(f"[bench] spectrum: deposit {min(dep_ms):.1f} ms, spectrum {sms:.1f} ms "
+          f"({alg_bytes / (sms * 1e-3) / 1e9:.0f} GB/s algorithmic)", file=sys.stderr, flush=True)
+    return {"workload": "sinusoidal orbit gamma 50 K 10, 37699 steps; line of 512 cells x 131072 "
+                        "slots at 1e5", "deposit_ms": min(dep_ms), "spectrum_ms": sms,
+            "interactions": chunk.n_steps * n_c,
+            "spectrum_roofline": {"bound": "hbm", "achieved": alg_bytes / (sms * 1e-3) / 1e9,
+                                  "peak": 8000.0, "unit": "GB/s",
+                                  "frac": alg_bytes / (sms * 1e-3) / 1e9 / 8000.0,
+                                  "algorithmic_bytes": alg_bytes, "pass_bytes": fft_bytes}}
+
+
 def measured_traffic(precision, workload):
     """HBM bytes per deposit launch from the committed rocprofv3 counter summary, or None
     when it was taken on another workload or on a different kernel source."""
@@ -367,6 +413,8 @@ def main():
         out["far_field"] = far
     if batch is not None:
         out["batch"] = batch
+    if not args.no_spectrum:
+        out["spectrum"] = spectrum_leg(radio, W, max(1, args.steps))
     if not args.no_serve:
         precs = [args.precision] + (["fp64"] if args.precision != "fp64" and not args.no_fp64 else [])
         out["serve"] = serve_leg(radio, W, precs, args.serve_chunks, args.serve_load)
