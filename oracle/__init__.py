@@ -33,8 +33,10 @@ _LIB = os.path.join(_HERE, "libradio_oracle.so")
 
 _lib = None
 
-FAR_FIELD = 1   # Eq. 3 arrival time and the cell's direction and distance in Eq. 1
-ACCEL_ONLY = 2  # only the acceleration term of Eq. 1
+FAR_FIELD = 1      # Eq. 3 arrival time and the cell's direction and distance in Eq. 1
+ACCEL_ONLY = 2     # only the acceleration term of Eq. 1
+HOLD_PREVIOUS = 4  # segment s holds the field of state s-1 (Fig. 5 walk-through)
+HOLD_LINEAR = 8    # the field varies linearly in arrival time between the two states
 
 
 def build(force: bool = True) -> str:

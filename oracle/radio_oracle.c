@@ -56,6 +56,19 @@
  *       dot = (x0*n0 + x1*n1) + x2*n2, tau = t_s + (R_cell - dot) * (1/c).
  *   ACCEL_ONLY (2): only the second (acceleration) term of Eq. 1, which the
  *       paper keeps when R gamma^2 |betadot| / c >> 1 (Sec. 2).
+ *   HOLD_PREVIOUS (4): segment s holds the field of state s-1 (the reading of
+ *       the Fig. 5 walk-through, "the time until the next deposition"),
+ *       instead of the field of state s (Alg. 1, the default).
+ *   HOLD_LINEAR (8): the field varies linearly in arrival time from E_{s-1}
+ *       at tau_{s-1} to E_s at tau_s (the higher-order interpolation the
+ *       paper names as an extension, Sec. 6): slot j receives the overlap
+ *       times the interpolant at the overlap's midpoint.  Each state's field
+ *       then takes the centred difference betadot_s = (beta_{s+1} -
+ *       beta_{s-1}) / (2 dt), one-sided at the chunk's first and last state,
+ *       so that both ends of a segment are evaluated at their own times.
+ *   With HOLD_PREVIOUS, the field of a chunk's first state takes
+ *   betadot_0 = (beta_1 - beta_0) / dt, the only difference the chunk holds;
+ *   every other state keeps the backward difference.
  *
  * Conventions: Gaussian units, c given (1 in normalised units), signed
  * charge q per particle (a NULL charge array means q = -1, electrons).
@@ -72,6 +85,8 @@
 
 #define ORACLE_FAR_FIELD 1
 #define ORACLE_ACCEL_ONLY 2
+#define ORACLE_HOLD_PREVIOUS 4
+#define ORACLE_HOLD_LINEAR 8
 
 /* beta and 1/gamma^2 from the momentum u = gamma beta (Alg. 1). */
 EXPORT void radio_oracle_kinematics(const double u[3], double beta[3], double* inv_gamma2)
@@ -196,11 +211,53 @@ static void deposit_interval(double* Dc, int64_t n_t, double lo, double hi, cons
     }
 }
 
+/* Add the linear interpolant from Fa at slot coordinate a to Fb at b, integrated
+   over each slot's overlap with [min(a,b), max(a,b)]: overlap times the
+   interpolant at the overlap's midpoint. */
+static void deposit_interval_linear(double* Dc, int64_t n_t, double a, double b,
+                                    const double Fa[6], const double Fb[6])
+{
+    double lo = a < b ? a : b;
+    double hi = a < b ? b : a;
+    if (!(hi > 0.0) || !(lo < (double)n_t) || !(hi > lo))
+        return;
+    int64_t j_lo = lo <= 0.0 ? 0 : (int64_t)floor(lo);
+    int64_t j_hi = hi >= (double)n_t ? n_t - 1 : (int64_t)floor(hi);
+    for (int64_t j = j_lo; j <= j_hi; ++j) {
+        double p = lo > (double)j ? lo : (double)j;
+        double q = hi < (double)(j + 1) ? hi : (double)(j + 1);
+        double w = q - p;
+        if (w > 0.0) {
+            double f = (0.5 * (p + q) - a) / (b - a); /* position of the midpoint, 0 at a */
+            double* Dj = Dc + 6 * j;
+            for (int k = 0; k < 6; ++k)
+                Dj[k] += (Fa[k] + (Fb[k] - Fa[k]) * f) * w;
+        }
+    }
+}
+
 static void load_state(const double* a, int64_t n_states, int64_t n_p, int64_t s, int64_t p,
                        double out[3])
 {
     for (int k = 0; k < 3; ++k)
         out[k] = a[((int64_t)k * n_states + s) * n_p + p];
+}
+
+/* Centred betadot of state s, (beta_{s+1} - beta_{s-1}) / (2 dt), one-sided at the
+   chunk's ends. */
+static void state_betadot(const double* u, int64_t n_states, int64_t n_p, int64_t n_steps,
+                          int64_t s, int64_t p, double dt, double bd[3])
+{
+    int64_t a = s > 0 ? s - 1 : 0;
+    int64_t b = s < n_steps ? s + 1 : n_steps;
+    double ua[3], ub[3], ba[3], bb[3], ga, gb;
+    load_state(u, n_states, n_p, a, p, ua);
+    load_state(u, n_states, n_p, b, p, ub);
+    radio_oracle_kinematics(ua, ba, &ga);
+    radio_oracle_kinematics(ub, bb, &gb);
+    double span = (double)(b - a) * dt;
+    for (int k = 0; k < 3; ++k)
+        bd[k] = (bb[k] - ba[k]) / span;
 }
 
 /*
@@ -255,8 +312,34 @@ EXPORT int radio_oracle_deposit(const double* cells, int64_t n_cells, double t0,
                     tau_prev = radio_oracle_arrival(xc, x_prev, t_prev, c);
                     tau = radio_oracle_arrival(xc, x_cur, t_cur, c);
                 }
-                double F[6];
-                radio_oracle_field_opts(xc, x_cur, beta, g2, betadot, qp, c, options, F, F + 3);
+                double F[6], Fp[6];
+                if (options & ORACLE_HOLD_LINEAR) {
+                    /* both ends, each with the centred betadot at its own state */
+                    double bd_s[3], bd_p[3];
+                    state_betadot(u, n_states, n_p, n_steps, s, p, dt, bd_s);
+                    state_betadot(u, n_states, n_p, n_steps, s - 1, p, dt, bd_p);
+                    radio_oracle_field_opts(xc, x_cur, beta, g2, bd_s, qp, c, options, F, F + 3);
+                    radio_oracle_field_opts(xc, x_prev, beta_prev, g2p, bd_p, qp, c, options, Fp,
+                                            Fp + 3);
+                } else if (options & ORACLE_HOLD_PREVIOUS) {
+                    /* the field of state s-1, with its own backward betadot */
+                    double bd_prev[3];
+                    if (s >= 2) {
+                        double u_pp[3], beta_pp[3], g2pp;
+                        load_state(u, n_states, n_p, s - 2, p, u_pp);
+                        radio_oracle_kinematics(u_pp, beta_pp, &g2pp);
+                        for (int k = 0; k < 3; ++k)
+                            bd_prev[k] = (beta_prev[k] - beta_pp[k]) / dt;
+                    } else {
+                        for (int k = 0; k < 3; ++k)
+                            bd_prev[k] = betadot[k];
+                    }
+                    radio_oracle_field_opts(xc, x_prev, beta_prev, g2p, bd_prev, qp, c, options,
+                                            Fp, Fp + 3);
+                } else {
+                    radio_oracle_field_opts(xc, x_cur, beta, g2, betadot, qp, c, options, F,
+                                            F + 3);
+                }
                 double a = (tau_prev - t0) * inv_dt_det;
                 double b = (tau - t0) * inv_dt_det;
                 double lo = a < b ? a : b;
@@ -265,7 +348,12 @@ EXPORT int radio_oracle_deposit(const double* cells, int64_t n_cells, double t0,
                     ++nonmono;
                 if (lo < 0.0 || hi > (double)n_t)
                     ++clipped;
-                deposit_interval(Dc, n_t, lo, hi, F);
+                if (options & ORACLE_HOLD_LINEAR)
+                    deposit_interval_linear(Dc, n_t, a, b, Fp, F);
+                else if (options & ORACLE_HOLD_PREVIOUS)
+                    deposit_interval(Dc, n_t, lo, hi, Fp);
+                else
+                    deposit_interval(Dc, n_t, lo, hi, F);
             }
         }
     }

@@ -664,3 +664,134 @@ def test_far_field_deposit_equals_exact_for_a_charge_at_the_origin(oracle_mod):
                              options=oracle_mod.FAR_FIELD)
     assert np.abs(exact).max() > 0.0
     assert np.array_equal(exact, far)
+
+
+# ---------------------------------------------------------------- hold rules (previous state, linear)
+
+def _three_state_charge(oracle_mod, options):
+    """A unit charge at rest at three points on the line to the cell, whose arrivals
+    fall at slot coordinates 1.0, 2.3 and 4.6 (the second segment is the Fig. 5
+    walk-through); fields E_s = 1/(R - d_s)^2 along +x."""
+    R, dt_det, dt = 10.0, 0.125, 1.0
+    d = np.array([0.0, dt - 1.3 * dt_det, 0.0])
+    d[2] = d[1] + dt - 2.3 * dt_det
+    x = np.zeros((3, 3, 1))
+    x[0, :, 0] = d
+    u = np.zeros((3, 3, 1))
+    t0 = (R - d[0]) - 1.0 * dt_det
+    D = oracle_mod.deposit(np.array([[R, 0.0, 0.0]]), t0, dt_det, 8, x, u, np.ones(1), 0.0, dt,
+                           options=options)
+    E = 1.0 / (R - d) ** 2
+    return D[0, :, 0], E
+
+
+def test_hold_previous_is_the_fig5_walkthrough(oracle_mod):
+    """Variant B deposits, over [t'_3, t'_4], the field of the deposition at t'_3."""
+    got, E = _three_state_charge(oracle_mod, oracle_mod.HOLD_PREVIOUS)
+    expect = np.zeros(8)
+    expect[1] = 1.0 * E[0]
+    expect[2] = 0.3 * E[0] + 0.7 * E[1]
+    expect[3] = 1.0 * E[1]
+    expect[4] = 0.6 * E[1]
+    np.testing.assert_allclose(got, expect, rtol=1e-12, atol=1e-16)
+    got_a, _ = _three_state_charge(oracle_mod, 0)   # the default holds the current field
+    expect_a = np.zeros(8)
+    expect_a[1] = 1.0 * E[1]
+    expect_a[2] = 0.3 * E[1] + 0.7 * E[2]
+    expect_a[3] = 1.0 * E[2]
+    expect_a[4] = 0.6 * E[2]
+    np.testing.assert_allclose(got_a, expect_a, rtol=1e-12, atol=1e-16)
+
+
+def test_hold_linear_brute_force_and_trapezoid(oracle_mod):
+    got, E = _three_state_charge(oracle_mod, oracle_mod.HOLD_LINEAR)
+    # brute force: sample the piecewise-linear signal finely and average per slot
+    knots_u = np.array([1.0, 2.3, 4.6])
+    us = (np.arange(8 * 20000) + 0.5) / 20000.0
+    sig = np.interp(us, knots_u, E, left=0.0, right=0.0)
+    sig[(us < knots_u[0]) | (us > knots_u[-1])] = 0.0
+    brute = sig.reshape(8, 20000).mean(axis=1)
+    np.testing.assert_allclose(got, brute, rtol=1e-6, atol=1e-12)
+    # integral of the deposit = trapezoid rule over the segments
+    trap = 0.5 * (E[0] + E[1]) * 1.3 + 0.5 * (E[1] + E[2]) * 2.3
+    assert got.sum() == pytest.approx(trap, rel=1e-13)
+
+
+def test_hold_rules_agree_for_a_constant_field(oracle_mod):
+    chunk = W.static_charges(np.array([[0.5, -1.0, 2.0], [3.0, 0.2, -0.4]]), n_steps=30, dt=0.07,
+                             q=-1.0)
+    cells = np.array([[40.0, 5.0, -3.0], [-20.0, 30.0, 10.0]])
+    t0, dt_det, n_t = _window_for(cells, chunk, n_t=60)
+    base = oracle_mod.deposit(cells, t0, dt_det, n_t, chunk.x, chunk.u, chunk.q, 0.0, chunk.dt)
+    for opt in (oracle_mod.HOLD_PREVIOUS, oracle_mod.HOLD_LINEAR):
+        other = oracle_mod.deposit(cells, t0, dt_det, n_t, chunk.x, chunk.u, chunk.q, 0.0,
+                                   chunk.dt, options=opt)
+        np.testing.assert_allclose(other, base, rtol=1e-14, atol=1e-18)
+
+
+def _circular_reference(cell, T, t0, dt_det, n_t, gamma=5.0, q=-1.0, n_fine=400000):
+    """Slot averages of the continuous field of uniform circular motion (radius 1),
+    from the motion in closed form: E(t) of Eq. 1 with the exact beta and betadot,
+    arrival tau(t) = t + |x_c - x(t)|, integrated over tau on a fine grid."""
+    beta = math.sqrt(1 - 1 / gamma ** 2)
+    om = beta
+    t = np.linspace(0.0, T, n_fine + 1)
+    ph = om * t
+    x = np.stack([np.cos(ph), np.sin(ph), 0 * ph], axis=1)
+    b = beta * np.stack([-np.sin(ph), np.cos(ph), 0 * ph], axis=1)
+    bd = -beta * om * np.stack([np.cos(ph), np.sin(ph), 0 * ph], axis=1)
+    d = cell[None, :] - x
+    R = np.linalg.norm(d, axis=1)
+    n = d / R[:, None]
+    w = n - b
+    kap = 1 - (n * b).sum(axis=1)
+    E = q * (w / (gamma ** 2 * kap[:, None] ** 3 * R[:, None] ** 2)
+             + np.cross(n, np.cross(w, bd)) / (kap[:, None] ** 3 * R[:, None]))
+    tau = t + R
+    u = (tau - t0) / dt_det
+    # cumulative integral of E over slot units, read at the slot edges
+    cum = np.concatenate([np.zeros((1, 3)),
+                          np.cumsum(0.5 * (E[1:] + E[:-1]) * np.diff(u)[:, None], axis=0)])
+    edges = np.arange(n_t + 1, dtype=np.float64)
+    at = np.stack([np.interp(edges, u, cum[:, k]) for k in range(3)], axis=1)
+    return np.diff(at, axis=0)
+
+
+@pytest.mark.parametrize("geometry", ["axis", "plane"])
+def test_hold_rule_convergence_orders(oracle_mod, geometry):
+    """Convergence in dt against the continuous field (the empirical side of reading
+    R2).  With betadot the backward difference, the current state's field (A)
+    pairs a segment with betadot at its own midpoint: second order where the
+    field is set by betadot (on the orbit's axis), first order where position
+    and velocity move it (in the orbit's plane).  The previous state's field (B)
+    is first order in both; the linear interpolation with centred betadot is
+    second order in both."""
+    cell = np.array([0.0, 0.0, 1000.0]) if geometry == "axis" else np.array([1000.0, 300.0, 0.0])
+    T = 2 * np.pi / 0.9797958971132712 * 0.8
+    dt_det = 0.05 if geometry == "axis" else 0.02
+    Rc = np.linalg.norm(cell)
+    t0 = Rc - 2.0
+    n_t = int((T + 4.0) / dt_det)
+    ref = _circular_reference(cell, T, t0, dt_det, n_t)
+
+    def dep(n_steps, opt):
+        chunk = W.circular_orbit(gamma=5.0, radius=1.0, n_steps=n_steps, dt=T / n_steps, q=-1.0)
+        D = oracle_mod.deposit(cell[None, :], t0, dt_det, n_t, chunk.x, chunk.u, chunk.q, 0.0,
+                               chunk.dt, options=opt)
+        return D[0, :, :3]
+
+    steps = (400, 800, 1600, 3200, 6400)
+    errs, orders = {}, {}
+    for name, opt in (("A", 0), ("B", oracle_mod.HOLD_PREVIOUS), ("linear", oracle_mod.HOLD_LINEAR)):
+        e = np.array([np.linalg.norm(dep(n, opt) - ref) / np.linalg.norm(ref) for n in steps])
+        errs[name] = e
+        orders[name] = np.log2(e[0] / e[-1]) / (len(steps) - 1)  # mean order over the range
+    print(f"[hold] {geometry} mean convergence orders:",
+          {k: round(float(v), 2) for k, v in orders.items()})
+    assert abs(orders["B"] - 1.0) < 0.1
+    assert abs(orders["linear"] - 2.0) < 0.1
+    if geometry == "axis":
+        assert orders["A"] > 1.5
+        assert np.all(errs["A"] < errs["B"] / 50)
+    else:
+        assert abs(orders["A"] - 1.0) < 0.1
