@@ -68,6 +68,14 @@ extern "C" {
                               compared with R_cell */
 #define RADIO_ACCEL_ONLY 2 /* only the acceleration (second) term of Eq. 1, enough when
                               R gamma^2 |betadot| / c >> 1 (Sec. 2) */
+#define RADIO_HOLD_PREVIOUS 4 /* segment s holds the field of state s-1 (the Fig. 5
+                                 walk-through) instead of that of state s (Alg. 1, the
+                                 default); a chunk's first state takes the forward
+                                 difference for betadot */
+#define RADIO_HOLD_LINEAR 8   /* the field varies linearly in arrival time from E_{s-1} to
+                                 E_s, each with betadot centred at its state (one-sided at
+                                 the chunk's ends): the higher-order interpolation named as
+                                 an extension in Sec. 6.  Excludes RADIO_HOLD_PREVIOUS */
 
 /* detector cell geometry (Sec. 3.1: spherical grids centred at the origin and
    cartesian planes) */
@@ -99,7 +107,8 @@ typedef struct radio_detector_desc {
     double dt_det;        /* slot width, > 0 */
     int64_t n_t;          /* number of slots, >= 1 */
     double c;             /* speed of light, > 0 (1 in normalised units) */
-    int32_t options;      /* RADIO_FAR_FIELD | RADIO_ACCEL_ONLY, or 0 (Eq. 2 and all of Eq. 1) */
+    int32_t options;      /* RADIO_FAR_FIELD | RADIO_ACCEL_ONLY | RADIO_HOLD_*, or 0 (Eq. 2,
+                             all of Eq. 1, the current state's field held) */
 } radio_detector_desc;
 
 /*

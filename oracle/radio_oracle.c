@@ -228,7 +228,10 @@ static void deposit_interval_linear(double* Dc, int64_t n_t, double a, double b,
         double q = hi < (double)(j + 1) ? hi : (double)(j + 1);
         double w = q - p;
         if (w > 0.0) {
-            double f = (0.5 * (p + q) - a) / (b - a); /* position of the midpoint, 0 at a */
+            /* position of the midpoint, 0 at a, from differences with a (exact for the
+               coordinates of one segment), so that a segment much shorter than a slot
+               keeps its relative accuracy */
+            double f = 0.5 * ((p - a) + (q - a)) / (b - a);
             double* Dj = Dc + 6 * j;
             for (int k = 0; k < 6; ++k)
                 Dj[k] += (Fa[k] + (Fb[k] - Fa[k]) * f) * w;

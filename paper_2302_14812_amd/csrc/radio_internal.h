@@ -85,6 +85,7 @@ struct DepositJob {
     uint8_t* ring_sel;              // workspace [n_tiles]: 1 where a tile takes the large ring
     const double* far;              // far-field detector: [n_c][4] n_cell, R_cell; else nullptr
     double vscale;                  // 1, or 0 for an acceleration-only detector
+    int64_t hold;                   // field a segment holds: 0 current, 1 previous, 2 linear
     int64_t n_c, n_t, n_p, n_s;
     double t_first, dt;             // state s at t_first + (s0 + s)*dt
     int64_t s0;                     // the chunk's first state within its run
@@ -113,11 +114,17 @@ hipError_t launch_kinematics(const DepositJob& job, int mode, hipStream_t s);
 hipError_t launch_order(const DepositJob& job, hipStream_t s);
 hipError_t launch_ring_choice(const DepositJob& job, int mode, hipStream_t s);
 hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s);
+// Persistent kernel variants: v = mode + 3 * (far + 2 * hold).
+constexpr int kKernelVariants = 18;
+inline int kernel_variant(int mode, const DepositJob& J)
+{
+    return mode + 3 * ((J.far ? 1 : 0) + 2 * (int)J.hold);
+}
 // next: two work counters (small-ring and large-ring workgroups)
 hipError_t launch_deposit_batch(const DepositJob* jobs, const WorkItem* items, int64_t n_items,
-                                unsigned long long* next, int mode, bool far, int blocks_small,
+                                unsigned long long* next, int variant, int blocks_small,
                                 int blocks_large, hipStream_t s);
-int persistent_blocks_per_cu(int mode, bool far, bool large_ring);
+int persistent_blocks_per_cu(int variant, bool large_ring);
 hipError_t launch_readout(const double* acc, int64_t n_c, int64_t n_t, const int64_t* user_index,
                           bool pairs, double* E, double* B, hipStream_t s);
 // spectral post-processing (radio_spectrum.hip): one group of G cells (internal

@@ -362,6 +362,110 @@ __device__ __forceinline__ void add_segment(Carry<T>& C, const Sink& sink, int n
     }
 }
 
+// The linear rule: the field runs from Fa at slot coordinate a to Fb at b, and
+// each slot receives its overlap with the segment times the interpolant at the
+// overlap's midpoint (the exact integral of a linear function).  Same fast and
+// general paths as add_segment.
+template <typename T>
+__device__ __forceinline__ void lerp_field(const T Fa[6], const T dF[6], T f, T out[6])
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        out[k] = Fa[k] + dF[k] * f;
+}
+
+template <typename T, typename Sink>
+__device__ __forceinline__ void add_segment_linear_general(Carry<T>& C, const Sink& sink, int n_t,
+                                                           double a, double b, const T Fa[6],
+                                                           const T dF[6], double inv_len)
+{
+    const double ntd = (double)n_t;
+    const double lo = fmin(fmax(fmin(a, b), 0.0), ntd);
+    const double hi = fmin(fmax(fmax(a, b), 0.0), ntd);
+    if (!(lo < hi))
+        return;
+    const int jl = (int)floor(lo);
+    const int jh = (int)floor(hi);
+    if (jl != C.J) {
+        sink.flush(C.J, C.V);
+        carry_open(C, jl);
+    }
+    T F[6];
+    auto piece = [&](double p, double q) {  // the interpolant times the overlap [p, q]
+        lerp_field(Fa, dF, T(0.5 * ((p - a) + (q - a)) * inv_len), F);
+        const T w = T(q - p);
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            F[k] *= w;
+    };
+    if (jh == jl) {
+        piece(lo, hi);
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            C.V[k] += F[k];
+        return;
+    }
+    piece(lo, (double)(jl + 1));
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        C.V[k] += F[k];
+    sink.flush(jl, C.V);
+    for (int j = jl + 1; j < jh; ++j) {
+        piece((double)j, (double)(j + 1));
+        sink.flush(j, F);
+    }
+    piece((double)jh, hi);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        C.V[k] = F[k];
+    C.J = jh;
+}
+
+template <typename T, typename Sink>
+__device__ __forceinline__ void add_segment_linear(Carry<T>& C, const Sink& sink, int n_t,
+                                                   double a, double b, const T Fa[6],
+                                                   const T Fb[6])
+{
+    if (!(a != b))  // no length (or NaN): nothing to hold
+        return;
+    T dF[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        dF[k] = Fb[k] - Fa[k];
+    const double inv_len = 1.0 / (b - a);
+    const double Jd = (double)C.J;
+    const bool fast = (b > a) & (a >= Jd) & (b < Jd + (kFastSlots + 1.0)) & (Jd >= -1.0) &
+                      (b < (double)n_t + 1.0);
+    if (fast) {
+        const double fb = floor(b);
+        const int n = (int)(fb - Jd);
+        const double e0 = n == 0 ? b : Jd + 1.0;
+        T F[6];
+        lerp_field(Fa, dF, T(0.5 * (e0 - a) * inv_len), F);
+        const T w0 = T(e0 - a);
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            C.V[k] += F[k] * w0;
+        if (n >= 1) {
+            sink.flush(C.J, C.V);
+            for (int i = 1; i < n; ++i) {  // whole slots: the interpolant at their middle
+                lerp_field(Fa, dF, T(0.5 * ((Jd + (double)i - a) + (Jd + (double)(i + 1) - a)) *
+                                     inv_len),
+                           F);
+                sink.flush(C.J + i, F);
+            }
+            lerp_field(Fa, dF, T(0.5 * ((fb - a) + (b - a)) * inv_len), F);
+            const T wb = T(b - fb);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                C.V[k] = F[k] * wb;
+            C.J += n;
+        }
+    } else {
+        add_segment_linear_general(C, sink, n_t, a, b, Fa, dF, inv_len);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // field evaluation
 // ---------------------------------------------------------------------------
@@ -588,11 +692,17 @@ __device__ __forceinline__ double slot_coord_mixed(const double xc[3], const dou
 // ---------------------------------------------------------------------------
 
 // One thread per (particle, state): the state record of mode M, particle-major.
+// betadot of a state: kBdBackward (beta_s - beta_{s-1})/dt, zero at the chunk's first
+// state (it carries no segment); kBdBackwardFirst the same but the forward difference
+// at the first state (its field is held by the previous-state rule); kBdCentred
+// (beta_{s+1} - beta_{s-1})/(2 dt), one-sided at the chunk's ends (linear rule)
+constexpr int kBdBackward = 0, kBdBackwardFirst = 1, kBdCentred = 2;
+
 template <int M>
 __global__ __launch_bounds__(256) void kinematics_kernel(const double* __restrict__ x,
                                                          const double* __restrict__ u,
                                                          int64_t n_p, int64_t n_s, double dt,
-                                                         void* __restrict__ recs_out)
+                                                         int bd_rule, void* __restrict__ recs_out)
 {
     using Rec = typename std::conditional<M == kModeF64, RecF64, RecMix>::type;
     Rec* recs = reinterpret_cast<Rec*>(recs_out);
@@ -610,13 +720,24 @@ __global__ __launch_bounds__(256) void kinematics_kernel(const double* __restric
         r.x[2] = x[off + 2 * stride];
         canon_kinematics(u[off], u[off + stride], u[off + 2 * stride], r.b, &r.g2i);
         double bd[3] = {0.0, 0.0, 0.0};
-        if (s > 0) {
-            double bp[3], gp;
-            const int64_t o2 = off - n_p;
-            canon_kinematics(u[o2], u[o2 + stride], u[o2 + 2 * stride], bp, &gp);
+        if (bd_rule == kBdCentred && n_s > 0) {
+            const int64_t sa = s > 0 ? s - 1 : 0;
+            const int64_t sb = s < n_s ? s + 1 : n_s;
+            double ba[3], bb[3], g;
+            const int64_t oa = sa * n_p + p, ob = sb * n_p + p;
+            canon_kinematics(u[oa], u[oa + stride], u[oa + 2 * stride], ba, &g);
+            canon_kinematics(u[ob], u[ob + stride], u[ob + 2 * stride], bb, &g);
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                bd[c] = canon_betadot(r.b[c], bp[c], dt);
+                bd[c] = canon_betadot(bb[c], ba[c], (double)(sb - sa) * dt);
+        } else if (s > 0 || (bd_rule == kBdBackwardFirst && n_s > 0)) {
+            // backward difference; at the first state, the forward one
+            double bo[3], go;
+            const int64_t o2 = s > 0 ? off - n_p : off + n_p;
+            canon_kinematics(u[o2], u[o2 + stride], u[o2 + 2 * stride], bo, &go);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                bd[c] = s > 0 ? canon_betadot(r.b[c], bo[c], dt) : canon_betadot(bo[c], r.b[c], dt);
         }
         if constexpr (M == kModeF64) {
 #pragma unroll
@@ -839,7 +960,9 @@ struct DepositShared {
 // lanes of a wavefront's row hold different cells, so one ring update
 // instruction touches different rings, and the four groups of a wavefront
 // read their particles' records as LDS broadcasts.
-template <int M, int R, bool FAR>
+// HOLD: which field a segment holds (0 the current state's, 1 the previous
+// state's, 2 the linear interpolation between the two)
+template <int M, int R, bool FAR, int HOLD>
 __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, int64_t split,
                                              DepositShared<M, R>& sh)
 {
@@ -1004,7 +1127,26 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         if (active && g < np) {
             Sink sink{my_ring, row, base, n_t, &n_bypass};
             const double q = sh.sq[g];
-            double u_prev = slot_of(sh.rec[g][0], t_a);
+            // the field of one staged state and its slot coordinate
+            auto field_at = [&](const Rec& st, double t_s, T F[6]) {
+                if constexpr (FAR) {
+                    if constexpr (MIX)
+                        return field_far_mixed(fc, Rinv, st, t_s, (float)q, K, F);
+                    else
+                        return field_far_fp64(fc, Rinv, st, t_s, q, K, F);
+                } else {
+                    if constexpr (MIX)
+                        return field_mixed(xc, st, t_s, (float)q, K, F);
+                    else
+                        return field_fp64(xc, st, t_s, q, K, F);
+                }
+            };
+            T Fp[6];  // the previous state's field (HOLD != 0)
+            double u_prev;
+            if constexpr (HOLD != 0)
+                u_prev = field_at(sh.rec[g][0], t_a, Fp);
+            else
+                u_prev = slot_of(sh.rec[g][0], t_a);
             Carry<T> C;
             // open the slot where the run starts (a start far outside the window
             // leaves the first segment to the general path)
@@ -1015,22 +1157,21 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
                 T F[6];
                 sk += 1.0;
                 const double t_s = canon_state_time(J.t_first, sk, J.dt);
-                double uk;
-                if constexpr (FAR) {
-                    if constexpr (MIX)
-                        uk = field_far_mixed(fc, Rinv, sh.rec[g][k], t_s, (float)q, K, F);
-                    else
-                        uk = field_far_fp64(fc, Rinv, sh.rec[g][k], t_s, q, K, F);
-                } else {
-                    if constexpr (MIX)
-                        uk = field_mixed(xc, sh.rec[g][k], t_s, (float)q, K, F);
-                    else
-                        uk = field_fp64(xc, sh.rec[g][k], t_s, q, K, F);
-                }
+                const double uk = field_at(sh.rec[g][k], t_s, F);
                 const bool back = uk < u_prev;
                 n_back += back ? 1u : 0u;
                 n_clip += (fmin(uk, u_prev) < 0.0 || fmax(uk, u_prev) > (double)n_t) ? 1u : 0u;
-                add_segment(C, sink, n_t, u_prev, uk, F);
+                if constexpr (HOLD == 0) {
+                    add_segment(C, sink, n_t, u_prev, uk, F);
+                } else {
+                    if constexpr (HOLD == 1)
+                        add_segment(C, sink, n_t, u_prev, uk, Fp);
+                    else
+                        add_segment_linear(C, sink, n_t, u_prev, uk, Fp, F);
+#pragma unroll
+                    for (int c = 0; c < 6; ++c)
+                        Fp[c] = F[c];
+                }
                 u_prev = uk;
             }
             sink.flush(C.J, C.V);
@@ -1052,7 +1193,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
 
 // One workgroup per work item of a single deposit; the tiles that take the
 // other ring size leave at once.
-template <int M, int R, bool FAR>
+template <int M, int R, bool FAR, int HOLD>
 __global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
 {
     __shared__ __align__(16) DepositShared<M, R> sh;
@@ -1066,7 +1207,7 @@ __global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
     const int64_t tile = logical % J.n_tiles;
     if (gptr(J.ring_sel)[tile] != (R == kRingLarge ? 1 : 0))
         return;
-    deposit_item<M, R, FAR>(J, tile, logical / J.n_tiles, sh);
+    deposit_item<M, R, FAR, HOLD>(J, tile, logical / J.n_tiles, sh);
 }
 
 // Persistent workgroups for many independent deposits: each takes the next work
@@ -1074,7 +1215,7 @@ __global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
 // the list is exhausted, so uneven jobs share one launch without a tail of idle
 // workgroups; items whose tile takes the other ring size are skipped.  Every
 // workgroup leaves once the counter passes n_items.
-template <int M, int R, bool FAR>
+template <int M, int R, bool FAR, int HOLD>
 __global__ __launch_bounds__(kDepositThreads) void deposit_persistent_kernel(
     const DepositJob* __restrict__ jobs, const WorkItem* __restrict__ items, int64_t n_items,
     unsigned long long* __restrict__ next)
@@ -1093,7 +1234,7 @@ __global__ __launch_bounds__(kDepositThreads) void deposit_persistent_kernel(
         const DepositJob J = jobs[w.job];
         if (gptr(J.ring_sel)[w.tile] != (R == kRingLarge ? 1 : 0))
             continue;
-        deposit_item<M, R, FAR>(J, w.tile, w.split, sh);
+        deposit_item<M, R, FAR, HOLD>(J, w.tile, w.split, sh);
     }
 }
 
@@ -1203,12 +1344,13 @@ hipError_t launch_kinematics(const DepositJob& job, int mode, hipStream_t s)
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536)
         blocks = 65536;
+    const int rule = job.hold == 2 ? kBdCentred : (job.hold == 1 ? kBdBackwardFirst : kBdBackward);
     if (mode == kModeF64)
         hipLaunchKernelGGL(kinematics_kernel<kModeF64>, dim3((unsigned)blocks), dim3(256), 0, s,
-                           job.x, job.u, job.n_p, job.n_s, job.dt, job.recs);
+                           job.x, job.u, job.n_p, job.n_s, job.dt, rule, job.recs);
     else
         hipLaunchKernelGGL(kinematics_kernel<kModeMix>, dim3((unsigned)blocks), dim3(256), 0, s,
-                           job.x, job.u, job.n_p, job.n_s, job.dt, job.recs);
+                           job.x, job.u, job.n_p, job.n_s, job.dt, rule, job.recs);
     return hipGetLastError();
 }
 
@@ -1232,24 +1374,36 @@ hipError_t launch_ring_choice(const DepositJob& job, int mode, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int M, bool FAR>
-static void launch_deposit_mode(const DepositJob& job, dim3 grid, hipStream_t s)
+// kernel variants: precision mode x ring size x far field x hold rule
+template <int M, bool FAR, int HOLD>
+static void launch_deposit_v(const DepositJob& job, dim3 grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((deposit_kernel<M, kRingSmall, FAR>), grid, dim3(kDepositThreads), 0, s,
-                       job);
-    hipLaunchKernelGGL((deposit_kernel<M, kRingLarge, FAR>), grid, dim3(kDepositThreads), 0, s,
-                       job);
+    hipLaunchKernelGGL((deposit_kernel<M, kRingSmall, FAR, HOLD>), grid, dim3(kDepositThreads), 0,
+                       s, job);
+    hipLaunchKernelGGL((deposit_kernel<M, kRingLarge, FAR, HOLD>), grid, dim3(kDepositThreads), 0,
+                       s, job);
+}
+
+template <int M, bool FAR>
+static void launch_deposit_hold(const DepositJob& job, dim3 grid, hipStream_t s)
+{
+    if (job.hold == 1)
+        launch_deposit_v<M, FAR, 1>(job, grid, s);
+    else if (job.hold == 2)
+        launch_deposit_v<M, FAR, 2>(job, grid, s);
+    else
+        launch_deposit_v<M, FAR, 0>(job, grid, s);
 }
 
 template <bool FAR>
 static void launch_deposit_far(const DepositJob& job, int mode, dim3 grid, hipStream_t s)
 {
     if (mode == kModeMix)
-        launch_deposit_mode<kModeMix, FAR>(job, grid, s);
+        launch_deposit_hold<kModeMix, FAR>(job, grid, s);
     else if (mode == kModeMixTwoSum)
-        launch_deposit_mode<kModeMixTwoSum, FAR>(job, grid, s);
+        launch_deposit_hold<kModeMixTwoSum, FAR>(job, grid, s);
     else
-        launch_deposit_mode<kModeF64, FAR>(job, grid, s);
+        launch_deposit_hold<kModeF64, FAR>(job, grid, s);
 }
 
 hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s)
@@ -1266,77 +1420,76 @@ hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int M, bool FAR>
-static void launch_persistent_mode(const DepositJob* jobs, const WorkItem* items, int64_t n_items,
-                                   unsigned long long* next, int blocks_small, int blocks_large,
-                                   hipStream_t s)
+template <int M, bool FAR, int HOLD>
+static void launch_persistent_v(const DepositJob* jobs, const WorkItem* items, int64_t n_items,
+                                unsigned long long* next, int blocks_small, int blocks_large,
+                                hipStream_t s)
 {
-    hipLaunchKernelGGL((deposit_persistent_kernel<M, kRingSmall, FAR>),
+    hipLaunchKernelGGL((deposit_persistent_kernel<M, kRingSmall, FAR, HOLD>),
                        dim3((unsigned)blocks_small), dim3(kDepositThreads), 0, s, jobs, items,
                        n_items, next);
-    hipLaunchKernelGGL((deposit_persistent_kernel<M, kRingLarge, FAR>),
+    hipLaunchKernelGGL((deposit_persistent_kernel<M, kRingLarge, FAR, HOLD>),
                        dim3((unsigned)blocks_large), dim3(kDepositThreads), 0, s, jobs, items,
                        n_items, next + 1);
 }
 
-template <bool FAR>
-static void launch_persistent_far(const DepositJob* jobs, const WorkItem* items, int64_t n_items,
-                                  unsigned long long* next, int mode, int blocks_small,
-                                  int blocks_large, hipStream_t s)
+// the variant index v = mode + 3 * (far + 2 * hold), v < kKernelVariants
+template <int V>
+static void launch_persistent_index(const DepositJob* jobs, const WorkItem* items,
+                                    int64_t n_items, unsigned long long* next, int blocks_small,
+                                    int blocks_large, hipStream_t s)
 {
-    if (mode == kModeMix)
-        launch_persistent_mode<kModeMix, FAR>(jobs, items, n_items, next, blocks_small,
-                                              blocks_large, s);
-    else if (mode == kModeMixTwoSum)
-        launch_persistent_mode<kModeMixTwoSum, FAR>(jobs, items, n_items, next, blocks_small,
-                                                    blocks_large, s);
-    else
-        launch_persistent_mode<kModeF64, FAR>(jobs, items, n_items, next, blocks_small,
-                                              blocks_large, s);
+    launch_persistent_v<V % 3, (V / 3) % 2 == 1, V / 6>(jobs, items, n_items, next, blocks_small,
+                                                        blocks_large, s);
 }
 
-hipError_t launch_deposit_batch(const DepositJob* jobs, const WorkItem* items, int64_t n_items,
-                                unsigned long long* next, int mode, bool far, int blocks_small,
-                                int blocks_large, hipStream_t s)
-{
-    if (n_items <= 0)
-        return hipSuccess;
-    hipError_t e = launch_zero_u64(next, 2, s);
-    if (e != hipSuccess)
-        return e;
-    if (far)
-        launch_persistent_far<true>(jobs, items, n_items, next, mode, blocks_small, blocks_large,
-                                    s);
-    else
-        launch_persistent_far<false>(jobs, items, n_items, next, mode, blocks_small, blocks_large,
-                                     s);
-    return hipGetLastError();
-}
-
-template <int M, bool FAR>
-static int blocks_per_cu(bool large_ring)
+template <int V>
+static int blocks_per_cu_index(bool large_ring)
 {
     int n = 0;
+    constexpr int M = V % 3;
+    constexpr bool FAR = (V / 3) % 2 == 1;
+    constexpr int HOLD = V / 6;
     const void* f =
-        large_ring ? reinterpret_cast<const void*>(deposit_persistent_kernel<M, kRingLarge, FAR>)
-                   : reinterpret_cast<const void*>(deposit_persistent_kernel<M, kRingSmall, FAR>);
+        large_ring
+            ? reinterpret_cast<const void*>(deposit_persistent_kernel<M, kRingLarge, FAR, HOLD>)
+            : reinterpret_cast<const void*>(deposit_persistent_kernel<M, kRingSmall, FAR, HOLD>);
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kDepositThreads, 0);
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 
-template <bool FAR>
-static int blocks_per_cu_far(int mode, bool large_ring)
+template <int... V>
+struct VariantTable {
+    using Launch = void (*)(const DepositJob*, const WorkItem*, int64_t, unsigned long long*,
+                            int, int, hipStream_t);
+    using Occ = int (*)(bool);
+    static constexpr Launch launch[] = {&launch_persistent_index<V>...};
+    static constexpr Occ occupancy[] = {&blocks_per_cu_index<V>...};
+};
+using Variants = VariantTable<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17>;
+static_assert(sizeof(Variants::launch) / sizeof(Variants::launch[0]) == kKernelVariants,
+              "one entry per kernel variant");
+
+hipError_t launch_deposit_batch(const DepositJob* jobs, const WorkItem* items, int64_t n_items,
+                                unsigned long long* next, int variant, int blocks_small,
+                                int blocks_large, hipStream_t s)
 {
-    if (mode == kModeMix)
-        return blocks_per_cu<kModeMix, FAR>(large_ring);
-    if (mode == kModeMixTwoSum)
-        return blocks_per_cu<kModeMixTwoSum, FAR>(large_ring);
-    return blocks_per_cu<kModeF64, FAR>(large_ring);
+    if (n_items <= 0)
+        return hipSuccess;
+    if (variant < 0 || variant >= kKernelVariants)
+        return hipErrorInvalidValue;
+    hipError_t e = launch_zero_u64(next, 2, s);
+    if (e != hipSuccess)
+        return e;
+    Variants::launch[variant](jobs, items, n_items, next, blocks_small, blocks_large, s);
+    return hipGetLastError();
 }
 
-int persistent_blocks_per_cu(int mode, bool far, bool large_ring)
+int persistent_blocks_per_cu(int variant, bool large_ring)
 {
-    return far ? blocks_per_cu_far<true>(mode, large_ring) : blocks_per_cu_far<false>(mode, large_ring);
+    if (variant < 0 || variant >= kKernelVariants)
+        return 1;
+    return Variants::occupancy[variant](large_ring);
 }
 
 hipError_t launch_readout(const double* acc, int64_t n_c, int64_t n_t, const int64_t* user_index,

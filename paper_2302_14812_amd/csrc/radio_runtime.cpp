@@ -294,6 +294,7 @@ radio::DepositJob make_job(radio_detector* det, const radio_chunk* k)
     J.s0 = k->first_step;
     J.far = det->d_far;
     J.vscale = (det->options & RADIO_ACCEL_ONLY) ? 0.0 : 1.0;
+    J.hold = (det->options & RADIO_HOLD_LINEAR) ? 2 : ((det->options & RADIO_HOLD_PREVIOUS) ? 1 : 0);
     J.dt = k->dt;
     J.t0 = det->t0;
     J.inv_dt_det = 1.0 / det->dt_det;
@@ -381,7 +382,7 @@ struct BatchArena {
 // while the previous one still runs, and only the batch before that must have
 // finished.
 constexpr int kArenas = 2;
-constexpr int kVariants = 6;  // precision modes x {exact, far-field}
+constexpr int kVariants = radio::kKernelVariants;
 std::mutex g_arena_mu;
 std::map<int, BatchArena*> g_arenas[kArenas];
 std::map<int, int> g_arena_next;
@@ -448,7 +449,7 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
     int bpc[kVariants][2];  // resident workgroups per CU: [variant][large ring]
     for (int v = 0; v < kVariants; ++v)
         for (int r = 0; r < 2; ++r)
-            bpc[v][r] = radio::persistent_blocks_per_cu(v % 3, v >= 3, r == 1);
+            bpc[v][r] = radio::persistent_blocks_per_cu(v, r == 1);
     const double resident = (double)A->n_cus * (double)bpc[0][0];
     const double item_work = std::max(total / (resident * (double)tun.items_per_workgroup), 1.0);
     struct Item {
@@ -472,8 +473,7 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
         rps = std::max<int64_t>(1, std::min<int64_t>(rps, J.n_runs));
         J.runs_per_split = rps;
         J.n_splits = (J.n_runs + rps - 1) / rps;
-        // kernel variant: precision mode, plus 3 for a far-field detector
-        const int mode = prec + (J.far ? 3 : 0);
+        const int mode = radio::kernel_variant(prec, J);  // kernel variant
         for (int64_t sp = 0; sp < J.n_splits; ++sp) {
             const int64_t runs = std::min<int64_t>(rps, J.n_runs - sp * rps);
             for (int64_t t = 0; t < J.n_tiles; ++t)
@@ -506,9 +506,8 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
         while (e < items.size() && items[e].mode == mode)
             ++e;
         if (radio::launch_deposit_batch(A->d_jobs, A->d_items + b, (int64_t)(e - b),
-                                        A->d_next + 2 * mode, mode % 3, mode >= 3,
-                                        A->n_cus * bpc[mode][0], A->n_cus * bpc[mode][1],
-                                        s) != hipSuccess)
+                                        A->d_next + 2 * mode, mode, A->n_cus * bpc[mode][0],
+                                        A->n_cus * bpc[mode][1], s) != hipSuccess)
             return RADIO_EDEVICE;
         b = e;
     }
@@ -560,7 +559,9 @@ int radio_detector_create(const radio_detector_desc* desc, void* stream, radio_d
         return RADIO_EINVAL;
     if (!std::isfinite(desc->c) || !(desc->c > 0.0))
         return RADIO_EINVAL;
-    if ((desc->options & ~(RADIO_FAR_FIELD | RADIO_ACCEL_ONLY)) != 0)
+    if ((desc->options &
+         ~(RADIO_FAR_FIELD | RADIO_ACCEL_ONLY | RADIO_HOLD_PREVIOUS | RADIO_HOLD_LINEAR)) != 0 ||
+        ((desc->options & RADIO_HOLD_PREVIOUS) && (desc->options & RADIO_HOLD_LINEAR)))
         return RADIO_EINVAL;
     std::vector<double> cells;
     int rc = build_cells(*desc, cells);

@@ -89,7 +89,9 @@ def test_invalid_arguments_rejected_before_any_device_work():
     d.precision = 7
     assert lib.radio_detector_create(ctypes.byref(d), None, ctypes.byref(h)) == radio.EINVAL
     d.precision = 0
-    d.options = 4  # unknown option bit
+    d.options = 16  # unknown option bit
+    assert lib.radio_detector_create(ctypes.byref(d), None, ctypes.byref(h)) == radio.EINVAL
+    d.options = radio.HOLD_PREVIOUS | radio.HOLD_LINEAR  # two hold rules at once
     assert lib.radio_detector_create(ctypes.byref(d), None, ctypes.byref(h)) == radio.EINVAL
     d.options = radio.FAR_FIELD | radio.ACCEL_ONLY
     d.geometry = 9

@@ -1,5 +1,6 @@
-"""Detector options on the device: far-field geometry (Eq. 3) and the
-acceleration-only field, each against the oracle with the same options."""
+"""Detector options on the device: far-field geometry (Eq. 3), the
+acceleration-only field and the hold rules (previous state's field, linear
+interpolation), each against the oracle with the same options."""
 import dataclasses
 
 import numpy as np
@@ -11,7 +12,9 @@ from paper_2302_14812_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOLS = {"fp64": 1e-12, "mixed": 1e-5, "mixed_twosum": 1e-5}
-OPTIONS = [1, 2, 3]  # far field, acceleration only, both
+# far field, accel only, both; hold previous (alone, with far field); hold linear (alone,
+# with far field, with accel only)
+OPTIONS = [1, 2, 3, 4, 5, 8, 9, 10]
 
 
 @pytest.fixture(scope="module")
