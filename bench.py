@@ -44,7 +44,8 @@ def parse():
                     help="skip the batched-launch leg (64 uneven sets, one persistent launch "
                          "vs 64 separate launches)")
     ap.add_argument("--no-serve", action="store_true", help="skip the streaming-service leg")
-    ap.add_argument("--no-far", action="store_true", help="skip the far-field option leg")
+    ap.add_argument("--no-options", action="store_true",
+                    help="skip the detector-options leg (far field, hold rules)")
     ap.add_argument("--no-spectrum", action="store_true",
                     help="skip the spectral post-processing leg")
     ap.add_argument("--serve-chunks", type=int, default=30,
@@ -93,30 +94,34 @@ def time_precision(radio, wl, chunk_dev, precision, steps, warmup, options=0, ke
     return wall / steps * 1e3, kernel_ms
 
 
-def far_leg(radio, wl, chunk_dev, precision, steps, warmup):
-    """The far-field detector option (Eq. 3 arrival time, cell direction and distance in
-    Eq. 1) on the benchmark workload: throughput, and its departure from the exact
-    deposit (a property of the approximation, not of the kernel)."""
+def options_leg(radio, wl, chunk_dev, precision, steps, warmup):
+    """Detector options on the benchmark workload: far field (Eq. 3 arrival time, cell
+    direction and distance in Eq. 1), far field with the acceleration term alone, the
+    previous state's field held, and the linear interpolation.  Throughput of each and
+    its departure from the default deposit (a property of the option, not of the
+    kernel: every option matches the oracle with the same option in the tests)."""
     import torch
     out = {"precision": precision}
     fields = {}
-    for name, opt in (("exact", 0), ("far_field", radio.FAR_FIELD),
-                      ("far_field_accel_only", radio.FAR_FIELD | radio.ACCEL_ONLY)):
+    legs = (("default", 0), ("far_field", radio.FAR_FIELD),
+            ("far_field_accel_only", radio.FAR_FIELD | radio.ACCEL_ONLY),
+            ("hold_previous", radio.HOLD_PREVIOUS), ("hold_linear", radio.HOLD_LINEAR))
+    for name, opt in legs:
         ms, kms, EB = time_precision(radio, wl, chunk_dev, precision, steps if opt else 1,
                                      warmup if opt else 0, options=opt, keep=True)
-        fields[name] = EB
+        fields[name] = EB[0]
+        del EB
         inter = wl.interactions
         if opt:
-            out[name] = {"ms_per_step": ms, "deposit_kernel_ms": kms,
+            out[name] = {"options": opt, "ms_per_step": ms, "deposit_kernel_ms": kms,
                          "value": inter / (ms * 1e-3)}
         print(f"[bench] {precision} options={opt}: {ms:.1f} ms/step, "
               f"{inter / (ms * 1e-3):.3e} interactions/s", file=sys.stderr, flush=True)
-    Ee = fields["exact"][0]
-    for name in ("far_field", "far_field_accel_only"):
-        Ef = fields[name][0]
-        out[name]["rel_l2_vs_exact"] = float(torch.linalg.vector_norm(Ef - Ee) /
-                                             torch.linalg.vector_norm(Ee))
-    del fields, Ee, Ef
+    Ee = fields.pop("default")
+    for name, Ef in fields.items():
+        out[name]["rel_l2_vs_default"] = float(torch.linalg.vector_norm(Ef - Ee) /
+                                               torch.linalg.vector_norm(Ee))
+    del fields, Ee
     torch.cuda.synchronize()
     return out
 
@@ -381,8 +386,7 @@ def main():
               f"{legs[prec]['value']:.3e} interactions/s", file=sys.stderr, flush=True)
 
     main_leg = legs[args.precision]
-    far = None if args.no_far else far_leg(radio, wl, chunk_dev, args.precision, args.steps,
-                                           args.warmup)
+    opts = None if args.no_options else options_leg(radio, wl, chunk_dev, args.precision, 1, 1)
     del chunk_dev
     batch = None if args.no_batch else batch_leg(radio, W, args.precision, args.steps, args.warmup)
     out = {
@@ -409,8 +413,8 @@ def main():
         out["mixed_vs_fp64_speedup"] = legs["fp64"]["ms_per_step"] / main_leg["ms_per_step"]
     if "mixed_twosum" in legs and args.precision != "mixed_twosum":
         out["mixed_twosum"] = legs["mixed_twosum"]
-    if far is not None:
-        out["far_field"] = far
+    if opts is not None:
+        out["options"] = opts
     if batch is not None:
         out["batch"] = batch
     if not args.no_spectrum:
