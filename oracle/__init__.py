@@ -17,6 +17,8 @@ Functions and the passages they follow:
                            the piecewise-constant field over the slot / dt_det)
   spectrum(...)            Sec. 4: detector fields Fourier transformed in time,
                            d2I/domega dOmega, dI/domega, dI/dOmega
+  boris_push(...)          the particle push that precedes the run-time deposit
+                           (Sec. 3.1): Boris method in external fields
 """
 from __future__ import annotations
 
@@ -199,3 +201,50 @@ def spectrum(E, dt_det: float, cells, n_fft: Optional[int] = None, weights=None,
     dIdw = w @ d2I
     dIdO = c * R2 / (4.0 * np.pi) * (E * E).sum(axis=(1, 2)) * dt_det
     return omega, d2I, dIdw, dIdO
+
+
+def push_fields(x, t, fields):
+    """External fields at positions x (3, Np) and time t: uniform E and B plus a
+    plane wave E = a pol cos(omega (t - k.x) + phase), B = k x E."""
+    E = np.repeat(np.asarray(fields.get("E", (0, 0, 0)), dtype=np.float64)[:, None], x.shape[1], 1)
+    B = np.repeat(np.asarray(fields.get("B", (0, 0, 0)), dtype=np.float64)[:, None], x.shape[1], 1)
+    a = float(fields.get("wave_amplitude", 0.0))
+    if a != 0.0:
+        k = np.asarray(fields["wave_dir"], dtype=np.float64)
+        pol = np.asarray(fields["wave_pol"], dtype=np.float64)
+        ph = fields.get("wave_omega", 1.0) * (t - k @ x) + fields.get("wave_phase", 0.0)
+        Ew = a * pol[:, None] * np.cos(ph)[None, :]
+        E = E + Ew
+        B = B + np.cross(k[:, None], Ew, axis=0)
+    return E, B
+
+
+def boris_push(x0, u0, qm: float, dt: float, n_steps: int, fields: dict, t_first: float = 0.0,
+               first_step: int = 0) -> Tuple[np.ndarray, np.ndarray]:
+    """States 0..n_steps of particles pushed by the Boris method (Boris 1970) in
+    the external fields of push_fields, c = 1, u = gamma beta.  One step: half
+    drift, the Boris kick with the fields at the half step (half electric kick,
+    magnetic rotation, half electric kick), half drift, so that x and u are
+    samples at the same times t_first + (first_step + s) dt (the run-time mode's
+    push, Sec. 3.1).  Returns x, u of shape (3, n_steps + 1, Np)."""
+    x = np.empty((3, n_steps + 1, np.shape(x0)[1]))
+    u = np.empty_like(x)
+    x[:, 0] = x0
+    u[:, 0] = u0
+    h = 0.5 * qm * dt
+    for s in range(n_steps):
+        xs, us = x[:, s], u[:, s]
+        g = np.sqrt(1.0 + (us * us).sum(axis=0))
+        xh = xs + 0.5 * dt * us / g
+        th = t_first + (first_step + s + 0.5) * dt
+        E, B = push_fields(xh, th, fields)
+        um = us + h * E
+        gm = np.sqrt(1.0 + (um * um).sum(axis=0))
+        tv = h * B / gm
+        up = um + np.cross(um, tv, axis=0)
+        sv = 2.0 * tv / (1.0 + (tv * tv).sum(axis=0))
+        un = um + np.cross(up, sv, axis=0) + h * E
+        gn = np.sqrt(1.0 + (un * un).sum(axis=0))
+        u[:, s + 1] = un
+        x[:, s + 1] = xh + 0.5 * dt * un / gn
+    return x, u
