@@ -216,6 +216,39 @@ RADIO_API int radio_detector_shape(const radio_detector* det, int64_t* n_cells, 
 RADIO_API int radio_detector_cells(const radio_detector* det, double* out);
 
 /*
+ * External fields of the run-time push: uniform E and B plus an optional plane
+ * wave E_w = wave_amplitude * wave_pol * cos(wave_omega (t - wave_dir . x) +
+ * wave_phase), B_w = wave_dir x E_w (c = 1; wave_dir and wave_pol unit and
+ * perpendicular).
+ */
+typedef struct radio_push_desc {
+    double qm;              /* charge-to-mass ratio in the units of E and B (-1: electrons) */
+    double dt;              /* time step, > 0 */
+    double E[3];
+    double B[3];
+    double wave_amplitude;  /* 0: no wave */
+    double wave_dir[3];
+    double wave_pol[3];
+    double wave_omega;
+    double wave_phase;
+} radio_push_desc;
+
+/*
+ * The particle push of the run-time mode (Sec. 3.1: the deposit is a sub-step
+ * right after each push, reading the new and the stored states).  Boris method
+ * with x and u kept as samples at the same times: half drift, Boris kick with
+ * the fields at the half step, half drift.  x and u are DEVICE arrays
+ * [3][n_steps+1][n_particles] (the chunk layout of radio_chunk); state 0 is
+ * read, states 1..n_steps are written.  State s is at t_first +
+ * (first_step + s) dt, so the arrays then form a chunk that
+ * radio_deposit_trajectory_chunk (or radio_deposit_batch) takes as it is, with
+ * no copy through the host.  Asynchronous on `stream`.  RADIO_EINVAL for a
+ * NULL or invalid argument.
+ */
+RADIO_API int radio_push(const radio_push_desc* d, int64_t n_particles, int64_t n_steps,
+                         double t_first, int64_t first_step, double* x, double* u, void* stream);
+
+/*
  * Spectral post-processing (Sec. 4: the detector data Fourier transformed with
  * respect to time, the route by which the paper checks its deposit against the
  * spectra of Eq. 7 and Eq. 8).  A slot holds the field averaged over the slot,

@@ -30,7 +30,7 @@ EXPORTS = (
     "radio_deposit_trajectory_chunk", "radio_deposit_batch", "radio_read_detector",
     "radio_detector_stats", "radio_detector_shape", "radio_detector_cells",
     "radio_arrival_times", "radio_status_string", "radio_set_tuning", "radio_get_tuning",
-    "radio_spectrum",
+    "radio_spectrum", "radio_push",
 )
 
 
@@ -59,6 +59,16 @@ class _Chunk(ctypes.Structure):
         ("n_particles", ctypes.c_int64), ("n_steps", ctypes.c_int64),
         ("t_first", ctypes.c_double), ("dt", ctypes.c_double), ("first_step", ctypes.c_int64),
         ("x", ctypes.c_void_p), ("u", ctypes.c_void_p), ("q", ctypes.c_void_p),
+    ]
+
+
+class _Push(ctypes.Structure):
+    _fields_ = [
+        ("qm", ctypes.c_double), ("dt", ctypes.c_double),
+        ("E", ctypes.c_double * 3), ("B", ctypes.c_double * 3),
+        ("wave_amplitude", ctypes.c_double), ("wave_dir", ctypes.c_double * 3),
+        ("wave_pol", ctypes.c_double * 3), ("wave_omega", ctypes.c_double),
+        ("wave_phase", ctypes.c_double),
     ]
 
 
@@ -100,6 +110,8 @@ def _lib():
         lib.radio_detector_cells.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         lib.radio_arrival_times.argtypes = [vp, vp, vp, i64, ctypes.c_double, vp, vp]
         lib.radio_spectrum.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double), vp, vp, vp, vp]
+        lib.radio_push.argtypes = [ctypes.POINTER(_Push), i64, i64, ctypes.c_double, i64, vp, vp,
+                                   vp]
         lib.radio_set_tuning.argtypes = [ctypes.POINTER(_Tuning)]
         lib.radio_get_tuning.argtypes = [ctypes.POINTER(_Tuning)]
         for name in EXPORTS:
@@ -368,6 +380,25 @@ def set_tuning(target_blocks: Optional[int] = None, items_per_workgroup: Optiona
                 int(items_per_workgroup if items_per_workgroup is not None
                     else cur["items_per_workgroup"]))
     _check(_lib().radio_set_tuning(ctypes.byref(t)), "radio_set_tuning")
+
+
+def push(chunk: "Chunk", qm: float = -1.0, E=(0.0, 0.0, 0.0), B=(0.0, 0.0, 0.0),
+         wave_amplitude: float = 0.0, wave_dir=(1.0, 0.0, 0.0), wave_pol=(0.0, 1.0, 0.0),
+         wave_omega: float = 1.0, wave_phase: float = 0.0, stream=None) -> "Chunk":
+    """Fill states 1..S of a device chunk from its state 0 with the run-time push
+    (radio_push), at the chunk's own dt, t_first and first_step; returns the chunk."""
+    d = _Push()
+    d.qm, d.dt = float(qm), float(chunk.dt)
+    d.E[:] = [float(v) for v in E]
+    d.B[:] = [float(v) for v in B]
+    d.wave_amplitude = float(wave_amplitude)
+    d.wave_dir[:] = [float(v) for v in wave_dir]
+    d.wave_pol[:] = [float(v) for v in wave_pol]
+    d.wave_omega, d.wave_phase = float(wave_omega), float(wave_phase)
+    _check(_lib().radio_push(ctypes.byref(d), chunk.n_particles, chunk.n_steps, chunk.t_first,
+                             chunk.first_step, chunk.x.data_ptr(), chunk.u.data_ptr(),
+                             _stream(stream)), "radio_push")
+    return chunk
 
 
 def arrival_times(cells, points, t, c: float = 1.0, stream=None):

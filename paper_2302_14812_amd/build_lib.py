@@ -23,7 +23,7 @@ COMMON = [
     "-Wall", "-Wno-unused-result",
 ]
 
-SOURCES = ["radio_kernels.hip", "radio_spectrum.hip", "radio_runtime.cpp"]
+SOURCES = ["radio_kernels.hip", "radio_spectrum.hip", "radio_push.hip", "radio_runtime.cpp"]
 
 
 def build(verbose: bool = False) -> str:

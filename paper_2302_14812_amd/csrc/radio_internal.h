@@ -137,6 +137,16 @@ hipError_t launch_spectrum_group(const double* acc, bool pairs, int64_t n_t, int
 hipError_t launch_spectrum_parseval(const double* acc, bool pairs, int64_t n_c, int64_t n_t,
                                     const double* cells, const int64_t* user_index, double dt,
                                     double c, double* dIdO, hipStream_t s);
+// the run-time push (radio_push.hip)
+struct PushParams {
+    double qm, dt;
+    double E[3], B[3];
+    double wave_amplitude;
+    double wave_dir[3], wave_pol[3];
+    double wave_omega, wave_phase;
+};
+hipError_t launch_push(const PushParams& P, int64_t n_p, int64_t n_s, double t_first,
+                       int64_t first_step, double* x, double* u, hipStream_t s);
 hipError_t launch_arrival(const double* cells, const double* pts, const double* t, int64_t n,
                           double inv_c, double* out, hipStream_t s);
 

@@ -817,6 +817,40 @@ int radio_arrival_times(const double* cells, const double* points, const double*
     return RADIO_OK;
 }
 
+int radio_push(const radio_push_desc* d, int64_t n_particles, int64_t n_steps, double t_first,
+               int64_t first_step, double* x, double* u, void* stream)
+{
+    if (!d || n_particles < 0 || n_steps < 0 || first_step < 0 || !std::isfinite(t_first) ||
+        !std::isfinite(d->qm) || !std::isfinite(d->dt) || !(d->dt > 0.0) ||
+        !std::isfinite(d->wave_amplitude) || !std::isfinite(d->wave_omega) ||
+        !std::isfinite(d->wave_phase))
+        return RADIO_EINVAL;
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(d->E[k]) || !std::isfinite(d->B[k]) || !std::isfinite(d->wave_dir[k]) ||
+            !std::isfinite(d->wave_pol[k]))
+            return RADIO_EINVAL;
+    if (n_particles == 0 || n_steps == 0)
+        return RADIO_OK;
+    if (!x || !u || n_particles > INT32_MAX || n_steps > INT32_MAX - 1)
+        return RADIO_EINVAL;
+    radio::PushParams P;
+    P.qm = d->qm;
+    P.dt = d->dt;
+    for (int k = 0; k < 3; ++k) {
+        P.E[k] = d->E[k];
+        P.B[k] = d->B[k];
+        P.wave_dir[k] = d->wave_dir[k];
+        P.wave_pol[k] = d->wave_pol[k];
+    }
+    P.wave_amplitude = d->wave_amplitude;
+    P.wave_omega = d->wave_omega;
+    P.wave_phase = d->wave_phase;
+    if (radio::launch_push(P, n_particles, n_steps, t_first, first_step, x, u,
+                           (hipStream_t)stream) != hipSuccess)
+        return RADIO_EDEVICE;
+    return RADIO_OK;
+}
+
 int radio_spectrum(const radio_detector* det, int64_t n_fft, const double* weights, double* d2I,
                    double* dIdw, double* dIdO, void* stream)
 {

@@ -39,7 +39,7 @@ def _struct_fields(name):
     return names
 
 
-@pytest.mark.parametrize("cname,pyname", [("radio_chunk", "_Chunk"), ("radio_detector_desc", "_Desc"),
+@pytest.mark.parametrize("cname,pyname", [("radio_chunk", "_Chunk"), ("radio_detector_desc", "_Desc"), ("radio_push_desc", "_Push"),
                                           ("radio_stats", "_Stats"), ("radio_tuning", "_Tuning")])
 def test_binding_structs_follow_the_header(cname, pyname):
     import paper_2302_14812_amd as radio

@@ -1,0 +1,105 @@
+"""The run-time mode on the device: the Boris push (radio_push) against the
+oracle's pusher, and push-deposit blocks against one push and one deposit of
+the whole run, and against the oracle's deposit of the same trajectory."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_14812_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+WAVE = {"wave_amplitude": 1.5, "wave_dir": [1.0, 0.0, 0.0], "wave_pol": [0.0, 1.0, 0.0],
+        "wave_omega": 1.0, "wave_phase": 0.3}
+
+
+@pytest.fixture(scope="module")
+def radio():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2302_14812_amd as radio
+    radio._lib()
+    return radio
+
+
+def rel_l2(a, b):
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b)) / (nb if nb > 0 else 1.0)
+
+
+def _initial(n_p, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x0 = rng.normal(0.0, 0.5, size=(3, n_p))
+    u0 = rng.normal(0.0, 0.2, size=(3, n_p))
+    return x0, u0
+
+
+@pytest.mark.parametrize("fields", [
+    dict(WAVE),
+    {"E": [0.02, -0.01, 0.05], "B": [0.0, 0.3, 0.1]},
+    dict(WAVE, E=[0.0, 0.0, 0.01], B=[0.05, 0.0, 0.0]),
+])
+def test_push_matches_oracle(radio, fields):
+    import torch
+    x0, u0 = _initial(200, 7)
+    n_s, dt = 400, 0.05
+    x = torch.zeros((3, n_s + 1, 200), dtype=torch.float64, device="cuda")
+    u = torch.zeros_like(x)
+    x[:, 0] = torch.from_numpy(x0).cuda()
+    u[:, 0] = torch.from_numpy(u0).cuda()
+    ch = radio.Chunk(x, u, None, 0.1, dt, 3)
+    radio.push(ch, qm=-1.0, **fields)
+    xo, uo = oracle.boris_push(x0, u0, -1.0, dt, n_s, fields, t_first=0.1, first_step=3)
+    ex, eu = rel_l2(x.cpu().numpy(), xo), rel_l2(u.cpu().numpy(), uo)
+    print(f"[push] {sorted(fields)}: relL2 x {ex:.2e} u {eu:.2e}", flush=True)
+    assert max(ex, eu) <= 1e-12
+
+
+def test_runtime_blocks_equal_one_shot_and_oracle(radio):
+    import torch
+    from paper_2302_14812_amd.runtime import RunTimeDiagnostic
+    n_p, block, n_blocks, dt = 64, 16, 12, 0.05
+    x0, u0 = _initial(n_p, 11)
+    # the forward (Thomson) direction of the wave, at 200
+    cells = W.sphere_cap_cells(200.0, [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], 6, 5, 0.3, 0.2)
+    n_s = block * n_blocks
+    xo, uo = oracle.boris_push(x0, u0, -1.0, dt, n_s, WAVE)
+    ref_chunk = W.Chunk(x=xo, u=uo, q=np.full(n_p, -1.0), t_first=0.0, dt=dt)
+    t0, dtd = W.arrival_window(cells, ref_chunk, 400, pad_frac=0.05)
+    spec = W.DetectorSpec(cells=cells, t0=t0, dt_det=dtd, n_t=400)
+    dets = [radio.Detector.from_spec(spec, precision=p) for p in ("fp64", "mixed")]
+    rt = RunTimeDiagnostic(dets, x0, u0, None, dt=dt, block_steps=block, fields=dict(WAVE, qm=-1.0))
+    rt.advance(n_blocks)
+    assert rt.step == n_s
+    # one push of the whole run, one deposit
+    x = torch.zeros((3, n_s + 1, n_p), dtype=torch.float64, device="cuda")
+    u = torch.zeros_like(x)
+    x[:, 0] = torch.from_numpy(x0).cuda()
+    u[:, 0] = torch.from_numpy(u0).cuda()
+    whole = radio.push(radio.Chunk(x, u, None, 0.0, dt), qm=-1.0, **WAVE)
+    xe, ue = rt.state()
+    np.testing.assert_array_equal(xe.cpu().numpy(), x[:, -1].cpu().numpy())
+    np.testing.assert_array_equal(ue.cpu().numpy(), u[:, -1].cpu().numpy())
+    one = radio.Detector.from_spec(spec, precision="fp64")
+    one.deposit(whole)
+    E1, B1 = one.read()
+    Eb, Bb = dets[0].read()
+    torch.cuda.synchronize()
+    e = max(rel_l2(Eb.cpu().numpy(), E1.cpu().numpy()), rel_l2(Bb.cpu().numpy(), B1.cpu().numpy()))
+    print(f"[runtime] blocks vs one shot relL2 {e:.2e}", flush=True)
+    assert e <= 1e-13
+    # the oracle's deposit of the device's own trajectory
+    dev_chunk = W.Chunk(x=x.cpu().numpy(), u=u.cpu().numpy(), q=np.full(n_p, -1.0), t_first=0.0,
+                        dt=dt)
+    Eo, Bo = oracle.read(oracle.deposit_workload(spec, dev_chunk))
+    for d, tol in zip(dets, (1e-12, 1e-5)):
+        Ed, Bd = d.read()
+        torch.cuda.synchronize()
+        e = max(rel_l2(Ed.cpu().numpy(), Eo), rel_l2(Bd.cpu().numpy(), Bo))
+        print(f"[runtime] {d.precision} vs oracle relL2 {e:.2e}", flush=True)
+        assert np.abs(Eo).max() > 0 and e <= tol
+    for d in dets + [one]:
+        d.close()
