@@ -39,6 +39,7 @@ FAR_FIELD = 1      # Eq. 3 arrival time and the cell's direction and distance in
 ACCEL_ONLY = 2     # only the acceleration term of Eq. 1
 HOLD_PREVIOUS = 4  # segment s holds the field of state s-1 (Fig. 5 walk-through)
 HOLD_LINEAR = 8    # the field varies linearly in arrival time between the two states
+POTENTIALS = 16    # Lienard-Wiechert potentials (A, phi) instead of (E, B)
 
 
 def build(force: bool = True) -> str:

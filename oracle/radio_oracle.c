@@ -66,6 +66,11 @@
  *       then takes the centred difference betadot_s = (beta_{s+1} -
  *       beta_{s-1}) / (2 dt), one-sided at the chunk's first and last state,
  *       so that both ends of a segment are evaluated at their own times.
+ *   POTENTIALS (16): the Lienard-Wiechert potentials instead of the fields
+ *       (the extension named in Sec. 6): phi = q / (kappa R) and
+ *       A = q beta / (kappa R) at the same retarded state (Gaussian units,
+ *       c = 1 in A's normalisation as in Eq. 1); the six accumulators hold
+ *       (A_x, A_y, A_z, phi, 0, 0).  Excludes ACCEL_ONLY.
  *   With HOLD_PREVIOUS, the field of a chunk's first state takes
  *   betadot_0 = (beta_1 - beta_0) / dt, the only difference the chunk holds;
  *   every other state keeps the backward difference.
@@ -87,6 +92,7 @@
 #define ORACLE_ACCEL_ONLY 2
 #define ORACLE_HOLD_PREVIOUS 4
 #define ORACLE_HOLD_LINEAR 8
+#define ORACLE_POTENTIALS 16
 
 /* beta and 1/gamma^2 from the momentum u = gamma beta (Alg. 1). */
 EXPORT void radio_oracle_kinematics(const double u[3], double beta[3], double* inv_gamma2)
@@ -179,6 +185,17 @@ EXPORT void radio_oracle_field_opts(const double x_cell[3], const double x_part[
         n[0] = d[0] * rinv;
         n[1] = d[1] * rinv;
         n[2] = d[2] * rinv;
+    }
+    if (options & ORACLE_POTENTIALS) {
+        double w[3] = {n[0] - beta[0], n[1] - beta[1], n[2] - beta[2]};
+        double kappa = 0.5 * (((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]) + inv_gamma2);
+        double phi = q / (kappa * R);
+        for (int k = 0; k < 3; ++k)
+            E[k] = phi * beta[k];
+        B[0] = phi;
+        B[1] = 0.0;
+        B[2] = 0.0;
+        return;
     }
     lw_field(n, R, R2, beta, inv_gamma2, betadot, q, c, (options & ORACLE_ACCEL_ONLY) != 0, E,
              B);

@@ -795,3 +795,40 @@ def test_hold_rule_convergence_orders(oracle_mod, geometry):
         assert np.all(errs["A"] < errs["B"] / 50)
     else:
         assert abs(orders["A"] - 1.0) < 0.1
+
+
+# ---------------------------------------------------------------- potentials
+
+def test_potentials_of_a_static_charge_are_coulomb(oracle_mod):
+    q = -2.5
+    xc = np.array([7.0, -3.0, 12.0])
+    xp = np.array([1.0, 1.0, -1.0])
+    A, P = oracle_mod.field(xc, xp, [0.0, 0.0, 0.0], 1.0, [0.0, 0.0, 0.0], q=q,
+                            options=oracle_mod.POTENTIALS)
+    np.testing.assert_allclose(P, [q / np.linalg.norm(xc - xp), 0.0, 0.0], rtol=1e-14)
+    assert np.abs(A).max() == 0.0
+
+
+def test_potentials_of_uniform_motion_present_position_form(oracle_mod):
+    """Uniform motion (Griffiths 10.3.2): phi = q / (R_p sqrt(1 - beta^2 sin^2 theta)),
+    R_p from the charge's present position, theta between R_p and the velocity;
+    A = beta phi."""
+    q = 1.0
+    beta = np.array([0.6, 0.0, 0.3])
+    g2 = 1.0 - beta @ beta
+    rng = np.random.Generator(np.random.PCG64(17))
+    for _ in range(10):
+        xc = rng.normal(size=3) * 20
+        t_obs = 5.0
+        # retarded time of a charge at beta * t: |xc - beta t_r| = t_obs - t_r
+        tr = t_obs - 30.0
+        for _ in range(200):
+            tr = t_obs - np.linalg.norm(xc - beta * tr)
+        xr = beta * tr
+        A, P = oracle_mod.field(xc, xr, beta, g2, [0.0, 0.0, 0.0], q=q,
+                                options=oracle_mod.POTENTIALS)
+        Rp = xc - beta * t_obs
+        sin2 = 1 - (Rp @ beta) ** 2 / ((Rp @ Rp) * (beta @ beta))
+        phi = q / (np.linalg.norm(Rp) * np.sqrt(1 - (beta @ beta) * sin2))
+        assert P[0] == pytest.approx(phi, rel=1e-12)
+        np.testing.assert_allclose(A, beta * phi, rtol=1e-12)
