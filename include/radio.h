@@ -76,6 +76,11 @@ extern "C" {
                                  E_s, each with betadot centred at its state (one-sided at
                                  the chunk's ends): the higher-order interpolation named as
                                  an extension in Sec. 6.  Excludes RADIO_HOLD_PREVIOUS */
+#define RADIO_POTENTIALS 16   /* the Lienard-Wiechert potentials phi = q/(kappa R) and
+                                 A = q beta/(kappa R) instead of the fields (the extension
+                                 named in Sec. 6), deposited with the same hold rule and
+                                 weights; radio_read_detector then returns A in E's place
+                                 and (phi, 0, 0) in B's.  Excludes RADIO_ACCEL_ONLY */
 
 /* detector cell geometry (Sec. 3.1: spherical grids centred at the origin and
    cartesian planes) */

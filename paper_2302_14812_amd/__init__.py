@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libradio.so")
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4
 FP64, MIXED, MIXED_TWOSUM = 0, 1, 2
 GEOM_EXPLICIT, GEOM_PLANE, GEOM_SPHERE = 0, 1, 2
-FAR_FIELD, ACCEL_ONLY, HOLD_PREVIOUS, HOLD_LINEAR = 1, 2, 4, 8  # detector options (bit flags)
+# detector options (bit flags)
+FAR_FIELD, ACCEL_ONLY, HOLD_PREVIOUS, HOLD_LINEAR, POTENTIALS = 1, 2, 4, 8, 16
 _PRECISIONS = {"fp64": FP64, "mixed": MIXED, "mixed_twosum": MIXED_TWOSUM}
 
 # every function the C header declares

@@ -86,6 +86,7 @@ struct DepositJob {
     const double* far;              // far-field detector: [n_c][4] n_cell, R_cell; else nullptr
     double vscale;                  // 1, or 0 for an acceleration-only detector
     int64_t hold;                   // field a segment holds: 0 current, 1 previous, 2 linear
+    int64_t potentials;             // 1: deposit the potentials (A, phi) instead of (E, B)
     int64_t n_c, n_t, n_p, n_s;
     double t_first, dt;             // state s at t_first + (s0 + s)*dt
     int64_t s0;                     // the chunk's first state within its run
@@ -114,11 +115,12 @@ hipError_t launch_kinematics(const DepositJob& job, int mode, hipStream_t s);
 hipError_t launch_order(const DepositJob& job, hipStream_t s);
 hipError_t launch_ring_choice(const DepositJob& job, int mode, hipStream_t s);
 hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s);
-// Persistent kernel variants: v = mode + 3 * (far + 2 * hold).
-constexpr int kKernelVariants = 18;
+// Deposit kernel variants: v = mode + 3 * (G + 4 * hold), G = far + 2 * potentials.
+constexpr int kKernelVariants = 36;
 inline int kernel_variant(int mode, const DepositJob& J)
 {
-    return mode + 3 * ((J.far ? 1 : 0) + 2 * (int)J.hold);
+    const int G = (J.far ? 1 : 0) + (J.potentials ? 2 : 0);
+    return mode + 3 * (G + 4 * (int)J.hold);
 }
 // next: two work counters (small-ring and large-ring workgroups)
 hipError_t launch_deposit_batch(const DepositJob* jobs, const WorkItem* items, int64_t n_items,

@@ -44,6 +44,7 @@
 
 #include <climits>
 #include <type_traits>
+#include <utility>
 
 namespace radio {
 
@@ -670,6 +671,37 @@ __device__ __forceinline__ double field_far_mixed(const double fc[4], double Rin
     return u;
 }
 
+// Lienard-Wiechert potentials phi = q/(kappa R), A = q beta/(kappa R) at a
+// staged state (the potentials option): F = (A_x, A_y, A_z, phi, 0, 0).  FAR:
+// the cell's direction and distance.  (The caller takes the slot coordinate
+// from the same expression its other deposits use.)
+template <bool FAR, typename Rec, typename T>
+__device__ __forceinline__ void potentials_at(const double xc[3], const double fc[4],
+                                              const Rec& st, double q, T F[6])
+{
+    double kap, rinv;
+    if constexpr (FAR) {
+        double w[3];
+        canon_far_w(fc, st.b, w);
+        kap = canon_kappa(w, st.g2i);
+        rinv = 1.0 / fc[3];
+    } else {
+        double d[3] = {xc[0] - st.x[0], xc[1] - st.x[1], xc[2] - st.x[2]};
+        const double R = __builtin_sqrt(canon_norm2(d[0], d[1], d[2]));
+        rinv = 1.0 / R;
+        double n[3], w[3];
+        canon_direction(d, rinv, st.b, n, w);
+        kap = canon_kappa(w, st.g2i);
+    }
+    const double phi = q * rinv / kap;
+    F[0] = T(phi * st.b[0]);
+    F[1] = T(phi * st.b[1]);
+    F[2] = T(phi * st.b[2]);
+    F[3] = T(phi);
+    F[4] = T(0);
+    F[5] = T(0);
+}
+
 __device__ __forceinline__ double slot_coord_fp64(const double xc[3], const double x[3],
                                                   double t_s, const Consts& K)
 {
@@ -962,10 +994,13 @@ struct DepositShared {
 // read their particles' records as LDS broadcasts.
 // HOLD: which field a segment holds (0 the current state's, 1 the previous
 // state's, 2 the linear interpolation between the two)
-template <int M, int R, bool FAR, int HOLD>
+// G: bit 0 the far-field geometry, bit 1 potentials instead of fields
+template <int M, int R, int G, int HOLD>
 __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, int64_t split,
                                              DepositShared<M, R>& sh)
 {
+    constexpr bool FAR = (G & 1) != 0;
+    constexpr bool POT = (G & 2) != 0;
     constexpr bool MIX = ModeTypes<M>::MIX;
     using T = typename ModeTypes<M>::T;
     using Acc = typename ModeTypes<M>::Acc;
@@ -1129,7 +1164,10 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
             const double q = sh.sq[g];
             // the field of one staged state and its slot coordinate
             auto field_at = [&](const Rec& st, double t_s, T F[6]) {
-                if constexpr (FAR) {
+                if constexpr (POT) {
+                    potentials_at<FAR>(xc, fc, st, q, F);
+                    return slot_of(st, t_s);
+                } else if constexpr (FAR) {
                     if constexpr (MIX)
                         return field_far_mixed(fc, Rinv, st, t_s, (float)q, K, F);
                     else
@@ -1193,7 +1231,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
 
 // One workgroup per work item of a single deposit; the tiles that take the
 // other ring size leave at once.
-template <int M, int R, bool FAR, int HOLD>
+template <int M, int R, int G, int HOLD>
 __global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
 {
     __shared__ __align__(16) DepositShared<M, R> sh;
@@ -1207,7 +1245,7 @@ __global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
     const int64_t tile = logical % J.n_tiles;
     if (gptr(J.ring_sel)[tile] != (R == kRingLarge ? 1 : 0))
         return;
-    deposit_item<M, R, FAR, HOLD>(J, tile, logical / J.n_tiles, sh);
+    deposit_item<M, R, G, HOLD>(J, tile, logical / J.n_tiles, sh);
 }
 
 // Persistent workgroups for many independent deposits: each takes the next work
@@ -1215,7 +1253,7 @@ __global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
 // the list is exhausted, so uneven jobs share one launch without a tail of idle
 // workgroups; items whose tile takes the other ring size are skipped.  Every
 // workgroup leaves once the counter passes n_items.
-template <int M, int R, bool FAR, int HOLD>
+template <int M, int R, int G, int HOLD>
 __global__ __launch_bounds__(kDepositThreads) void deposit_persistent_kernel(
     const DepositJob* __restrict__ jobs, const WorkItem* __restrict__ items, int64_t n_items,
     unsigned long long* __restrict__ next)
@@ -1234,7 +1272,7 @@ __global__ __launch_bounds__(kDepositThreads) void deposit_persistent_kernel(
         const DepositJob J = jobs[w.job];
         if (gptr(J.ring_sel)[w.tile] != (R == kRingLarge ? 1 : 0))
             continue;
-        deposit_item<M, R, FAR, HOLD>(J, w.tile, w.split, sh);
+        deposit_item<M, R, G, HOLD>(J, w.tile, w.split, sh);
     }
 }
 
@@ -1374,37 +1412,65 @@ hipError_t launch_ring_choice(const DepositJob& job, int mode, hipStream_t s)
     return hipGetLastError();
 }
 
-// kernel variants: precision mode x ring size x far field x hold rule
-template <int M, bool FAR, int HOLD>
+// kernel variants: precision mode x ring size x geometry/quantity (far field,
+// potentials) x hold rule
+template <int M, int G, int HOLD>
 static void launch_deposit_v(const DepositJob& job, dim3 grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((deposit_kernel<M, kRingSmall, FAR, HOLD>), grid, dim3(kDepositThreads), 0,
+    hipLaunchKernelGGL((deposit_kernel<M, kRingSmall, G, HOLD>), grid, dim3(kDepositThreads), 0,
                        s, job);
-    hipLaunchKernelGGL((deposit_kernel<M, kRingLarge, FAR, HOLD>), grid, dim3(kDepositThreads), 0,
+    hipLaunchKernelGGL((deposit_kernel<M, kRingLarge, G, HOLD>), grid, dim3(kDepositThreads), 0,
                        s, job);
 }
 
-template <int M, bool FAR>
-static void launch_deposit_hold(const DepositJob& job, dim3 grid, hipStream_t s)
+template <int V>
+static void launch_deposit_index(const DepositJob& job, dim3 grid, hipStream_t s)
 {
-    if (job.hold == 1)
-        launch_deposit_v<M, FAR, 1>(job, grid, s);
-    else if (job.hold == 2)
-        launch_deposit_v<M, FAR, 2>(job, grid, s);
-    else
-        launch_deposit_v<M, FAR, 0>(job, grid, s);
+    launch_deposit_v<V % 3, (V / 3) % 4, V / 12>(job, grid, s);
 }
 
-template <bool FAR>
-static void launch_deposit_far(const DepositJob& job, int mode, dim3 grid, hipStream_t s)
+template <int V>
+static void launch_persistent_index(const DepositJob* jobs, const WorkItem* items,
+                                    int64_t n_items, unsigned long long* next, int blocks_small,
+                                    int blocks_large, hipStream_t s)
 {
-    if (mode == kModeMix)
-        launch_deposit_hold<kModeMix, FAR>(job, grid, s);
-    else if (mode == kModeMixTwoSum)
-        launch_deposit_hold<kModeMixTwoSum, FAR>(job, grid, s);
-    else
-        launch_deposit_hold<kModeF64, FAR>(job, grid, s);
+    constexpr int M = V % 3, G = (V / 3) % 4, HOLD = V / 12;
+    hipLaunchKernelGGL((deposit_persistent_kernel<M, kRingSmall, G, HOLD>),
+                       dim3((unsigned)blocks_small), dim3(kDepositThreads), 0, s, jobs, items,
+                       n_items, next);
+    hipLaunchKernelGGL((deposit_persistent_kernel<M, kRingLarge, G, HOLD>),
+                       dim3((unsigned)blocks_large), dim3(kDepositThreads), 0, s, jobs, items,
+                       n_items, next + 1);
 }
+
+template <int V>
+static int blocks_per_cu_index(bool large_ring)
+{
+    int n = 0;
+    constexpr int M = V % 3, G = (V / 3) % 4, HOLD = V / 12;
+    const void* f =
+        large_ring ? reinterpret_cast<const void*>(deposit_persistent_kernel<M, kRingLarge, G, HOLD>)
+                   : reinterpret_cast<const void*>(deposit_persistent_kernel<M, kRingSmall, G, HOLD>);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kDepositThreads, 0);
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+template <int... V>
+struct VariantTable {
+    using Single = void (*)(const DepositJob&, dim3, hipStream_t);
+    using Launch = void (*)(const DepositJob*, const WorkItem*, int64_t, unsigned long long*,
+                            int, int, hipStream_t);
+    using Occ = int (*)(bool);
+    static constexpr Single single[] = {&launch_deposit_index<V>...};
+    static constexpr Launch launch[] = {&launch_persistent_index<V>...};
+    static constexpr Occ occupancy[] = {&blocks_per_cu_index<V>...};
+};
+template <int... V>
+constexpr VariantTable<V...> make_table(std::integer_sequence<int, V...>)
+{
+    return {};
+}
+using Variants = decltype(make_table(std::make_integer_sequence<int, kKernelVariants>{}));
 
 hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s)
 {
@@ -1412,63 +1478,12 @@ hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s)
     if (blocks <= 0)
         return hipSuccess;
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;  // a multiple of the XCD count
-    const dim3 grid((unsigned)blocks);
-    if (job.far)
-        launch_deposit_far<true>(job, mode, grid, s);
-    else
-        launch_deposit_far<false>(job, mode, grid, s);
+    const int v = kernel_variant(mode, job);
+    if (v < 0 || v >= kKernelVariants)
+        return hipErrorInvalidValue;
+    Variants::single[v](job, dim3((unsigned)blocks), s);
     return hipGetLastError();
 }
-
-template <int M, bool FAR, int HOLD>
-static void launch_persistent_v(const DepositJob* jobs, const WorkItem* items, int64_t n_items,
-                                unsigned long long* next, int blocks_small, int blocks_large,
-                                hipStream_t s)
-{
-    hipLaunchKernelGGL((deposit_persistent_kernel<M, kRingSmall, FAR, HOLD>),
-                       dim3((unsigned)blocks_small), dim3(kDepositThreads), 0, s, jobs, items,
-                       n_items, next);
-    hipLaunchKernelGGL((deposit_persistent_kernel<M, kRingLarge, FAR, HOLD>),
-                       dim3((unsigned)blocks_large), dim3(kDepositThreads), 0, s, jobs, items,
-                       n_items, next + 1);
-}
-
-// the variant index v = mode + 3 * (far + 2 * hold), v < kKernelVariants
-template <int V>
-static void launch_persistent_index(const DepositJob* jobs, const WorkItem* items,
-                                    int64_t n_items, unsigned long long* next, int blocks_small,
-                                    int blocks_large, hipStream_t s)
-{
-    launch_persistent_v<V % 3, (V / 3) % 2 == 1, V / 6>(jobs, items, n_items, next, blocks_small,
-                                                        blocks_large, s);
-}
-
-template <int V>
-static int blocks_per_cu_index(bool large_ring)
-{
-    int n = 0;
-    constexpr int M = V % 3;
-    constexpr bool FAR = (V / 3) % 2 == 1;
-    constexpr int HOLD = V / 6;
-    const void* f =
-        large_ring
-            ? reinterpret_cast<const void*>(deposit_persistent_kernel<M, kRingLarge, FAR, HOLD>)
-            : reinterpret_cast<const void*>(deposit_persistent_kernel<M, kRingSmall, FAR, HOLD>);
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kDepositThreads, 0);
-    return (e == hipSuccess && n > 0) ? n : 1;
-}
-
-template <int... V>
-struct VariantTable {
-    using Launch = void (*)(const DepositJob*, const WorkItem*, int64_t, unsigned long long*,
-                            int, int, hipStream_t);
-    using Occ = int (*)(bool);
-    static constexpr Launch launch[] = {&launch_persistent_index<V>...};
-    static constexpr Occ occupancy[] = {&blocks_per_cu_index<V>...};
-};
-using Variants = VariantTable<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17>;
-static_assert(sizeof(Variants::launch) / sizeof(Variants::launch[0]) == kKernelVariants,
-              "one entry per kernel variant");
 
 hipError_t launch_deposit_batch(const DepositJob* jobs, const WorkItem* items, int64_t n_items,
                                 unsigned long long* next, int variant, int blocks_small,

@@ -295,6 +295,7 @@ radio::DepositJob make_job(radio_detector* det, const radio_chunk* k)
     J.far = det->d_far;
     J.vscale = (det->options & RADIO_ACCEL_ONLY) ? 0.0 : 1.0;
     J.hold = (det->options & RADIO_HOLD_LINEAR) ? 2 : ((det->options & RADIO_HOLD_PREVIOUS) ? 1 : 0);
+    J.potentials = (det->options & RADIO_POTENTIALS) ? 1 : 0;
     J.dt = k->dt;
     J.t0 = det->t0;
     J.inv_dt_det = 1.0 / det->dt_det;
@@ -559,9 +560,10 @@ int radio_detector_create(const radio_detector_desc* desc, void* stream, radio_d
         return RADIO_EINVAL;
     if (!std::isfinite(desc->c) || !(desc->c > 0.0))
         return RADIO_EINVAL;
-    if ((desc->options &
-         ~(RADIO_FAR_FIELD | RADIO_ACCEL_ONLY | RADIO_HOLD_PREVIOUS | RADIO_HOLD_LINEAR)) != 0 ||
-        ((desc->options & RADIO_HOLD_PREVIOUS) && (desc->options & RADIO_HOLD_LINEAR)))
+    if ((desc->options & ~(RADIO_FAR_FIELD | RADIO_ACCEL_ONLY | RADIO_HOLD_PREVIOUS |
+                           RADIO_HOLD_LINEAR | RADIO_POTENTIALS)) != 0 ||
+        ((desc->options & RADIO_HOLD_PREVIOUS) && (desc->options & RADIO_HOLD_LINEAR)) ||
+        ((desc->options & RADIO_POTENTIALS) && (desc->options & RADIO_ACCEL_ONLY)))
         return RADIO_EINVAL;
     std::vector<double> cells;
     int rc = build_cells(*desc, cells);

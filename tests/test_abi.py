@@ -89,9 +89,11 @@ def test_invalid_arguments_rejected_before_any_device_work():
     d.precision = 7
     assert lib.radio_detector_create(ctypes.byref(d), None, ctypes.byref(h)) == radio.EINVAL
     d.precision = 0
-    d.options = 16  # unknown option bit
-    assert lib.radio_detector_create(ctypes.byref(d), None, ctypes.byref(h)) == radio.EINVAL
     d.options = radio.HOLD_PREVIOUS | radio.HOLD_LINEAR  # two hold rules at once
+    assert lib.radio_detector_create(ctypes.byref(d), None, ctypes.byref(h)) == radio.EINVAL
+    d.options = radio.POTENTIALS | radio.ACCEL_ONLY  # potentials have no acceleration term
+    assert lib.radio_detector_create(ctypes.byref(d), None, ctypes.byref(h)) == radio.EINVAL
+    d.options = 32  # unknown option bit
     assert lib.radio_detector_create(ctypes.byref(d), None, ctypes.byref(h)) == radio.EINVAL
     d.options = radio.FAR_FIELD | radio.ACCEL_ONLY
     d.geometry = 9

@@ -1,6 +1,7 @@
 """Detector options on the device: far-field geometry (Eq. 3), the
-acceleration-only field and the hold rules (previous state's field, linear
-interpolation), each against the oracle with the same options."""
+acceleration-only field, the hold rules (previous state's field, linear
+interpolation) and the potentials, each against the oracle with the same
+options."""
 import dataclasses
 
 import numpy as np
@@ -13,8 +14,8 @@ pytestmark = pytest.mark.gpu
 
 TOLS = {"fp64": 1e-12, "mixed": 1e-5, "mixed_twosum": 1e-5}
 # far field, accel only, both; hold previous (alone, with far field); hold linear (alone,
-# with far field, with accel only)
-OPTIONS = [1, 2, 3, 4, 5, 8, 9, 10]
+# with far field, with accel only); potentials (alone, far field, hold previous, hold linear)
+OPTIONS = [1, 2, 3, 4, 5, 8, 9, 10, 16, 17, 20, 24]
 
 
 @pytest.fixture(scope="module")
