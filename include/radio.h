@@ -112,8 +112,14 @@ typedef struct radio_detector_desc {
     double dt_det;        /* slot width, > 0 */
     int64_t n_t;          /* number of slots, >= 1 */
     double c;             /* speed of light, > 0 (1 in normalised units) */
-    int32_t options;      /* RADIO_FAR_FIELD | RADIO_ACCEL_ONLY | RADIO_HOLD_*, or 0 (Eq. 2,
-                             all of Eq. 1, the current state's field held) */
+    int32_t options;      /* RADIO_FAR_FIELD | RADIO_ACCEL_ONLY | RADIO_HOLD_* |
+                             RADIO_POTENTIALS, or 0 (Eq. 2, all of Eq. 1, the current state's
+                             field held) */
+    int64_t n3;           /* SPHERE: concentric shells (0 or 1: one) of radii radius +
+                             k radius_step, k < n3 (Sec. 3.1: spherical grids of several
+                             radii about the origin); cell index = (k n2 + i2) n1 + i1.
+                             Other geometries: 0 or 1 */
+    double radius_step;   /* SPHERE: radial spacing of the shells */
 } radio_detector_desc;
 
 /*

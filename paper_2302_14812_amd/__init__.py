@@ -52,6 +52,7 @@ class _Desc(ctypes.Structure):
         ("half1", ctypes.c_double), ("half2", ctypes.c_double),
         ("t0", ctypes.c_double), ("dt_det", ctypes.c_double), ("n_t", ctypes.c_int64),
         ("c", ctypes.c_double), ("options", ctypes.c_int32),
+        ("n3", ctypes.c_int64), ("radius_step", ctypes.c_double),
     ]
 
 
@@ -259,10 +260,13 @@ class Detector:
         return cls(_desc=d, **kw)
 
     @classmethod
-    def sphere(cls, radius, axis, e1, n1, n2, half1, half2, **kw) -> "Detector":
+    def sphere(cls, radius, axis, e1, n1, n2, half1, half2, shells: int = 1,
+               radius_step: float = 0.0, **kw) -> "Detector":
+        """Cells on `shells` concentric spherical caps of radii radius + k radius_step."""
         d = _Desc()
         d.geometry = GEOM_SPHERE
         d.radius = float(radius)
+        d.n3, d.radius_step = int(shells), float(radius_step)
         d.axis[:] = [float(v) for v in axis]
         d.e1[:] = [float(v) for v in e1]
         d.n1, d.n2, d.half1, d.half2 = int(n1), int(n2), float(half1), float(half2)

@@ -85,7 +85,12 @@ int build_cells(const radio_detector_desc& d, std::vector<double>& out)
     if (!std::isfinite(d.half1) || !std::isfinite(d.half2) || d.half1 < 0.0 || d.half2 < 0.0)
         return RADIO_EINVAL;
     const int64_t n1 = d.n1, n2 = d.n2;
-    out.resize((size_t)(3 * n1 * n2));
+    const int64_t n3 = d.n3 > 0 ? d.n3 : 1;  // spherical shells
+    if (d.geometry != RADIO_GEOM_SPHERE && n3 != 1)
+        return RADIO_EINVAL;
+    if (n3 > 4096 || n1 * n2 * n3 > (int64_t)1 << 32)
+        return RADIO_EINVAL;
+    out.resize((size_t)(3 * n1 * n2 * n3));
     if (d.geometry == RADIO_GEOM_PLANE) {
         if (!finite3(d.origin) || !finite3(d.e1) || !finite3(d.e2))
             return RADIO_EINVAL;
@@ -106,7 +111,8 @@ int build_cells(const radio_detector_desc& d, std::vector<double>& out)
         return RADIO_OK;
     }
     if (d.geometry == RADIO_GEOM_SPHERE) {
-        if (!finite3(d.axis) || !finite3(d.e1) || !(d.radius > 0.0) || !std::isfinite(d.radius))
+        if (!finite3(d.axis) || !finite3(d.e1) || !(d.radius > 0.0) || !std::isfinite(d.radius) ||
+            !std::isfinite(d.radius_step) || !(d.radius + (double)(n3 - 1) * d.radius_step > 0.0))
             return RADIO_EINVAL;
         const double la = norm3(d.axis);
         if (!(la > 0.0))
@@ -121,14 +127,19 @@ int build_cells(const radio_detector_desc& d, std::vector<double>& out)
             v /= l1;
         const double e2[3] = {ax[1] * e1[2] - ax[2] * e1[1], ax[2] * e1[0] - ax[0] * e1[2],
                               ax[0] * e1[1] - ax[1] * e1[0]};
-        for (int64_t i2 = 0; i2 < n2; ++i2) {
-            const double lat = -d.half2 + ((double)i2 + 0.5) * (2.0 * d.half2 / (double)n2);
-            for (int64_t i1 = 0; i1 < n1; ++i1) {
-                const double lon = -d.half1 + ((double)i1 + 0.5) * (2.0 * d.half1 / (double)n1);
-                double* p = &out[(size_t)(3 * (i2 * n1 + i1))];
-                for (int k = 0; k < 3; ++k)
-                    p[k] = d.radius * (std::cos(lat) * (std::cos(lon) * ax[k] + std::sin(lon) * e1[k]) +
-                                       std::sin(lat) * e2[k]);
+        for (int64_t i3 = 0; i3 < n3; ++i3) {
+            const double radius = d.radius + (double)i3 * d.radius_step;
+            for (int64_t i2 = 0; i2 < n2; ++i2) {
+                const double lat = -d.half2 + ((double)i2 + 0.5) * (2.0 * d.half2 / (double)n2);
+                for (int64_t i1 = 0; i1 < n1; ++i1) {
+                    const double lon =
+                        -d.half1 + ((double)i1 + 0.5) * (2.0 * d.half1 / (double)n1);
+                    double* p = &out[(size_t)(3 * ((i3 * n2 + i2) * n1 + i1))];
+                    for (int k = 0; k < 3; ++k)
+                        p[k] = radius * (std::cos(lat) * (std::cos(lon) * ax[k] +
+                                                          std::sin(lon) * e1[k]) +
+                                         std::sin(lat) * e2[k]);
+                }
             }
         }
         return RADIO_OK;
@@ -141,7 +152,7 @@ int build_cells(const radio_detector_desc& d, std::vector<double>& out)
 // Morton code of each cell's direction projected on the plane normal to the
 // mean direction.  Cells with similar directions see similar arrival-time
 // offsets between particles, which is what the deposit's slot rings rely on.
-std::vector<int64_t> order_cells(const std::vector<double>& cells)
+std::vector<int64_t> order_cells(const std::vector<double>& cells, int64_t per_group)
 {
     const int64_t n = (int64_t)(cells.size() / 3);
     std::vector<double> dir(3 * n, 0.0);
@@ -202,8 +213,12 @@ std::vector<int64_t> order_cells(const std::vector<double>& cells)
     }
     std::vector<int64_t> idx(n);
     std::iota(idx.begin(), idx.end(), (int64_t)0);
-    std::stable_sort(idx.begin(), idx.end(),
-                     [&](int64_t x, int64_t y) { return code[x] < code[y]; });
+    // cells of one group (a spherical shell) stay together: their arrival times differ
+    // from another shell's by the radial distance
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
+        const int64_t gx = x / per_group, gy = y / per_group;
+        return gx != gy ? gx < gy : code[x] < code[y];
+    });
     return idx;
 }
 
@@ -589,7 +604,9 @@ int radio_detector_create(const radio_detector_desc* desc, void* stream, radio_d
     det->c = desc->c;
     det->h_cells.swap(cells);
     hipStream_t s = (hipStream_t)stream;
-    const std::vector<int64_t> user = order_cells(det->h_cells);
+    const int64_t per_shell =
+        (desc->geometry == RADIO_GEOM_SPHERE && desc->n3 > 1) ? n_c / desc->n3 : n_c;
+    const std::vector<int64_t> user = order_cells(det->h_cells, per_shell);
     std::vector<double> internal((size_t)(3 * n_c));
     for (int64_t r = 0; r < n_c; ++r)
         for (int k = 0; k < 3; ++k)

@@ -146,6 +146,13 @@ def sphere_cap_cells(radius: float, axis, e1, n1: int, n2: int,
     return np.ascontiguousarray((radius * d).reshape(n1 * n2, 3))
 
 
+def sphere_shell_cells(radii: Sequence[float], axis, e1, n1: int, n2: int, half1: float,
+                       half2: float) -> np.ndarray:
+    """Concentric caps, one per radius, in the order of the radii."""
+    return np.ascontiguousarray(np.concatenate(
+        [sphere_cap_cells(r, axis, e1, n1, n2, half1, half2) for r in radii]))
+
+
 def arrival_window(cells: np.ndarray, chunk: Chunk, n_t: int, pad_frac: float = 0.02,
                    max_particles: int = 64, cell_index: Optional[Sequence[int]] = None,
                    seed: int = 0, c: float = 1.0) -> Tuple[float, float]:

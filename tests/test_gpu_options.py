@@ -115,3 +115,37 @@ def test_acceleration_only_of_uniform_motion_is_zero(radio):
         torch.cuda.synchronize()
         assert float(E.abs().max()) == 0.0 and float(B.abs().max()) == 0.0
         det.close()
+
+
+def test_concentric_spherical_shells(radio):
+    """A detector of three concentric caps (spherical grids of several radii about the
+    origin): its cells, its deposit against the oracle, and the radiation seen by
+    the outer shell -- the inner shell's, delayed by the radial distance and scaled
+    by the ratio of the radii (the acceleration field falls as 1/R)."""
+    import torch
+    radii = [1000.0, 1250.0, 1500.0]
+    det = radio.Detector.sphere(radii[0], [0.0, 0.0, 1.0], [1.0, 0.0, 0.0], 8, 6, 0.08, 0.05,
+                                shells=3, radius_step=250.0, t0=990.0, dt_det=0.05, n_t=11000,
+                                precision="fp64", options=radio.ACCEL_ONLY)
+    cells = W.sphere_shell_cells(radii, [0.0, 0.0, 1.0], [1.0, 0.0, 0.0], 8, 6, 0.08, 0.05)
+    np.testing.assert_allclose(det.cells(), cells, rtol=1e-13, atol=1e-9)
+    chunk = W.circular_orbit(gamma=3.0, radius=1.0, n_steps=1500, dt=0.02, q=-1.0)
+    det.deposit(radio.Chunk.from_numpy(chunk))
+    E, B = det.read()
+    torch.cuda.synchronize()
+    E = E.cpu().numpy()
+    spec = W.DetectorSpec(cells=cells, t0=990.0, dt_det=0.05, n_t=11000, options=radio.ACCEL_ONLY)
+    idx = [0, 20, 47, 48 + 20, 96 + 20, 143]
+    Eo, Bo = oracle.read(oracle.deposit_workload(spec, chunk, cell_index=idx))
+    e = max(rel_l2(E[idx], Eo), rel_l2(B.cpu().numpy()[idx], Bo))
+    print(f"[shells] device vs oracle relL2 {e:.2e}", flush=True)
+    assert e <= 1e-12
+    # the same direction on the inner and outer shells: 500 / 0.05 = 10000 slots later
+    inner, outer = E[20], E[96 + 20]
+    shift = 10000
+    lhs = outer[shift:shift + 800]
+    rhs = inner[:800] * (radii[0] / radii[2])
+    r = rel_l2(lhs, rhs)
+    print(f"[shells] outer vs delayed, scaled inner relL2 {r:.2e}", flush=True)
+    assert np.abs(inner).max() > 0 and r < 0.02
+    det.close()
