@@ -48,6 +48,8 @@ def parse():
                     help="skip the detector-options leg (far field, hold rules)")
     ap.add_argument("--no-spectrum", action="store_true",
                     help="skip the spectral post-processing leg")
+    ap.add_argument("--no-runtime", action="store_true",
+                    help="skip the run-time (push and deposit) leg")
     ap.add_argument("--serve-chunks", type=int, default=30,
                     help="timed chunks of the streaming leg (after a fifth as many warm-up)")
     ap.add_argument("--serve-load", type=float, default=0.8,
@@ -298,6 +300,62 @@ def spectrum_leg(radio, W, steps):
                                   "algorithmic_bytes": alg_bytes, "pass_bytes": fft_bytes}}
 
 
+def runtime_leg(radio, W, precision):
+    """The run-time mode: 10^4 electrons in a plane wave (a = 1.5, omega = 1, along +x)
+    pushed on the device by radio_push 16 steps at a time (dt = 0.05, 1024 steps) and
+    each block deposited right away into a 128 x 128 cap at 1e4 about +x with 2048
+    slots; nothing leaves device memory."""
+    import numpy as np
+    import torch
+
+    from paper_2302_14812_amd.runtime import RunTimeDiagnostic
+    n_p, block, n_blocks, dt = 10000, 16, 64, 0.05
+    rng = np.random.Generator(np.random.PCG64(W.BASE_SEED + 700))
+    x0 = rng.uniform(-2.0, 2.0, size=(3, n_p))
+    u0 = np.zeros((3, n_p))
+    wave = {"qm": -1.0, "wave_amplitude": 1.5, "wave_dir": [1.0, 0.0, 0.0],
+            "wave_pol": [0.0, 1.0, 0.0], "wave_omega": 1.0, "wave_phase": 0.0}
+    # window from a sample pushed by the oracle-free device pusher itself
+    xs = torch.zeros((3, block * n_blocks + 1, 64), dtype=torch.float64, device="cuda")
+    us = torch.zeros_like(xs)
+    xs[:, 0] = torch.from_numpy(x0[:, :64]).cuda()
+    sample = radio.push(radio.Chunk(xs, us, None, 0.0, dt), **wave)
+    cells = W.sphere_cap_cells(1e4, [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], 128, 128, 0.3, 0.3)
+    host = W.Chunk(x=sample.x.cpu().numpy(), u=sample.u.cpu().numpy(), q=np.full(64, -1.0),
+                   t_first=0.0, dt=dt)
+    t0, dtd = W.arrival_window(cells, host, 2048, pad_frac=0.05)
+    det = radio.Detector(cells, t0=t0, dt_det=dtd, n_t=2048, precision=precision)
+    rt = RunTimeDiagnostic([det], x0, u0, None, dt=dt, block_steps=block, fields=wave)
+    rt.advance(1)  # warm
+    torch.cuda.synchronize()
+    det.reset()
+    rt = RunTimeDiagnostic([det], x0, u0, None, dt=dt, block_steps=block, fields=wave)
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    rt.advance(n_blocks)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    # the push alone, same blocks
+    c, d = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c.record(stream)
+    for _ in range(n_blocks):
+        radio.push(rt.chunk, **wave)
+    d.record(stream)
+    torch.cuda.synchronize()
+    push_ms = c.elapsed_time(d)
+    inter = n_p * block * n_blocks * det.n_cells
+    det.close()
+    print(f"[bench] runtime ({precision}): {ms:.1f} ms for {n_blocks} push-deposit blocks, "
+          f"push {push_ms:.1f} ms, {inter / (ms * 1e-3):.3e} interactions/s", file=sys.stderr,
+          flush=True)
+    return {"workload": "1e4 electrons in a plane wave (a 1.5), 1024 steps in blocks of 16; "
+                        "128x128 cap at 1e4, 2048 slots", "precision": precision,
+            "total_ms": ms, "push_ms": push_ms, "interactions": inter,
+            "value": inter / (ms * 1e-3)}
+
+
 def measured_traffic(precision, workload):
     """HBM bytes per deposit launch from the committed rocprofv3 counter summary, or None
     when it was taken on another workload or on a different kernel source."""
@@ -419,6 +477,8 @@ def main():
         out["batch"] = batch
     if not args.no_spectrum:
         out["spectrum"] = spectrum_leg(radio, W, max(1, args.steps))
+    if not args.no_runtime:
+        out["runtime"] = runtime_leg(radio, W, args.precision)
     if not args.no_serve:
         precs = [args.precision] + (["fp64"] if args.precision != "fp64" and not args.no_fp64 else [])
         out["serve"] = serve_leg(radio, W, precs, args.serve_chunks, args.serve_load)
