@@ -9,8 +9,10 @@ namespace radio {
 // One trajectory state as the deposit reads it, laid out per arithmetic mode
 // (the states of one particle are contiguous): position, beta, 1/gamma^2 and
 // betadot = (beta_s - beta_{s-1})/dt (zero for the first state of a chunk,
-// which carries no segment).  The mixed modes keep betadot and a copy of
-// 1/gamma^2 in single precision.  Both records are 80 bytes.
+// which carries no segment).  The mixed modes keep position and beta, which
+// enter the arrival time and n - beta, in double and betadot and 1/gamma^2 in
+// single precision.  Records are 80 (double) and 64 (mixed) bytes, multiples
+// of 16 so that staging copies and LDS reads stay 16-byte aligned.
 struct RecF64 {
     double x[3];
     double b[3];
@@ -20,12 +22,10 @@ struct RecF64 {
 struct RecMix {
     double x[3];
     double b[3];
-    double g2i;
     float bdf[3];
     float g2if;
-    double pad;  // to 80 bytes: records stay 16-byte aligned, and so do their LDS reads
 };
-static_assert(sizeof(RecF64) == 80 && sizeof(RecMix) == 80, "state record layouts");
+static_assert(sizeof(RecF64) == 80 && sizeof(RecMix) == 64, "state record layouts");
 
 // arithmetic of a deposit: field in double, accumulation in double; field in
 // single, accumulation in double; field in single, accumulation in compensated

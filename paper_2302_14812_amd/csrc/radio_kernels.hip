@@ -7,8 +7,9 @@
 // weights of Sec. 3.2 / Alg. 2.  Four kernels run per deposit:
 //
 // 1. kinematics_kernel (Alg. 1, velocity and acceleration lines): one thread
-//    per trajectory state turns (x, u) into an 80-byte record with x, beta,
-//    betadot and 1/gamma^2 (betadot in single precision for the mixed modes),
+//    per trajectory state turns (x, u) into a record with x, beta, betadot and
+//    1/gamma^2 (80 bytes; 64 with betadot and 1/gamma^2 in single precision
+//    for the mixed modes),
 //    laid out particle-major so that the states of one particle's run are
 //    contiguous.
 //
@@ -213,11 +214,11 @@ struct CellSink<double, R> {
     int base;
     int n_t;
     unsigned* n_bypass;
+    // The ring covers [base, base + R) with 0 <= base, so a slot in it is >= 0;
+    // slots at or past n_t that it holds (n_t < R) are dropped when it moves.
     template <typename F>
     __device__ __forceinline__ void flush(int j, const F a[6]) const
     {
-        if (j < 0 || j >= n_t)
-            return;
         double v[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k)
@@ -227,7 +228,7 @@ struct CellSink<double, R> {
 #pragma unroll
             for (int k = 0; k < 6; ++k)
                 __hip_atomic_fetch_add(q + k, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        } else {
+        } else if ((unsigned)j < (unsigned)n_t) {
             *n_bypass += 1u;
             global_add(row, j, v);
         }
@@ -244,8 +245,6 @@ struct CellSink<float, R> {
     unsigned* n_bypass;
     __device__ __forceinline__ void flush(int j, const float a[6]) const
     {
-        if (j < 0 || j >= n_t)
-            return;
         if ((unsigned)(j - base) < (unsigned)R) {
             RADIO_LDS float* q = ring + (j & (R - 1)) * W;
 #pragma unroll
@@ -255,7 +254,7 @@ struct CellSink<float, R> {
                 __hip_atomic_fetch_add(q + 6 + k, two_sum_err(old, a[k], old + a[k]),
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
-        } else {
+        } else if ((unsigned)j < (unsigned)n_t) {
             *n_bypass += 1u;
             global_add(row, j, a);
         }
@@ -272,94 +271,110 @@ struct CellSink<float, R> {
 // (Alg. 2), so each segment contributes the same numbers the definition
 // gives; only the order of the additions differs.  Slots outside [0, n_t)
 // are dropped by the sink, which is how the window clips (Alg. 1).
+//
+// The carry keeps J + 1 as a double (J1) and the bound `lim` of the fast path:
+// a segment [a, b] with a <= b < lim starts in the open slot (a in [J, J+1)),
+// with J >= -1, and ends at most kFastSlots slots further and below n_t + 1.
+// lim is -inf whenever the next segment's start is not known to lie in the
+// open slot; that segment then takes the general path.
+constexpr double kFastSlots = 6.0;
+
 template <typename T>
 struct Carry {
-    int J;     // open slot; may be -1 or n_t (outside the window: dropped on emission)
-    T V[6];    // integral of the held field over slot J so far
+    double J1;   // open slot + 1; the slot may be -1 or n_t, or far below 0 when none is open
+    double lim;  // fast-path bound of the next segment
+    T V[6];      // integral of the held field over the open slot so far
 };
 
 template <typename T>
-__device__ __forceinline__ void carry_open(Carry<T>& C, int J)
+__device__ __forceinline__ void carry_open(Carry<T>& C, double J)
 {
-    C.J = J;
+    C.J1 = J + 1.0;
 #pragma unroll
     for (int k = 0; k < 6; ++k)
         C.V[k] = T(0);
 }
 
+// the fast-path bound when the open slot is J and the next segment starts at a
+__device__ __forceinline__ double fast_limit(double J, double a, double ntd)
+{
+    return ((J >= -1.0) & (a >= J) & (a < J + 1.0)) ? fmin(J + (kFastSlots + 1.0), ntd + 1.0)
+                                                     : -INFINITY;
+}
+
 // General case: hold F over the slot-coordinate interval between a and b,
 // clipped to [0, n_t]; any order, any length.  A segment that does not start
 // in the open slot closes it first, which is exact because deposits add.
+// Backward segments are counted here (the fast path takes none).
 template <typename T, typename Sink>
-__device__ __forceinline__ void add_segment_general(Carry<T>& C, const Sink& sink, int n_t, double a,
-                                                 double b, const T F[6])
+__device__ __forceinline__ void add_segment_general(Carry<T>& C, const Sink& sink, int n_t,
+                                                    double a, double b, const T F[6],
+                                                    unsigned& n_back)
 {
+    n_back += (b < a) ? 1u : 0u;
     const double ntd = (double)n_t;
     const double lo = fmin(fmax(fmin(a, b), 0.0), ntd);
     const double hi = fmin(fmax(fmax(a, b), 0.0), ntd);
-    if (!(lo < hi))  // empty, entirely outside, or NaN
-        return;
-    const int jl = (int)floor(lo);  // lo < n_t
-    const int jh = (int)floor(hi);  // <= n_t; n_t only when hi reaches the end
-    if (jl != C.J) {
-        sink.flush(C.J, C.V);
-        carry_open(C, jl);
+    if (lo < hi) {  // else empty, entirely outside, or NaN
+        const double fl = floor(lo);  // < n_t
+        const double fh = floor(hi);  // <= n_t; n_t only when hi reaches the end
+        if (fl != C.J1 - 1.0) {
+            sink.flush((int)(C.J1 - 1.0), C.V);
+            carry_open(C, fl);
+        }
+        if (fh == fl) {
+            const T w = T(hi - lo);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                C.V[k] += F[k] * w;
+        } else {
+            const T wa = T((fl + 1.0) - lo);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                C.V[k] += F[k] * wa;
+            const int jl = (int)fl, jh = (int)fh;
+            sink.flush(jl, C.V);
+            for (int j = jl + 1; j < jh; ++j)  // whole slots hold F
+                sink.flush(j, F);
+            const T wb = T(hi - fh);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                C.V[k] = F[k] * wb;
+            C.J1 = fh + 1.0;
+        }
     }
-    if (jh == jl) {
-        const T w = T(hi - lo);
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-            C.V[k] += F[k] * w;
-        return;
-    }
-    const T wa = T((double)(jl + 1) - lo);
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        C.V[k] += F[k] * wa;
-    sink.flush(jl, C.V);
-    for (int j = jl + 1; j < jh; ++j)  // whole slots hold F
-        sink.flush(j, F);
-    const T wb = T(hi - (double)jh);
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        C.V[k] = F[k] * wb;
-    C.J = jh;
+    C.lim = fast_limit(C.J1 - 1.0, b, ntd);
 }
 
-// One segment [a, b] of a lane's run.  Fast path, taken when the segment
-// runs forward from inside the open slot J (J in [-1, n_t]) and ends at most
-// kFastSlots slots further: the overlaps are b - a (same slot) or J + 1 - a,
-// whole slots, and b - floor(b) -- those of the definition -- and the
-// emissions are guarded by the crossing count only.  Everything else goes
-// through add_segment_general.
-constexpr double kFastSlots = 6.0;
-
+// One segment [a, b] of a lane's run.  Fast path (a <= b < lim): the overlaps
+// are b - a (same slot) or J + 1 - a, whole slots, and b - floor(b) -- those
+// of the definition -- and the emissions are guarded by the crossing count
+// only.  Everything else goes through add_segment_general.
 template <typename T, typename Sink>
 __device__ __forceinline__ void add_segment(Carry<T>& C, const Sink& sink, int n_t, double a,
-                                            double b, const T F[6])
+                                            double b, const T F[6], unsigned& n_back)
 {
-    const double Jd = (double)C.J;
-    const bool fast = (b >= a) & (a >= Jd) & (b < Jd + (kFastSlots + 1.0)) & (Jd >= -1.0) &
-                      (b < (double)n_t + 1.0);
-    if (fast) {
-        const double fb = floor(b);
-        const int n = (int)(fb - Jd);  // slots crossed, at most kFastSlots
-        const T w0 = T((n == 0 ? b : Jd + 1.0) - a);
+    if ((b >= a) & (b < C.lim)) {
+        const T w0 = T(fmin(b, C.J1) - a);
 #pragma unroll
         for (int k = 0; k < 6; ++k)
             C.V[k] += F[k] * w0;
-        if (n >= 1) {
-            sink.flush(C.J, C.V);
+        if (b >= C.J1) {  // the segment leaves the open slot
+            const double fb = floor(b);
+            const int J = (int)C.J1 - 1;
+            const int n = (int)(fb - C.J1) + 1;  // slots crossed, 1 .. kFastSlots
+            sink.flush(J, C.V);
             for (int i = 1; i < n; ++i)  // whole slots hold F
-                sink.flush(C.J + i, F);
+                sink.flush(J + i, F);
             const T wb = T(b - fb);
 #pragma unroll
             for (int k = 0; k < 6; ++k)
                 C.V[k] = F[k] * wb;
-            C.J += n;
+            C.J1 = fb + 1.0;
+            C.lim = fmin(fb + (kFastSlots + 1.0), (double)n_t + 1.0);
         }
     } else {
-        add_segment_general(C, sink, n_t, a, b, F);
+        add_segment_general(C, sink, n_t, a, b, F, n_back);
     }
 }
 
@@ -378,92 +393,96 @@ __device__ __forceinline__ void lerp_field(const T Fa[6], const T dF[6], T f, T 
 template <typename T, typename Sink>
 __device__ __forceinline__ void add_segment_linear_general(Carry<T>& C, const Sink& sink, int n_t,
                                                            double a, double b, const T Fa[6],
-                                                           const T dF[6], double inv_len)
+                                                           const T dF[6], double inv_len,
+                                                           unsigned& n_back)
 {
+    n_back += (b < a) ? 1u : 0u;
     const double ntd = (double)n_t;
     const double lo = fmin(fmax(fmin(a, b), 0.0), ntd);
     const double hi = fmin(fmax(fmax(a, b), 0.0), ntd);
-    if (!(lo < hi))
-        return;
-    const int jl = (int)floor(lo);
-    const int jh = (int)floor(hi);
-    if (jl != C.J) {
-        sink.flush(C.J, C.V);
-        carry_open(C, jl);
+    if (lo < hi) {
+        const double fl = floor(lo);
+        const double fh = floor(hi);
+        if (fl != C.J1 - 1.0) {
+            sink.flush((int)(C.J1 - 1.0), C.V);
+            carry_open(C, fl);
+        }
+        T F[6];
+        auto piece = [&](double p, double q) {  // the interpolant times the overlap [p, q]
+            lerp_field(Fa, dF, T(0.5 * ((p - a) + (q - a)) * inv_len), F);
+            const T w = T(q - p);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                F[k] *= w;
+        };
+        if (fh == fl) {
+            piece(lo, hi);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                C.V[k] += F[k];
+        } else {
+            const int jl = (int)fl, jh = (int)fh;
+            piece(lo, fl + 1.0);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                C.V[k] += F[k];
+            sink.flush(jl, C.V);
+            for (int j = jl + 1; j < jh; ++j) {
+                piece((double)j, (double)(j + 1));
+                sink.flush(j, F);
+            }
+            piece(fh, hi);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                C.V[k] = F[k];
+            C.J1 = fh + 1.0;
+        }
     }
-    T F[6];
-    auto piece = [&](double p, double q) {  // the interpolant times the overlap [p, q]
-        lerp_field(Fa, dF, T(0.5 * ((p - a) + (q - a)) * inv_len), F);
-        const T w = T(q - p);
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-            F[k] *= w;
-    };
-    if (jh == jl) {
-        piece(lo, hi);
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-            C.V[k] += F[k];
-        return;
-    }
-    piece(lo, (double)(jl + 1));
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        C.V[k] += F[k];
-    sink.flush(jl, C.V);
-    for (int j = jl + 1; j < jh; ++j) {
-        piece((double)j, (double)(j + 1));
-        sink.flush(j, F);
-    }
-    piece((double)jh, hi);
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        C.V[k] = F[k];
-    C.J = jh;
+    C.lim = fast_limit(C.J1 - 1.0, b, ntd);
 }
 
 template <typename T, typename Sink>
 __device__ __forceinline__ void add_segment_linear(Carry<T>& C, const Sink& sink, int n_t,
                                                    double a, double b, const T Fa[6],
-                                                   const T Fb[6])
+                                                   const T Fb[6], unsigned& n_back)
 {
-    if (!(a != b))  // no length (or NaN): nothing to hold
+    if (a == b)  // no length: nothing to hold, and the carry still fits the next start
         return;
     T dF[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k)
         dF[k] = Fb[k] - Fa[k];
     const double inv_len = 1.0 / (b - a);
-    const double Jd = (double)C.J;
-    const bool fast = (b > a) & (a >= Jd) & (b < Jd + (kFastSlots + 1.0)) & (Jd >= -1.0) &
-                      (b < (double)n_t + 1.0);
-    if (fast) {
-        const double fb = floor(b);
-        const int n = (int)(fb - Jd);
-        const double e0 = n == 0 ? b : Jd + 1.0;
+    if ((b > a) & (b < C.lim)) {
+        const double Jd = C.J1 - 1.0;
+        const double e0 = fmin(b, C.J1);
         T F[6];
         lerp_field(Fa, dF, T(0.5 * (e0 - a) * inv_len), F);
         const T w0 = T(e0 - a);
 #pragma unroll
         for (int k = 0; k < 6; ++k)
             C.V[k] += F[k] * w0;
-        if (n >= 1) {
-            sink.flush(C.J, C.V);
+        if (b >= C.J1) {
+            const double fb = floor(b);
+            const int J = (int)C.J1 - 1;
+            const int n = (int)(fb - C.J1) + 1;
+            sink.flush(J, C.V);
             for (int i = 1; i < n; ++i) {  // whole slots: the interpolant at their middle
                 lerp_field(Fa, dF, T(0.5 * ((Jd + (double)i - a) + (Jd + (double)(i + 1) - a)) *
                                      inv_len),
                            F);
-                sink.flush(C.J + i, F);
+                sink.flush(J + i, F);
             }
             lerp_field(Fa, dF, T(0.5 * ((fb - a) + (b - a)) * inv_len), F);
             const T wb = T(b - fb);
 #pragma unroll
             for (int k = 0; k < 6; ++k)
                 C.V[k] = F[k] * wb;
-            C.J += n;
+            C.J1 = fb + 1.0;
+            C.lim = fmin(fb + (kFastSlots + 1.0), (double)n_t + 1.0);
         }
     } else {
-        add_segment_linear_general(C, sink, n_t, a, b, Fa, dF, inv_len);
+        add_segment_linear_general(C, sink, n_t, a, b, Fa, dF, inv_len, n_back);
     }
 }
 
@@ -473,10 +492,39 @@ __device__ __forceinline__ void add_segment_linear(Carry<T>& C, const Sink& sink
 
 struct Consts {
     double t0, inv_dt_det, inv_c;
-    float inv_cf;
-    double vs;   // weight of the velocity term: 1, or 0 for an acceleration-only detector
-    float vsf;
+    double kR;  // inv_c * inv_dt_det: slots per unit of distance (mixed modes)
 };
+
+// E and B of Eq. 1 from the unit vector n to the cell, w = n - beta, 1/kappa,
+// 1/R and the state's 1/gamma^2 and betadot, for a charge with qc = q/c and
+// qv = q times the weight of the velocity term.  The acceleration term is
+// regrouped with the identity n x (w x bd) = w (n.bd) - bd (n.w):
+//   E = c1 w - c2 bd,  c1 = (qc n.bd + qv g2i / R) / (kappa^3 R),
+//                      c2 = qc (n.w) / (kappa^3 R),
+//   B = n x E.
+// nwk is (n.w)/kappa.  For a unit n, n.w = 1 - n.beta = kappa and nwk = 1,
+// which the single-precision field takes: it is the more accurate value there.
+// The double field passes the product of its rounded n and w, as the cross
+// products of Eq. 1 would use them (with kappa of order 1/gamma^2, the last
+// bits of |n| shift n.w by up to ~1e-12 of itself).
+template <typename T>
+__device__ __forceinline__ void lw_fields(const T n[3], const T w[3], T kinv, T rinv, T g2i,
+                                          const T bd[3], T qc, T qv, T nwk, T F[6])
+{
+    const T nbd = n[0] * bd[0] + n[1] * bd[1] + n[2] * bd[2];
+    const T rk2 = rinv * (kinv * kinv);
+    const T c1 = (qc * nbd + qv * g2i * rinv) * (rk2 * kinv);
+    const T c2 = qc * rk2 * nwk;
+    const T E0 = c1 * w[0] - c2 * bd[0];
+    const T E1 = c1 * w[1] - c2 * bd[1];
+    const T E2 = c1 * w[2] - c2 * bd[2];
+    F[0] = E0;
+    F[1] = E1;
+    F[2] = E2;
+    F[3] = n[1] * E2 - n[2] * E1;
+    F[4] = n[2] * E0 - n[0] * E2;
+    F[5] = n[0] * E1 - n[1] * E0;
+}
 
 // 1/x from the hardware reciprocal refined by two Newton steps (within an ulp
 // or two; used where Eq. 1 needs no particular rounding)
@@ -493,7 +541,7 @@ __device__ __forceinline__ double recip(double x)
 // returns the state's slot coordinate.  Everything after the canonical part may
 // use FMAs.
 __device__ __forceinline__ double field_fp64(const double xc[3], const RecF64& st, double t_s,
-                                             double q, const Consts& K, double F[6])
+                                             double qc, double qv, const Consts& K, double F[6])
 {
     double d[3] = {xc[0] - st.x[0], xc[1] - st.x[1], xc[2] - st.x[2]};
     double R2 = canon_norm2(d[0], d[1], d[2]);
@@ -502,26 +550,9 @@ __device__ __forceinline__ double field_fp64(const double xc[3], const RecF64& s
     double rinv = 1.0 / R;
     double n[3], w[3];
     canon_direction(d, rinv, st.b, n, w);
-    double kap = canon_kappa(w, st.g2i);
-    double k3inv = recip(kap * kap * kap);
-    double ca = q * k3inv * rinv * K.inv_c;               // (q/c) / (kappa^3 R)
-    double cv = K.vs * q * st.g2i * k3inv * rinv * rinv;  // q / (gamma^2 kappa^3 R^2)
-    // w x betadot, then n x (w x betadot)
-    double a0 = w[1] * st.bd[2] - w[2] * st.bd[1];
-    double a1 = w[2] * st.bd[0] - w[0] * st.bd[2];
-    double a2 = w[0] * st.bd[1] - w[1] * st.bd[0];
-    double m0 = n[1] * a2 - n[2] * a1;
-    double m1 = n[2] * a0 - n[0] * a2;
-    double m2 = n[0] * a1 - n[1] * a0;
-    double E0 = cv * w[0] + ca * m0;
-    double E1 = cv * w[1] + ca * m1;
-    double E2 = cv * w[2] + ca * m2;
-    F[0] = E0;
-    F[1] = E1;
-    F[2] = E2;
-    F[3] = n[1] * E2 - n[2] * E1;
-    F[4] = n[2] * E0 - n[0] * E2;
-    F[5] = n[0] * E1 - n[1] * E0;
+    const double kinv = recip(canon_kappa(w, st.g2i));
+    const double nwk = (n[0] * w[0] + n[1] * w[1] + n[2] * w[2]) * kinv;
+    lw_fields<double>(n, w, kinv, rinv, st.g2i, st.bd, qc, qv, nwk, F);
     return canon_slot(tau, K.t0, K.inv_dt_det);
 }
 
@@ -540,40 +571,23 @@ __device__ __forceinline__ void fast_norm(double R2, double* R, double* rinv)
 }
 
 // The mixed-precision field: double for what cancels (arrival time, slot
-// coordinate, n - beta and kappa), single for the rest of Eq. 1.
-__device__ __forceinline__ double field_mixed(const double xc[3], const RecMix& st, double t_s,
-                                              float q, const Consts& K, float F[6])
+// coordinate, n - beta and kappa), single for the rest of Eq. 1.  ub is the
+// state's (t_s - t0) / dt_det; the slot coordinate is ub + R / (c dt_det).
+__device__ __forceinline__ double field_mixed(const double xc[3], const RecMix& st, double ub,
+                                              float qc, float qv, const Consts& K, float F[6])
 {
     double d[3] = {xc[0] - st.x[0], xc[1] - st.x[1], xc[2] - st.x[2]};
     double R2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     double R, rinv;
     fast_norm(R2, &R, &rinv);
-    const double u = canon_slot(t_s + R * K.inv_c, K.t0, K.inv_dt_det);
+    const double u = fma(R, K.kR, ub);
     double nd[3] = {d[0] * rinv, d[1] * rinv, d[2] * rinv};
     double wd[3] = {nd[0] - st.b[0], nd[1] - st.b[1], nd[2] - st.b[2]};
-    const double kap = 0.5 * ((wd[0] * wd[0] + wd[1] * wd[1] + wd[2] * wd[2]) + st.g2i);
+    const double kap = 0.5 * ((wd[0] * wd[0] + wd[1] * wd[1] + wd[2] * wd[2]) + (double)st.g2if);
     const float n[3] = {(float)nd[0], (float)nd[1], (float)nd[2]};
     const float w[3] = {(float)wd[0], (float)wd[1], (float)wd[2]};
-    const float kinv = __builtin_amdgcn_rcpf((float)kap);
-    const float k3inv = kinv * kinv * kinv;
-    const float rinvf = (float)rinv;
-    const float ca = q * k3inv * rinvf * K.inv_cf;
-    const float cv = K.vsf * q * st.g2if * k3inv * rinvf * rinvf;
-    const float a0 = w[1] * st.bdf[2] - w[2] * st.bdf[1];
-    const float a1 = w[2] * st.bdf[0] - w[0] * st.bdf[2];
-    const float a2 = w[0] * st.bdf[1] - w[1] * st.bdf[0];
-    const float m0 = n[1] * a2 - n[2] * a1;
-    const float m1 = n[2] * a0 - n[0] * a2;
-    const float m2 = n[0] * a1 - n[1] * a0;
-    const float E0 = cv * w[0] + ca * m0;
-    const float E1 = cv * w[1] + ca * m1;
-    const float E2 = cv * w[2] + ca * m2;
-    F[0] = E0;
-    F[1] = E1;
-    F[2] = E2;
-    F[3] = n[1] * E2 - n[2] * E1;
-    F[4] = n[2] * E0 - n[0] * E2;
-    F[5] = n[0] * E1 - n[1] * E0;
+    lw_fields<float>(n, w, __builtin_amdgcn_rcpf((float)kap), (float)rinv, st.g2if, st.bdf, qc, qv,
+                     1.0f, F);
     return u;
 }
 
@@ -597,11 +611,11 @@ __device__ __forceinline__ void canon_far_w(const double fc[4], const double b[3
     w[2] = fc[2] - b[2];
 }
 
-__device__ __forceinline__ double slot_far_mixed(const double fc[4], const double x[3], double t_s,
+// ub = (t_s - t0) / dt_det, as for field_mixed
+__device__ __forceinline__ double slot_far_mixed(const double fc[4], const double x[3], double ub,
                                                  const Consts& K)
 {
-    return canon_slot(t_s + (fc[3] - (x[0] * fc[0] + x[1] * fc[1] + x[2] * fc[2])) * K.inv_c,
-                      K.t0, K.inv_dt_det);
+    return fma(fc[3] - (x[0] * fc[0] + x[1] * fc[1] + x[2] * fc[2]), K.kR, ub);
 }
 
 __device__ __forceinline__ double slot_far_fp64(const double fc[4], const double x[3], double t_s,
@@ -612,64 +626,34 @@ __device__ __forceinline__ double slot_far_fp64(const double fc[4], const double
 
 // Eq. 1 with the far-field geometry n = n_cell, R = R_cell; Rinv = 1/R_cell
 __device__ __forceinline__ double field_far_fp64(const double fc[4], double Rinv,
-                                                 const RecF64& st, double t_s, double q,
-                                                 const Consts& K, double F[6])
+                                                 const RecF64& st, double t_s, double qc,
+                                                 double qv, const Consts& K, double F[6])
 {
     double w[3];
     canon_far_w(fc, st.b, w);
-    const double kap = canon_kappa(w, st.g2i);
-    const double k3inv = recip(kap * kap * kap);
-    const double ca = q * k3inv * Rinv * K.inv_c;
-    const double cv = K.vs * q * st.g2i * k3inv * Rinv * Rinv;
-    const double a0 = w[1] * st.bd[2] - w[2] * st.bd[1];
-    const double a1 = w[2] * st.bd[0] - w[0] * st.bd[2];
-    const double a2 = w[0] * st.bd[1] - w[1] * st.bd[0];
-    const double m0 = fc[1] * a2 - fc[2] * a1;
-    const double m1 = fc[2] * a0 - fc[0] * a2;
-    const double m2 = fc[0] * a1 - fc[1] * a0;
-    const double E0 = cv * w[0] + ca * m0;
-    const double E1 = cv * w[1] + ca * m1;
-    const double E2 = cv * w[2] + ca * m2;
-    F[0] = E0;
-    F[1] = E1;
-    F[2] = E2;
-    F[3] = fc[1] * E2 - fc[2] * E1;
-    F[4] = fc[2] * E0 - fc[0] * E2;
-    F[5] = fc[0] * E1 - fc[1] * E0;
+    const double kinv = recip(canon_kappa(w, st.g2i));
+    const double nwk = (fc[0] * w[0] + fc[1] * w[1] + fc[2] * w[2]) * kinv;
+    lw_fields<double>(fc, w, kinv, Rinv, st.g2i, st.bd, qc, qv, nwk, F);
     return slot_far_fp64(fc, st.x, t_s, K);
 }
 
 __device__ __forceinline__ double field_far_mixed(const double fc[4], double Rinv,
-                                                  const RecMix& st, double t_s, float q,
+                                                  const RecMix& st, double ub, float qc, float qv,
                                                   const Consts& K, float F[6])
 {
-    const double u = slot_far_mixed(fc, st.x, t_s, K);
+    const double u = slot_far_mixed(fc, st.x, ub, K);
     const double wd[3] = {fc[0] - st.b[0], fc[1] - st.b[1], fc[2] - st.b[2]};
-    const double kap = 0.5 * ((wd[0] * wd[0] + wd[1] * wd[1] + wd[2] * wd[2]) + st.g2i);
+    const double kap = 0.5 * ((wd[0] * wd[0] + wd[1] * wd[1] + wd[2] * wd[2]) + (double)st.g2if);
     const float n[3] = {(float)fc[0], (float)fc[1], (float)fc[2]};
     const float w[3] = {(float)wd[0], (float)wd[1], (float)wd[2]};
-    const float kinv = __builtin_amdgcn_rcpf((float)kap);
-    const float k3inv = kinv * kinv * kinv;
-    const float rinvf = (float)Rinv;
-    const float ca = q * k3inv * rinvf * K.inv_cf;
-    const float cv = K.vsf * q * st.g2if * k3inv * rinvf * rinvf;
-    const float a0 = w[1] * st.bdf[2] - w[2] * st.bdf[1];
-    const float a1 = w[2] * st.bdf[0] - w[0] * st.bdf[2];
-    const float a2 = w[0] * st.bdf[1] - w[1] * st.bdf[0];
-    const float m0 = n[1] * a2 - n[2] * a1;
-    const float m1 = n[2] * a0 - n[0] * a2;
-    const float m2 = n[0] * a1 - n[1] * a0;
-    const float E0 = cv * w[0] + ca * m0;
-    const float E1 = cv * w[1] + ca * m1;
-    const float E2 = cv * w[2] + ca * m2;
-    F[0] = E0;
-    F[1] = E1;
-    F[2] = E2;
-    F[3] = n[1] * E2 - n[2] * E1;
-    F[4] = n[2] * E0 - n[0] * E2;
-    F[5] = n[0] * E1 - n[1] * E0;
+    lw_fields<float>(n, w, __builtin_amdgcn_rcpf((float)kap), (float)Rinv, st.g2if, st.bdf, qc,
+                     qv, 1.0f, F);
     return u;
 }
+
+// 1/gamma^2 of a staged state
+__device__ __forceinline__ double rec_g2i(const RecF64& st) { return st.g2i; }
+__device__ __forceinline__ double rec_g2i(const RecMix& st) { return (double)st.g2if; }
 
 // Lienard-Wiechert potentials phi = q/(kappa R), A = q beta/(kappa R) at a
 // staged state (the potentials option): F = (A_x, A_y, A_z, phi, 0, 0).  FAR:
@@ -683,7 +667,7 @@ __device__ __forceinline__ void potentials_at(const double xc[3], const double f
     if constexpr (FAR) {
         double w[3];
         canon_far_w(fc, st.b, w);
-        kap = canon_kappa(w, st.g2i);
+        kap = canon_kappa(w, rec_g2i(st));
         rinv = 1.0 / fc[3];
     } else {
         double d[3] = {xc[0] - st.x[0], xc[1] - st.x[1], xc[2] - st.x[2]};
@@ -691,7 +675,7 @@ __device__ __forceinline__ void potentials_at(const double xc[3], const double f
         rinv = 1.0 / R;
         double n[3], w[3];
         canon_direction(d, rinv, st.b, n, w);
-        kap = canon_kappa(w, st.g2i);
+        kap = canon_kappa(w, rec_g2i(st));
     }
     const double phi = q * rinv / kap;
     F[0] = T(phi * st.b[0]);
@@ -710,13 +694,14 @@ __device__ __forceinline__ double slot_coord_fp64(const double xc[3], const doub
     return canon_slot(canon_arrival(t_s, R, K.inv_c), K.t0, K.inv_dt_det);
 }
 
+// ub = (t_s - t0) / dt_det, as for field_mixed
 __device__ __forceinline__ double slot_coord_mixed(const double xc[3], const double x[3],
-                                                   double t_s, const Consts& K)
+                                                   double ub, const Consts& K)
 {
     double d[3] = {xc[0] - x[0], xc[1] - x[1], xc[2] - x[2]};
     double R, rinv;
     fast_norm(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], &R, &rinv);
-    return canon_slot(t_s + R * K.inv_c, K.t0, K.inv_dt_det);
+    return fma(R, K.kR, ub);
 }
 
 // ---------------------------------------------------------------------------
@@ -750,7 +735,8 @@ __global__ __launch_bounds__(256) void kinematics_kernel(const double* __restric
         r.x[0] = x[off];
         r.x[1] = x[off + stride];
         r.x[2] = x[off + 2 * stride];
-        canon_kinematics(u[off], u[off + stride], u[off + 2 * stride], r.b, &r.g2i);
+        double g2i;
+        canon_kinematics(u[off], u[off + stride], u[off + 2 * stride], r.b, &g2i);
         double bd[3] = {0.0, 0.0, 0.0};
         if (bd_rule == kBdCentred && n_s > 0) {
             const int64_t sa = s > 0 ? s - 1 : 0;
@@ -775,11 +761,12 @@ __global__ __launch_bounds__(256) void kinematics_kernel(const double* __restric
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 r.bd[c] = bd[c];
+            r.g2i = g2i;
         } else {
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 r.bdf[c] = (float)bd[c];
-            r.g2if = (float)r.g2i;
+            r.g2if = (float)g2i;
         }
         recs[p * n_states + s] = r;
     }
@@ -1015,7 +1002,17 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
     const int64_t row_i = tile * kTileCells + cl;  // internal (tile-ordered) cell row
     const bool active = row_i < J.n_c;
     const int n_t = (int)J.n_t;
-    const Consts K{J.t0, J.inv_dt_det, J.inv_c, (float)J.inv_c, J.vscale, (float)J.vscale};
+    const Consts K{J.t0, J.inv_dt_det, J.inv_c, J.inv_c * J.inv_dt_det};
+    const double ntd = (double)n_t;
+    // the time argument of the field and slot functions for state index sk: the
+    // state time t_s (double mode, canonical rounding), or (t_s - t0) / dt_det
+    const double ub0 = (J.t_first - J.t0) * J.inv_dt_det, dtu = J.dt * J.inv_dt_det;
+    auto clock = [&](double sk) {
+        if constexpr (MIX)
+            return fma(sk, dtu, ub0);
+        else
+            return canon_state_time(J.t_first, sk, J.dt);
+    };
     double xc[3] = {0.0, 0.0, 0.0};
     double fc[4] = {0.0, 0.0, 0.0, 1.0};  // far field: the cell's direction and distance
     RADIO_GLOBAL Acc* row = nullptr;
@@ -1035,11 +1032,11 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
     }
     const double Rinv = 1.0 / fc[3];
     // slot coordinate of a state, the same expression the field functions use
-    auto slot_of = [&](const Rec& st, double t_s) {
+    auto slot_of = [&](const Rec& st, double tk) {
         if constexpr (FAR)
-            return MIX ? slot_far_mixed(fc, st.x, t_s, K) : slot_far_fp64(fc, st.x, t_s, K);
+            return MIX ? slot_far_mixed(fc, st.x, tk, K) : slot_far_fp64(fc, st.x, tk, K);
         else
-            return MIX ? slot_coord_mixed(xc, st.x, t_s, K) : slot_coord_fp64(xc, st.x, t_s, K);
+            return MIX ? slot_coord_mixed(xc, st.x, tk, K) : slot_coord_fp64(xc, st.x, tk, K);
     };
     RADIO_LDS Acc* my_ring = (RADIO_LDS Acc*)&sh.ring[cl * DepositShared<M, R>::kStride];
     RADIO_LDS int* nb = (RADIO_LDS int*)&sh.nb[0][0];
@@ -1049,7 +1046,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         sh.cnt[tid] = 0;
     if (tid < 2 * kTileCells)
         nb[tid] = INT_MAX;
-    int base = -1;  // ring covers [base, base + R); -1 until the first batch
+    int base = 0;  // the ring covers [base, base + R), 0 <= base <= max(n_t - R, 0)
     unsigned n_clip = 0, n_back = 0, n_bypass = 0;
     const RADIO_GLOBAL int32_t* order = gptr(J.perm + tile * J.n_p);
     const RADIO_GLOBAL double* charges = J.q ? gptr(J.q) : nullptr;
@@ -1087,7 +1084,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
     // Move the ring to start at new_base: slots leaving it go to HBM.  The
     // cell's kGroups lanes share the work.
     auto move_ring = [&](int new_base) {
-        if (base >= 0 && active) {
+        if (active) {
             int lo = base, hi = base + R;  // slots to flush
             if (new_base > base && new_base < base + R)
                 hi = new_base;
@@ -1122,7 +1119,6 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         const int64_t bt = it % n_batches;
         const int64_t s_a = rb * kRunL;
         const int len = (int)min((int64_t)kRunL, J.n_s - s_a);
-        const double t_a = canon_state_time(J.t_first, (double)(J.s0 + s_a), J.dt);
         const int64_t i0 = bt * kGroups;
         const int np = (int)min((int64_t)kGroups, J.n_p - i0);
         // slide the ring to this batch's earliest start (every lane of the
@@ -1162,57 +1158,60 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         if (active && g < np) {
             Sink sink{my_ring, row, base, n_t, &n_bypass};
             const double q = sh.sq[g];
+            const T qc = T(q * J.inv_c), qv = T(q * J.vscale);
             // the field of one staged state and its slot coordinate
-            auto field_at = [&](const Rec& st, double t_s, T F[6]) {
+            auto field_at = [&](const Rec& st, double tk, T F[6]) {
                 if constexpr (POT) {
                     potentials_at<FAR>(xc, fc, st, q, F);
-                    return slot_of(st, t_s);
+                    return slot_of(st, tk);
                 } else if constexpr (FAR) {
                     if constexpr (MIX)
-                        return field_far_mixed(fc, Rinv, st, t_s, (float)q, K, F);
+                        return field_far_mixed(fc, Rinv, st, tk, qc, qv, K, F);
                     else
-                        return field_far_fp64(fc, Rinv, st, t_s, q, K, F);
+                        return field_far_fp64(fc, Rinv, st, tk, qc, qv, K, F);
                 } else {
                     if constexpr (MIX)
-                        return field_mixed(xc, st, t_s, (float)q, K, F);
+                        return field_mixed(xc, st, tk, qc, qv, K, F);
                     else
-                        return field_fp64(xc, st, t_s, q, K, F);
+                        return field_fp64(xc, st, tk, qc, qv, K, F);
                 }
             };
+            double sk = (double)(J.s0 + s_a);  // state index, exact below 2^53
             T Fp[6];  // the previous state's field (HOLD != 0)
             double u_prev;
             if constexpr (HOLD != 0)
-                u_prev = field_at(sh.rec[g][0], t_a, Fp);
+                u_prev = field_at(sh.rec[g][0], clock(sk), Fp);
             else
-                u_prev = slot_of(sh.rec[g][0], t_a);
+                u_prev = slot_of(sh.rec[g][0], clock(sk));
             Carry<T> C;
             // open the slot where the run starts (a start far outside the window
             // leaves the first segment to the general path)
-            carry_open(C, (u_prev >= -1.0 && u_prev < (double)n_t + 1.0) ? (int)floor(u_prev)
-                                                                           : INT_MIN / 2);
-            double sk = (double)(J.s0 + s_a);  // state index, exact below 2^53
+            const bool inside = u_prev >= -1.0 && u_prev < ntd + 1.0;
+            carry_open(C, inside ? floor(u_prev) : (double)(INT_MIN / 2));
+            C.lim = fast_limit(C.J1 - 1.0, u_prev, ntd);
+            // a segment is clipped when either end lies outside [0, n_t]
+            bool out_prev = (u_prev < 0.0) | (u_prev > ntd);
             for (int k = 1; k <= len; ++k) {
                 T F[6];
                 sk += 1.0;
-                const double t_s = canon_state_time(J.t_first, sk, J.dt);
-                const double uk = field_at(sh.rec[g][k], t_s, F);
-                const bool back = uk < u_prev;
-                n_back += back ? 1u : 0u;
-                n_clip += (fmin(uk, u_prev) < 0.0 || fmax(uk, u_prev) > (double)n_t) ? 1u : 0u;
+                const double uk = field_at(sh.rec[g][k], clock(sk), F);
+                const bool out = (uk < 0.0) | (uk > ntd);
+                n_clip += (out | out_prev) ? 1u : 0u;
+                out_prev = out;
                 if constexpr (HOLD == 0) {
-                    add_segment(C, sink, n_t, u_prev, uk, F);
+                    add_segment(C, sink, n_t, u_prev, uk, F, n_back);
                 } else {
                     if constexpr (HOLD == 1)
-                        add_segment(C, sink, n_t, u_prev, uk, Fp);
+                        add_segment(C, sink, n_t, u_prev, uk, Fp, n_back);
                     else
-                        add_segment_linear(C, sink, n_t, u_prev, uk, Fp, F);
+                        add_segment_linear(C, sink, n_t, u_prev, uk, Fp, F, n_back);
 #pragma unroll
                     for (int c = 0; c < 6; ++c)
                         Fp[c] = F[c];
                 }
                 u_prev = uk;
             }
-            sink.flush(C.J, C.V);
+            sink.flush((int)(C.J1 - 1.0), C.V);
         }
         __syncthreads();  // records and rings are free for the next batch
     }
