@@ -197,7 +197,8 @@ RADIO_API int radio_deposit_batch(radio_detector* const* dets, const radio_chunk
 /*
  * Launch tunables, process wide (the autotuner sets them):
  *   target_blocks        workgroups aimed at by a single deposit (the runs of a
- *                        chunk are split until tiles x splits reaches it)
+ *                        chunk are split until tiles x splits reaches it); 0, the
+ *                        default, splits into short items of one run or a few
  *   items_per_workgroup  work items per resident workgroup in a batched deposit
  *                        (finer items balance uneven jobs, coarser ones cost less)
  */

@@ -79,7 +79,7 @@ def _time_ms(fn, repeats: int) -> float:
 
 
 def tune_single(spec, chunk: "radio.Chunk", precision: str = "mixed",
-                candidates: Iterable[int] = (768, 1536, 3072, 6144, 12288), repeats: int = 2,
+                candidates: Iterable[int] = (0, 768, 1536, 3072, 6144, 12288), repeats: int = 2,
                 cache: Optional[Dict[str, dict]] = None) -> dict:
     """Pick target_blocks for deposits shaped like (spec, chunk)."""
     det = radio.Detector.from_spec(spec, precision=precision)

@@ -107,7 +107,16 @@ struct WorkItem {
     int32_t pad;
 };
 
-void plan_job(DepositJob& job, int target_blocks);
+// Work items are kept short (a run, or the few runs that make at least this
+// many batches of kGroups particles): workgroups running at the same time then
+// stream the records of few runs, which stay in cache for the many tiles that
+// read them.
+constexpr int64_t kMinItemBatches = 64;
+
+// Split the runs of a job into work items: until tiles x splits reaches
+// target_blocks when it is positive, else into short items (a run or a few)
+// while at least `capacity` items (the workgroups resident at once) remain.
+void plan_job(DepositJob& job, int target_blocks, int64_t capacity);
 
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);

@@ -43,6 +43,8 @@
 // particles only change rounding.
 #include "radio_internal.h"
 
+#include <algorithm>
+#include <atomic>
 #include <climits>
 #include <type_traits>
 #include <utility>
@@ -1054,24 +1056,34 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
     const int64_t n_batches = (J.n_p + kGroups - 1) / kGroups;
     const int64_t rb_begin = split * J.runs_per_split;
     const int64_t rb_end = min(rb_begin + J.runs_per_split, J.n_runs);
-    const int64_t n_it = (rb_end - rb_begin) * n_batches;  // batches of this item, run-major
-
-    // Lowest slot where the lane's particle of batch `it` starts, into nb[buf][cell]
-    // (from the record in HBM, so a batch's ring position is known before it is staged).
-    auto scout = [&](int64_t it, int buf) {
-        const int64_t i = (it % n_batches) * kGroups + g;
-        if (!active || i >= J.n_p)
-            return;
-        const int64_t s_a = (rb_begin + it / n_batches) * kRunL;
-        const RADIO_GLOBAL double* xr =
-            gptr(reinterpret_cast<const double*>(recs + order[i] * n_states + s_a));
+    // The item's batches are taken run-major: run rb (states rb * kRunL ...)
+    // of the particles order[bt * kGroups ...], bt = 0 .. n_batches - 1.
+    // Before a batch is computed, one round of global loads brings its
+    // records, its charges and the first positions of the next batch's
+    // particles, whose lowest start slot per cell places the ring for that
+    // batch before it is staged; the order entries these loads need were
+    // fetched in the round before.
+    auto advance = [&](int64_t& rb_, int64_t& bt_) {
+        if (++bt_ == n_batches) {
+            bt_ = 0;
+            ++rb_;
+        }
+    };
+    // the lane's particle of batch (rb_, bt_), or -1
+    auto lane_particle = [&](int64_t rb_, int64_t bt_, int lane_g) -> int {
+        const int64_t i = bt_ * kGroups + lane_g;
+        return (rb_ < rb_end && i < J.n_p) ? (int)order[i] : -1;
+    };
+    // lowest start slot of the cell over a batch: the lane's particle starts at x
+    // at state s_a (into nb[buf][cell])
+    auto scout = [&](const double x[3], int64_t s_a, int buf) {
         const double t = canon_state_time(J.t_first, (double)(J.s0 + s_a), J.dt);
         double u;
         if constexpr (FAR) {
-            u = (t + (fc[3] - (xr[0] * fc[0] + xr[1] * fc[1] + xr[2] * fc[2])) * K.inv_c - K.t0) *
+            u = (t + (fc[3] - (x[0] * fc[0] + x[1] * fc[1] + x[2] * fc[2])) * K.inv_c - K.t0) *
                 K.inv_dt_det;
         } else {
-            const double d0 = xc[0] - xr[0], d1 = xc[1] - xr[1], d2 = xc[2] - xr[2];
+            const double d0 = xc[0] - x[0], d1 = xc[1] - x[1], d2 = xc[2] - x[2];
             u = (t + __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2) * K.inv_c - K.t0) * K.inv_dt_det;
         }
         if (u == u) {
@@ -1079,6 +1091,9 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
             __hip_atomic_fetch_min(nb + buf * kTileCells + cl, f, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
         }
+    };
+    auto first_position = [&](int p, int64_t s_a) {
+        return gptr(reinterpret_cast<const double*>(recs + (int64_t)p * n_states + s_a));
     };
 
     // Move the ring to start at new_base: slots leaving it go to HBM.  The
@@ -1109,14 +1124,29 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         base = new_base;
     };
 
+    // staging: kStageLanes threads per particle; the thread index passes
+    // through an empty asm so that what is derived from it is recomputed per
+    // batch instead of being held in registers across the field loop
+    constexpr int kStageLanes = kDepositThreads / kGroups;
+    int t_stage = tid;
+    asm volatile("" : "+v"(t_stage));
+    int64_t rb = rb_begin, bt = 0;  // the current batch
+    int64_t rb1 = rb, bt1 = bt;     // the next one
+    advance(rb1, bt1);
+    int p_stage = -1, p_scout = -1;  // this thread's particle to stage; the lane's to scout
     __syncthreads();  // rings and start slots cleared
-    if (n_it > 0)
-        scout(0, 0);
+    if (rb_begin < rb_end && n_batches > 0) {
+        const int p0 = lane_particle(rb, bt, g);
+        if (active && p0 >= 0) {
+            const RADIO_GLOBAL double* x = first_position(p0, rb * kRunL);
+            const double xs[3] = {x[0], x[1], x[2]};
+            scout(xs, rb * kRunL, 0);
+        }
+        p_stage = lane_particle(rb, bt, t_stage / kStageLanes);
+        p_scout = lane_particle(rb1, bt1, g);
+    }
     __syncthreads();
-    for (int64_t it = 0; it < n_it; ++it) {
-        const int buf = (int)(it & 1);
-        const int64_t rb = rb_begin + it / n_batches;
-        const int64_t bt = it % n_batches;
+    for (int buf = 0; rb < rb_end && n_batches > 0; buf ^= 1) {
         const int64_t s_a = rb * kRunL;
         const int len = (int)min((int64_t)kRunL, J.n_s - s_a);
         const int64_t i0 = bt * kGroups;
@@ -1131,27 +1161,57 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
             if (nbase != base)
                 move_ring(nbase);
         }
-        // stage: particle order[i0 + gg], states s_a .. s_a + len (contiguous)
+        int64_t rb2 = rb1, bt2 = bt1;  // the batch after the next
+        advance(rb2, bt2);
         {
             // pieces of 16 bytes where the record size allows, else of 8
             using Piece = typename std::conditional<sizeof(Rec) % 16 == 0, v2i64, long long>::type;
             constexpr int kPieces = (int)(sizeof(Rec) / sizeof(Piece));
+            constexpr int kIter = ((kRunL + 1) * kPieces + kStageLanes - 1) / kStageLanes;
             const int per = (len + 1) * kPieces;
-            for (int i = tid; i < kGroups * per; i += kDepositThreads) {
-                const int gg = i / per;
-                const int r = i - gg * per;
-                if (gg < np) {
-                    const int64_t p = order[i0 + gg];
-                    const RADIO_GLOBAL Piece* src =
-                        gptr(reinterpret_cast<const Piece*>(recs + p * n_states + s_a)) + r;
-                    reinterpret_cast<Piece*>(&sh.rec[gg][0])[r] = *src;
-                }
+            int t = t_stage;
+            asm volatile("" : "+v"(t));
+            const int gg = t / kStageLanes;
+            const int r0 = t % kStageLanes;
+            // one round of loads: the records of particle p_stage (states
+            // s_a .. s_a + len, contiguous), its charge, the next batch's first
+            // position for the lane, and the order entries of the next round
+            Piece v[kIter];
+            double qs = 0.0;
+            if (p_stage >= 0) {
+                const RADIO_GLOBAL Piece* src =
+                    gptr(reinterpret_cast<const Piece*>(recs + (int64_t)p_stage * n_states + s_a));
+#pragma unroll
+                for (int j = 0; j < kIter; ++j)
+                    if (r0 + j * kStageLanes < per)
+                        v[j] = src[r0 + j * kStageLanes];
+                if (r0 == 0)
+                    qs = charges ? charges[p_stage] : -1.0;
             }
-            if (tid < kGroups)
-                sh.sq[tid] = (tid < np) ? (charges ? charges[order[i0 + tid]] : -1.0) : 0.0;
+            double xs[3] = {0.0, 0.0, 0.0};
+            const bool scouting = active && p_scout >= 0;
+            if (scouting) {
+                const RADIO_GLOBAL double* x = first_position(p_scout, rb1 * kRunL);
+                xs[0] = x[0];
+                xs[1] = x[1];
+                xs[2] = x[2];
+            }
+            const int p_stage_next = lane_particle(rb1, bt1, gg);
+            const int p_scout_next = lane_particle(rb2, bt2, g);
+            if (p_stage >= 0) {
+                Piece* dst = reinterpret_cast<Piece*>(&sh.rec[gg][0]);
+#pragma unroll
+                for (int j = 0; j < kIter; ++j)
+                    if (r0 + j * kStageLanes < per)
+                        dst[r0 + j * kStageLanes] = v[j];
+                if (r0 == 0)
+                    sh.sq[gg] = qs;
+            }
+            if (scouting)
+                scout(xs, rb1 * kRunL, buf ^ 1);
+            p_stage = p_stage_next;
+            p_scout = p_scout_next;
         }
-        if (it + 1 < n_it)
-            scout(it + 1, buf ^ 1);
         __syncthreads();
         if (tid < kTileCells)  // read by every lane before the barrier; next used two batches on
             nb[buf * kTileCells + tid] = INT_MAX;
@@ -1214,6 +1274,10 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
             sink.flush((int)(C.J1 - 1.0), C.V);
         }
         __syncthreads();  // records and rings are free for the next batch
+        rb = rb1;
+        bt = bt1;
+        rb1 = rb2;
+        bt1 = bt2;
     }
     move_ring(-1);  // flush what the ring still holds
     if (n_clip)
@@ -1228,23 +1292,26 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
                                __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One workgroup per work item of a single deposit; the tiles that take the
-// other ring size leave at once.
+// The work items of a single deposit, item = split * n_tiles + tile: one per
+// workgroup, in passes of the grid when there are more items than workgroups
+// (gridDim.x is a multiple of kXcds); items whose tile takes the other ring
+// size are skipped at once.
 template <int M, int R, int G, int HOLD>
 __global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
 {
     __shared__ __align__(16) DepositShared<M, R> sh;
     // Workgroups are dealt round-robin over the XCDs; give each XCD a contiguous
-    // range of (split, tile) indices so that neighbouring tiles, whose particle
-    // orders and record batches are alike, share that XCD's L2.
+    // range of items, so that the workgroups resident on one XCD work on
+    // neighbouring tiles of the same runs, whose records and particle orders
+    // are alike, and share that XCD's L2.
+    const int64_t n_items = J.n_tiles * J.n_splits;
     const int64_t per_xcd = (int64_t)gridDim.x / kXcds;
-    const int64_t logical = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
-    if (logical >= J.n_tiles * J.n_splits)
-        return;
-    const int64_t tile = logical % J.n_tiles;
-    if (gptr(J.ring_sel)[tile] != (R == kRingLarge ? 1 : 0))
-        return;
-    deposit_item<M, R, G, HOLD>(J, tile, logical / J.n_tiles, sh);
+    const int64_t slot = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+    for (int64_t logical = slot; logical < n_items; logical += gridDim.x) {
+        const int64_t tile = logical % J.n_tiles;
+        if (gptr(J.ring_sel)[tile] == (R == kRingLarge ? 1 : 0))
+            deposit_item<M, R, G, HOLD>(J, tile, logical / J.n_tiles, sh);
+    }
 }
 
 // Persistent workgroups for many independent deposits: each takes the next work
@@ -1343,11 +1410,25 @@ __global__ void arrival_kernel(const double* cells, const double* pts, const dou
 
 }  // namespace
 
-void plan_job(DepositJob& job, int target_blocks)
+constexpr int64_t kMaxDepositGrid = int64_t(1) << 22;  // workgroups of one deposit launch
+
+void plan_job(DepositJob& job, int target_blocks, int64_t capacity)
 {
     job.n_runs = (job.n_s + kRunL - 1) / kRunL;
     job.n_tiles = (job.n_c + kTileCells - 1) / kTileCells;
-    int64_t splits = (target_blocks + job.n_tiles - 1) / job.n_tiles;
+    int64_t splits = 1;
+    if (target_blocks > 0) {
+        splits = (target_blocks + job.n_tiles - 1) / job.n_tiles;
+    } else {
+        // short items (at least kMinItemBatches batches, so that an item's
+        // set-up and final ring flush stay small), unless that leaves fewer
+        // items than the device holds at once
+        const int64_t n_batches = (job.n_p + kGroups - 1) / kGroups;
+        const int64_t rps = std::max<int64_t>(1, (kMinItemBatches + n_batches - 1) / std::max<int64_t>(n_batches, 1));
+        splits = (job.n_runs + rps - 1) / rps;
+        if (job.n_tiles * splits < capacity)
+            splits = job.n_runs;
+    }
     if (splits < 1)
         splits = 1;
     if (splits > job.n_runs)
@@ -1477,6 +1558,7 @@ hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s)
     if (blocks <= 0)
         return hipSuccess;
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;  // a multiple of the XCD count
+    blocks = std::min<int64_t>(blocks, kMaxDepositGrid);  // more items run in passes
     const int v = kernel_variant(mode, job);
     if (v < 0 || v >= kKernelVariants)
         return hipErrorInvalidValue;
@@ -1503,7 +1585,15 @@ int persistent_blocks_per_cu(int variant, bool large_ring)
 {
     if (variant < 0 || variant >= kKernelVariants)
         return 1;
-    return Variants::occupancy[variant](large_ring);
+    // a property of the code object: asked once per kernel
+    static std::atomic<int> known[kKernelVariants][2];
+    const int r = large_ring ? 1 : 0;
+    int n = known[variant][r].load(std::memory_order_relaxed);
+    if (n <= 0) {
+        n = Variants::occupancy[variant](large_ring);
+        known[variant][r].store(n, std::memory_order_relaxed);
+    }
+    return n;
 }
 
 hipError_t launch_readout(const double* acc, int64_t n_c, int64_t n_t, const int64_t* user_index,

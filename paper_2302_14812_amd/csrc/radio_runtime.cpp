@@ -19,6 +19,7 @@
 
 struct radio_detector {
     int device = 0;
+    int n_cus = 1;  // compute units of the device
     int32_t precision = RADIO_FP64;
     int64_t n_c = 0;
     int64_t n_t = 0;
@@ -50,7 +51,7 @@ namespace {
 
 // launch tunables (radio_set_tuning)
 std::mutex g_tuning_mu;
-radio_tuning g_tuning = {3072, 4};
+radio_tuning g_tuning = {0, 4};
 
 radio_tuning current_tuning()
 {
@@ -316,7 +317,9 @@ radio::DepositJob make_job(radio_detector* det, const radio_chunk* k)
     J.inv_dt_det = 1.0 / det->dt_det;
     J.inv_c = 1.0 / det->c;
     J.c = det->c;
-    radio::plan_job(J, current_tuning().target_blocks);
+    const int per_cu =
+        radio::persistent_blocks_per_cu(radio::kernel_variant(det->precision, J), false);
+    radio::plan_job(J, current_tuning().target_blocks, (int64_t)det->n_cus * per_cu);
     return J;
 }
 
@@ -485,7 +488,10 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
         po += (size_t)(J.n_tiles * J.n_p);
         so += (size_t)J.n_tiles;
         const double run_work = (double)radio::kTileCells * (double)J.n_p * (double)radio::kRunL;
-        int64_t rps = (int64_t)std::ceil(item_work / run_work);
+        // items of similar work, and short (see kMinItemBatches)
+        const int64_t n_batches = (J.n_p + radio::kGroups - 1) / radio::kGroups;
+        const int64_t rps_short = (radio::kMinItemBatches + n_batches - 1) / n_batches;
+        int64_t rps = std::min<int64_t>((int64_t)std::ceil(item_work / run_work), rps_short);
         rps = std::max<int64_t>(1, std::min<int64_t>(rps, J.n_runs));
         J.runs_per_split = rps;
         J.n_splits = (J.n_runs + rps - 1) / rps;
@@ -591,7 +597,10 @@ int radio_detector_create(const radio_detector_desc* desc, void* stream, radio_d
     radio_detector* det = new (std::nothrow) radio_detector();
     if (!det)
         return RADIO_ENOMEM;
-    if (hipGetDevice(&det->device) != hipSuccess) {
+    if (hipGetDevice(&det->device) != hipSuccess ||
+        hipDeviceGetAttribute(&det->n_cus, hipDeviceAttributeMultiprocessorCount, det->device) !=
+            hipSuccess) {
+        (void)hipGetLastError();
         delete det;
         return RADIO_EDEVICE;
     }
@@ -742,7 +751,7 @@ int radio_deposit_batch(radio_detector* const* dets, const radio_chunk* chunks, 
 
 int radio_set_tuning(const radio_tuning* t)
 {
-    if (!t || t->target_blocks < 1 || t->target_blocks > (1 << 24) || t->items_per_workgroup < 1 ||
+    if (!t || t->target_blocks < 0 || t->target_blocks > (1 << 24) || t->items_per_workgroup < 1 ||
         t->items_per_workgroup > 4096)
         return RADIO_EINVAL;
     std::lock_guard<std::mutex> lk(g_tuning_mu);

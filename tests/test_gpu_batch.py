@@ -116,7 +116,9 @@ def test_tuning_roundtrip(radio):
     radio.set_tuning(target_blocks=1024, items_per_workgroup=2)
     assert radio.get_tuning() == {"target_blocks": 1024, "items_per_workgroup": 2}
     with pytest.raises(radio.RadioError):
-        radio.set_tuning(target_blocks=0)
+        radio.set_tuning(target_blocks=-1)
+    radio.set_tuning(target_blocks=0)  # automatic splits
+    assert radio.get_tuning()["target_blocks"] == 0
     radio.set_tuning(**cur)
     assert radio.get_tuning() == cur
 
