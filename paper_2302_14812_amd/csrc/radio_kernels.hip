@@ -276,14 +276,16 @@ struct CellSink<float, R> {
 //
 // The carry keeps J + 1 as a double (J1) and the bound `lim` of the fast path:
 // a segment [a, b] with a <= b < lim starts in the open slot (a in [J, J+1)),
-// with J >= -1, and ends at most kFastSlots slots further and below n_t + 1.
-// lim is -inf whenever the next segment's start is not known to lie in the
-// open slot; that segment then takes the general path.
+// with J >= 0, and ends at most kFastSlots slots further and below n_t, so it
+// lies inside the window.  lim is -inf whenever the next segment's start is
+// not known to lie in an open slot of the window; that segment then takes the
+// general path, which also counts the segments that reach outside [0, n_t]
+// (clipped) and those that run backward.
 constexpr double kFastSlots = 6.0;
 
 template <typename T>
 struct Carry {
-    double J1;   // open slot + 1; the slot may be -1 or n_t, or far below 0 when none is open
+    double J1;   // open slot + 1; the slot may lie outside [0, n_t), far below 0 when none is open
     double lim;  // fast-path bound of the next segment
     T V[6];      // integral of the held field over the open slot so far
 };
@@ -300,8 +302,14 @@ __device__ __forceinline__ void carry_open(Carry<T>& C, double J)
 // the fast-path bound when the open slot is J and the next segment starts at a
 __device__ __forceinline__ double fast_limit(double J, double a, double ntd)
 {
-    return ((J >= -1.0) & (a >= J) & (a < J + 1.0)) ? fmin(J + (kFastSlots + 1.0), ntd + 1.0)
-                                                     : -INFINITY;
+    return ((J >= 0.0) & (a >= J) & (a < J + 1.0)) ? fmin(J + (kFastSlots + 1.0), ntd)
+                                                    : -INFINITY;
+}
+
+// a segment between a and b reaches outside the window [0, n_t]
+__device__ __forceinline__ unsigned clipped(double a, double b, double ntd)
+{
+    return (fmin(a, b) < 0.0 || fmax(a, b) > ntd) ? 1u : 0u;
 }
 
 // General case: hold F over the slot-coordinate interval between a and b,
@@ -311,10 +319,11 @@ __device__ __forceinline__ double fast_limit(double J, double a, double ntd)
 template <typename T, typename Sink>
 __device__ __forceinline__ void add_segment_general(Carry<T>& C, const Sink& sink, int n_t,
                                                     double a, double b, const T F[6],
-                                                    unsigned& n_back)
+                                                    unsigned& n_back, unsigned& n_clip)
 {
-    n_back += (b < a) ? 1u : 0u;
     const double ntd = (double)n_t;
+    n_back += (b < a) ? 1u : 0u;
+    n_clip += clipped(a, b, ntd);
     const double lo = fmin(fmax(fmin(a, b), 0.0), ntd);
     const double hi = fmin(fmax(fmax(a, b), 0.0), ntd);
     if (lo < hi) {  // else empty, entirely outside, or NaN
@@ -354,7 +363,8 @@ __device__ __forceinline__ void add_segment_general(Carry<T>& C, const Sink& sin
 // only.  Everything else goes through add_segment_general.
 template <typename T, typename Sink>
 __device__ __forceinline__ void add_segment(Carry<T>& C, const Sink& sink, int n_t, double a,
-                                            double b, const T F[6], unsigned& n_back)
+                                            double b, const T F[6], unsigned& n_back,
+                                            unsigned& n_clip)
 {
     if ((b >= a) & (b < C.lim)) {
         const T w0 = T(fmin(b, C.J1) - a);
@@ -373,10 +383,10 @@ __device__ __forceinline__ void add_segment(Carry<T>& C, const Sink& sink, int n
             for (int k = 0; k < 6; ++k)
                 C.V[k] = F[k] * wb;
             C.J1 = fb + 1.0;
-            C.lim = fmin(fb + (kFastSlots + 1.0), (double)n_t + 1.0);
+            C.lim = fmin(fb + (kFastSlots + 1.0), (double)n_t);
         }
     } else {
-        add_segment_general(C, sink, n_t, a, b, F, n_back);
+        add_segment_general(C, sink, n_t, a, b, F, n_back, n_clip);
     }
 }
 
@@ -396,10 +406,11 @@ template <typename T, typename Sink>
 __device__ __forceinline__ void add_segment_linear_general(Carry<T>& C, const Sink& sink, int n_t,
                                                            double a, double b, const T Fa[6],
                                                            const T dF[6], double inv_len,
-                                                           unsigned& n_back)
+                                                           unsigned& n_back, unsigned& n_clip)
 {
-    n_back += (b < a) ? 1u : 0u;
     const double ntd = (double)n_t;
+    n_back += (b < a) ? 1u : 0u;
+    n_clip += clipped(a, b, ntd);
     const double lo = fmin(fmax(fmin(a, b), 0.0), ntd);
     const double hi = fmin(fmax(fmax(a, b), 0.0), ntd);
     if (lo < hi) {
@@ -446,10 +457,13 @@ __device__ __forceinline__ void add_segment_linear_general(Carry<T>& C, const Si
 template <typename T, typename Sink>
 __device__ __forceinline__ void add_segment_linear(Carry<T>& C, const Sink& sink, int n_t,
                                                    double a, double b, const T Fa[6],
-                                                   const T Fb[6], unsigned& n_back)
+                                                   const T Fb[6], unsigned& n_back,
+                                                   unsigned& n_clip)
 {
-    if (a == b)  // no length: nothing to hold, and the carry still fits the next start
+    if (a == b) {  // no length: nothing to hold, and the carry still fits the next start
+        n_clip += clipped(a, b, (double)n_t);
         return;
+    }
     T dF[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k)
@@ -481,10 +495,10 @@ __device__ __forceinline__ void add_segment_linear(Carry<T>& C, const Sink& sink
             for (int k = 0; k < 6; ++k)
                 C.V[k] = F[k] * wb;
             C.J1 = fb + 1.0;
-            C.lim = fmin(fb + (kFastSlots + 1.0), (double)n_t + 1.0);
+            C.lim = fmin(fb + (kFastSlots + 1.0), (double)n_t);
         }
     } else {
-        add_segment_linear_general(C, sink, n_t, a, b, Fa, dF, inv_len, n_back);
+        add_segment_linear_general(C, sink, n_t, a, b, Fa, dF, inv_len, n_back, n_clip);
     }
 }
 
@@ -1249,22 +1263,17 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
             const bool inside = u_prev >= -1.0 && u_prev < ntd + 1.0;
             carry_open(C, inside ? floor(u_prev) : (double)(INT_MIN / 2));
             C.lim = fast_limit(C.J1 - 1.0, u_prev, ntd);
-            // a segment is clipped when either end lies outside [0, n_t]
-            bool out_prev = (u_prev < 0.0) | (u_prev > ntd);
             for (int k = 1; k <= len; ++k) {
                 T F[6];
                 sk += 1.0;
                 const double uk = field_at(sh.rec[g][k], clock(sk), F);
-                const bool out = (uk < 0.0) | (uk > ntd);
-                n_clip += (out | out_prev) ? 1u : 0u;
-                out_prev = out;
                 if constexpr (HOLD == 0) {
-                    add_segment(C, sink, n_t, u_prev, uk, F, n_back);
+                    add_segment(C, sink, n_t, u_prev, uk, F, n_back, n_clip);
                 } else {
                     if constexpr (HOLD == 1)
-                        add_segment(C, sink, n_t, u_prev, uk, Fp, n_back);
+                        add_segment(C, sink, n_t, u_prev, uk, Fp, n_back, n_clip);
                     else
-                        add_segment_linear(C, sink, n_t, u_prev, uk, Fp, F, n_back);
+                        add_segment_linear(C, sink, n_t, u_prev, uk, Fp, F, n_back, n_clip);
 #pragma unroll
                     for (int c = 0; c < 6; ++c)
                         Fp[c] = F[c];
@@ -1292,26 +1301,26 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
                                __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// The work items of a single deposit, item = split * n_tiles + tile: one per
-// workgroup, in passes of the grid when there are more items than workgroups
-// (gridDim.x is a multiple of kXcds); items whose tile takes the other ring
-// size are skipped at once.
+// The work items item0 + [0, gridDim.x) of a single deposit, item =
+// split * n_tiles + tile, one per workgroup (gridDim.x is a multiple of
+// kXcds); items whose tile takes the other ring size leave at once.
 template <int M, int R, int G, int HOLD>
-__global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J)
+__global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J, int64_t item0)
 {
     __shared__ __align__(16) DepositShared<M, R> sh;
     // Workgroups are dealt round-robin over the XCDs; give each XCD a contiguous
     // range of items, so that the workgroups resident on one XCD work on
     // neighbouring tiles of the same runs, whose records and particle orders
     // are alike, and share that XCD's L2.
-    const int64_t n_items = J.n_tiles * J.n_splits;
     const int64_t per_xcd = (int64_t)gridDim.x / kXcds;
-    const int64_t slot = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
-    for (int64_t logical = slot; logical < n_items; logical += gridDim.x) {
-        const int64_t tile = logical % J.n_tiles;
-        if (gptr(J.ring_sel)[tile] == (R == kRingLarge ? 1 : 0))
-            deposit_item<M, R, G, HOLD>(J, tile, logical / J.n_tiles, sh);
-    }
+    const int64_t logical =
+        item0 + (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+    if (logical >= J.n_tiles * J.n_splits)
+        return;
+    const int64_t tile = logical % J.n_tiles;
+    if (gptr(J.ring_sel)[tile] != (R == kRingLarge ? 1 : 0))
+        return;
+    deposit_item<M, R, G, HOLD>(J, tile, logical / J.n_tiles, sh);
 }
 
 // Persistent workgroups for many independent deposits: each takes the next work
@@ -1423,8 +1432,8 @@ void plan_job(DepositJob& job, int target_blocks, int64_t capacity)
         // short items (at least kMinItemBatches batches, so that an item's
         // set-up and final ring flush stay small), unless that leaves fewer
         // items than the device holds at once
-        const int64_t n_batches = (job.n_p + kGroups - 1) / kGroups;
-        const int64_t rps = std::max<int64_t>(1, (kMinItemBatches + n_batches - 1) / std::max<int64_t>(n_batches, 1));
+        const int64_t n_batches = std::max<int64_t>((job.n_p + kGroups - 1) / kGroups, 1);
+        const int64_t rps = std::max<int64_t>(1, (kMinItemBatches + n_batches - 1) / n_batches);
         splits = (job.n_runs + rps - 1) / rps;
         if (job.n_tiles * splits < capacity)
             splits = job.n_runs;
@@ -1497,10 +1506,14 @@ hipError_t launch_ring_choice(const DepositJob& job, int mode, hipStream_t s)
 template <int M, int G, int HOLD>
 static void launch_deposit_v(const DepositJob& job, dim3 grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((deposit_kernel<M, kRingSmall, G, HOLD>), grid, dim3(kDepositThreads), 0,
-                       s, job);
-    hipLaunchKernelGGL((deposit_kernel<M, kRingLarge, G, HOLD>), grid, dim3(kDepositThreads), 0,
-                       s, job);
+    // more items than one launch holds run in several launches
+    const int64_t n_items = job.n_tiles * job.n_splits;
+    for (int64_t item0 = 0; item0 < n_items; item0 += grid.x)
+        hipLaunchKernelGGL((deposit_kernel<M, kRingSmall, G, HOLD>), grid, dim3(kDepositThreads),
+                           0, s, job, item0);
+    for (int64_t item0 = 0; item0 < n_items; item0 += grid.x)
+        hipLaunchKernelGGL((deposit_kernel<M, kRingLarge, G, HOLD>), grid, dim3(kDepositThreads),
+                           0, s, job, item0);
 }
 
 template <int V>
@@ -1558,7 +1571,7 @@ hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s)
     if (blocks <= 0)
         return hipSuccess;
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;  // a multiple of the XCD count
-    blocks = std::min<int64_t>(blocks, kMaxDepositGrid);  // more items run in passes
+    blocks = std::min<int64_t>(blocks, kMaxDepositGrid);  // more items: several launches
     const int v = kernel_variant(mode, job);
     if (v < 0 || v >= kKernelVariants)
         return hipErrorInvalidValue;
