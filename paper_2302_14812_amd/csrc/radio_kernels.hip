@@ -44,6 +44,7 @@
 #include "radio_internal.h"
 
 #include <algorithm>
+
 #include <atomic>
 #include <climits>
 #include <type_traits>
@@ -985,6 +986,7 @@ struct DepositShared {
     double sq[kGroups];                 // its charges
     Acc ring[kTileCells * kStride];     // per-cell slot rings
     int nb[2][kTileCells];              // per cell: lowest start slot of a coming batch
+    int ord[2][kGroups];                // particles of the staged rows, per batch parity
     unsigned long long cnt[3];          // clipped, nonmonotone, bypassed
 };
 
@@ -1138,9 +1140,15 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         base = new_base;
     };
 
-    // staging: kStageLanes threads per particle; the thread index passes
-    // through an empty asm so that what is derived from it is recomputed per
-    // batch instead of being held in registers across the field loop
+    // Staging of a batch's records.  Single-precision kernels load them from
+    // HBM straight into LDS (no registers held for them, which keeps their
+    // register count at five wavefronts per SIMD); the double kernel, whose LDS
+    // allows four workgroups per CU anyway, stages through registers with
+    // kStageLanes threads per particle, which takes fewer instructions.  In
+    // the latter the thread index passes through an empty asm so that what is
+    // derived from it is recomputed per batch instead of being held in
+    // registers across the field loop.
+    constexpr bool kStageDirect = MIX;
     constexpr int kStageLanes = kDepositThreads / kGroups;
     int t_stage = tid;
     asm volatile("" : "+v"(t_stage));
@@ -1156,7 +1164,12 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
             const double xs[3] = {x[0], x[1], x[2]};
             scout(xs, rb * kRunL, 0);
         }
-        p_stage = lane_particle(rb, bt, t_stage / kStageLanes);
+        if constexpr (kStageDirect) {
+            if (tid < kGroups)
+                sh.ord[0][tid] = lane_particle(rb, bt, tid);
+        } else {
+            p_stage = lane_particle(rb, bt, t_stage / kStageLanes);
+        }
         p_scout = lane_particle(rb1, bt1, g);
     }
     __syncthreads();
@@ -1177,7 +1190,63 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         }
         int64_t rb2 = rb1, bt2 = bt1;  // the batch after the next
         advance(rb2, bt2);
-        {
+        if constexpr (kStageDirect) {
+            // The records go from HBM straight to LDS (16 bytes a lane, no
+            // registers): round c of a wavefront fills the 64 pieces from
+            // piece c * 64 of the staged batch, lane i piece c * 64 + i, i.e.
+            // row gg = piece / kPer, piece r = piece % kPer of that row's
+            // particle run.  With them, in the same round of loads: the
+            // batch's charges, the order entries of the next batch and the
+            // next batch's first positions for the ring.
+            static_assert(sizeof(Rec) % 16 == 0, "records move in 16-byte pieces");
+            constexpr int kPieces = (int)(sizeof(Rec) / 16);
+            constexpr int kPer = (kRunL + 1) * kPieces;
+            constexpr int kWaves = kDepositThreads / 64;
+            const int per = (len + 1) * kPieces;
+            const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+            const int lane = tid % 64;
+            RADIO_LDS char* rec_lds = (RADIO_LDS char*)&sh.rec[0][0];
+            const RADIO_GLOBAL char* rec_hbm = reinterpret_cast<const RADIO_GLOBAL char*>(gptr(recs));
+            constexpr int kRounds = (kGroups * kPer + kDepositThreads - 1) / kDepositThreads;
+            int part[kRounds];  // each round's particle, read before the first load writes LDS
+#pragma unroll
+            for (int j = 0; j < kRounds; ++j) {
+                const int gg = ((wave + j * kWaves) * 64 + lane) / kPer;
+                part[j] = sh.ord[buf][min(gg, kGroups - 1)];  // used only where gg < np
+            }
+#pragma unroll
+            for (int j = 0; j < kRounds; ++j) {
+                const int c = wave + j * kWaves;
+                const int P = c * 64 + lane;
+                const int gg = P / kPer;
+                const int r = P - gg * kPer;
+                if (gg < np && r < per)
+                    __builtin_amdgcn_global_load_lds(
+                        rec_hbm + ((int64_t)part[j] * n_states + s_a) * (int64_t)sizeof(Rec) + r * 16,
+                        rec_lds + c * 64 * 16, 16, 0, 0);
+            }
+            double qs = 0.0;
+            if (tid < np)
+                qs = charges ? charges[sh.ord[buf][tid]] : -1.0;
+            const int ord_next = tid < kGroups ? lane_particle(rb1, bt1, tid) : -1;
+            double xs[3] = {0.0, 0.0, 0.0};
+            const bool scouting = active && p_scout >= 0;
+            if (scouting) {
+                const RADIO_GLOBAL double* x = first_position(p_scout, rb1 * kRunL);
+                xs[0] = x[0];
+                xs[1] = x[1];
+                xs[2] = x[2];
+            }
+            const int p_scout_next = lane_particle(rb2, bt2, g);
+            if (tid < np)
+                sh.sq[tid] = qs;
+            if (tid < kGroups)
+                sh.ord[buf ^ 1][tid] = ord_next;
+            if (scouting)
+                scout(xs, rb1 * kRunL, buf ^ 1);
+            p_scout = p_scout_next;
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the records are in LDS
+        } else {
             // pieces of 16 bytes where the record size allows, else of 8
             using Piece = typename std::conditional<sizeof(Rec) % 16 == 0, v2i64, long long>::type;
             constexpr int kPieces = (int)(sizeof(Rec) / sizeof(Piece));
