@@ -277,12 +277,11 @@ struct CellSink<float, R> {
 //
 // The carry keeps J + 1 as a double (J1) and the bound `lim` of the fast path:
 // a segment [a, b] with a <= b < lim starts in the open slot (a in [J, J+1)),
-// with J >= 0, and ends at most kFastSlots slots further and below n_t, so it
-// lies inside the window.  lim is -inf whenever the next segment's start is
-// not known to lie in an open slot of the window; that segment then takes the
-// general path, which also counts the segments that reach outside [0, n_t]
-// (clipped) and those that run backward.
-constexpr double kFastSlots = 6.0;
+// with J >= 0, and ends below n_t, so it lies inside the window.  lim is n_t
+// while the next segment's start is known to lie in the open slot, inside the
+// window, and -inf otherwise; such a segment takes the general path, which
+// also counts the segments that reach outside [0, n_t] (clipped) and those
+// that run backward.
 
 template <typename T>
 struct Carry {
@@ -303,8 +302,7 @@ __device__ __forceinline__ void carry_open(Carry<T>& C, double J)
 // the fast-path bound when the open slot is J and the next segment starts at a
 __device__ __forceinline__ double fast_limit(double J, double a, double ntd)
 {
-    return ((J >= 0.0) & (a >= J) & (a < J + 1.0)) ? fmin(J + (kFastSlots + 1.0), ntd)
-                                                    : -INFINITY;
+    return ((J >= 0.0) & (a >= J) & (a < J + 1.0)) ? ntd : -INFINITY;
 }
 
 // a segment between a and b reaches outside the window [0, n_t]
@@ -374,17 +372,15 @@ __device__ __forceinline__ void add_segment(Carry<T>& C, const Sink& sink, int n
             C.V[k] += F[k] * w0;
         if (b >= C.J1) {  // the segment leaves the open slot
             const double fb = floor(b);
-            const int J = (int)C.J1 - 1;
-            const int n = (int)(fb - C.J1) + 1;  // slots crossed, 1 .. kFastSlots
-            sink.flush(J, C.V);
-            for (int i = 1; i < n; ++i)  // whole slots hold F
-                sink.flush(J + i, F);
+            sink.flush((int)C.J1 - 1, C.V);
+            if (fb > C.J1)  // whole slots J + 1 .. floor(b) - 1 hold F
+                for (int j = (int)C.J1; j < (int)fb; ++j)
+                    sink.flush(j, F);
             const T wb = T(b - fb);
 #pragma unroll
             for (int k = 0; k < 6; ++k)
                 C.V[k] = F[k] * wb;
             C.J1 = fb + 1.0;
-            C.lim = fmin(fb + (kFastSlots + 1.0), (double)n_t);
         }
     } else {
         add_segment_general(C, sink, n_t, a, b, F, n_back, n_clip);
@@ -482,7 +478,7 @@ __device__ __forceinline__ void add_segment_linear(Carry<T>& C, const Sink& sink
         if (b >= C.J1) {
             const double fb = floor(b);
             const int J = (int)C.J1 - 1;
-            const int n = (int)(fb - C.J1) + 1;
+            const int n = (int)(fb - C.J1) + 1;  // slots crossed
             sink.flush(J, C.V);
             for (int i = 1; i < n; ++i) {  // whole slots: the interpolant at their middle
                 lerp_field(Fa, dF, T(0.5 * ((Jd + (double)i - a) + (Jd + (double)(i + 1) - a)) *
@@ -496,7 +492,6 @@ __device__ __forceinline__ void add_segment_linear(Carry<T>& C, const Sink& sink
             for (int k = 0; k < 6; ++k)
                 C.V[k] = F[k] * wb;
             C.J1 = fb + 1.0;
-            C.lim = fmin(fb + (kFastSlots + 1.0), (double)n_t);
         }
     } else {
         add_segment_linear_general(C, sink, n_t, a, b, Fa, dF, inv_len, n_back, n_clip);
@@ -600,11 +595,13 @@ __device__ __forceinline__ double field_mixed(const double xc[3], const RecMix& 
     const double u = fma(R, K.kR, ub);
     double nd[3] = {d[0] * rinv, d[1] * rinv, d[2] * rinv};
     double wd[3] = {nd[0] - st.b[0], nd[1] - st.b[1], nd[2] - st.b[2]};
-    const double kap = 0.5 * ((wd[0] * wd[0] + wd[1] * wd[1] + wd[2] * wd[2]) + (double)st.g2if);
     const float n[3] = {(float)nd[0], (float)nd[1], (float)nd[2]};
     const float w[3] = {(float)wd[0], (float)wd[1], (float)wd[2]};
-    lw_fields<float>(n, w, __builtin_amdgcn_rcpf((float)kap), (float)rinv, st.g2if, st.bdf, qc, qv,
-                     1.0f, F);
+    // kappa = (|n - beta|^2 + 1/gamma^2) / 2: a sum of positive terms, formed in
+    // single precision from the double difference n - beta
+    const float kap = 0.5f * ((w[0] * w[0] + w[1] * w[1] + w[2] * w[2]) + st.g2if);
+    lw_fields<float>(n, w, __builtin_amdgcn_rcpf(kap), (float)rinv, st.g2if, st.bdf, qc, qv, 1.0f,
+                     F);
     return u;
 }
 
@@ -660,11 +657,11 @@ __device__ __forceinline__ double field_far_mixed(const double fc[4], double Rin
 {
     const double u = slot_far_mixed(fc, st.x, ub, K);
     const double wd[3] = {fc[0] - st.b[0], fc[1] - st.b[1], fc[2] - st.b[2]};
-    const double kap = 0.5 * ((wd[0] * wd[0] + wd[1] * wd[1] + wd[2] * wd[2]) + (double)st.g2if);
     const float n[3] = {(float)fc[0], (float)fc[1], (float)fc[2]};
     const float w[3] = {(float)wd[0], (float)wd[1], (float)wd[2]};
-    lw_fields<float>(n, w, __builtin_amdgcn_rcpf((float)kap), (float)Rinv, st.g2if, st.bdf, qc,
-                     qv, 1.0f, F);
+    const float kap = 0.5f * ((w[0] * w[0] + w[1] * w[1] + w[2] * w[2]) + st.g2if);
+    lw_fields<float>(n, w, __builtin_amdgcn_rcpf(kap), (float)Rinv, st.g2if, st.bdf, qc, qv, 1.0f,
+                     F);
     return u;
 }
 
@@ -1192,38 +1189,41 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         advance(rb2, bt2);
         if constexpr (kStageDirect) {
             // The records go from HBM straight to LDS (16 bytes a lane, no
-            // registers): round c of a wavefront fills the 64 pieces from
-            // piece c * 64 of the staged batch, lane i piece c * 64 + i, i.e.
-            // row gg = piece / kPer, piece r = piece % kPer of that row's
-            // particle run.  With them, in the same round of loads: the
-            // batch's charges, the order entries of the next batch and the
-            // next batch's first positions for the ring.
+            // registers).  A wavefront stages whole rows: row gg (the run of
+            // particle ord[gg], contiguous in HBM and in LDS) in rounds of 64
+            // pieces, lane i taking piece h * 64 + i.  The particle is the same
+            // for the whole wavefront, so the addressing is scalar but for the
+            // lane's offset.  With the records, in the same round of loads: the
+            // batch's charges, the order entries of the next batch and the next
+            // batch's first positions for the ring.
             static_assert(sizeof(Rec) % 16 == 0, "records move in 16-byte pieces");
             constexpr int kPieces = (int)(sizeof(Rec) / 16);
-            constexpr int kPer = (kRunL + 1) * kPieces;
+            constexpr int kPer = (kRunL + 1) * kPieces;  // pieces of a full row
             constexpr int kWaves = kDepositThreads / 64;
+            constexpr int kRowsPerWave = kGroups / kWaves;
+            constexpr int kHalves = (kPer + 63) / 64;  // rounds per row
             const int per = (len + 1) * kPieces;
             const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
             const int lane = tid % 64;
             RADIO_LDS char* rec_lds = (RADIO_LDS char*)&sh.rec[0][0];
             const RADIO_GLOBAL char* rec_hbm = reinterpret_cast<const RADIO_GLOBAL char*>(gptr(recs));
-            constexpr int kRounds = (kGroups * kPer + kDepositThreads - 1) / kDepositThreads;
-            int part[kRounds];  // each round's particle, read before the first load writes LDS
+            int part[kRowsPerWave];  // the rows' particles, read before the first load writes LDS
 #pragma unroll
-            for (int j = 0; j < kRounds; ++j) {
-                const int gg = ((wave + j * kWaves) * 64 + lane) / kPer;
-                part[j] = sh.ord[buf][min(gg, kGroups - 1)];  // used only where gg < np
-            }
+            for (int k = 0; k < kRowsPerWave; ++k)
+                part[k] = __builtin_amdgcn_readfirstlane(sh.ord[buf][wave + k * kWaves]);
 #pragma unroll
-            for (int j = 0; j < kRounds; ++j) {
-                const int c = wave + j * kWaves;
-                const int P = c * 64 + lane;
-                const int gg = P / kPer;
-                const int r = P - gg * kPer;
-                if (gg < np && r < per)
-                    __builtin_amdgcn_global_load_lds(
-                        rec_hbm + ((int64_t)part[j] * n_states + s_a) * (int64_t)sizeof(Rec) + r * 16,
-                        rec_lds + c * 64 * 16, 16, 0, 0);
+            for (int k = 0; k < kRowsPerWave; ++k) {
+                const int gg = wave + k * kWaves;
+                if (gg < np) {
+                    const RADIO_GLOBAL char* src =
+                        rec_hbm + ((int64_t)part[k] * n_states + s_a) * (int64_t)sizeof(Rec);
+#pragma unroll
+                    for (int h = 0; h < kHalves; ++h)
+                        if (h * 64 + lane < per)
+                            __builtin_amdgcn_global_load_lds(src + (h * 64 + lane) * 16,
+                                                             rec_lds + (gg * kPer + h * 64) * 16, 16,
+                                                             0, 0);
+                }
             }
             double qs = 0.0;
             if (tid < np)
