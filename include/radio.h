@@ -278,12 +278,14 @@ RADIO_API int radio_push(const radio_push_desc* d, int64_t n_particles, int64_t 
  *   d2I     DEVICE [n_cells][n_fft/2 + 1] in the caller's cell order, or NULL
  *   dIdw    DEVICE [n_fft/2 + 1], or NULL
  *   dIdO    DEVICE [n_cells] in the caller's cell order, or NULL
- * Work is enqueued on `stream`, after the deposits already there; the call
- * allocates a workspace of at most ~1 GiB (two complex arrays per group of
- * cells), waits for the stream and frees it before returning.  RADIO_EINVAL for
- * a bad n_fft or no output, RADIO_ENOMEM if the workspace cannot be had.
+ * Work is enqueued on `stream`, after the deposits already there, and the call
+ * waits for the stream before returning.  The detector keeps the workspace of
+ * d2I and dIdw (two complex arrays per group of cells: about 1 GiB, or
+ * 64 n_fft bytes when one cell needs more) for later spectra;
+ * radio_detector_destroy releases it.  RADIO_EINVAL for a bad n_fft or
+ * no output, RADIO_ENOMEM if the workspace cannot be had.
  */
-RADIO_API int radio_spectrum(const radio_detector* det, int64_t n_fft, const double* weights,
+RADIO_API int radio_spectrum(radio_detector* det, int64_t n_fft, const double* weights,
                              double* d2I, double* dIdw, double* dIdO, void* stream);
 
 /*

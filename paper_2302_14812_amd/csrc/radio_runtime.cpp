@@ -38,6 +38,8 @@ struct radio_detector {
     size_t sel_cap = 0;
     int32_t options = 0;                       // RADIO_FAR_FIELD | RADIO_ACCEL_ONLY
     double* d_far = nullptr;                   // FAR_FIELD: [n_c][4] n_cell, R_cell per row
+    double2* d_spec = nullptr;                 // spectrum workspace, grown on demand
+    size_t spec_cap = 0;                       // in complex values
     int64_t interactions = 0;
     int64_t chunks = 0;
     std::vector<double> h_cells;               // caller's order
@@ -686,6 +688,8 @@ int radio_detector_destroy(radio_detector* det)
             (void)hipFree(det->d_perm);
         if (det->d_sel)
             (void)hipFree(det->d_sel);
+        if (det->d_spec)
+            (void)hipFree(det->d_spec);
         if (det->d_far)
             (void)hipFree(det->d_far);
     }
@@ -879,7 +883,7 @@ int radio_push(const radio_push_desc* d, int64_t n_particles, int64_t n_steps, d
     return RADIO_OK;
 }
 
-int radio_spectrum(const radio_detector* det, int64_t n_fft, const double* weights, double* d2I,
+int radio_spectrum(radio_detector* det, int64_t n_fft, const double* weights, double* d2I,
                    double* dIdw, double* dIdO, void* stream)
 {
     if (!det || (!d2I && !dIdw && !dIdO))
@@ -904,11 +908,11 @@ int radio_spectrum(const radio_detector* det, int64_t n_fft, const double* weigh
     double2* w1 = nullptr;
     double* d_w = nullptr;
     int rc = RADIO_OK;
-    if ((d2I || dIdw) &&
-        (hipMalloc((void**)&w0, (size_t)(2 * G * N) * sizeof(double2)) != hipSuccess ||
-         hipMalloc((void**)&w1, (size_t)(2 * G * N) * sizeof(double2)) != hipSuccess)) {
-        (void)hipGetLastError();
-        rc = RADIO_ENOMEM;
+    if (d2I || dIdw) {
+        // the two work arrays, kept by the detector for later spectra
+        rc = grow(&det->d_spec, &det->spec_cap, (size_t)(4 * G * N));
+        w0 = det->d_spec;
+        w1 = det->d_spec + 2 * G * N;
     }
     if (rc == RADIO_OK && weights && dIdw) {
         if (hipMalloc((void**)&d_w, (size_t)det->n_c * sizeof(double)) != hipSuccess) {
@@ -935,10 +939,6 @@ int radio_spectrum(const radio_detector* det, int64_t n_fft, const double* weigh
         rc = RADIO_EDEVICE;
     if (hipStreamSynchronize(s) != hipSuccess && rc == RADIO_OK)
         rc = RADIO_EDEVICE;
-    if (w0)
-        (void)hipFree(w0);
-    if (w1)
-        (void)hipFree(w1);
     if (d_w)
         (void)hipFree(d_w);
     return rc;

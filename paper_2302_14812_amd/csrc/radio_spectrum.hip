@@ -11,16 +11,23 @@
 // at omega_m = 2 pi m / (N dt), m = 0 .. N/2, the signal zero beyond its
 // n_t slots (N a power of two >= n_t).
 //
-// Kernels, per group of cells that fits the workspace:
-//   spec_load_kernel   packs Ex + i Ey and Ez + 0i of each cell as two complex
-//                      signals of length N (zero padded);
-//   spec_fft_pass      one radix-2 Stockham pass (natural order in and out,
-//                      no bit reversal), log2(N) launches ping-ponging
-//                      between two buffers;
-//   spec_power_kernel  one thread per frequency: |X|^2 + |Y|^2 of the two
-//                      real signals packed in Z from Z(m) and Z(N - m),
-//                      scaled to d2I, and the weighted sum over the group's
-//                      cells added to dI/domega;
+// Each cell gives two complex signals of length N (zero padded): Ex + i Ey and
+// Ez + 0i.  Kernels, per group of cells that fits the workspace:
+//   spec_cols_kernel   (N = N1 * N2, N1 and N2 <= kFftTile) the first of the
+//                      two steps of the four-step FFT: with n = N2 n1 + n2,
+//                      tiles of columns (fixed n2, n1 = 0 .. N1 - 1) are read
+//                      from the detector, transformed in LDS, multiplied by
+//                      exp(-2 pi i n2 k1 / N) and stored at N2 k1 + n2;
+//   spec_rows_kernel   the second step: tiles of rows (fixed k1, contiguous)
+//                      transformed in LDS and stored at k1 + N1 k2, the
+//                      spectrum in natural order.  For N <= kFftTile the
+//                      first step alone is the transform (N2 = 1);
+//   spec_load_kernel + spec_fft_pass   for N > kFftTile^2: packing, then
+//                      log2(N) radix-2 Stockham passes between two buffers;
+//   spec_power_kernel  a thread per frequency and block of cells: |X|^2 +
+//                      |Y|^2 of the two real signals packed in Z from Z(m)
+//                      and Z(N - m), scaled to d2I, and the weighted sum over
+//                      its cells added to dI/domega (atomically);
 // and spec_parseval_kernel, one workgroup per cell, for dI/dOmega.
 #include "radio_internal.h"
 
@@ -29,6 +36,164 @@ namespace radio {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+constexpr int kFftTileLg = 11;
+constexpr int kFftTile = 1 << kFftTileLg;  // complex values transformed per workgroup in LDS
+constexpr int kFftThreads = 256;
+
+// value n (< N) of signal s (2 g: Ex + i Ey of cell r0 + g; 2 g + 1: Ez) of the
+// detector's accumulator; zero past its n_t slots
+template <bool PAIRS>
+__device__ __forceinline__ double2 signal_at(const double* __restrict__ acc, int64_t n_t,
+                                             int64_t r0, int64_t s, int64_t n)
+{
+    if (n >= n_t)
+        return make_double2(0.0, 0.0);
+    const int64_t i = (r0 + (s >> 1)) * n_t + n;
+    double e[3];
+    if (PAIRS) {
+        const float* q = reinterpret_cast<const float*>(acc) + i * 12;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            e[k] = (double)q[k] + (double)q[6 + k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            e[k] = acc[i * 6 + k];
+    }
+    return (s & 1) ? make_double2(e[2], 0.0) : make_double2(e[0], e[1]);
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// exp(-2 pi i k / len) for k = 0 .. len/2 - 1, into tw
+__device__ __forceinline__ void fill_twiddles(double2* tw, int len)
+{
+    for (int k = threadIdx.x; k < len / 2; k += blockDim.x) {
+        double sn, cs;
+        sincospi(-2.0 * (double)k / (double)len, &sn, &cs);
+        tw[k] = make_double2(cs, sn);
+    }
+}
+
+// In-place radix-2 transform (decimation in time) of T sequences of length
+// len = 2^lg in LDS, sequence t at buf[t * len], loaded in bit-reversed order;
+// leaves them in natural order.  Ends with a barrier.
+__device__ __forceinline__ void lds_fft(double2* buf, const double2* tw, int lg, int T)
+{
+    const int len = 1 << lg;
+    const int halfn = len >> 1;
+    for (int h = 1, tws = halfn; h < len; h <<= 1, tws >>= 1) {
+        __syncthreads();
+        for (int b = threadIdx.x; b < T * halfn; b += blockDim.x) {
+            const int t = b >> (lg - 1);
+            const int i = b & (halfn - 1);
+            const int k = i & (h - 1);
+            double2* x = buf + t * len + ((i - k) << 1) + k;
+            const double2 a = x[0];
+            const double2 c = cmul(x[h], tw[k * tws]);
+            x[0] = make_double2(a.x + c.x, a.y + c.y);
+            x[h] = make_double2(a.x - c.x, a.y - c.y);
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int bitrev(int v, int lg)
+{
+    return lg == 0 ? 0 : (int)(__builtin_bitreverse32((unsigned)v) >> (32 - lg));
+}
+
+// First step: tile = T columns c (c = s * N2 + n2 over the group's 2 G signals)
+// of N1 = 2^lg1 values each.  Output Y[s][N2 k1 + n2] = twiddled column FFTs.
+template <bool PAIRS>
+__global__ __launch_bounds__(kFftThreads) void spec_cols_kernel(const double* __restrict__ acc,
+                                                                 int64_t n_t, int64_t r0,
+                                                                 int64_t n_sig, int lg1, int lg2,
+                                                                 double2* __restrict__ Y)
+{
+    extern __shared__ double2 lds[];
+    const int N1 = 1 << lg1;
+    const int64_t N2 = (int64_t)1 << lg2;
+    const int64_t N = (int64_t)N1 * N2;
+    const int lgT = kFftTileLg - lg1;  // lg1 <= kFftTileLg
+    const int T = 1 << lgT;             // columns per tile
+    double2* buf = lds;
+    double2* tw = lds + T * N1;
+    const int64_t c0 = (int64_t)blockIdx.x * T;
+    const int64_t n_cols = n_sig * N2;
+    fill_twiddles(tw, N1);
+    // load: consecutive threads take consecutive columns of one row n1
+    for (int e = threadIdx.x; e < T * N1; e += blockDim.x) {
+        const int n1 = e >> lgT;
+        const int t = e & (T - 1);
+        const int64_t c = c0 + t;
+        double2 v = make_double2(0.0, 0.0);
+        if (c < n_cols) {
+            const int64_t sg = c >> lg2;
+            const int64_t n2 = c & (N2 - 1);
+            v = signal_at<PAIRS>(acc, n_t, r0, sg, N2 * n1 + n2);
+        }
+        buf[t * N1 + bitrev(n1, lg1)] = v;
+    }
+    lds_fft(buf, tw, lg1, T);
+    for (int e = threadIdx.x; e < T * N1; e += blockDim.x) {
+        const int k1 = e >> lgT;
+        const int t = e & (T - 1);
+        const int64_t c = c0 + t;
+        if (c >= n_cols)
+            continue;
+        const int64_t sg = c >> lg2;
+        const int64_t n2 = c & (N2 - 1);
+        double2 v = buf[t * N1 + k1];
+        if (lg2 > 0) {
+            // exp(-2 pi i n2 k1 / N), argument reduced exactly
+            const int64_t r = (n2 * (int64_t)k1) & (N - 1);
+            double sn, cs;
+            sincospi(-2.0 * (double)r / (double)N, &sn, &cs);
+            v = cmul(v, make_double2(cs, sn));
+        }
+        Y[sg * N + N2 * k1 + n2] = v;
+    }
+}
+
+// Second step: tile = R rows (k1) of N2 = 2^lg2 contiguous values of one
+// signal; X[s][k1 + N1 k2] = FFT over n2 of Y[s][N2 k1 + n2].
+__global__ __launch_bounds__(kFftThreads) void spec_rows_kernel(const double2* __restrict__ Y,
+                                                                 int64_t n_sig, int lg1, int lg2,
+                                                                 double2* __restrict__ X)
+{
+    extern __shared__ double2 lds[];
+    const int64_t N1 = (int64_t)1 << lg1;
+    const int N2 = 1 << lg2;
+    const int64_t N = N1 * N2;
+    const int lgR = kFftTileLg - lg2;  // lg2 <= kFftTileLg <= lg1 + lg2
+    const int R = 1 << lgR;             // rows per tile (N1 is a multiple of R)
+    double2* buf = lds;
+    double2* tw = lds + R * N2;
+    const int64_t tiles_per_sig = N1 / R;
+    const int64_t sg = blockIdx.x / tiles_per_sig;
+    const int64_t k10 = (blockIdx.x - sg * tiles_per_sig) * R;
+    if (sg >= n_sig)
+        return;
+    fill_twiddles(tw, N2);
+    const double2* y = Y + sg * N + N2 * k10;  // R contiguous rows
+    for (int e = threadIdx.x; e < R * N2; e += blockDim.x) {
+        const int r = e >> lg2;
+        const int n2 = e & (N2 - 1);
+        buf[r * N2 + bitrev(n2, lg2)] = y[e];
+    }
+    lds_fft(buf, tw, lg2, R);
+    // store: consecutive threads take consecutive rows of one k2
+    double2* x = X + sg * N + k10;
+    for (int e = threadIdx.x; e < R * N2; e += blockDim.x) {
+        const int k2 = e >> lgR;
+        const int r = e & (R - 1);
+        x[N1 * k2 + r] = buf[r * N2 + k2];
+    }
+}
 
 template <bool PAIRS>
 __global__ __launch_bounds__(256) void spec_load_kernel(const double* __restrict__ acc,
@@ -86,11 +251,15 @@ __global__ __launch_bounds__(256) void spec_fft_pass(const double2* __restrict__
     }
 }
 
+// d2I of kPowerCells cells of the group per thread, one thread per frequency
+// m of a block; their weighted sum is added to dIdw[m] (zeroed beforehand)
+constexpr int kPowerCells = 16;
+
 __global__ __launch_bounds__(256) void spec_power_kernel(
     const double2* __restrict__ Z, int64_t N, int64_t G, int64_t r0,
     const double* __restrict__ cells, const int64_t* __restrict__ user_index,
     const double* __restrict__ weights, double dt, double c, double* __restrict__ d2I,
-    double* __restrict__ dIdw, bool first_group)
+    double* __restrict__ dIdw)
 {
     const int64_t n_f = N / 2 + 1;
     const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -105,8 +274,10 @@ __global__ __launch_bounds__(256) void spec_power_kernel(
         W2 = s * s;
     }
     const int64_t mm = (N - m) & (N - 1);
-    double sum = (first_group || !dIdw) ? 0.0 : dIdw[m];
-    for (int64_t g = 0; g < G; ++g) {
+    double sum = 0.0;
+    const int64_t g0 = (int64_t)blockIdx.y * kPowerCells;
+    const int64_t g1 = g0 + kPowerCells < G ? g0 + kPowerCells : G;
+    for (int64_t g = g0; g < g1; ++g) {
         const double2* z1 = Z + (2 * g) * N;
         const double2* z2 = z1 + N;
         const double p = 0.5 * ((z1[m].x * z1[m].x + z1[m].y * z1[m].y) +
@@ -123,7 +294,14 @@ __global__ __launch_bounds__(256) void spec_power_kernel(
         sum += (weights ? weights[cell] : 1.0) * S;
     }
     if (dIdw)
-        dIdw[m] = sum;
+        unsafeAtomicAdd(dIdw + m, sum);
+}
+
+__global__ __launch_bounds__(256) void spec_zero_kernel(double* __restrict__ p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
 }
 
 template <bool PAIRS>
@@ -165,6 +343,23 @@ __global__ __launch_bounds__(256) void spec_parseval_kernel(const double* __rest
     }
 }
 
+unsigned grid_for(int64_t n);
+
+// power spectra of a group from its transforms Z in natural order; dIdw is
+// zeroed before the first group adds to it
+hipError_t launch_power(const double2* Z, int64_t N, int64_t G, int64_t r0, const double* cells,
+                        const int64_t* user_index, const double* weights, double dt, double c,
+                        double* d2I, double* dIdw, bool first_group, hipStream_t s)
+{
+    const int64_t n_f = N / 2 + 1;
+    if (dIdw && first_group)
+        hipLaunchKernelGGL(spec_zero_kernel, dim3(grid_for(n_f)), dim3(256), 0, s, dIdw, n_f);
+    const dim3 grid((unsigned)((n_f + 255) / 256), (unsigned)((G + kPowerCells - 1) / kPowerCells));
+    hipLaunchKernelGGL(spec_power_kernel, grid, dim3(256), 0, s, Z, N, G, r0, cells, user_index,
+                       weights, dt, c, d2I, dIdw);
+    return hipGetLastError();
+}
+
 unsigned grid_for(int64_t n)
 {
     int64_t b = (n + 255) / 256;
@@ -179,6 +374,38 @@ hipError_t launch_spectrum_group(const double* acc, bool pairs, int64_t n_t, int
                                  double c, double2* work0, double2* work1, double* d2I,
                                  double* dIdw, bool first_group, hipStream_t s)
 {
+    int lg = 0;
+    while (((int64_t)1 << lg) < N)
+        ++lg;
+    if (N <= (int64_t)kFftTile * kFftTile) {
+        // four-step: N1 = 2^lg1 in the columns step, N2 = 2^lg2 in the rows
+        // step, both <= kFftTile; LDS per workgroup <= 48 KiB
+        const int lg1 = lg <= kFftTileLg ? lg : (lg + 1) / 2;
+        const int lg2 = lg - lg1;
+        const int64_t n_sig = 2 * G;
+        const int T = kFftTile >> lg1;
+        const int64_t n_cols = n_sig << lg2;
+        const unsigned blocks_a = (unsigned)((n_cols + T - 1) / T);
+        const size_t lds_a = ((size_t)T * ((size_t)1 << lg1) + ((size_t)1 << lg1) / 2 + 1) *
+                             sizeof(double2);
+        double2* out_a = lg2 > 0 ? work0 : work1;
+        if (pairs)
+            hipLaunchKernelGGL(spec_cols_kernel<true>, dim3(blocks_a), dim3(kFftThreads), lds_a, s,
+                               acc, n_t, r0, n_sig, lg1, lg2, out_a);
+        else
+            hipLaunchKernelGGL(spec_cols_kernel<false>, dim3(blocks_a), dim3(kFftThreads), lds_a, s,
+                               acc, n_t, r0, n_sig, lg1, lg2, out_a);
+        if (lg2 > 0) {
+            const int R = kFftTile >> lg2;
+            const unsigned blocks_b = (unsigned)(n_sig * (((int64_t)1 << lg1) / R));
+            const size_t lds_b = ((size_t)R * ((size_t)1 << lg2) + ((size_t)1 << lg2) / 2 + 1) *
+                                 sizeof(double2);
+            hipLaunchKernelGGL(spec_rows_kernel, dim3(blocks_b), dim3(kFftThreads), lds_b, s, work0,
+                               n_sig, lg1, lg2, work1);
+        }
+        return launch_power(work1, N, G, r0, cells, user_index, weights, dt, c, d2I, dIdw,
+                            first_group, s);
+    }
     if (pairs)
         hipLaunchKernelGGL(spec_load_kernel<true>, dim3(grid_for(G * N)), dim3(256), 0, s, acc,
                            n_t, r0, G, N, work0);
@@ -194,10 +421,8 @@ hipError_t launch_spectrum_group(const double* acc, bool pairs, int64_t n_t, int
         x = y;
         y = t;
     }
-    const int64_t n_f = N / 2 + 1;
-    hipLaunchKernelGGL(spec_power_kernel, dim3((unsigned)((n_f + 255) / 256)), dim3(256), 0, s, x,
-                       N, G, r0, cells, user_index, weights, dt, c, d2I, dIdw, first_group);
-    return hipGetLastError();
+    return launch_power(x, N, G, r0, cells, user_index, weights, dt, c, d2I, dIdw, first_group,
+                        s);
 }
 
 hipError_t launch_spectrum_parseval(const double* acc, bool pairs, int64_t n_c, int64_t n_t,

@@ -27,11 +27,14 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b)) / (nb if nb > 0 else 1.0)
 
 
-@pytest.mark.parametrize("n_t,n_fft,precision", [(256, 0, "fp64"), (300, 0, "fp64"),
-                                                 (300, 2048, "mixed"), (200, 0, "mixed_twosum")])
-def test_spectrum_matches_oracle(radio, n_t, n_fft, precision):
+# transform sizes: one LDS tile (up to 2048), the two-step transform (4096,
+# 8192) and the radix-2 passes beyond 2^22
+@pytest.mark.parametrize("n_t,n_fft,precision,n_side", [
+    (256, 0, "fp64", 6), (300, 0, "fp64", 6), (300, 2048, "mixed", 6), (200, 0, "mixed_twosum", 6),
+    (3000, 0, "fp64", 6), (300, 8192, "mixed", 6), (300, 1 << 23, "fp64", 2)])
+def test_spectrum_matches_oracle(radio, n_t, n_fft, precision, n_side):
     import torch
-    wl = W.undulator_workload(n_particles=30, n_steps=200, n_side=6, n_t=n_t)
+    wl = W.undulator_workload(n_particles=30, n_steps=200, n_side=n_side, n_t=n_t)
     det = radio.Detector.from_spec(wl.detector, precision=precision)
     det.deposit(radio.Chunk.from_numpy(wl.chunk))
     rng = np.random.Generator(np.random.PCG64(n_t))
