@@ -385,7 +385,7 @@ def cpu_baseline(wl, n_cells):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     threads = max(1, min(threads, os.cpu_count() or 1))
     if n_cells <= 0:
-        n_cells = 2 * threads
+        n_cells = 6 * threads  # about 15 s of oracle work on the benchmark workload
     n_c = wl.detector.n_cells
     idx = np.linspace(0, n_c - 1, n_cells).round().astype(np.int64)
     t0 = time.perf_counter()

@@ -199,12 +199,16 @@ RADIO_API int radio_deposit_batch(radio_detector* const* dets, const radio_chunk
  *   target_blocks        workgroups aimed at by a single deposit (the runs of a
  *                        chunk are split until tiles x splits reaches it); 0, the
  *                        default, splits into short items of one run or a few
+ *   max_grid             workgroups of one launch of a single deposit (1 ..
+ *                        2^22, the default): more work items run as several
+ *                        launches
  *   items_per_workgroup  work items per resident workgroup in a batched deposit
  *                        (finer items balance uneven jobs, coarser ones cost less)
  */
 typedef struct radio_tuning {
     int32_t target_blocks;
     int32_t items_per_workgroup;
+    int32_t max_grid;
 } radio_tuning;
 
 RADIO_API int radio_set_tuning(const radio_tuning* t);

@@ -75,7 +75,8 @@ class _Push(ctypes.Structure):
 
 
 class _Tuning(ctypes.Structure):
-    _fields_ = [("target_blocks", ctypes.c_int32), ("items_per_workgroup", ctypes.c_int32)]
+    _fields_ = [("target_blocks", ctypes.c_int32), ("items_per_workgroup", ctypes.c_int32),
+                ("max_grid", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -376,14 +377,18 @@ def deposit_batch(detectors: Sequence[Detector], chunks: Sequence[Chunk], stream
 def get_tuning() -> dict:
     t = _Tuning()
     _check(_lib().radio_get_tuning(ctypes.byref(t)), "radio_get_tuning")
-    return {"target_blocks": int(t.target_blocks), "items_per_workgroup": int(t.items_per_workgroup)}
+    return {"target_blocks": int(t.target_blocks), "items_per_workgroup": int(t.items_per_workgroup),
+            "max_grid": int(t.max_grid)}
 
 
-def set_tuning(target_blocks: Optional[int] = None, items_per_workgroup: Optional[int] = None) -> None:
+def set_tuning(target_blocks: Optional[int] = None, items_per_workgroup: Optional[int] = None,
+               max_grid: Optional[int] = None) -> None:
+    """Set the launch tunables (radio_tuning); unnamed ones keep their values."""
     cur = get_tuning()
-    t = _Tuning(int(target_blocks if target_blocks is not None else cur["target_blocks"]),
-                int(items_per_workgroup if items_per_workgroup is not None
-                    else cur["items_per_workgroup"]))
+    new = {"target_blocks": target_blocks, "items_per_workgroup": items_per_workgroup,
+           "max_grid": max_grid}
+    t = _Tuning(*[int(new[k] if new[k] is not None else cur[k])
+                  for k in ("target_blocks", "items_per_workgroup", "max_grid")])
     _check(_lib().radio_set_tuning(ctypes.byref(t)), "radio_set_tuning")
 
 

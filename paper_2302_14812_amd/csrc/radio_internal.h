@@ -123,7 +123,7 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
 hipError_t launch_kinematics(const DepositJob& job, int mode, hipStream_t s);
 hipError_t launch_order(const DepositJob& job, hipStream_t s);
 hipError_t launch_ring_choice(const DepositJob& job, int mode, hipStream_t s);
-hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s);
+hipError_t launch_deposit(const DepositJob& job, int mode, int64_t max_grid, hipStream_t s);
 // Deposit kernel variants: v = mode + 3 * (G + 4 * hold), G = far + 2 * potentials.
 constexpr int kKernelVariants = 36;
 inline int kernel_variant(int mode, const DepositJob& J)

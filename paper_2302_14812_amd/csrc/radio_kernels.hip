@@ -1634,13 +1634,15 @@ constexpr VariantTable<V...> make_table(std::integer_sequence<int, V...>)
 }
 using Variants = decltype(make_table(std::make_integer_sequence<int, kKernelVariants>{}));
 
-hipError_t launch_deposit(const DepositJob& job, int mode, hipStream_t s)
+hipError_t launch_deposit(const DepositJob& job, int mode, int64_t max_grid, hipStream_t s)
 {
     int64_t blocks = job.n_tiles * job.n_splits;
     if (blocks <= 0)
         return hipSuccess;
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;  // a multiple of the XCD count
-    blocks = std::min<int64_t>(blocks, kMaxDepositGrid);  // more items: several launches
+    // more items than max_grid (and kMaxDepositGrid) run in several launches
+    const int64_t cap = std::max<int64_t>(kXcds, std::min<int64_t>(max_grid, kMaxDepositGrid));
+    blocks = std::min<int64_t>(blocks, cap / kXcds * kXcds);
     const int v = kernel_variant(mode, job);
     if (v < 0 || v >= kKernelVariants)
         return hipErrorInvalidValue;

@@ -53,7 +53,7 @@ namespace {
 
 // launch tunables (radio_set_tuning)
 std::mutex g_tuning_mu;
-radio_tuning g_tuning = {0, 4};
+radio_tuning g_tuning = {0, 4, 1 << 22};
 
 radio_tuning current_tuning()
 {
@@ -370,7 +370,7 @@ int enqueue_deposit(radio_detector* det, const radio_chunk* k, hipStream_t s)
     if (radio::launch_kinematics(J, det->precision, s) != hipSuccess ||
         radio::launch_order(J, s) != hipSuccess ||
         radio::launch_ring_choice(J, det->precision, s) != hipSuccess ||
-        radio::launch_deposit(J, det->precision, s) != hipSuccess)
+        radio::launch_deposit(J, det->precision, current_tuning().max_grid, s) != hipSuccess)
         return RADIO_EDEVICE;
     det->interactions += k->n_particles * k->n_steps * det->n_c;
     return RADIO_OK;
@@ -756,7 +756,7 @@ int radio_deposit_batch(radio_detector* const* dets, const radio_chunk* chunks, 
 int radio_set_tuning(const radio_tuning* t)
 {
     if (!t || t->target_blocks < 0 || t->target_blocks > (1 << 24) || t->items_per_workgroup < 1 ||
-        t->items_per_workgroup > 4096)
+        t->items_per_workgroup > 4096 || t->max_grid < 1 || t->max_grid > (1 << 22))
         return RADIO_EINVAL;
     std::lock_guard<std::mutex> lk(g_tuning_mu);
     g_tuning = *t;

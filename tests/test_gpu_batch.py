@@ -114,7 +114,12 @@ def test_batch_rejects_invalid_pairs_without_work(radio, sets):
 def test_tuning_roundtrip(radio):
     cur = radio.get_tuning()
     radio.set_tuning(target_blocks=1024, items_per_workgroup=2)
-    assert radio.get_tuning() == {"target_blocks": 1024, "items_per_workgroup": 2}
+    assert radio.get_tuning() == {"target_blocks": 1024, "items_per_workgroup": 2,
+                                  "max_grid": cur["max_grid"]}
+    with pytest.raises(radio.RadioError):
+        radio.set_tuning(max_grid=0)
+    with pytest.raises(radio.RadioError):
+        radio.set_tuning(max_grid=(1 << 22) + 1)
     with pytest.raises(radio.RadioError):
         radio.set_tuning(target_blocks=-1)
     radio.set_tuning(target_blocks=0)  # automatic splits

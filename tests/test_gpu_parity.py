@@ -127,6 +127,29 @@ def test_parity_random_ragged(radio, precision, seed, n_p, n_s, n_side, n_t, cli
         assert cnt[0] > 0
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_deposit_in_several_launches(radio, precision):
+    """Work items beyond one launch's grid (max_grid) run as further launches with
+    an item offset: the result equals the single launch and the oracle."""
+    chunk = W.random_chunk(33, 95, seed=5, dt=0.07, gamma_max=30.0, t_first=1.5)
+    cells = W.plane_cells([1.0, -2.0, 30.0], [1, 0.2, 0], [0, 1, 0.1], 17, 31, 12.0, 9.0)
+    t0, dtd = _window(cells, chunk, 200)
+    spec = W.DetectorSpec(cells=cells, t0=t0, dt_det=dtd, n_t=200)
+    E1, B1, _ = gpu_deposit(radio, spec, chunk, precision)
+    cur = radio.get_tuning()
+    try:
+        radio.set_tuning(max_grid=24)  # 33 tiles x 6 runs = 198 items: 9 launches of 24
+        E2, B2, st = gpu_deposit(radio, spec, chunk, precision)
+    finally:
+        radio.set_tuning(**cur)
+    assert st["interactions"] == 33 * 95 * 17 * 31
+    e = max(rel_l2(E2, E1), rel_l2(B2, B1))
+    print(f"[launches] {precision}: several launches vs one relL2 {e:.3e}", flush=True)
+    assert e <= (1e-13 if precision == "fp64" else 1e-6)
+    Eo, Bo, _ = oracle_deposit(spec, chunk)
+    check_parity(E2, B2, Eo, Bo, TOLS[precision], f"several launches {precision}")
+
+
 @PRECISIONS
 def test_parity_undulator_small(radio, precision):
     wl = W.undulator_workload(n_particles=64, n_steps=600, n_side=24, n_t=512)
