@@ -39,7 +39,9 @@ def parse():
     ap.add_argument("--twosum", action="store_true",
                     help="also time the compensated single-precision accumulation")
     ap.add_argument("--cpu-cells", type=int, default=0,
-                    help="cells in the oracle sample (default: two per host thread)")
+                    help="cells in the oracle sample (default: six per host thread)")
+    ap.add_argument("--no-atomics", action="store_true",
+                    help="skip the atomic-add throughput measurement")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-launch leg (64 uneven sets, one persistent launch "
                          "vs 64 separate launches)")
@@ -378,6 +380,29 @@ def measured_traffic(precision, workload):
     return None if leg is None else leg["hbm_bytes"]
 
 
+def atomics_leg():
+    """Floating-point atomic-add throughput of the GPU (the measurement program built
+    with the library), the rates the deposit's ring flushes and slot emissions run
+    against.  Runs as a child process, so it is called before this process touches
+    the GPU, and not at all under a profiler (whose preloaded library has touched it
+    already)."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_2302_14812_amd", "radio_atomics_bench")
+    if not os.path.exists(exe):
+        return {"skipped": "measurement program not built"}
+    if "rocprof" in os.environ.get("LD_PRELOAD", "") or any(k.startswith("ROCPROF")
+                                                             for k in os.environ):
+        return {"skipped": "under a profiler"}
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    if r.returncode != 0:
+        return {"failed": r.returncode, "stderr": r.stderr[-400:]}
+    res = json.loads(r.stdout.strip().splitlines()[-1])
+    print(f"[bench] atomics: global f64 {res['global_f64_spread']:.3e}/s coalesced, "
+          f"{res['global_f64_wave']:.3e}/s one address per wave; LDS f64 "
+          f"{res['lds_f64_spread']:.3e}/s", file=sys.stderr, flush=True)
+    return res
+
+
 def cpu_baseline(wl, n_cells):
     import numpy as np
 
@@ -392,9 +417,25 @@ def cpu_baseline(wl, n_cells):
     oracle.deposit_workload(wl.detector, wl.chunk, cell_index=idx, n_threads=threads)
     el = time.perf_counter() - t0
     inter = wl.chunk.n_particles * wl.chunk.n_steps * len(idx)
+    # the same on one thread, over two of those cells
+    idx1 = idx[[0, len(idx) // 2]] if len(idx) > 1 else idx
+    t1 = time.perf_counter()
+    oracle.deposit_workload(wl.detector, wl.chunk, cell_index=idx1, n_threads=1)
+    el1 = time.perf_counter() - t1
+    inter1 = wl.chunk.n_particles * wl.chunk.n_steps * len(idx1)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": inter / el, "unit": "interactions/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(idx)} evenly spaced cells x all {wl.chunk.n_particles} particles x "
-                      f"all {wl.chunk.n_steps} segments ({inter:.3e} interactions, {el:.1f} s)"}
+                      f"all {wl.chunk.n_steps} segments ({inter:.3e} interactions, {el:.1f} s)",
+            "value_1thread": inter1 / el1,
+            "sample_1thread": f"{len(idx1)} of those cells on one thread ({inter1:.3e} "
+                              f"interactions, {el1:.1f} s)",
+            "nproc": os.cpu_count(), "cpu_model": model}
 
 
 def main():
@@ -403,6 +444,9 @@ def main():
         print("bench.py runs on one GPU only: the deposit is measured on a single MI355X "
               "(see the sharding paragraph of the design notes); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    # the atomics program runs first, as a child process, while this one has not
+    # touched the GPU yet
+    atomics = None if args.no_atomics else atomics_leg()
     import torch
 
     import paper_2302_14812_amd as radio
@@ -469,6 +513,21 @@ def main():
                    "interactions_per_step": inter},
         "roofline": main_leg["roofline"],
     }
+    # ceilings of the interaction rate at F_int flops per interaction: double at the FP64
+    # vector peak; mixed as its 25 double + 59 single flops at the two vector peaks
+    # (single at the packed rate), and with every flop at 78.6 (this build runs no
+    # packed single-precision instructions)
+    fp64_ceiling = PEAK_TFLOPS["fp64"] * 1e12 / FLOPS_PER_INTERACTION
+    blended = 1.0 / (25.0 / (PEAK_TFLOPS["fp64"] * 1e12) + 59.0 / (PEAK_TFLOPS["mixed"] * 1e12))
+    out["ceilings"] = {"unit": "interactions/s", "fp64": fp64_ceiling, "mixed_blended": blended,
+                       "mixed_unpacked": fp64_ceiling}
+    if args.precision == "fp64":
+        out["ceilings"]["frac_fp64"] = main_leg["value"] / fp64_ceiling
+    else:
+        out["ceilings"]["frac_mixed_blended"] = main_leg["value"] / blended
+        out["ceilings"]["frac_mixed_unpacked"] = main_leg["value"] / fp64_ceiling
+        if "fp64" in legs:
+            out["ceilings"]["frac_fp64"] = legs["fp64"]["value"] / fp64_ceiling
     if "fp64" in legs and args.precision != "fp64":
         out["fp64"] = legs["fp64"]
         out["mixed_vs_fp64_speedup"] = legs["fp64"]["ms_per_step"] / main_leg["ms_per_step"]
@@ -485,6 +544,8 @@ def main():
     if not args.no_serve:
         precs = [args.precision] + (["fp64"] if args.precision != "fp64" and not args.no_fp64 else [])
         out["serve"] = serve_leg(radio, W, precs, args.serve_chunks, args.serve_load)
+    if atomics is not None:
+        out["atomics"] = atomics
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, args.cpu_cells)
         out["cpu_baseline"] = cb

@@ -24,6 +24,8 @@ COMMON = [
 ]
 
 SOURCES = ["radio_kernels.hip", "radio_spectrum.hip", "radio_push.hip", "radio_runtime.cpp"]
+# measurement program: floating-point atomic-add throughput (run by bench.py)
+ATOMICS_BENCH = os.path.join(HERE, "radio_atomics_bench")
 
 
 def build(verbose: bool = False) -> str:
@@ -43,6 +45,12 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     for o in objs:
         os.remove(o)
+    cmd = [HIPCC] + [c for c in COMMON if c not in ("-fPIC", "-fvisibility=hidden")] + [
+        os.path.join(CSRC, "atomics_bench.hip"), "-o", ATOMICS_BENCH + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(ATOMICS_BENCH + ".tmp", ATOMICS_BENCH)
     return LIB
 
 
