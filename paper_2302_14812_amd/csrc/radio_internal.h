@@ -81,7 +81,7 @@ struct DepositJob {
     const double* u;                // [3][n_s+1][n_p]
     const double* q;                // [n_p] or nullptr (all -1)
     void* recs;                     // workspace [n_p][n_s+1] records of the job's mode
-    int32_t* perm;                  // workspace [n_tiles][n_p]
+    int32_t* perm;                  // workspace [n_groups][n_tiles][n_p]: particle orders
     uint8_t* ring_sel;              // workspace [n_tiles]: 1 where a tile takes the large ring
     const double* far;              // far-field detector: [n_c][4] n_cell, R_cell; else nullptr
     double vscale;                  // 1, or 0 for an acceleration-only detector
@@ -95,8 +95,13 @@ struct DepositJob {
     // work decomposition, filled by plan_job()
     int64_t n_tiles;                // tiles of kTileCells cells
     int64_t n_runs;                 // runs of kRunL segments
-    int64_t runs_per_split;         // runs per workgroup
-    int64_t n_splits;               // workgroups per tile
+    int64_t runs_per_split;         // runs per work item
+    int64_t n_splits;               // run ranges per tile
+    int64_t batches_per_part;       // batches of kGroups particles per work item
+    int64_t n_parts;                // particle ranges per tile and run range
+    int64_t runs_per_group;         // runs sharing one particle order per tile (a power of 2)
+    int64_t group_shift;            // log2(runs_per_group)
+    int64_t n_groups;               // particle orders per tile
 };
 
 // One unit of a batched deposit: a tile of cells against a range of runs of one job.
@@ -104,7 +109,7 @@ struct WorkItem {
     int32_t job;
     int32_t tile;
     int32_t split;
-    int32_t pad;
+    int32_t part;
 };
 
 // Work items are kept short (a run, or the few runs that make at least this
@@ -115,8 +120,17 @@ constexpr int64_t kMinItemBatches = 64;
 
 // Split the runs of a job into work items: until tiles x splits reaches
 // target_blocks when it is positive, else into short items (a run or a few)
-// while at least `capacity` items (the workgroups resident at once) remain.
+// while at least `capacity` items (the workgroups resident at once) remain;
+// with fewer than two rounds of items, also into ranges of the tile's sorted
+// particles (parts of at least 16 batches).
 void plan_job(DepositJob& job, int target_blocks, int64_t capacity);
+// the tile's sorted batches in `parts` contiguous ranges (1: all of them)
+void set_parts(DepositJob& job, int64_t parts);
+// One particle order per tile for each group of runs (sorted at the group's
+// middle state), as many groups as keep the orders within the size of the
+// state records (and at least 1 GiB): arrival offsets that drift apart over a
+// long chunk are re-sorted along it.
+void set_groups(DepositJob& job, size_t rec_bytes);
 
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);

@@ -793,7 +793,8 @@ __global__ __launch_bounds__(256) void kinematics_kernel(const double* __restric
 constexpr int kOrderBins = 4096;
 
 __global__ __launch_bounds__(256) void order_kernel(const double* __restrict__ x, int64_t n_p,
-                                                    int64_t n_s, int64_t s_key,
+                                                    int64_t n_s, int64_t n_tiles,
+                                                    int64_t steps_per_group,
                                                     const double* __restrict__ cells, int64_t n_c,
                                                     double inv_c, double inv_dt_det,
                                                     int32_t* __restrict__ perm)
@@ -802,7 +803,10 @@ __global__ __launch_bounds__(256) void order_kernel(const double* __restrict__ x
     __shared__ double red_lo[256], red_hi[256];
     __shared__ double ctr[3];
     const int tid = threadIdx.x;
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = blockIdx.x % n_tiles;
+    const int64_t group = blockIdx.x / n_tiles;
+    // the group's middle state
+    const int64_t s_key = min(n_s, group * steps_per_group + steps_per_group / 2);
     const int64_t c0 = tile * kTileCells;
     const int64_t c1 = min(c0 + (int64_t)kTileCells, n_c);
     if (tid < 3) {
@@ -863,7 +867,7 @@ __global__ __launch_bounds__(256) void order_kernel(const double* __restrict__ x
         }
     }
     __syncthreads();
-    int32_t* out = perm + tile * n_p;
+    int32_t* out = perm + (group * n_tiles + tile) * n_p;
     for (int64_t p = tid; p < n_p; p += 256) {
         const unsigned pos = atomicAdd(&hist[bin_of(p)], 1u);
         out[pos] = (int32_t)p;
@@ -885,6 +889,7 @@ constexpr double kRingBypassLimit = 0.05;   // emissions to HBM per interaction
 __global__ __launch_bounds__(256) void ring_choice_kernel(const char* __restrict__ recs,
                                                           int64_t rec_size,
                                                           const int32_t* __restrict__ perm,
+                                                          int64_t n_tiles, int64_t runs_per_group,
                                                           const double* __restrict__ cells,
                                                           const double* __restrict__ far,
                                                           int64_t n_c, int64_t n_p, int64_t n_s,
@@ -918,8 +923,8 @@ __global__ __launch_bounds__(256) void ring_choice_kernel(const char* __restrict
     const bool on = smp < kSamples && pi < n_p && len > 0;
     const double* xc = cells + 3 * c0;
     const double* fc = far ? far + 4 * c0 : nullptr;
-    const char* pr =
-        on ? recs + ((int64_t)perm[tile * n_p + pi] * n_states + s_a) * rec_size : nullptr;
+    const int32_t* order = perm + ((run / runs_per_group) * n_tiles + tile) * n_p;  // once a thread
+    const char* pr = on ? recs + ((int64_t)order[pi] * n_states + s_a) * rec_size : nullptr;
     // position of state k of this lane's particle: the first three doubles of its record
     auto pos = [&](int k) { return reinterpret_cast<const double*>(pr + (int64_t)k * rec_size); };
     auto slot_of = [&](const double* x, int64_t st) {
@@ -988,8 +993,9 @@ struct DepositShared {
 };
 
 // One work item: a tile of kTileCells cells against the runs
-// [split * runs_per_split, ...) of every particle of job J, in the tile's
-// particle order.  Called by all kDepositThreads threads of a workgroup.
+// [split * runs_per_split, ...) of the particles in batches
+// [part * batches_per_part, ...) of the tile's particle order (job J).
+// Called by all kDepositThreads threads of a workgroup.
 // Lane (cell, group) = (lane % kTileCells, lane / kTileCells): the sixteen
 // lanes of a wavefront's row hold different cells, so one ring update
 // instruction touches different rings, and the four groups of a wavefront
@@ -999,7 +1005,7 @@ struct DepositShared {
 // G: bit 0 the far-field geometry, bit 1 potentials instead of fields
 template <int M, int R, int G, int HOLD>
 __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, int64_t split,
-                                             DepositShared<M, R>& sh)
+                                             int64_t part, DepositShared<M, R>& sh)
 {
     constexpr bool FAR = (G & 1) != 0;
     constexpr bool POT = (G & 2) != 0;
@@ -1063,29 +1069,34 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         nb[tid] = INT_MAX;
     int base = 0;  // the ring covers [base, base + R), 0 <= base <= max(n_t - R, 0)
     unsigned n_clip = 0, n_back = 0, n_bypass = 0;
-    const RADIO_GLOBAL int32_t* order = gptr(J.perm + tile * J.n_p);
+    // the tile's particle order for run rb (one order per group of runs)
+    auto order_of = [&](int64_t rb_) {
+        return gptr(J.perm + ((rb_ >> J.group_shift) * J.n_tiles + tile) * J.n_p);
+    };
     const RADIO_GLOBAL double* charges = J.q ? gptr(J.q) : nullptr;
     const int64_t n_states = J.n_s + 1;
-    const int64_t n_batches = (J.n_p + kGroups - 1) / kGroups;
+    const int64_t bt_begin = part * J.batches_per_part;
+    const int64_t bt_end = min(bt_begin + J.batches_per_part, (J.n_p + kGroups - 1) / kGroups);
+    const int64_t n_batches = bt_end - bt_begin;  // per run
     const int64_t rb_begin = split * J.runs_per_split;
     const int64_t rb_end = min(rb_begin + J.runs_per_split, J.n_runs);
     // The item's batches are taken run-major: run rb (states rb * kRunL ...)
-    // of the particles order[bt * kGroups ...], bt = 0 .. n_batches - 1.
+    // of the particles order[bt * kGroups ...], bt = bt_begin .. bt_end - 1.
     // Before a batch is computed, one round of global loads brings its
     // records, its charges and the first positions of the next batch's
     // particles, whose lowest start slot per cell places the ring for that
     // batch before it is staged; the order entries these loads need were
     // fetched in the round before.
     auto advance = [&](int64_t& rb_, int64_t& bt_) {
-        if (++bt_ == n_batches) {
-            bt_ = 0;
+        if (++bt_ == bt_end) {
+            bt_ = bt_begin;
             ++rb_;
         }
     };
     // the lane's particle of batch (rb_, bt_), or -1
     auto lane_particle = [&](int64_t rb_, int64_t bt_, int lane_g) -> int {
         const int64_t i = bt_ * kGroups + lane_g;
-        return (rb_ < rb_end && i < J.n_p) ? (int)order[i] : -1;
+        return (rb_ < rb_end && i < J.n_p) ? (int)order_of(rb_)[i] : -1;
     };
     // lowest start slot of the cell over a batch: the lane's particle starts at x
     // at state s_a (into nb[buf][cell])
@@ -1149,7 +1160,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
     constexpr int kStageLanes = kDepositThreads / kGroups;
     int t_stage = tid;
     asm volatile("" : "+v"(t_stage));
-    int64_t rb = rb_begin, bt = 0;  // the current batch
+    int64_t rb = rb_begin, bt = bt_begin;  // the current batch
     int64_t rb1 = rb, bt1 = bt;     // the next one
     advance(rb1, bt1);
     int p_stage = -1, p_scout = -1;  // this thread's particle to stage; the lane's to scout
@@ -1384,12 +1395,13 @@ __global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J, 
     const int64_t per_xcd = (int64_t)gridDim.x / kXcds;
     const int64_t logical =
         item0 + (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
-    if (logical >= J.n_tiles * J.n_splits)
+    if (logical >= J.n_tiles * J.n_splits * J.n_parts)
         return;
     const int64_t tile = logical % J.n_tiles;
     if (gptr(J.ring_sel)[tile] != (R == kRingLarge ? 1 : 0))
         return;
-    deposit_item<M, R, G, HOLD>(J, tile, logical / J.n_tiles, sh);
+    const int64_t rest = logical / J.n_tiles;  // split-major, then part
+    deposit_item<M, R, G, HOLD>(J, tile, rest / J.n_parts, rest % J.n_parts, sh);
 }
 
 // Persistent workgroups for many independent deposits: each takes the next work
@@ -1416,7 +1428,7 @@ __global__ __launch_bounds__(kDepositThreads) void deposit_persistent_kernel(
         const DepositJob J = jobs[w.job];
         if (gptr(J.ring_sel)[w.tile] != (R == kRingLarge ? 1 : 0))
             continue;
-        deposit_item<M, R, G, HOLD>(J, w.tile, w.split, sh);
+        deposit_item<M, R, G, HOLD>(J, w.tile, w.split, w.part, sh);
     }
 }
 
@@ -1513,6 +1525,38 @@ void plan_job(DepositJob& job, int target_blocks, int64_t capacity)
         splits = job.n_runs;
     job.runs_per_split = (job.n_runs + splits - 1) / splits;
     job.n_splits = (job.n_runs + job.runs_per_split - 1) / job.runs_per_split;
+    // few runs (a short chunk): ranges of the sorted particles as well
+    const int64_t n_batches = std::max<int64_t>((job.n_p + kGroups - 1) / kGroups, 1);
+    int64_t parts = 1;
+    const int64_t items = job.n_tiles * job.n_splits;
+    if (target_blocks <= 0 && items < 2 * capacity) {
+        parts = (2 * capacity + items - 1) / items;
+        parts = std::max<int64_t>(1, std::min<int64_t>(parts, n_batches / 16));
+    }
+    set_parts(job, parts);
+}
+
+void set_groups(DepositJob& job, size_t rec_bytes)
+{
+    const double per_group = (double)job.n_tiles * (double)job.n_p * sizeof(int32_t);
+    const double budget = std::max((double)(job.n_s + 1) * (double)job.n_p * (double)rec_bytes,
+                                   (double)(int64_t(1) << 30));
+    int64_t groups = (int64_t)std::min((double)job.n_runs, std::max(1.0, budget / per_group));
+    groups = std::max<int64_t>(1, groups);
+    const int64_t want = (job.n_runs + groups - 1) / groups;
+    job.group_shift = 0;
+    while ((int64_t(1) << job.group_shift) < want)
+        ++job.group_shift;
+    job.runs_per_group = int64_t(1) << job.group_shift;
+    job.n_groups = (job.n_runs + job.runs_per_group - 1) / job.runs_per_group;
+}
+
+void set_parts(DepositJob& job, int64_t parts)
+{
+    const int64_t n_batches = std::max<int64_t>((job.n_p + kGroups - 1) / kGroups, 1);
+    parts = std::max<int64_t>(1, std::min<int64_t>(parts, n_batches));
+    job.batches_per_part = (n_batches + parts - 1) / parts;
+    job.n_parts = (n_batches + job.batches_per_part - 1) / job.batches_per_part;
 }
 
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s)
@@ -1552,9 +1596,9 @@ hipError_t launch_kinematics(const DepositJob& job, int mode, hipStream_t s)
 
 hipError_t launch_order(const DepositJob& job, hipStream_t s)
 {
-    hipLaunchKernelGGL(order_kernel, dim3((unsigned)job.n_tiles), dim3(256), 0, s, job.x, job.n_p,
-                       job.n_s, job.n_s / 2, job.cells, job.n_c, job.inv_c, job.inv_dt_det,
-                       job.perm);
+    hipLaunchKernelGGL(order_kernel, dim3((unsigned)(job.n_tiles * job.n_groups)), dim3(256), 0, s,
+                       job.x, job.n_p, job.n_s, job.n_tiles, job.runs_per_group * kRunL,
+                       job.cells, job.n_c, job.inv_c, job.inv_dt_det, job.perm);
     return hipGetLastError();
 }
 
@@ -1564,7 +1608,8 @@ hipError_t launch_ring_choice(const DepositJob& job, int mode, hipStream_t s)
         return hipSuccess;
     hipLaunchKernelGGL(ring_choice_kernel, dim3((unsigned)job.n_tiles), dim3(256), 0, s,
                        reinterpret_cast<const char*>(job.recs), (int64_t)rec_bytes(mode),
-                       job.perm, job.cells, job.far, job.n_c, job.n_p, job.n_s, job.n_runs,
+                       job.perm, job.n_tiles, job.runs_per_group, job.cells, job.far, job.n_c,
+                       job.n_p, job.n_s, job.n_runs,
                        job.t_first,
                        job.s0, job.dt, job.t0, job.inv_dt_det, job.inv_c, job.n_t, job.ring_sel);
     return hipGetLastError();
@@ -1576,7 +1621,7 @@ template <int M, int G, int HOLD>
 static void launch_deposit_v(const DepositJob& job, dim3 grid, hipStream_t s)
 {
     // more items than one launch holds run in several launches
-    const int64_t n_items = job.n_tiles * job.n_splits;
+    const int64_t n_items = job.n_tiles * job.n_splits * job.n_parts;
     for (int64_t item0 = 0; item0 < n_items; item0 += grid.x)
         hipLaunchKernelGGL((deposit_kernel<M, kRingSmall, G, HOLD>), grid, dim3(kDepositThreads),
                            0, s, job, item0);
@@ -1636,7 +1681,7 @@ using Variants = decltype(make_table(std::make_integer_sequence<int, kKernelVari
 
 hipError_t launch_deposit(const DepositJob& job, int mode, int64_t max_grid, hipStream_t s)
 {
-    int64_t blocks = job.n_tiles * job.n_splits;
+    int64_t blocks = job.n_tiles * job.n_splits * job.n_parts;
     if (blocks <= 0)
         return hipSuccess;
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;  // a multiple of the XCD count

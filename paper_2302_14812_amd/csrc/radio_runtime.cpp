@@ -322,6 +322,7 @@ radio::DepositJob make_job(radio_detector* det, const radio_chunk* k)
     const int per_cu =
         radio::persistent_blocks_per_cu(radio::kernel_variant(det->precision, J), false);
     radio::plan_job(J, current_tuning().target_blocks, (int64_t)det->n_cus * per_cu);
+    radio::set_groups(J, radio::rec_bytes(det->precision));
     return J;
 }
 
@@ -359,7 +360,7 @@ int enqueue_deposit(radio_detector* det, const radio_chunk* k, hipStream_t s)
                   (size_t)(J.n_p * (J.n_s + 1)) * radio::rec_bytes(det->precision));
     if (rc != RADIO_OK)
         return rc;
-    rc = grow(&det->d_perm, &det->perm_cap, (size_t)(J.n_tiles * J.n_p));
+    rc = grow(&det->d_perm, &det->perm_cap, (size_t)(J.n_groups * J.n_tiles * J.n_p));
     if (rc == RADIO_OK)
         rc = grow(&det->d_sel, &det->sel_cap, (size_t)J.n_tiles);
     if (rc != RADIO_OK)
@@ -444,7 +445,7 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
             continue;
         radio::DepositJob J = make_job(dets[i], k);
         recs_need += (size_t)(J.n_p * (J.n_s + 1)) * radio::rec_bytes(dets[i]->precision);
-        perm_need += (size_t)(J.n_tiles * J.n_p);
+        perm_need += (size_t)(J.n_groups * J.n_tiles * J.n_p);
         sel_need += (size_t)J.n_tiles;
         A->h_jobs.push_back(J);
         idx.push_back(i);
@@ -487,7 +488,7 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
         J.perm = A->d_perm + po;
         J.ring_sel = A->d_sel + so;
         ro += (size_t)(J.n_p * (J.n_s + 1)) * radio::rec_bytes(prec);
-        po += (size_t)(J.n_tiles * J.n_p);
+        po += (size_t)(J.n_groups * J.n_tiles * J.n_p);
         so += (size_t)J.n_tiles;
         const double run_work = (double)radio::kTileCells * (double)J.n_p * (double)radio::kRunL;
         // items of similar work, and short (see kMinItemBatches)
@@ -497,6 +498,7 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
         rps = std::max<int64_t>(1, std::min<int64_t>(rps, J.n_runs));
         J.runs_per_split = rps;
         J.n_splits = (J.n_runs + rps - 1) / rps;
+        radio::set_parts(J, 1);  // batch items cover all of a tile's particles
         const int mode = radio::kernel_variant(prec, J);  // kernel variant
         for (int64_t sp = 0; sp < J.n_splits; ++sp) {
             const int64_t runs = std::min<int64_t>(rps, J.n_runs - sp * rps);

@@ -150,6 +150,30 @@ def test_deposit_in_several_launches(radio, precision):
     check_parity(E2, B2, Eo, Bo, TOLS[precision], f"several launches {precision}")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_deposit_in_particle_parts(radio, precision):
+    """A short chunk (two runs) of many particles on few tiles: the automatic
+    plan cuts each tile's sorted particles into parts (here seven of 125 batches);
+    the result equals a deposit with one item per tile and the oracle."""
+    chunk = W.random_chunk(2000, 20, seed=11, dt=0.07, gamma_max=30.0, t_first=0.4)
+    cells = W.plane_cells([1.0, -2.0, 30.0], [1, 0.2, 0], [0, 1, 0.1], 8, 8, 12.0, 9.0)
+    t0, dtd = _window(cells, chunk, 300)
+    spec = W.DetectorSpec(cells=cells, t0=t0, dt_det=dtd, n_t=300)
+    E1, B1, st = gpu_deposit(radio, spec, chunk, precision)
+    cur = radio.get_tuning()
+    try:
+        radio.set_tuning(target_blocks=1)  # one item per tile: no parts
+        E2, B2, _ = gpu_deposit(radio, spec, chunk, precision)
+    finally:
+        radio.set_tuning(**cur)
+    assert st["interactions"] == 2000 * 20 * 64
+    e = max(rel_l2(E1, E2), rel_l2(B1, B2))
+    print(f"[parts] {precision}: particle parts vs one item per tile relL2 {e:.3e}", flush=True)
+    assert e <= (1e-13 if precision == "fp64" else 1e-6)
+    Eo, Bo, _ = oracle_deposit(spec, chunk)
+    check_parity(E1, B1, Eo, Bo, TOLS[precision], f"particle parts {precision}")
+
+
 @PRECISIONS
 def test_parity_undulator_small(radio, precision):
     wl = W.undulator_workload(n_particles=64, n_steps=600, n_side=24, n_t=512)
