@@ -129,7 +129,8 @@ void set_parts(DepositJob& job, int64_t parts);
 // One particle order per tile for each group of runs (sorted at the group's
 // middle state), as many groups as keep the orders within the size of the
 // state records (and at least 1 GiB): arrival offsets that drift apart over a
-// long chunk are re-sorted along it.
+// long chunk are re-sorted along it.  Chunks of fewer than 16 batches of
+// particles keep one order.
 void set_groups(DepositJob& job, size_t rec_bytes);
 
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);

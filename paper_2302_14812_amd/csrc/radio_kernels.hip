@@ -1536,12 +1536,17 @@ void plan_job(DepositJob& job, int target_blocks, int64_t capacity)
     set_parts(job, parts);
 }
 
+constexpr int64_t kMinGroupParticles = 16 * kGroups;  // 16 batches
+
 void set_groups(DepositJob& job, size_t rec_bytes)
 {
     const double per_group = (double)job.n_tiles * (double)job.n_p * sizeof(int32_t);
     const double budget = std::max((double)(job.n_s + 1) * (double)job.n_p * (double)rec_bytes,
                                    (double)(int64_t(1) << 30));
     int64_t groups = (int64_t)std::min((double)job.n_runs, std::max(1.0, budget / per_group));
+    // a few batches gain nothing from re-sorting, and each order costs a histogram
+    if (job.n_p < kMinGroupParticles)
+        groups = 1;
     groups = std::max<int64_t>(1, groups);
     const int64_t want = (job.n_runs + groups - 1) / groups;
     job.group_shift = 0;
