@@ -366,11 +366,12 @@ __device__ __forceinline__ void add_segment(Carry<T>& C, const Sink& sink, int n
                                             unsigned& n_clip)
 {
     if ((b >= a) & (b < C.lim)) {
-        const T w0 = T(fmin(b, C.J1) - a);
+        const bool leaves = b >= C.J1;  // the segment leaves the open slot
+        const T w0 = T((leaves ? C.J1 : b) - a);
 #pragma unroll
         for (int k = 0; k < 6; ++k)
             C.V[k] += F[k] * w0;
-        if (b >= C.J1) {  // the segment leaves the open slot
+        if (leaves) {
             const double fb = floor(b);
             sink.flush((int)C.J1 - 1, C.V);
             if (fb > C.J1)  // whole slots J + 1 .. floor(b) - 1 hold F
@@ -986,6 +987,7 @@ struct DepositShared {
     static constexpr int kStride = R * CellSink<Acc, R>::W + 1;
     typename ModeTypes<M>::Rec rec[kGroups][kRunL + 1];  // staged batch: a run per group
     double sq[kGroups];                 // its charges
+    double tk[kRunL + 1];               // its states' time arguments (the same for every lane)
     Acc ring[kTileCells * kStride];     // per-cell slot rings
     int nb[2][kTileCells];              // per cell: lowest start slot of a coming batch
     int ord[2][kGroups];                // particles of the staged rows, per batch parity
@@ -1108,7 +1110,9 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
                 K.inv_dt_det;
         } else {
             const double d0 = xc[0] - x[0], d1 = xc[1] - x[1], d2 = xc[2] - x[2];
-            u = (t + __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2) * K.inv_c - K.t0) * K.inv_dt_det;
+            double dist, rinv;  // to ~1e-15: ample for placing the ring
+            fast_norm(d0 * d0 + d1 * d1 + d2 * d2, &dist, &rinv);
+            u = (t + dist * K.inv_c - K.t0) * K.inv_dt_det;
         }
         if (u == u) {
             const int f = (int)floor(fmin(fmax(u, -1.0), (double)n_t + 1.0));
@@ -1306,6 +1310,8 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
             p_stage = p_stage_next;
             p_scout = p_scout_next;
         }
+        if (tid < len + 1)
+            sh.tk[tid] = clock((double)(J.s0 + s_a + tid));
         __syncthreads();
         if (tid < kTileCells)  // read by every lane before the barrier; next used two batches on
             nb[buf * kTileCells + tid] = INT_MAX;
@@ -1330,13 +1336,12 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
                         return field_fp64(xc, st, tk, qc, qv, K, F);
                 }
             };
-            double sk = (double)(J.s0 + s_a);  // state index, exact below 2^53
             T Fp[6];  // the previous state's field (HOLD != 0)
             double u_prev;
             if constexpr (HOLD != 0)
-                u_prev = field_at(sh.rec[g][0], clock(sk), Fp);
+                u_prev = field_at(sh.rec[g][0], sh.tk[0], Fp);
             else
-                u_prev = slot_of(sh.rec[g][0], clock(sk));
+                u_prev = slot_of(sh.rec[g][0], sh.tk[0]);
             Carry<T> C;
             // open the slot where the run starts (a start far outside the window
             // leaves the first segment to the general path)
@@ -1345,8 +1350,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
             C.lim = fast_limit(C.J1 - 1.0, u_prev, ntd);
             for (int k = 1; k <= len; ++k) {
                 T F[6];
-                sk += 1.0;
-                const double uk = field_at(sh.rec[g][k], clock(sk), F);
+                const double uk = field_at(sh.rec[g][k], sh.tk[k], F);
                 if constexpr (HOLD == 0) {
                     add_segment(C, sink, n_t, u_prev, uk, F, n_back, n_clip);
                 } else {
