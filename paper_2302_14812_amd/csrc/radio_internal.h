@@ -10,8 +10,9 @@ namespace radio {
 // (the states of one particle are contiguous): position, beta, 1/gamma^2 and
 // betadot = (beta_s - beta_{s-1})/dt (zero for the first state of a chunk,
 // which carries no segment).  The mixed modes keep position and beta, which
-// enter the arrival time and n - beta, in double and betadot and 1/gamma^2 in
-// single precision.  Records are 80 (double) and 64 (mixed) bytes, multiples
+// enter the arrival time and n - beta, in double, and the particle's
+// (q/c) betadot and 1/(2 gamma^2), the forms their field uses, in single
+// precision.  Records are 80 (double) and 64 (mixed) bytes, multiples
 // of 16 so that staging copies and LDS reads stay 16-byte aligned.
 struct RecF64 {
     double x[3];
@@ -22,8 +23,8 @@ struct RecF64 {
 struct RecMix {
     double x[3];
     double b[3];
-    float bdf[3];
-    float g2if;
+    float bdq[3];  // (q/c) betadot of the state's particle
+    float g2ih;    // 1/(2 gamma^2)
 };
 static_assert(sizeof(RecF64) == 80 && sizeof(RecMix) == 64, "state record layouts");
 

@@ -8,8 +8,8 @@
 //
 // 1. kinematics_kernel (Alg. 1, velocity and acceleration lines): one thread
 //    per trajectory state turns (x, u) into a record with x, beta, betadot and
-//    1/gamma^2 (80 bytes; 64 with betadot and 1/gamma^2 in single precision
-//    for the mixed modes),
+//    1/gamma^2 (80 bytes; 64 for the mixed modes, with (q/c) betadot and
+//    1/(2 gamma^2) in single precision),
 //    laid out particle-major so that the states of one particle's run are
 //    contiguous.
 //
@@ -305,10 +305,24 @@ __device__ __forceinline__ double fast_limit(double J, double a, double ntd)
     return ((J >= 0.0) & (a >= J) & (a < J + 1.0)) ? ntd : -INFINITY;
 }
 
-// a segment between a and b reaches outside the window [0, n_t]
+// a segment between a and b reaches outside the window [0, n_t] (a NaN end is
+// not counted as outside)
 __device__ __forceinline__ unsigned clipped(double a, double b, double ntd)
 {
-    return (fmin(a, b) < 0.0 || fmax(a, b) > ntd) ? 1u : 0u;
+    return ((a < 0.0) | (b < 0.0) | (a > ntd) | (b > ntd)) ? 1u : 0u;
+}
+
+// The ends of the segment between a and b, ordered and clamped to [0, n_t].
+// Compares and selects only: min/max instructions would make the compiler
+// quiet the operands of every state, general path taken or not.  A NaN end
+// gives a NaN bound, which the callers' lo < hi test treats as empty.
+__device__ __forceinline__ void clamp_segment(double a, double b, double ntd, double& lo,
+                                              double& hi)
+{
+    const bool back = b < a;
+    const double mn = back ? b : a, mx = back ? a : b;
+    lo = mn < 0.0 ? 0.0 : (mn > ntd ? ntd : mn);
+    hi = mx < 0.0 ? 0.0 : (mx > ntd ? ntd : mx);
 }
 
 // General case: hold F over the slot-coordinate interval between a and b,
@@ -323,8 +337,8 @@ __device__ __forceinline__ void add_segment_general(Carry<T>& C, const Sink& sin
     const double ntd = (double)n_t;
     n_back += (b < a) ? 1u : 0u;
     n_clip += clipped(a, b, ntd);
-    const double lo = fmin(fmax(fmin(a, b), 0.0), ntd);
-    const double hi = fmin(fmax(fmax(a, b), 0.0), ntd);
+    double lo, hi;
+    clamp_segment(a, b, ntd, lo, hi);
     if (lo < hi) {  // else empty, entirely outside, or NaN
         const double fl = floor(lo);  // < n_t
         const double fh = floor(hi);  // <= n_t; n_t only when hi reaches the end
@@ -409,8 +423,8 @@ __device__ __forceinline__ void add_segment_linear_general(Carry<T>& C, const Si
     const double ntd = (double)n_t;
     n_back += (b < a) ? 1u : 0u;
     n_clip += clipped(a, b, ntd);
-    const double lo = fmin(fmax(fmin(a, b), 0.0), ntd);
-    const double hi = fmin(fmax(fmax(a, b), 0.0), ntd);
+    double lo, hi;
+    clamp_segment(a, b, ntd, lo, hi);
     if (lo < hi) {
         const double fl = floor(lo);
         const double fh = floor(hi);
@@ -469,7 +483,7 @@ __device__ __forceinline__ void add_segment_linear(Carry<T>& C, const Sink& sink
     const double inv_len = 1.0 / (b - a);
     if ((b > a) & (b < C.lim)) {
         const double Jd = C.J1 - 1.0;
-        const double e0 = fmin(b, C.J1);
+        const double e0 = b < C.J1 ? b : C.J1;
         T F[6];
         lerp_field(Fa, dF, T(0.5 * (e0 - a) * inv_len), F);
         const T w0 = T(e0 - a);
@@ -516,10 +530,10 @@ struct Consts {
 //                      c2 = qc (n.w) / (kappa^3 R),
 //   B = n x E.
 // nwk is (n.w)/kappa.  For a unit n, n.w = 1 - n.beta = kappa and nwk = 1,
-// which the single-precision field takes: it is the more accurate value there.
-// The double field passes the product of its rounded n and w, as the cross
-// products of Eq. 1 would use them (with kappa of order 1/gamma^2, the last
-// bits of |n| shift n.w by up to ~1e-12 of itself).
+// which the single-precision field (lw_fields_mixed) takes: it is the more
+// accurate value there.  The double field passes the product of its rounded n
+// and w, as the cross products of Eq. 1 would use them (with kappa of order
+// 1/gamma^2, the last bits of |n| shift n.w by up to ~1e-12 of itself).
 template <typename T>
 __device__ __forceinline__ void lw_fields(const T n[3], const T w[3], T kinv, T rinv, T g2i,
                                           const T bd[3], T qc, T qv, T nwk, T F[6])
@@ -583,11 +597,37 @@ __device__ __forceinline__ void fast_norm(double R2, double* R, double* rinv)
     *rinv = y;
 }
 
+// lw_fields in single precision for a mixed-precision record, whose betadot
+// already carries the factor q/c (bdq = q bd / c) and whose g2ih is 1/(2 gamma^2):
+// kappa = |w|^2 / 2 + g2ih, and with n.w = kappa for a unit n,
+//   E = c1 w - bdq / (kappa^2 R),  c1 = (n.bdq + qvg / R) / (kappa^3 R),
+// where qvg = qv g2i = 2 qv g2ih.
+__device__ __forceinline__ void lw_fields_mixed(const float n[3], const float w[3], float rinv,
+                                                const RecMix& st, float qv2, float F[6])
+{
+    const float kinv =
+        __builtin_amdgcn_rcpf(fmaf(0.5f, w[0] * w[0] + w[1] * w[1] + w[2] * w[2], st.g2ih));
+    const float nbd = n[0] * st.bdq[0] + n[1] * st.bdq[1] + n[2] * st.bdq[2];
+    const float rk2 = rinv * (kinv * kinv);
+    const float c1 = fmaf(qv2 * st.g2ih, rinv, nbd) * (rk2 * kinv);
+    const float E0 = c1 * w[0] - rk2 * st.bdq[0];
+    const float E1 = c1 * w[1] - rk2 * st.bdq[1];
+    const float E2 = c1 * w[2] - rk2 * st.bdq[2];
+    F[0] = E0;
+    F[1] = E1;
+    F[2] = E2;
+    F[3] = n[1] * E2 - n[2] * E1;
+    F[4] = n[2] * E0 - n[0] * E2;
+    F[5] = n[0] * E1 - n[1] * E0;
+}
+
 // The mixed-precision field: double for what cancels (arrival time, slot
-// coordinate, n - beta and kappa), single for the rest of Eq. 1.  ub is the
+// coordinate, n - beta), single for the rest of Eq. 1, kappa included (a sum
+// of positive terms formed from the double difference n - beta).  ub is the
 // state's (t_s - t0) / dt_det; the slot coordinate is ub + R / (c dt_det).
+// qv2 = 2 q times the weight of the velocity term.
 __device__ __forceinline__ double field_mixed(const double xc[3], const RecMix& st, double ub,
-                                              float qc, float qv, const Consts& K, float F[6])
+                                              float qv2, const Consts& K, float F[6])
 {
     double d[3] = {xc[0] - st.x[0], xc[1] - st.x[1], xc[2] - st.x[2]};
     double R2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
@@ -598,11 +638,7 @@ __device__ __forceinline__ double field_mixed(const double xc[3], const RecMix& 
     double wd[3] = {nd[0] - st.b[0], nd[1] - st.b[1], nd[2] - st.b[2]};
     const float n[3] = {(float)nd[0], (float)nd[1], (float)nd[2]};
     const float w[3] = {(float)wd[0], (float)wd[1], (float)wd[2]};
-    // kappa = (|n - beta|^2 + 1/gamma^2) / 2: a sum of positive terms, formed in
-    // single precision from the double difference n - beta
-    const float kap = 0.5f * ((w[0] * w[0] + w[1] * w[1] + w[2] * w[2]) + st.g2if);
-    lw_fields<float>(n, w, __builtin_amdgcn_rcpf(kap), (float)rinv, st.g2if, st.bdf, qc, qv, 1.0f,
-                     F);
+    lw_fields_mixed(n, w, (float)rinv, st, qv2, F);
     return u;
 }
 
@@ -653,22 +689,20 @@ __device__ __forceinline__ double field_far_fp64(const double fc[4], double Rinv
 }
 
 __device__ __forceinline__ double field_far_mixed(const double fc[4], double Rinv,
-                                                  const RecMix& st, double ub, float qc, float qv,
+                                                  const RecMix& st, double ub, float qv2,
                                                   const Consts& K, float F[6])
 {
     const double u = slot_far_mixed(fc, st.x, ub, K);
     const double wd[3] = {fc[0] - st.b[0], fc[1] - st.b[1], fc[2] - st.b[2]};
     const float n[3] = {(float)fc[0], (float)fc[1], (float)fc[2]};
     const float w[3] = {(float)wd[0], (float)wd[1], (float)wd[2]};
-    const float kap = 0.5f * ((w[0] * w[0] + w[1] * w[1] + w[2] * w[2]) + st.g2if);
-    lw_fields<float>(n, w, __builtin_amdgcn_rcpf(kap), (float)Rinv, st.g2if, st.bdf, qc, qv, 1.0f,
-                     F);
+    lw_fields_mixed(n, w, (float)Rinv, st, qv2, F);
     return u;
 }
 
 // 1/gamma^2 of a staged state
 __device__ __forceinline__ double rec_g2i(const RecF64& st) { return st.g2i; }
-__device__ __forceinline__ double rec_g2i(const RecMix& st) { return (double)st.g2if; }
+__device__ __forceinline__ double rec_g2i(const RecMix& st) { return 2.0 * (double)st.g2ih; }
 
 // Lienard-Wiechert potentials phi = q/(kappa R), A = q beta/(kappa R) at a
 // staged state (the potentials option): F = (A_x, A_y, A_z, phi, 0, 0).  FAR:
@@ -730,11 +764,15 @@ __device__ __forceinline__ double slot_coord_mixed(const double xc[3], const dou
 // (beta_{s+1} - beta_{s-1})/(2 dt), one-sided at the chunk's ends (linear rule)
 constexpr int kBdBackward = 0, kBdBackwardFirst = 1, kBdCentred = 2;
 
+// Mixed-precision records carry the particle's q/c in betadot and half of
+// 1/gamma^2, the forms their field takes (q: [n_p] or nullptr, all -1).
 template <int M>
 __global__ __launch_bounds__(256) void kinematics_kernel(const double* __restrict__ x,
                                                          const double* __restrict__ u,
+                                                         const double* __restrict__ q,
                                                          int64_t n_p, int64_t n_s, double dt,
-                                                         int bd_rule, void* __restrict__ recs_out)
+                                                         double inv_c, int bd_rule,
+                                                         void* __restrict__ recs_out)
 {
     using Rec = typename std::conditional<M == kModeF64, RecF64, RecMix>::type;
     Rec* recs = reinterpret_cast<Rec*>(recs_out);
@@ -778,10 +816,11 @@ __global__ __launch_bounds__(256) void kinematics_kernel(const double* __restric
                 r.bd[c] = bd[c];
             r.g2i = g2i;
         } else {
+            const double qc = (q ? q[p] : -1.0) * inv_c;
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                r.bdf[c] = (float)bd[c];
-            r.g2if = (float)g2i;
+                r.bdq[c] = (float)(qc * bd[c]);
+            r.g2ih = (float)(0.5 * g2i);
         }
         recs[p * n_states + s] = r;
     }
@@ -1318,7 +1357,8 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         if (active && g < np) {
             Sink sink{my_ring, row, base, n_t, &n_bypass};
             const double q = sh.sq[g];
-            const T qc = T(q * J.inv_c), qv = T(q * J.vscale);
+            // (the mixed records carry q/c in their betadot)
+            const T qc = T(q * J.inv_c), qv = T(q * J.vscale), qv2 = T(2.0 * q * J.vscale);
             // the field of one staged state and its slot coordinate
             auto field_at = [&](const Rec& st, double tk, T F[6]) {
                 if constexpr (POT) {
@@ -1326,12 +1366,12 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
                     return slot_of(st, tk);
                 } else if constexpr (FAR) {
                     if constexpr (MIX)
-                        return field_far_mixed(fc, Rinv, st, tk, qc, qv, K, F);
+                        return field_far_mixed(fc, Rinv, st, tk, qv2, K, F);
                     else
                         return field_far_fp64(fc, Rinv, st, tk, qc, qv, K, F);
                 } else {
                     if constexpr (MIX)
-                        return field_mixed(xc, st, tk, qc, qv, K, F);
+                        return field_mixed(xc, st, tk, qv2, K, F);
                     else
                         return field_fp64(xc, st, tk, qc, qv, K, F);
                 }
@@ -1596,10 +1636,12 @@ hipError_t launch_kinematics(const DepositJob& job, int mode, hipStream_t s)
     const int rule = job.hold == 2 ? kBdCentred : (job.hold == 1 ? kBdBackwardFirst : kBdBackward);
     if (mode == kModeF64)
         hipLaunchKernelGGL(kinematics_kernel<kModeF64>, dim3((unsigned)blocks), dim3(256), 0, s,
-                           job.x, job.u, job.n_p, job.n_s, job.dt, rule, job.recs);
+                           job.x, job.u, job.q, job.n_p, job.n_s, job.dt, job.inv_c, rule,
+                           job.recs);
     else
         hipLaunchKernelGGL(kinematics_kernel<kModeMix>, dim3((unsigned)blocks), dim3(256), 0, s,
-                           job.x, job.u, job.n_p, job.n_s, job.dt, rule, job.recs);
+                           job.x, job.u, job.q, job.n_p, job.n_s, job.dt, job.inv_c, rule,
+                           job.recs);
     return hipGetLastError();
 }
 
