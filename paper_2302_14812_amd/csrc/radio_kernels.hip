@@ -565,8 +565,10 @@ __device__ __forceinline__ double recip(double x)
 }
 
 // Lienard-Wiechert E, B (Eq. 1) at a cell from one staged state, all in double;
-// returns the state's slot coordinate.  Everything after the canonical part may
-// use FMAs.
+// returns the state's slot coordinate.  Only the arrival time (R and tau) is
+// rounded canonically; n, w, kappa and the field, which decide no slot, use
+// FMAs and a Newton reciprocal (within an ulp or two of the correctly rounded
+// values).
 __device__ __forceinline__ double field_fp64(const double xc[3], const RecF64& st, double t_s,
                                              double qc, double qv, const Consts& K, double F[6])
 {
@@ -574,10 +576,12 @@ __device__ __forceinline__ double field_fp64(const double xc[3], const RecF64& s
     double R2 = canon_norm2(d[0], d[1], d[2]);
     double R = __builtin_sqrt(R2);
     double tau = canon_arrival(t_s, R, K.inv_c);
-    double rinv = 1.0 / R;
-    double n[3], w[3];
-    canon_direction(d, rinv, st.b, n, w);
-    const double kinv = recip(canon_kappa(w, st.g2i));
+    const double rinv = recip(R);
+    const double n[3] = {d[0] * rinv, d[1] * rinv, d[2] * rinv};
+    const double w[3] = {n[0] - st.b[0], n[1] - st.b[1], n[2] - st.b[2]};
+    // kappa = (|n - beta|^2 + 1/gamma^2) / 2, as canon_kappa but fused
+    const double kinv =
+        recip(0.5 * fma(w[0], w[0], fma(w[1], w[1], fma(w[2], w[2], st.g2i))));
     const double nwk = (n[0] * w[0] + n[1] * w[1] + n[2] * w[2]) * kinv;
     lw_fields<double>(n, w, kinv, rinv, st.g2i, st.bd, qc, qv, nwk, F);
     return canon_slot(tau, K.t0, K.inv_dt_det);
