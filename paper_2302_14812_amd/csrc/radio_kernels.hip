@@ -1432,8 +1432,27 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
 // The work items item0 + [0, gridDim.x) of a single deposit, item =
 // split * n_tiles + tile, one per workgroup (gridDim.x is a multiple of
 // kXcds); items whose tile takes the other ring size leave at once.
+// Waves per SIMD to ask of the register allocator.  A mixed-precision kernel with
+// the small ring fits five wavefronts per SIMD in 96 VGPRs (its LDS allows five
+// workgroups per CU).  For the exact-geometry, current-state kernel the
+// allocator stays within that by itself and its own schedule is the faster
+// one; the far-field, acceleration-only and held-field kernels go a few
+// registers over, and keeping them at five waves (at the cost of a few spilled
+// words in the hold kernels) is 4-6% faster on the undulator ensemble.  The
+// double kernels are held to four workgroups per CU by their LDS; the
+// previous-state hold fits the matching 128 VGPRs without spilling (6% faster),
+// the linear hold would spill and gains nothing.
 template <int M, int R, int G, int HOLD>
-__global__ __launch_bounds__(kDepositThreads) void deposit_kernel(DepositJob J, int64_t item0)
+constexpr int kMinWaves =
+    R != kRingSmall                      ? 1
+    : M != kModeF64 && (G != 0 || HOLD != 0) ? 5
+    : M == kModeF64 && HOLD == 1         ? 4
+                                         : 1;
+
+template <int M, int R, int G, int HOLD>
+__global__ __launch_bounds__(kDepositThreads)
+__attribute__((amdgpu_waves_per_eu(kMinWaves<M, R, G, HOLD>))) void deposit_kernel(
+    DepositJob J, int64_t item0)
 {
     __shared__ __align__(16) DepositShared<M, R> sh;
     // Workgroups are dealt round-robin over the XCDs; give each XCD a contiguous
