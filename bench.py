@@ -288,10 +288,12 @@ def spectrum_leg(radio, W, steps):
         spec_ms.append((time.perf_counter() - t) * 1e3)
     det.close()
     N = n_t
-    # bytes the kernels move (two-step transform): E in and the column transforms
-    # out, the row transforms in and out, the power spectra (both halves) in,
-    # E again for Parseval, d2I out
-    fft_bytes = n_c * N * (24 + 32 + 64 + 32) + n_c * n_t * 24 + n_c * (N // 2 + 1) * 8
+    # bytes the kernels move (two-step transform, both signals of a cell per
+    # tile): E in and the column transforms out, the column transforms in and
+    # the row-major |Z1|^2 + |Z2|^2 out, that in again for the power, E again
+    # for Parseval, d2I out
+    fft_bytes = (n_c * n_t * 24 + n_c * N * (32 + 32 + 8 + 8) + n_c * n_t * 24
+                 + n_c * (N // 2 + 1) * 8)
     alg_bytes = n_c * n_t * 24 + n_c * (N // 2 + 1) * 8       # E in, d2I out
     sms = min(spec_ms)
     print(f"[bench] spectrum: deposit {min(dep_ms):.1f} ms, spectrum {sms:.1f} ms "

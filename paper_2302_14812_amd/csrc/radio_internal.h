@@ -155,12 +155,14 @@ int persistent_blocks_per_cu(int variant, bool large_ring);
 hipError_t launch_readout(const double* acc, int64_t n_c, int64_t n_t, const int64_t* user_index,
                           bool pairs, double* E, double* B, hipStream_t s);
 // spectral post-processing (radio_spectrum.hip): one group of G cells (internal
-// rows r0 ..) through load, FFT passes and power; work0/work1 hold 2 G N values
+// rows r0 ..) through load, FFT passes and power; work0/work1 hold 2 G N values,
+// tables kSpecTableValues (twiddle tables, rewritten by each call)
+constexpr int64_t kSpecTableValues = 5120;
 hipError_t launch_spectrum_group(const double* acc, bool pairs, int64_t n_t, int64_t r0,
                                  int64_t G, int64_t N, const double* cells,
                                  const int64_t* user_index, const double* weights, double dt,
-                                 double c, double2* work0, double2* work1, double* d2I,
-                                 double* dIdw, bool first_group, hipStream_t s);
+                                 double c, double2* work0, double2* work1, double2* tables,
+                                 double* d2I, double* dIdw, bool first_group, hipStream_t s);
 hipError_t launch_spectrum_parseval(const double* acc, bool pairs, int64_t n_c, int64_t n_t,
                                     const double* cells, const int64_t* user_index, double dt,
                                     double c, double* dIdO, hipStream_t s);

@@ -912,7 +912,7 @@ int radio_spectrum(radio_detector* det, int64_t n_fft, const double* weights, do
     int rc = RADIO_OK;
     if (d2I || dIdw) {
         // the two work arrays, kept by the detector for later spectra
-        rc = grow(&det->d_spec, &det->spec_cap, (size_t)(4 * G * N));
+        rc = grow(&det->d_spec, &det->spec_cap, (size_t)(4 * G * N + radio::kSpecTableValues));
         w0 = det->d_spec;
         w1 = det->d_spec + 2 * G * N;
     }
@@ -930,7 +930,8 @@ int radio_spectrum(radio_detector* det, int64_t n_fft, const double* weights, do
             const int64_t Gi = std::min(G, det->n_c - r0);
             if (radio::launch_spectrum_group(det->d_acc, pairs, det->n_t, r0, Gi, N, det->d_cells,
                                              det->d_user_index, d_w, det->dt_det, det->c, w0, w1,
-                                             d2I, dIdw, r0 == 0, s) != hipSuccess)
+                                             det->d_spec + 4 * G * N, d2I, dIdw, r0 == 0,
+                                             s) != hipSuccess)
                 rc = RADIO_EDEVICE;
         }
     }

@@ -27,11 +27,14 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b)) / (nb if nb > 0 else 1.0)
 
 
-# transform sizes: one LDS tile (up to 2048), the two-step transform (4096,
-# 8192) and the radix-2 passes beyond 2^22
+# transform sizes: one LDS tile (up to 2048); the two-step transform with both
+# signals of a cell per tile in both steps (4096, 8192), with one signal per
+# column tile (2^21), and with one signal per tile in both steps (2^22); the
+# radix-2 passes beyond 2^22
 @pytest.mark.parametrize("n_t,n_fft,precision,n_side", [
     (256, 0, "fp64", 6), (300, 0, "fp64", 6), (300, 2048, "mixed", 6), (200, 0, "mixed_twosum", 6),
-    (3000, 0, "fp64", 6), (300, 8192, "mixed", 6), (300, 1 << 23, "fp64", 2)])
+    (3000, 0, "fp64", 6), (300, 8192, "mixed", 6), (300, 1 << 21, "mixed_twosum", 2),
+    (300, 1 << 22, "fp64", 2), (300, 1 << 23, "fp64", 2)])
 def test_spectrum_matches_oracle(radio, n_t, n_fft, precision, n_side):
     import torch
     wl = W.undulator_workload(n_particles=30, n_steps=200, n_side=n_side, n_t=n_t)
