@@ -289,11 +289,10 @@ def spectrum_leg(radio, W, steps):
     det.close()
     N = n_t
     # bytes the kernels move (two-step transform, both signals of a cell per
-    # tile): E in and the column transforms out, the column transforms in and
-    # the row-major |Z1|^2 + |Z2|^2 out, that in again for the power, E again
-    # for Parseval, d2I out
-    fft_bytes = (n_c * n_t * 24 + n_c * N * (32 + 32 + 8 + 8) + n_c * n_t * 24
-                 + n_c * (N // 2 + 1) * 8)
+    # tile, Parseval's sums taken in the column step): E in and the column
+    # transforms out, the column transforms in and the row-major |Z1|^2 + |Z2|^2
+    # out, that in again for the power, d2I out
+    fft_bytes = n_c * n_t * 24 + n_c * N * (32 + 32 + 8 + 8) + n_c * (N // 2 + 1) * 8
     alg_bytes = n_c * n_t * 24 + n_c * (N // 2 + 1) * 8       # E in, d2I out
     sms = min(spec_ms)
     print(f"[bench] spectrum: deposit {min(dep_ms):.1f} ms, spectrum {sms:.1f} ms "

@@ -156,13 +156,16 @@ hipError_t launch_readout(const double* acc, int64_t n_c, int64_t n_t, const int
                           bool pairs, double* E, double* B, hipStream_t s);
 // spectral post-processing (radio_spectrum.hip): one group of G cells (internal
 // rows r0 ..) through load, FFT passes and power; work0/work1 hold 2 G N values,
-// tables kSpecTableValues (twiddle tables, rewritten by each call)
+// tables kSpecTableValues (twiddle tables, rewritten by each call).  Where the
+// transform reads the detector in a way that allows it, the group's dI/dOmega
+// is computed on the way (dIdO set) and *parseval_done says so.
 constexpr int64_t kSpecTableValues = 5120;
 hipError_t launch_spectrum_group(const double* acc, bool pairs, int64_t n_t, int64_t r0,
                                  int64_t G, int64_t N, const double* cells,
                                  const int64_t* user_index, const double* weights, double dt,
                                  double c, double2* work0, double2* work1, double2* tables,
-                                 double* d2I, double* dIdw, bool first_group, hipStream_t s);
+                                 double* d2I, double* dIdw, double* dIdO, bool* parseval_done,
+                                 bool first_group, hipStream_t s);
 hipError_t launch_spectrum_parseval(const double* acc, bool pairs, int64_t n_c, int64_t n_t,
                                     const double* cells, const int64_t* user_index, double dt,
                                     double c, double* dIdO, hipStream_t s);

@@ -925,17 +925,21 @@ int radio_spectrum(radio_detector* det, int64_t n_fft, const double* weights, do
             rc = RADIO_EDEVICE;
         }
     }
+    bool parseval_done = false;  // every group computed its cells' dI/dOmega on the way
     if (rc == RADIO_OK && (d2I || dIdw)) {
+        parseval_done = true;
         for (int64_t r0 = 0; r0 < det->n_c && rc == RADIO_OK; r0 += G) {
             const int64_t Gi = std::min(G, det->n_c - r0);
+            bool done = false;
             if (radio::launch_spectrum_group(det->d_acc, pairs, det->n_t, r0, Gi, N, det->d_cells,
                                              det->d_user_index, d_w, det->dt_det, det->c, w0, w1,
-                                             det->d_spec + 4 * G * N, d2I, dIdw, r0 == 0,
-                                             s) != hipSuccess)
+                                             det->d_spec + 4 * G * N, d2I, dIdw, dIdO, &done,
+                                             r0 == 0, s) != hipSuccess)
                 rc = RADIO_EDEVICE;
+            parseval_done = parseval_done && done;
         }
     }
-    if (rc == RADIO_OK && dIdO &&
+    if (rc == RADIO_OK && dIdO && !parseval_done &&
         radio::launch_spectrum_parseval(det->d_acc, pairs, det->n_c, det->n_t, det->d_cells,
                                         det->d_user_index, det->dt_det, det->c, dIdO,
                                         s) != hipSuccess)

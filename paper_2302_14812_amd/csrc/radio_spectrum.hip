@@ -270,14 +270,18 @@ __global__ __launch_bounds__(kFftThreads) void spec_rows_kernel(const double2* _
 // First step for both signals of cell g at once: tile = Tc consecutive columns
 // n2 (Tc = kFftTile / (2 N1), so lg1 < kFftTileLg; N2 is a multiple of Tc),
 // buf[s][tc][N1] for signal s = 0 (Ex + i Ey) and 1 (Ez).  Each slot of the
-// detector is read once; the twiddle is shared by the two signals.
+// detector is read once; the twiddle is shared by the two signals.  With part
+// set, the tile also leaves the sum of |E|^2 over its slots in
+// part[g][tile] (Parseval, reduced per cell by spec_parseval_parts_kernel).
 template <bool PAIRS>
 __global__ __launch_bounds__(kFftThreads) void spec_cols2_kernel(const double* __restrict__ acc,
                                                                   int64_t n_t, int64_t r0,
                                                                   int64_t G, int lg1, int lg2,
                                                                   const double2* __restrict__ tab,
-                                                                  double2* __restrict__ Y)
+                                                                  double2* __restrict__ Y,
+                                                                  double* __restrict__ part)
 {
+    __shared__ double red[kFftThreads];
     extern __shared__ double2 lds[];
     const int N1 = 1 << lg1;
     const int64_t N2 = (int64_t)1 << lg2;
@@ -294,12 +298,26 @@ __global__ __launch_bounds__(kFftThreads) void spec_cols2_kernel(const double* _
     const int lgS = (lg1 + lg2 + 1) / 2;
     fill_twiddles(tw, tab, lg1);
     // load: consecutive threads take consecutive columns (slots) of one row n1
+    double e2 = 0.0;
     for (int e = threadIdx.x; e < Tc * N1; e += blockDim.x) {
         const int n1 = e >> lgTc;
         const int tc = e & (Tc - 1);
         const int j = bitrev(n1, lg1);
-        buf[tc * N1 + j] = signal_at<PAIRS>(acc, n_t, r0, 2 * g, N2 * n1 + n20 + tc);
-        buf[(Tc + tc) * N1 + j] = signal_at<PAIRS>(acc, n_t, r0, 2 * g + 1, N2 * n1 + n20 + tc);
+        const double2 v0 = signal_at<PAIRS>(acc, n_t, r0, 2 * g, N2 * n1 + n20 + tc);
+        const double2 v1 = signal_at<PAIRS>(acc, n_t, r0, 2 * g + 1, N2 * n1 + n20 + tc);
+        buf[tc * N1 + j] = v0;
+        buf[(Tc + tc) * N1 + j] = v1;
+        e2 += (v0.x * v0.x + v0.y * v0.y) + v1.x * v1.x;
+    }
+    if (part) {
+        red[threadIdx.x] = e2;
+        for (int w = kFftThreads / 2; w > 0; w >>= 1) {
+            __syncthreads();
+            if ((int)threadIdx.x < w)
+                red[threadIdx.x] += red[threadIdx.x + w];
+        }
+        if (threadIdx.x == 0)
+            part[blockIdx.x] = red[0];
     }
     lds_fft(buf, tw, lg1, 2 * Tc);
     double2* y1 = Y + (2 * g) * N;
@@ -588,6 +606,25 @@ __global__ __launch_bounds__(256) void spec_parseval_kernel(const double* __rest
     }
 }
 
+// dI/dOmega of the cells of a group from the per-tile sums of |E|^2 left by
+// spec_cols2_kernel (part[g][0 .. tiles_per_cell), added in order)
+__global__ __launch_bounds__(256) void spec_parseval_parts_kernel(
+    const double* __restrict__ part, int64_t tiles_per_cell, int64_t G, int64_t r0,
+    const double* __restrict__ cells, const int64_t* __restrict__ user_index, double dt, double c,
+    double* __restrict__ dIdO)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= G)
+        return;
+    double sum = 0.0;
+    for (int64_t i = 0; i < tiles_per_cell; ++i)
+        sum += part[g * tiles_per_cell + i];
+    const int64_t r = r0 + g;
+    const double* x = cells + 3 * r;
+    const double R2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+    dIdO[user_index[r]] = c * R2 / (4.0 * kPi) * sum * dt;
+}
+
 unsigned grid_for(int64_t n);
 
 // power spectra of a group from its transforms Z in natural order, or from
@@ -634,8 +671,10 @@ hipError_t launch_spectrum_group(const double* acc, bool pairs, int64_t n_t, int
                                  int64_t G, int64_t N, const double* cells,
                                  const int64_t* user_index, const double* weights, double dt,
                                  double c, double2* work0, double2* work1, double2* tables,
-                                 double* d2I, double* dIdw, bool first_group, hipStream_t s)
+                                 double* d2I, double* dIdw, double* dIdO, bool* parseval_done,
+                                 bool first_group, hipStream_t s)
 {
+    *parseval_done = false;
     int lg = 0;
     while (((int64_t)1 << lg) < N)
         ++lg;
@@ -653,15 +692,25 @@ hipError_t launch_spectrum_group(const double* acc, bool pairs, int64_t n_t, int
         const size_t lds_a = ((size_t)kFftTile + ((size_t)1 << lg1) / 2) * sizeof(double2);
         double2* out_a = lg2 > 0 ? work0 : work1;
         if (lg2 > 0 && lg1 < kFftTileLg) {
-            const int64_t tiles = G * ((int64_t)1 << (lg2 - (kFftTileLg - 1 - lg1)));
+            const int64_t tiles_per_cell = (int64_t)1 << (lg2 - (kFftTileLg - 1 - lg1));
+            const int64_t tiles = G * tiles_per_cell;
+            // Parseval's per-tile sums after the row step's output in work1 (G N
+            // doubles of its 4 G N)
+            double* part = dIdO ? reinterpret_cast<double*>(work1) + G * N : nullptr;
             if (pairs)
                 hipLaunchKernelGGL(spec_cols2_kernel<true>, dim3((unsigned)tiles),
                                    dim3(kFftThreads), lds_a, s, acc, n_t, r0, G, lg1, lg2, tables,
-                                   out_a);
+                                   out_a, part);
             else
                 hipLaunchKernelGGL(spec_cols2_kernel<false>, dim3((unsigned)tiles),
                                    dim3(kFftThreads), lds_a, s, acc, n_t, r0, G, lg1, lg2, tables,
-                                   out_a);
+                                   out_a, part);
+            if (part) {
+                hipLaunchKernelGGL(spec_parseval_parts_kernel, dim3((unsigned)((G + 255) / 256)),
+                                   dim3(256), 0, s, part, tiles_per_cell, G, r0, cells, user_index,
+                                   dt, c, dIdO);
+                *parseval_done = true;
+            }
         } else {
             const int T = kFftTile >> lg1;
             const int64_t n_cols = n_sig << lg2;
