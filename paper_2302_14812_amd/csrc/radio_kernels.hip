@@ -601,6 +601,16 @@ __device__ __forceinline__ void fast_norm(double R2, double* R, double* rinv)
     *rinv = y;
 }
 
+// |d|^2 for fast_norm, plus the smallest normal double.  That changes nothing
+// for distances above ~1e-146, and a state exactly at a cell (d = 0) then gets
+// R ~ 1e-154 and a finite slot coordinate -- the canonical R = 0 moves the
+// slot coordinate by no more -- instead of 0 * inf.  Its field is not finite,
+// as the definition's is there.
+__device__ __forceinline__ double norm2_fast(double d0, double d1, double d2)
+{
+    return fma(d2, d2, fma(d1, d1, fma(d0, d0, 0x1p-1022)));
+}
+
 // lw_fields in single precision for a mixed-precision record, whose betadot
 // already carries the factor q/c (bdq = q bd / c) and whose g2ih is 1/(2 gamma^2):
 // kappa = |w|^2 / 2 + g2ih, and with n.w = kappa for a unit n,
@@ -634,9 +644,8 @@ __device__ __forceinline__ double field_mixed(const double xc[3], const RecMix& 
                                               float qv2, const Consts& K, float F[6])
 {
     double d[3] = {xc[0] - st.x[0], xc[1] - st.x[1], xc[2] - st.x[2]};
-    double R2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     double R, rinv;
-    fast_norm(R2, &R, &rinv);
+    fast_norm(norm2_fast(d[0], d[1], d[2]), &R, &rinv);
     const double u = fma(R, K.kR, ub);
     double nd[3] = {d[0] * rinv, d[1] * rinv, d[2] * rinv};
     double wd[3] = {nd[0] - st.b[0], nd[1] - st.b[1], nd[2] - st.b[2]};
@@ -753,7 +762,7 @@ __device__ __forceinline__ double slot_coord_mixed(const double xc[3], const dou
 {
     double d[3] = {xc[0] - x[0], xc[1] - x[1], xc[2] - x[2]};
     double R, rinv;
-    fast_norm(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], &R, &rinv);
+    fast_norm(norm2_fast(d[0], d[1], d[2]), &R, &rinv);
     return fma(R, K.kR, ub);
 }
 
@@ -1154,7 +1163,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         } else {
             const double d0 = xc[0] - x[0], d1 = xc[1] - x[1], d2 = xc[2] - x[2];
             double dist, rinv;  // to ~1e-15: ample for placing the ring
-            fast_norm(d0 * d0 + d1 * d1 + d2 * d2, &dist, &rinv);
+            fast_norm(norm2_fast(d0, d1, d2), &dist, &rinv);
             u = (t + dist * K.inv_c - K.t0) * K.inv_dt_det;
         }
         if (u == u) {

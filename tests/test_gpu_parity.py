@@ -244,6 +244,40 @@ def test_edge_cases(radio):
     det2.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_state_at_a_cell(radio, precision):
+    """A degenerate case of Eq. 1: a particle passing exactly through a cell
+    (R = 0 at one state).  The field of the segment that ends there is not
+    finite in the definition, so the slots it covers at that cell are not
+    finite in the oracle; the device must leave exactly those slots non-finite
+    and match the oracle everywhere else (the segment that starts at that
+    state has a finite field and a finite arrival interval)."""
+    chunk = W.random_chunk(3, 40, seed=31, dt=0.05, gamma_max=8.0)
+    cells = W.plane_cells([0, 0, 20.0], [1, 0, 0], [0, 1, 0], 5, 4, 3.0, 3.0)
+    # particle 0 in uniform motion along x at beta = 1/2, at cell 7 at state 12
+    beta = 0.5
+    chunk.u[:, :, 0] = 0.0
+    chunk.u[0, :, 0] = beta / math.sqrt(1.0 - beta * beta)
+    s = np.arange(chunk.n_steps + 1)
+    chunk.x[0, :, 0] = cells[7, 0] + beta * (s - 12) * chunk.dt
+    chunk.x[1, :, 0] = cells[7, 1]
+    chunk.x[2, :, 0] = cells[7, 2]
+    assert np.array_equal(chunk.x[:, 12, 0], cells[7])
+    t0, dtd = _window(cells, chunk, 120)
+    spec = W.DetectorSpec(cells=cells, t0=t0, dt_det=dtd, n_t=120)
+    with np.errstate(all="ignore"):
+        Eo, Bo, _ = oracle_deposit(spec, chunk)
+    Eg, Bg, _ = gpu_deposit(radio, spec, chunk, precision=precision)
+    for g, o, what in ((Eg, Eo, "E"), (Bg, Bo, "B")):
+        bad_o = ~np.isfinite(o).all(axis=2)
+        bad_g = ~np.isfinite(g).all(axis=2)
+        assert bad_o.any() and set(np.nonzero(bad_o)[0]) == {7}
+        assert np.array_equal(bad_g, bad_o), (what, np.nonzero(bad_g), np.nonzero(bad_o))
+    ok = np.isfinite(Eo).all(axis=2) & np.isfinite(Bo).all(axis=2)
+    check_parity(Eg[ok], Bg[ok], Eo[ok], Bo[ok], TOLS[precision],
+                 f"state at a cell {precision} (finite slots)")
+
+
 def test_chunk_split_and_superposition(radio):
     chunk = W.random_chunk(23, 150, seed=12, dt=0.04, gamma_max=20.0)
     cells = W.plane_cells([0, 3.0, 40.0], [1, 0, 0], [0, 1, 0], 13, 11, 8.0, 8.0)
