@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--cpu-cells", type=int, default=0,
                     help="cells in the oracle sample (default: six per host thread)")
     ap.add_argument("--no-atomics", action="store_true",
-                    help="skip the atomic-add throughput measurement")
+                    help="skip the device measurement programs (atomic-add throughput, "
+                         "vector instruction issue costs)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-launch leg (64 uneven sets, one persistent launch "
                          "vs 64 separate launches)")
@@ -381,14 +382,13 @@ def measured_traffic(precision, workload):
     return None if leg is None else leg["hbm_bytes"]
 
 
-def atomics_leg():
-    """Floating-point atomic-add throughput of the GPU (the measurement program built
-    with the library), the rates the deposit's ring flushes and slot emissions run
-    against.  Runs as a child process, so it is called before this process touches
-    the GPU, and not at all under a profiler (whose preloaded library has touched it
-    already)."""
+def measurement_program(name):
+    """Run one of the device measurement programs built with the library and return
+    its JSON line.  Runs as a child process, so it is called before this process
+    touches the GPU, and not at all under a profiler (whose preloaded library has
+    touched it already)."""
     import subprocess
-    exe = os.path.join(ROOT, "paper_2302_14812_amd", "radio_atomics_bench")
+    exe = os.path.join(ROOT, "paper_2302_14812_amd", name)
     if not os.path.exists(exe):
         return {"skipped": "measurement program not built"}
     if "rocprof" in os.environ.get("LD_PRELOAD", "") or any(k.startswith("ROCPROF")
@@ -397,10 +397,29 @@ def atomics_leg():
     r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     if r.returncode != 0:
         return {"failed": r.returncode, "stderr": r.stderr[-400:]}
-    res = json.loads(r.stdout.strip().splitlines()[-1])
-    print(f"[bench] atomics: global f64 {res['global_f64_spread']:.3e}/s coalesced, "
-          f"{res['global_f64_wave']:.3e}/s one address per wave; LDS f64 "
-          f"{res['lds_f64_spread']:.3e}/s", file=sys.stderr, flush=True)
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def atomics_leg():
+    """Floating-point atomic-add throughput of the GPU, the rates the deposit's ring
+    flushes and slot emissions run against."""
+    res = measurement_program("radio_atomics_bench")
+    if "global_f64_spread" in res:
+        print(f"[bench] atomics: global f64 {res['global_f64_spread']:.3e}/s coalesced, "
+              f"{res['global_f64_wave']:.3e}/s one address per wave; LDS f64 "
+              f"{res['lds_f64_spread']:.3e}/s", file=sys.stderr, flush=True)
+    return res
+
+
+def valu_leg():
+    """Issue cost of the vector instructions the deposit is made of (cycles one
+    wavefront instruction occupies a SIMD): with the deposit's instruction counts by
+    type, the time its VALU work takes on this GPU."""
+    res = measurement_program("radio_valu_bench")
+    if "fma_f64" in res:
+        print("[bench] valu cycles per wavefront instruction: " +
+              ", ".join(f"{k} {v:.2f}" for k, v in res.items() if k not in ("unit", "clock_ghz")),
+              file=sys.stderr, flush=True)
     return res
 
 
@@ -445,9 +464,10 @@ def main():
         print("bench.py runs on one GPU only: the deposit is measured on a single MI355X "
               "(see the sharding paragraph of the design notes); use --gpus 1", file=sys.stderr)
         sys.exit(2)
-    # the atomics program runs first, as a child process, while this one has not
-    # touched the GPU yet
+    # the measurement programs run first, as child processes, while this one has
+    # not touched the GPU yet
     atomics = None if args.no_atomics else atomics_leg()
+    valu = None if args.no_atomics else valu_leg()
     import torch
 
     import paper_2302_14812_amd as radio
@@ -547,6 +567,8 @@ def main():
         out["serve"] = serve_leg(radio, W, precs, args.serve_chunks, args.serve_load)
     if atomics is not None:
         out["atomics"] = atomics
+    if valu is not None:
+        out["valu_issue_cycles"] = valu
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, args.cpu_cells)
         out["cpu_baseline"] = cb

@@ -24,8 +24,10 @@ COMMON = [
 ]
 
 SOURCES = ["radio_kernels.hip", "radio_spectrum.hip", "radio_push.hip", "radio_runtime.cpp"]
-# measurement program: floating-point atomic-add throughput (run by bench.py)
+# measurement programs run by bench.py: floating-point atomic-add throughput,
+# issue cost of the vector instructions the deposit uses
 ATOMICS_BENCH = os.path.join(HERE, "radio_atomics_bench")
+VALU_BENCH = os.path.join(HERE, "radio_valu_bench")
 
 
 def build(verbose: bool = False) -> str:
@@ -45,12 +47,13 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     for o in objs:
         os.remove(o)
-    cmd = [HIPCC] + [c for c in COMMON if c not in ("-fPIC", "-fvisibility=hidden")] + [
-        os.path.join(CSRC, "atomics_bench.hip"), "-o", ATOMICS_BENCH + ".tmp"]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(ATOMICS_BENCH + ".tmp", ATOMICS_BENCH)
+    for src, exe in (("atomics_bench.hip", ATOMICS_BENCH), ("valu_bench.hip", VALU_BENCH)):
+        cmd = [HIPCC] + [c for c in COMMON if c not in ("-fPIC", "-fvisibility=hidden")] + [
+            os.path.join(CSRC, src), "-o", exe + ".tmp"]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(exe + ".tmp", exe)
     return LIB
 
 
