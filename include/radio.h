@@ -204,11 +204,20 @@ RADIO_API int radio_deposit_batch(radio_detector* const* dets, const radio_chunk
  *                        launches
  *   items_per_workgroup  work items per resident workgroup in a batched deposit
  *                        (finer items balance uneven jobs, coarser ones cost less)
+ *   order_budget_mib     device memory (MiB) the per-tile particle orders of one
+ *                        deposit may take; 0, the default, allows the size of the
+ *                        chunk's state records and at least 1 GiB.  A single
+ *                        deposit keeps each order to at most two runs of 16
+ *                        segments (arrival offsets drift apart along a chunk);
+ *                        a chunk whose orders exceed the budget is deposited in
+ *                        time slices that fit it, with the same result up to
+ *                        summation order
  */
 typedef struct radio_tuning {
     int32_t target_blocks;
     int32_t items_per_workgroup;
     int32_t max_grid;
+    int32_t order_budget_mib;
 } radio_tuning;
 
 RADIO_API int radio_set_tuning(const radio_tuning* t);

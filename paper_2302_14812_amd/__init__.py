@@ -76,7 +76,7 @@ class _Push(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("target_blocks", ctypes.c_int32), ("items_per_workgroup", ctypes.c_int32),
-                ("max_grid", ctypes.c_int32)]
+                ("max_grid", ctypes.c_int32), ("order_budget_mib", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -378,17 +378,17 @@ def get_tuning() -> dict:
     t = _Tuning()
     _check(_lib().radio_get_tuning(ctypes.byref(t)), "radio_get_tuning")
     return {"target_blocks": int(t.target_blocks), "items_per_workgroup": int(t.items_per_workgroup),
-            "max_grid": int(t.max_grid)}
+            "max_grid": int(t.max_grid), "order_budget_mib": int(t.order_budget_mib)}
 
 
 def set_tuning(target_blocks: Optional[int] = None, items_per_workgroup: Optional[int] = None,
-               max_grid: Optional[int] = None) -> None:
+               max_grid: Optional[int] = None, order_budget_mib: Optional[int] = None) -> None:
     """Set the launch tunables (radio_tuning); unnamed ones keep their values."""
     cur = get_tuning()
     new = {"target_blocks": target_blocks, "items_per_workgroup": items_per_workgroup,
-           "max_grid": max_grid}
+           "max_grid": max_grid, "order_budget_mib": order_budget_mib}
     t = _Tuning(*[int(new[k] if new[k] is not None else cur[k])
-                  for k in ("target_blocks", "items_per_workgroup", "max_grid")])
+                  for k in ("target_blocks", "items_per_workgroup", "max_grid", "order_budget_mib")])
     _check(_lib().radio_set_tuning(ctypes.byref(t)), "radio_set_tuning")
 
 

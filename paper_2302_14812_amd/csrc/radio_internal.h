@@ -78,8 +78,8 @@ struct DepositJob {
     double* acc;                    // [n_c][n_t][6] doubles, or [n_c][n_t][12] floats (hi, lo)
                                     // for the compensated single mode
     unsigned long long* counters;   // [3]: clipped, nonmonotone, ring bypasses
-    const double* x;                // [3][n_s+1][n_p]
-    const double* u;                // [3][n_s+1][n_p]
+    const double* x;                // state 0 of [3][...][n_p] (components xs_stride apart)
+    const double* u;                // the same for u
     const double* q;                // [n_p] or nullptr (all -1)
     void* recs;                     // workspace [n_p][n_s+1] records of the job's mode
     int32_t* perm;                  // workspace [n_groups][n_tiles][n_p]: particle orders
@@ -91,6 +91,9 @@ struct DepositJob {
     int64_t n_c, n_t, n_p, n_s;
     double t_first, dt;             // state s at t_first + (s0 + s)*dt
     int64_t s0;                     // the chunk's first state within its run
+    int64_t xs_stride;              // elements between the components of x and u
+    int64_t s_before, s_after;      // states x and u hold before state 0 and after state n_s
+                                    // (a time slice of a longer chunk: its neighbours)
     double t0, inv_dt_det;          // slot coordinate (t_det - t0) * inv_dt_det
     double inv_c, c;
     // work decomposition, filled by plan_job()
@@ -128,11 +131,16 @@ void plan_job(DepositJob& job, int target_blocks, int64_t capacity);
 // the tile's sorted batches in `parts` contiguous ranges (1: all of them)
 void set_parts(DepositJob& job, int64_t parts);
 // One particle order per tile for each group of runs (sorted at the group's
-// middle state), as many groups as keep the orders within the size of the
-// state records (and at least 1 GiB): arrival offsets that drift apart over a
-// long chunk are re-sorted along it.  Chunks of fewer than 16 batches of
-// particles keep one order.
-void set_groups(DepositJob& job, size_t rec_bytes);
+// middle state): arrival offsets that drift apart over a long chunk are
+// re-sorted along it.  max_order_groups is how many orders fit the budget
+// (budget_mib, or when 0 the size of the chunk's state records and at least
+// 1 GiB); set_groups spreads the job's runs over at most that many groups.
+// Chunks of fewer than 16 batches of particles keep one order.
+int64_t max_order_groups(const DepositJob& job, size_t rec_bytes, int64_t budget_mib);
+void set_groups(DepositJob& job, int64_t max_groups);
+// Runs per order group that a deposit keeps to, by depositing a longer chunk
+// in time slices whose orders fit the budget.
+constexpr int64_t kRunsPerGroup = 2;
 
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);

@@ -778,12 +778,16 @@ __device__ __forceinline__ double slot_coord_mixed(const double xc[3], const dou
 constexpr int kBdBackward = 0, kBdBackwardFirst = 1, kBdCentred = 2;
 
 // Mixed-precision records carry the particle's q/c in betadot and half of
-// 1/gamma^2, the forms their field takes (q: [n_p] or nullptr, all -1).
+// 1/gamma^2, the forms their field takes (q: [n_p] or nullptr, all -1).  x and
+// u point at the job's state 0, with components `stride` elements apart; they
+// hold states s_lo <= 0 .. s_hi >= n_s (a time slice of a longer chunk reads
+// its neighbours, so that its records equal those of the whole chunk).
 template <int M>
 __global__ __launch_bounds__(256) void kinematics_kernel(const double* __restrict__ x,
                                                          const double* __restrict__ u,
                                                          const double* __restrict__ q,
-                                                         int64_t n_p, int64_t n_s, double dt,
+                                                         int64_t n_p, int64_t n_s, int64_t stride,
+                                                         int64_t s_lo, int64_t s_hi, double dt,
                                                          double inv_c, int bd_rule,
                                                          void* __restrict__ recs_out)
 {
@@ -791,7 +795,6 @@ __global__ __launch_bounds__(256) void kinematics_kernel(const double* __restric
     Rec* recs = reinterpret_cast<Rec*>(recs_out);
     const int64_t n_states = n_s + 1;
     const int64_t total = n_p * n_states;
-    const int64_t stride = n_states * n_p;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t s = i / n_p;  // consecutive threads read consecutive particles
@@ -804,9 +807,9 @@ __global__ __launch_bounds__(256) void kinematics_kernel(const double* __restric
         double g2i;
         canon_kinematics(u[off], u[off + stride], u[off + 2 * stride], r.b, &g2i);
         double bd[3] = {0.0, 0.0, 0.0};
-        if (bd_rule == kBdCentred && n_s > 0) {
-            const int64_t sa = s > 0 ? s - 1 : 0;
-            const int64_t sb = s < n_s ? s + 1 : n_s;
+        if (bd_rule == kBdCentred && s_hi > s_lo) {
+            const int64_t sa = s > s_lo ? s - 1 : s_lo;
+            const int64_t sb = s < s_hi ? s + 1 : s_hi;
             double ba[3], bb[3], g;
             const int64_t oa = sa * n_p + p, ob = sb * n_p + p;
             canon_kinematics(u[oa], u[oa + stride], u[oa + 2 * stride], ba, &g);
@@ -814,14 +817,15 @@ __global__ __launch_bounds__(256) void kinematics_kernel(const double* __restric
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 bd[c] = canon_betadot(bb[c], ba[c], (double)(sb - sa) * dt);
-        } else if (s > 0 || (bd_rule == kBdBackwardFirst && n_s > 0)) {
+        } else if (s > s_lo || (bd_rule == kBdBackwardFirst && s_hi > s_lo)) {
             // backward difference; at the first state, the forward one
             double bo[3], go;
-            const int64_t o2 = s > 0 ? off - n_p : off + n_p;
+            const int64_t o2 = s > s_lo ? off - n_p : off + n_p;
             canon_kinematics(u[o2], u[o2 + stride], u[o2 + 2 * stride], bo, &go);
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                bd[c] = s > 0 ? canon_betadot(r.b[c], bo[c], dt) : canon_betadot(bo[c], r.b[c], dt);
+                bd[c] = s > s_lo ? canon_betadot(r.b[c], bo[c], dt)
+                                 : canon_betadot(bo[c], r.b[c], dt);
         }
         if constexpr (M == kModeF64) {
 #pragma unroll
@@ -846,7 +850,8 @@ __global__ __launch_bounds__(256) void kinematics_kernel(const double* __restric
 constexpr int kOrderBins = 4096;
 
 __global__ __launch_bounds__(256) void order_kernel(const double* __restrict__ x, int64_t n_p,
-                                                    int64_t n_s, int64_t n_tiles,
+                                                    int64_t n_s, int64_t xs_stride,
+                                                    int64_t n_tiles,
                                                     int64_t steps_per_group,
                                                     const double* __restrict__ cells, int64_t n_c,
                                                     double inv_c, double inv_dt_det,
@@ -871,7 +876,7 @@ __global__ __launch_bounds__(256) void order_kernel(const double* __restrict__ x
     for (int i = tid; i < kOrderBins; i += 256)
         hist[i] = 0u;
     __syncthreads();
-    const int64_t stride = (n_s + 1) * n_p;
+    const int64_t stride = xs_stride;
     const int64_t base = s_key * n_p;
     const double cx = ctr[0], cy = ctr[1], cz = ctr[2];
     auto key = [&](int64_t p) {
@@ -1614,12 +1619,19 @@ void plan_job(DepositJob& job, int target_blocks, int64_t capacity)
 
 constexpr int64_t kMinGroupParticles = 16 * kGroups;  // 16 batches
 
-void set_groups(DepositJob& job, size_t rec_bytes)
+int64_t max_order_groups(const DepositJob& job, size_t rec_bytes, int64_t budget_mib)
 {
     const double per_group = (double)job.n_tiles * (double)job.n_p * sizeof(int32_t);
-    const double budget = std::max((double)(job.n_s + 1) * (double)job.n_p * (double)rec_bytes,
-                                   (double)(int64_t(1) << 30));
-    int64_t groups = (int64_t)std::min((double)job.n_runs, std::max(1.0, budget / per_group));
+    const double budget =
+        budget_mib > 0 ? (double)budget_mib * (double)(int64_t(1) << 20)
+                       : std::max((double)(job.n_s + 1) * (double)job.n_p * (double)rec_bytes,
+                                  (double)(int64_t(1) << 30));
+    return (int64_t)std::max(1.0, std::min(budget / per_group, (double)INT32_MAX));
+}
+
+void set_groups(DepositJob& job, int64_t max_groups)
+{
+    int64_t groups = std::min(job.n_runs, std::max<int64_t>(1, max_groups));
     // a few batches gain nothing from re-sorting, and each order costs a histogram
     if (job.n_p < kMinGroupParticles)
         groups = 1;
@@ -1668,19 +1680,20 @@ hipError_t launch_kinematics(const DepositJob& job, int mode, hipStream_t s)
     const int rule = job.hold == 2 ? kBdCentred : (job.hold == 1 ? kBdBackwardFirst : kBdBackward);
     if (mode == kModeF64)
         hipLaunchKernelGGL(kinematics_kernel<kModeF64>, dim3((unsigned)blocks), dim3(256), 0, s,
-                           job.x, job.u, job.q, job.n_p, job.n_s, job.dt, job.inv_c, rule,
-                           job.recs);
+                           job.x, job.u, job.q, job.n_p, job.n_s, job.xs_stride, -job.s_before,
+                           job.n_s + job.s_after, job.dt, job.inv_c, rule, job.recs);
     else
         hipLaunchKernelGGL(kinematics_kernel<kModeMix>, dim3((unsigned)blocks), dim3(256), 0, s,
-                           job.x, job.u, job.q, job.n_p, job.n_s, job.dt, job.inv_c, rule,
-                           job.recs);
+                           job.x, job.u, job.q, job.n_p, job.n_s, job.xs_stride, -job.s_before,
+                           job.n_s + job.s_after, job.dt, job.inv_c, rule, job.recs);
     return hipGetLastError();
 }
 
 hipError_t launch_order(const DepositJob& job, hipStream_t s)
 {
     hipLaunchKernelGGL(order_kernel, dim3((unsigned)(job.n_tiles * job.n_groups)), dim3(256), 0, s,
-                       job.x, job.n_p, job.n_s, job.n_tiles, job.runs_per_group * kRunL,
+                       job.x, job.n_p, job.n_s, job.xs_stride, job.n_tiles,
+                       job.runs_per_group * kRunL,
                        job.cells, job.n_c, job.inv_c, job.inv_dt_det, job.perm);
     return hipGetLastError();
 }

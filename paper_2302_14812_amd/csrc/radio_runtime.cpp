@@ -53,7 +53,7 @@ namespace {
 
 // launch tunables (radio_set_tuning)
 std::mutex g_tuning_mu;
-radio_tuning g_tuning = {0, 4, 1 << 22};
+radio_tuning g_tuning = {0, 4, 1 << 22, 0};
 
 radio_tuning current_tuning()
 {
@@ -310,6 +310,9 @@ radio::DepositJob make_job(radio_detector* det, const radio_chunk* k)
     J.n_s = k->n_steps;
     J.t_first = k->t_first;
     J.s0 = k->first_step;
+    J.xs_stride = (k->n_steps + 1) * k->n_particles;
+    J.s_before = 0;
+    J.s_after = 0;
     J.far = det->d_far;
     J.vscale = (det->options & RADIO_ACCEL_ONLY) ? 0.0 : 1.0;
     J.hold = (det->options & RADIO_HOLD_LINEAR) ? 2 : ((det->options & RADIO_HOLD_PREVIOUS) ? 1 : 0);
@@ -322,7 +325,29 @@ radio::DepositJob make_job(radio_detector* det, const radio_chunk* k)
     const int per_cu =
         radio::persistent_blocks_per_cu(radio::kernel_variant(det->precision, J), false);
     radio::plan_job(J, current_tuning().target_blocks, (int64_t)det->n_cus * per_cu);
-    radio::set_groups(J, radio::rec_bytes(det->precision));
+    radio::set_groups(J, radio::max_order_groups(J, radio::rec_bytes(det->precision), current_tuning().order_budget_mib));
+    return J;
+}
+
+// The job of the time slice [r_a, r_b) of the runs of the whole-chunk job W:
+// its states, with the neighbours the kinematics reads, and its own work
+// decomposition, with at most max_groups particle orders.
+radio::DepositJob slice_job(const radio_detector* det, const radio::DepositJob& W, int64_t r_a,
+                            int64_t r_b, int64_t max_groups)
+{
+    radio::DepositJob J = W;
+    const int64_t a = r_a * radio::kRunL;
+    const int64_t b = std::min(r_b * radio::kRunL, W.n_s);
+    J.x = W.x + a * W.n_p;
+    J.u = W.u + a * W.n_p;
+    J.n_s = b - a;
+    J.s0 = W.s0 + a;
+    J.s_before = W.s_before + a;
+    J.s_after = W.s_after + (W.n_s - b);
+    const int per_cu =
+        radio::persistent_blocks_per_cu(radio::kernel_variant(det->precision, J), false);
+    radio::plan_job(J, current_tuning().target_blocks, (int64_t)det->n_cus * per_cu);
+    radio::set_groups(J, max_groups);
     return J;
 }
 
@@ -355,24 +380,38 @@ int enqueue_deposit(radio_detector* det, const radio_chunk* k, hipStream_t s)
         return RADIO_OK;
     if (k->n_particles > INT32_MAX || k->n_steps > INT32_MAX - 1)
         return RADIO_EINVAL;
-    radio::DepositJob J = make_job(det, k);
-    int rc = grow(&det->d_recs, &det->recs_cap,
-                  (size_t)(J.n_p * (J.n_s + 1)) * radio::rec_bytes(det->precision));
-    if (rc != RADIO_OK)
-        return rc;
-    rc = grow(&det->d_perm, &det->perm_cap, (size_t)(J.n_groups * J.n_tiles * J.n_p));
-    if (rc == RADIO_OK)
-        rc = grow(&det->d_sel, &det->sel_cap, (size_t)J.n_tiles);
-    if (rc != RADIO_OK)
-        return rc;
-    J.recs = det->d_recs;
-    J.perm = det->d_perm;
-    J.ring_sel = det->d_sel;
-    if (radio::launch_kinematics(J, det->precision, s) != hipSuccess ||
-        radio::launch_order(J, s) != hipSuccess ||
-        radio::launch_ring_choice(J, det->precision, s) != hipSuccess ||
-        radio::launch_deposit(J, det->precision, current_tuning().max_grid, s) != hipSuccess)
-        return RADIO_EDEVICE;
+    const radio::DepositJob W = make_job(det, k);
+    // Particle orders of at most kRunsPerGroup runs: a chunk whose orders would
+    // not fit the budget is deposited in time slices that each do.  The slices
+    // share the state-time origin and read their neighbour states, so that the
+    // sum of their deposits is the chunk's, up to summation order.
+    const int64_t max_groups = radio::max_order_groups(W, radio::rec_bytes(det->precision), current_tuning().order_budget_mib);
+    const int64_t slice_runs = W.n_p < 16 * radio::kGroups || W.runs_per_group <= radio::kRunsPerGroup
+                                   ? W.n_runs
+                                   : max_groups * radio::kRunsPerGroup;
+    const int64_t n_slices = (W.n_runs + slice_runs - 1) / slice_runs;
+    const int64_t runs_each = (W.n_runs + n_slices - 1) / n_slices;
+    for (int64_t r_a = 0; r_a < W.n_runs; r_a += runs_each) {
+        radio::DepositJob J =
+            n_slices == 1 ? W : slice_job(det, W, r_a, std::min(r_a + runs_each, W.n_runs), max_groups);
+        int rc = grow(&det->d_recs, &det->recs_cap,
+                      (size_t)(J.n_p * (J.n_s + 1)) * radio::rec_bytes(det->precision));
+        if (rc != RADIO_OK)
+            return rc;
+        rc = grow(&det->d_perm, &det->perm_cap, (size_t)(J.n_groups * J.n_tiles * J.n_p));
+        if (rc == RADIO_OK)
+            rc = grow(&det->d_sel, &det->sel_cap, (size_t)J.n_tiles);
+        if (rc != RADIO_OK)
+            return rc;
+        J.recs = det->d_recs;
+        J.perm = det->d_perm;
+        J.ring_sel = det->d_sel;
+        if (radio::launch_kinematics(J, det->precision, s) != hipSuccess ||
+            radio::launch_order(J, s) != hipSuccess ||
+            radio::launch_ring_choice(J, det->precision, s) != hipSuccess ||
+            radio::launch_deposit(J, det->precision, current_tuning().max_grid, s) != hipSuccess)
+            return RADIO_EDEVICE;
+    }
     det->interactions += k->n_particles * k->n_steps * det->n_c;
     return RADIO_OK;
 }
@@ -758,7 +797,8 @@ int radio_deposit_batch(radio_detector* const* dets, const radio_chunk* chunks, 
 int radio_set_tuning(const radio_tuning* t)
 {
     if (!t || t->target_blocks < 0 || t->target_blocks > (1 << 24) || t->items_per_workgroup < 1 ||
-        t->items_per_workgroup > 4096 || t->max_grid < 1 || t->max_grid > (1 << 22))
+        t->items_per_workgroup > 4096 || t->max_grid < 1 || t->max_grid > (1 << 22) ||
+        t->order_budget_mib < 0)
         return RADIO_EINVAL;
     std::lock_guard<std::mutex> lk(g_tuning_mu);
     g_tuning = *t;

@@ -115,7 +115,10 @@ def test_tuning_roundtrip(radio):
     cur = radio.get_tuning()
     radio.set_tuning(target_blocks=1024, items_per_workgroup=2)
     assert radio.get_tuning() == {"target_blocks": 1024, "items_per_workgroup": 2,
-                                  "max_grid": cur["max_grid"]}
+                                  "max_grid": cur["max_grid"],
+                                  "order_budget_mib": cur["order_budget_mib"]}
+    with pytest.raises(radio.RadioError):
+        radio.set_tuning(order_budget_mib=-1)
     with pytest.raises(radio.RadioError):
         radio.set_tuning(max_grid=0)
     with pytest.raises(radio.RadioError):

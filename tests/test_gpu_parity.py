@@ -278,6 +278,42 @@ def test_state_at_a_cell(radio, precision):
                  f"state at a cell {precision} (finite slots)")
 
 
+@pytest.mark.parametrize("precision,options", [("fp64", 0), ("fp64", 4), ("fp64", 8), ("mixed", 0)])
+def test_time_slices_equal_whole_chunk(radio, precision, options):
+    """A chunk whose per-tile particle orders (at most two runs each) exceed the
+    order budget is deposited in time slices, each reading its neighbour states
+    for betadot: the result is the whole chunk's up to summation order, for every
+    hold rule (options 4, 8: previous, linear), and the oracle's."""
+    import torch
+    chunk = W.random_chunk(2000, 150, seed=41, dt=0.05, gamma_max=10.0)
+    cells = W.plane_cells([0, 0, 30.0], [1, 0, 0], [0, 1, 0], 32, 32, 6.0, 6.0)
+    t0, dtd = W.arrival_window(cells, chunk, 400, pad_frac=0.05,
+                               cell_index=W.grid_corner_cells(32, 32), seed=41)
+    spec = W.DetectorSpec(cells=cells, t0=t0, dt_det=dtd, n_t=400)
+
+    def run():
+        det = radio.Detector.from_spec(spec, precision=precision, options=options)
+        det.deposit(radio.Chunk.from_numpy(chunk))
+        E, B = det.read()
+        torch.cuda.synchronize()
+        det.close()
+        return E.cpu().numpy(), B.cpu().numpy()
+
+    cur = radio.get_tuning()
+    try:
+        Ew, Bw = run()
+        # 64 tiles x 2000 particles x 4 bytes: one MiB holds two orders, so the
+        # ten runs go in three slices of four, four and two
+        radio.set_tuning(order_budget_mib=1)
+        Es, Bs = run()
+    finally:
+        radio.set_tuning(**cur)
+    check_parity(Es, Bs, Ew, Bw, 1e-13, f"time slices vs whole chunk {precision} options={options}")
+    if options == 0:
+        Eo, Bo, _ = oracle_deposit(spec, chunk)
+        check_parity(Es, Bs, Eo, Bo, TOLS[precision], f"time slices vs oracle {precision}")
+
+
 def test_chunk_split_and_superposition(radio):
     chunk = W.random_chunk(23, 150, seed=12, dt=0.04, gamma_max=20.0)
     cells = W.plane_cells([0, 3.0, 40.0], [1, 0, 0], [0, 1, 0], 13, 11, 8.0, 8.0)
