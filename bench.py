@@ -92,6 +92,8 @@ def time_precision(radio, wl, chunk_dev, precision, steps, warmup, options=0, ke
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kernel_ms = sum(a.elapsed_time(b) for a, b in evs) / steps
+    # deposit launches in the last step (a long chunk runs as time slices)
+    time_precision.launches = det.stats()["slices"]
     det.close()
     if keep:
         return wall / steps * 1e3, kernel_ms, (E, B)
@@ -501,8 +503,12 @@ def main():
     for prec in order:
         ms, kms = time_precision(radio, wl, chunk_dev, prec, args.steps, args.warmup)
         flops = inter * FLOPS_PER_INTERACTION
+        # the deposit call of a step is `launches` deposit-kernel launches of equal
+        # work (time slices); flops / time is the same per launch and per step, and
+        # roofline.traffic is per launch
         legs[prec] = {
             "value": inter / (ms * 1e-3), "ms_per_step": ms, "deposit_kernel_ms": kms,
+            "deposit_launches_per_step": time_precision.launches,
             "roofline": {"bound": "alu", "achieved": flops / (kms * 1e-3) / 1e12,
                          "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
                          "frac": flops / (kms * 1e-3) / 1e12 / PEAK_TFLOPS[prec],

@@ -154,6 +154,9 @@ typedef struct radio_stats {
     int64_t bytes;        /* device bytes held by the detector (with its workspace) */
     int64_t bypassed;     /* slot updates that missed the on-chip slot window and went
                              straight to device memory (a performance counter) */
+    int64_t slices;       /* deposit launches made for those chunks: a single deposit
+                             of a long chunk runs as time slices (radio_tuning), a
+                             batched one as one job per chunk */
 } radio_stats;
 
 /*

@@ -81,7 +81,7 @@ class _Tuning(ctypes.Structure):
 
 class _Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
-                ("interactions", "clipped", "nonmonotone", "chunks", "bytes", "bypassed")]
+                ("interactions", "clipped", "nonmonotone", "chunks", "bytes", "bypassed", "slices")]
 
 
 _LIB = None

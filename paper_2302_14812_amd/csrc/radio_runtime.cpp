@@ -42,6 +42,7 @@ struct radio_detector {
     size_t spec_cap = 0;                       // in complex values
     int64_t interactions = 0;
     int64_t chunks = 0;
+    int64_t slices = 0;  // deposit jobs launched (time slices of single deposits)
     std::vector<double> h_cells;               // caller's order
 };
 
@@ -411,6 +412,7 @@ int enqueue_deposit(radio_detector* det, const radio_chunk* k, hipStream_t s)
             radio::launch_ring_choice(J, det->precision, s) != hipSuccess ||
             radio::launch_deposit(J, det->precision, current_tuning().max_grid, s) != hipSuccess)
             return RADIO_EDEVICE;
+        det->slices += 1;
     }
     det->interactions += k->n_particles * k->n_steps * det->n_c;
     return RADIO_OK;
@@ -582,6 +584,7 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
     for (size_t j = 0; j < idx.size(); ++j) {
         const radio_chunk* k = &chunks[idx[j]];
         dets[idx[j]]->interactions += k->n_particles * k->n_steps * dets[idx[j]]->n_c;
+        dets[idx[j]]->slices += 1;
     }
     for (int i = 0; i < n; ++i)
         dets[i]->chunks += 1;
@@ -751,6 +754,7 @@ int radio_detector_reset(radio_detector* det, void* stream)
         return RADIO_EDEVICE;
     det->interactions = 0;
     det->chunks = 0;
+    det->slices = 0;
     return RADIO_OK;
 }
 
@@ -845,6 +849,7 @@ int radio_detector_stats(const radio_detector* det, radio_stats* out)
     out->nonmonotone = (int64_t)cnt[1];
     out->bypassed = (int64_t)cnt[2];
     out->chunks = det->chunks;
+    out->slices = det->slices;
     out->bytes = (int64_t)(det->n_c * det->n_t * 6 * (int64_t)sizeof(double) +
                            det->n_c * 3 * (int64_t)sizeof(double) +
                            det->n_c * (int64_t)sizeof(int64_t) +

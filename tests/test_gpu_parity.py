@@ -296,18 +296,20 @@ def test_time_slices_equal_whole_chunk(radio, precision, options):
         det.deposit(radio.Chunk.from_numpy(chunk))
         E, B = det.read()
         torch.cuda.synchronize()
+        slices = det.stats()["slices"]
         det.close()
-        return E.cpu().numpy(), B.cpu().numpy()
+        return E.cpu().numpy(), B.cpu().numpy(), slices
 
     cur = radio.get_tuning()
     try:
-        Ew, Bw = run()
+        Ew, Bw, n_whole = run()
         # 64 tiles x 2000 particles x 4 bytes: one MiB holds two orders, so the
         # ten runs go in three slices of four, four and two
         radio.set_tuning(order_budget_mib=1)
-        Es, Bs = run()
+        Es, Bs, n_sliced = run()
     finally:
         radio.set_tuning(**cur)
+    assert (n_whole, n_sliced) == (1, 3)
     check_parity(Es, Bs, Ew, Bw, 1e-13, f"time slices vs whole chunk {precision} options={options}")
     if options == 0:
         Eo, Bo, _ = oracle_deposit(spec, chunk)
