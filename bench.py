@@ -539,6 +539,7 @@ def main():
                    "n_t": wl.detector.n_t, "precision": args.precision,
                    "interactions_per_step": inter},
         "roofline": main_leg["roofline"],
+        "deposit_launches_per_step": main_leg["deposit_launches_per_step"],
     }
     # ceilings of the interaction rate at F_int flops per interaction: double at the FP64
     # vector peak; mixed as its 25 double + 59 single flops at the two vector peaks
