@@ -131,9 +131,10 @@ __device__ __forceinline__ void fill_twiddles(double2* tw, const double2* __rest
 // len = 2^lg in LDS, sequence t at buf[t * len], loaded in bit-reversed order;
 // leaves them in natural order.  Two consecutive stages (spans h and 2h) are
 // done per pass on the four values k, k + h, k + 2h, k + 3h of each block of
-// 4h -- the same butterflies and twiddles as two radix-2 stages, with half the
-// passes, barriers and LDS traffic; an odd lg starts with one stage of span 1.
-// tw holds exp(-2 pi i j / len), j < len / 2.  Ends with a barrier.
+// 4h -- the same butterflies as two radix-2 stages, with half the passes,
+// barriers and LDS traffic; an odd lg starts with one stage of span 1.  tw holds
+// exp(-2 pi i j / len), j < len / 2; a pass reads one twiddle per butterfly
+// and derives the other two.  Ends with a barrier.
 __device__ __forceinline__ void lds_fft(double2* buf, const double2* tw, int lg, int T)
 {
     const int len = 1 << lg;
@@ -157,9 +158,10 @@ __device__ __forceinline__ void lds_fft(double2* buf, const double2* tw, int lg,
             const int k = b & (h - 1);
             double2* x = buf + ((b >> lgh) << (lgh + 2)) + k;
             const double2 a0 = x[0], a1 = x[h], a2 = x[2 * h], a3 = x[3 * h];
-            const double2 w1 = tw[k * tws];
+            // W_4h^k from the table; W_2h^k = (W_4h^k)^2 and W_4h^(k+h) = -i W_4h^k
             const double2 w2 = tw[k * (tws >> 1)];
-            const double2 w3 = tw[(k + h) * (tws >> 1)];
+            const double2 w1 = cmul(w2, w2);
+            const double2 w3 = make_double2(w2.y, -w2.x);
             const double2 t1 = cmul(a1, w1), t3 = cmul(a3, w1);
             const double2 b0 = make_double2(a0.x + t1.x, a0.y + t1.y);
             const double2 b1 = make_double2(a0.x - t1.x, a0.y - t1.y);
