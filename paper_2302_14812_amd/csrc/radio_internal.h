@@ -139,8 +139,10 @@ void set_parts(DepositJob& job, int64_t parts);
 int64_t max_order_groups(const DepositJob& job, size_t rec_bytes, int64_t budget_mib);
 void set_groups(DepositJob& job, int64_t max_groups);
 // Runs per order group that a deposit keeps to, by depositing a longer chunk
-// in time slices whose orders fit the budget.
+// in time slices whose orders fit the budget; particles below which a chunk
+// keeps a single order (16 batches).
 constexpr int64_t kRunsPerGroup = 2;
+constexpr int64_t kMinGroupParticles = 16 * kGroups;
 
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);

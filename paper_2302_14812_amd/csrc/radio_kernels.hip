@@ -1622,8 +1622,6 @@ void plan_job(DepositJob& job, int target_blocks, int64_t capacity)
     set_parts(job, parts);
 }
 
-constexpr int64_t kMinGroupParticles = 16 * kGroups;  // 16 batches
-
 int64_t max_order_groups(const DepositJob& job, size_t rec_bytes, int64_t budget_mib)
 {
     const double per_group = (double)job.n_tiles * (double)job.n_p * sizeof(int32_t);

@@ -326,7 +326,8 @@ radio::DepositJob make_job(radio_detector* det, const radio_chunk* k)
     const int per_cu =
         radio::persistent_blocks_per_cu(radio::kernel_variant(det->precision, J), false);
     radio::plan_job(J, current_tuning().target_blocks, (int64_t)det->n_cus * per_cu);
-    radio::set_groups(J, radio::max_order_groups(J, radio::rec_bytes(det->precision), current_tuning().order_budget_mib));
+    radio::set_groups(J, radio::max_order_groups(J, radio::rec_bytes(det->precision),
+                                                 current_tuning().order_budget_mib));
     return J;
 }
 
@@ -385,16 +386,19 @@ int enqueue_deposit(radio_detector* det, const radio_chunk* k, hipStream_t s)
     // Particle orders of at most kRunsPerGroup runs: a chunk whose orders would
     // not fit the budget is deposited in time slices that each do.  The slices
     // share the state-time origin and read their neighbour states, so that the
-    // sum of their deposits is the chunk's, up to summation order.
-    const int64_t max_groups = radio::max_order_groups(W, radio::rec_bytes(det->precision), current_tuning().order_budget_mib);
-    const int64_t slice_runs = W.n_p < 16 * radio::kGroups || W.runs_per_group <= radio::kRunsPerGroup
-                                   ? W.n_runs
-                                   : max_groups * radio::kRunsPerGroup;
+    // sum of their deposits is the chunk's, up to summation order.  The first
+    // slice is the largest, so only it can grow the workspaces: a later one
+    // cannot fail for memory after earlier ones were enqueued.
+    const int64_t max_groups = radio::max_order_groups(W, radio::rec_bytes(det->precision),
+                                                       current_tuning().order_budget_mib);
+    const bool slice = W.n_p >= radio::kMinGroupParticles &&
+                       W.runs_per_group > radio::kRunsPerGroup;
+    const int64_t slice_runs = slice ? max_groups * radio::kRunsPerGroup : W.n_runs;
     const int64_t n_slices = (W.n_runs + slice_runs - 1) / slice_runs;
     const int64_t runs_each = (W.n_runs + n_slices - 1) / n_slices;
     for (int64_t r_a = 0; r_a < W.n_runs; r_a += runs_each) {
-        radio::DepositJob J =
-            n_slices == 1 ? W : slice_job(det, W, r_a, std::min(r_a + runs_each, W.n_runs), max_groups);
+        const int64_t r_b = std::min(r_a + runs_each, W.n_runs);
+        radio::DepositJob J = n_slices == 1 ? W : slice_job(det, W, r_a, r_b, max_groups);
         int rc = grow(&det->d_recs, &det->recs_cap,
                       (size_t)(J.n_p * (J.n_s + 1)) * radio::rec_bytes(det->precision));
         if (rc != RADIO_OK)
