@@ -89,6 +89,38 @@ __device__ __forceinline__ double canon_state_time(double t_first, double s, dou
     return t_first + s * dt;
 }
 
+// sqrt(x) correctly rounded for x = 0 and 2^-767 <= x < inf (every distance of
+// physical size), with 1/sqrt(x) to an ulp or two beside it.  A hardware
+// reciprocal square root seed (about 23 bits) is refined by one coupled
+// Goldschmidt step, g ~ sqrt(x) and h ~ 1/(2 sqrt(x)), and g by two residual
+// corrections g += (x - g^2) h, each rounded once -- the sequence the compiler
+// emits for a correctly rounded double sqrt, without its rescaling of inputs
+// below 2^-767 and its special-value checks (0 is handled here; inf and NaN do
+// not occur).  The reciprocal is one Newton step on 1/g from 2h; for x = 0 it
+// is NaN, as d (1/R) is when d = 0.
+__device__ __forceinline__ double canon_sqrt(double x, double* rinv)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y;
+    double h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    d = fma(-g, g, x);
+    g = fma(d, h, g);
+    const double q = 2.0 * h;
+    *rinv = fma(q, fma(-g, q, 1.0), q);
+    return x == 0.0 ? 0.0 : g;
+}
+
+__device__ __forceinline__ double canon_sqrt(double x)
+{
+    double unused;
+    return canon_sqrt(x, &unused);
+}
+
 __device__ __forceinline__ double canon_arrival(double t, double R, double inv_c)
 {
 #pragma clang fp contract(off)
@@ -567,16 +599,15 @@ __device__ __forceinline__ double recip(double x)
 // Lienard-Wiechert E, B (Eq. 1) at a cell from one staged state, all in double;
 // returns the state's slot coordinate.  Only the arrival time (R and tau) is
 // rounded canonically; n, w, kappa and the field, which decide no slot, use
-// FMAs and a Newton reciprocal (within an ulp or two of the correctly rounded
-// values).
+// FMAs, 1/R from canon_sqrt and a Newton reciprocal for 1/kappa (within an ulp
+// or two of the correctly rounded values).
 __device__ __forceinline__ double field_fp64(const double xc[3], const RecF64& st, double t_s,
                                              double qc, double qv, const Consts& K, double F[6])
 {
     double d[3] = {xc[0] - st.x[0], xc[1] - st.x[1], xc[2] - st.x[2]};
-    double R2 = canon_norm2(d[0], d[1], d[2]);
-    double R = __builtin_sqrt(R2);
+    double rinv;
+    const double R = canon_sqrt(canon_norm2(d[0], d[1], d[2]), &rinv);
     double tau = canon_arrival(t_s, R, K.inv_c);
-    const double rinv = recip(R);
     const double n[3] = {d[0] * rinv, d[1] * rinv, d[2] * rinv};
     const double w[3] = {n[0] - st.b[0], n[1] - st.b[1], n[2] - st.b[2]};
     // kappa = (|n - beta|^2 + 1/gamma^2) / 2, as canon_kappa but fused
@@ -733,7 +764,7 @@ __device__ __forceinline__ void potentials_at(const double xc[3], const double f
         rinv = 1.0 / fc[3];
     } else {
         double d[3] = {xc[0] - st.x[0], xc[1] - st.x[1], xc[2] - st.x[2]};
-        const double R = __builtin_sqrt(canon_norm2(d[0], d[1], d[2]));
+        const double R = canon_sqrt(canon_norm2(d[0], d[1], d[2]));
         rinv = 1.0 / R;
         double n[3], w[3];
         canon_direction(d, rinv, st.b, n, w);
@@ -752,7 +783,7 @@ __device__ __forceinline__ double slot_coord_fp64(const double xc[3], const doub
                                                   double t_s, const Consts& K)
 {
     double d[3] = {xc[0] - x[0], xc[1] - x[1], xc[2] - x[2]};
-    double R = __builtin_sqrt(canon_norm2(d[0], d[1], d[2]));
+    const double R = canon_sqrt(canon_norm2(d[0], d[1], d[2]));
     return canon_slot(canon_arrival(t_s, R, K.inv_c), K.t0, K.inv_dt_det);
 }
 
@@ -1580,7 +1611,7 @@ __global__ void arrival_kernel(const double* cells, const double* pts, const dou
         double d0 = cells[3 * i] - pts[3 * i];
         double d1 = cells[3 * i + 1] - pts[3 * i + 1];
         double d2 = cells[3 * i + 2] - pts[3 * i + 2];
-        out[i] = canon_arrival(t[i], __builtin_sqrt(canon_norm2(d0, d1, d2)), inv_c);
+        out[i] = canon_arrival(t[i], canon_sqrt(canon_norm2(d0, d1, d2)), inv_c);
     }
 }
 

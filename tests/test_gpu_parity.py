@@ -92,6 +92,28 @@ def test_arrival_times_bit_exact(radio, oracle_mod):
         assert bad.size == 0, (c, bad[:5], out[bad[:5]] - ref[bad[:5]])
 
 
+def test_arrival_times_bit_exact_hard_cases(radio, oracle_mod):
+    """Arrival times where the square root's rounding is hardest: distances along
+    an axis (|d|^2 the rounded square of one coordinate, whose root lies next to
+    a representable value), integer Pythagorean-like offsets, and magnitudes from
+    1e-3 to 1e7; every one must equal the oracle's bit for bit."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(7))
+    n = 30000
+    pts = rng.normal(size=(3 * n, 3)) * rng.uniform(0, 10, size=(3 * n, 1))
+    d = np.zeros((3 * n, 3))
+    d[:n, 0] = 10.0 ** rng.uniform(-3, 7, size=n) * rng.choice([-1.0, 1.0], size=n)
+    d[n:2 * n, :2] = rng.integers(-10 ** 6, 10 ** 6, size=(n, 2)).astype(np.float64)
+    d[2 * n:] = rng.normal(size=(n, 3)) * (10.0 ** rng.uniform(-3, 7, size=(n, 1)))
+    cells = pts + d
+    t = rng.uniform(-50, 500, size=3 * n)
+    out = radio.arrival_times(torch.from_numpy(cells).cuda(), torch.from_numpy(pts).cuda(),
+                              torch.from_numpy(t).cuda(), c=1.0).cpu().numpy()
+    ref = np.array([oracle_mod.arrival(cells[i], pts[i], t[i], 1.0) for i in range(3 * n)])
+    bad = np.flatnonzero(out != ref)
+    assert bad.size == 0, (bad[:5], out[bad[:5]] - ref[bad[:5]])
+
+
 @PRECISIONS
 def test_parity_circular_orbit(radio, precision):
     wl = W.circular_workload()
