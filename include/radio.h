@@ -51,13 +51,15 @@ extern "C" {
 
 /* arithmetic of the deposit */
 #define RADIO_FP64 0         /* every step in IEEE double */
-#define RADIO_MIXED 1        /* arrival time, slot coordinate, n - beta and kappa in
-                                double; the rest of the field and the slot weights in
-                                single; slot accumulation in double */
-#define RADIO_MIXED_TWOSUM 2 /* as RADIO_MIXED, but slots accumulate in single precision
-                                with compensation: each slot holds a (hi, lo) pair and
-                                every add carries its exact rounding error (two-sum)
-                                into lo */
+#define RADIO_MIXED 1        /* arrival time, slot coordinate and n - beta in double;
+                                kappa (a sum of positive terms), the rest of the field
+                                and the slot weights in single; slot accumulation in
+                                double */
+#define RADIO_MIXED_TWOSUM 2 /* as RADIO_MIXED, but the detector's slots in device
+                                memory are (hi, lo) single-precision pairs: every add
+                                to them carries its exact rounding error (two-sum) into
+                                lo; the on-chip sums that reach them are formed in
+                                double */
 
 /* detector options (bit flags in radio_detector_desc.options) */
 #define RADIO_FAR_FIELD 1  /* far-field arrival time, Eq. 3: t + R_cell/c - x_part . n_cell/c

@@ -30,7 +30,7 @@ static_assert(sizeof(RecF64) == 80 && sizeof(RecMix) == 64, "state record layout
 
 // arithmetic of a deposit: field in double, accumulation in double; field in
 // single, accumulation in double; field in single, accumulation in compensated
-// single pairs
+// single pairs in HBM (the on-chip slot ring sums in double in every mode)
 constexpr int kModeF64 = 0;
 constexpr int kModeMix = 1;
 constexpr int kModeMixTwoSum = 2;

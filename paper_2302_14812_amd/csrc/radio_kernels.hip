@@ -231,13 +231,12 @@ __device__ __forceinline__ void global_add_pair(RADIO_GLOBAL float* row, int j, 
 
 // One cell's ring of slots in LDS, covering slots [base, base + R); slot j lives
 // at position j mod R.  Emissions inside go to the ring (LDS atomic add: the
-// kGroups lanes of a cell share it), anything else straight to HBM.
-//
-// Double accumulation (Acc = double): 6 values per slot; the emission (double
-// or single) is widened and added.  Compensated single accumulation (Acc =
-// float): the pair hi[6], lo[6] per slot, updated like the HBM pair -- the LDS
-// atomic returns the old hi and the lane adds the rounding error of its own
-// add (two-sum) to lo.
+// kGroups lanes of a cell share it), anything else straight to HBM.  The ring
+// holds 6 doubles per slot in every mode; the emission (double or single) is
+// widened and added.  Acc is the element of the HBM accumulator: double, or
+// for compensated single accumulation (Acc = float) the pair hi[6], lo[6] per
+// slot, which a slot leaving the ring reaches as the double split into hi and
+// lo, and a bypassing emission as itself (two-sum into the pair).
 template <typename Acc, int R>
 struct CellSink;
 
@@ -272,23 +271,20 @@ struct CellSink<double, R> {
 
 template <int R>
 struct CellSink<float, R> {
-    static constexpr int W = 12;  // hi[6], lo[6]
-    RADIO_LDS float* ring;
-    RADIO_GLOBAL float* row;
+    static constexpr int W = 6;  // ring values per slot
+    RADIO_LDS double* ring;
+    RADIO_GLOBAL float* row;      // hi[6], lo[6] per slot
     int base;
     int n_t;
     unsigned* n_bypass;
     __device__ __forceinline__ void flush(int j, const float a[6]) const
     {
         if ((unsigned)(j - base) < (unsigned)R) {
-            RADIO_LDS float* q = ring + (j & (R - 1)) * W;
+            RADIO_LDS double* q = ring + (j & (R - 1)) * W;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                const float old = __hip_atomic_fetch_add(q + k, a[k], __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
-                __hip_atomic_fetch_add(q + 6 + k, two_sum_err(old, a[k], old + a[k]),
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
+            for (int k = 0; k < 6; ++k)
+                __hip_atomic_fetch_add(q + k, (double)a[k], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
         } else if ((unsigned)j < (unsigned)n_t) {
             *n_bypass += 1u;
             global_add(row, j, a);
@@ -1076,7 +1072,7 @@ struct DepositShared {
     typename ModeTypes<M>::Rec rec[kGroups][kRunL + 1];  // staged batch: a run per group
     double sq[kGroups];                 // its charges
     double tk[kRunL + 1];               // its states' time arguments (the same for every lane)
-    Acc ring[kTileCells * kStride];     // per-cell slot rings
+    double ring[kTileCells * kStride];  // per-cell slot rings
     int nb[2][kTileCells];              // per cell: lowest start slot of a coming batch
     int ord[2][kGroups];                // particles of the staged rows, per batch parity
     unsigned long long cnt[3];          // clipped, nonmonotone, bypassed
@@ -1149,10 +1145,10 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         else
             return MIX ? slot_coord_mixed(xc, st.x, tk, K) : slot_coord_fp64(xc, st.x, tk, K);
     };
-    RADIO_LDS Acc* my_ring = (RADIO_LDS Acc*)&sh.ring[cl * DepositShared<M, R>::kStride];
+    RADIO_LDS double* my_ring = (RADIO_LDS double*)&sh.ring[cl * DepositShared<M, R>::kStride];
     RADIO_LDS int* nb = (RADIO_LDS int*)&sh.nb[0][0];
     for (int i = g; i < R * RW; i += kGroups)
-        my_ring[i] = Acc(0);
+        my_ring[i] = 0.0;
     if (tid < 3)
         sh.cnt[tid] = 0;
     if (tid < 2 * kTileCells)
@@ -1220,20 +1216,28 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
             if (new_base > base && new_base < base + R)
                 hi = new_base;
             for (int j = lo + g; j < hi; j += kGroups) {
-                RADIO_LDS Acc* q = my_ring + (j & (R - 1)) * RW;
-                Acc a[RW];
+                RADIO_LDS double* q = my_ring + (j & (R - 1)) * RW;
+                double a[RW];
                 bool nz = false;
 #pragma unroll
                 for (int k = 0; k < RW; ++k) {
                     a[k] = q[k];
-                    q[k] = Acc(0);
-                    nz |= (a[k] != Acc(0));
+                    q[k] = 0.0;
+                    nz |= (a[k] != 0.0);
                 }
                 if (nz && j < n_t) {
-                    if constexpr (M == kModeMixTwoSum)
-                        global_add_pair(row, j, a, a + 6);
-                    else
+                    if constexpr (M == kModeMixTwoSum) {
+                        // the slot's double sum as a compensated pair
+                        float hi[6], lo[6];
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) {
+                            hi[k] = (float)a[k];
+                            lo[k] = (float)(a[k] - (double)hi[k]);
+                        }
+                        global_add_pair(row, j, hi, lo);
+                    } else {
                         global_add(row, j, a);
+                    }
                 }
             }
         }
