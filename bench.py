@@ -36,8 +36,8 @@ def parse():
     ap.add_argument("--precision", choices=["mixed", "fp64", "mixed_twosum"], default="mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the double-precision leg")
-    ap.add_argument("--twosum", action="store_true",
-                    help="also time the compensated single-precision accumulation")
+    ap.add_argument("--no-twosum", action="store_true",
+                    help="skip the compensated single-precision accumulation leg")
     ap.add_argument("--cpu-cells", type=int, default=0,
                     help="cells in the oracle sample (default: six per host thread)")
     ap.add_argument("--no-atomics", action="store_true",
@@ -497,11 +497,13 @@ def main():
         del src, dst
 
     legs = {}
+    fields = {}  # each leg's E, B (device) for the relative L2 against the double path
     order = [args.precision] + ([] if args.no_fp64 or args.precision == "fp64" else ["fp64"])
-    if args.twosum and args.precision != "mixed_twosum":
+    if not args.no_twosum and args.precision != "mixed_twosum":
         order.append("mixed_twosum")
     for prec in order:
-        ms, kms = time_precision(radio, wl, chunk_dev, prec, args.steps, args.warmup)
+        ms, kms, fields[prec] = time_precision(radio, wl, chunk_dev, prec, args.steps,
+                                               args.warmup, keep=True)
         flops = inter * FLOPS_PER_INTERACTION
         # the deposit call of a step is `launches` deposit-kernel launches of equal
         # work (time slices); flops / time is the same per launch and per step, and
@@ -516,6 +518,19 @@ def main():
         }
         print(f"[bench] {prec}: {ms:.1f} ms/step, deposit kernel {kms:.1f} ms, "
               f"{legs[prec]['value']:.3e} interactions/s", file=sys.stderr, flush=True)
+    # error of each single-precision result, as relative L2 over the whole detector
+    # against the double path (which the parity tests hold within 5e-14 of the
+    # oracle); the larger of E and B
+    if "fp64" in fields:
+        E64, B64 = fields["fp64"]
+        for prec, (E, B) in fields.items():
+            if prec != "fp64":
+                err = max(float(torch.linalg.vector_norm(E - E64) / torch.linalg.vector_norm(E64)),
+                          float(torch.linalg.vector_norm(B - B64) / torch.linalg.vector_norm(B64)))
+                legs[prec]["rel_l2_vs_fp64_path"] = err
+                print(f"[bench] {prec}: relative L2 against the double path {err:.2e}",
+                      file=sys.stderr, flush=True)
+    del fields
 
     main_leg = legs[args.precision]
     opts = None if args.no_options else options_leg(radio, wl, chunk_dev, args.precision, 1, 1)
@@ -540,6 +555,7 @@ def main():
                    "interactions_per_step": inter},
         "roofline": main_leg["roofline"],
         "deposit_launches_per_step": main_leg["deposit_launches_per_step"],
+        "rel_l2_vs_fp64_path": main_leg.get("rel_l2_vs_fp64_path"),
     }
     # ceilings of the interaction rate at F_int flops per interaction: double at the FP64
     # vector peak; mixed as its 25 double + 59 single flops at the two vector peaks
