@@ -33,7 +33,8 @@ def rel_l2(a, b):
 # radix-2 passes beyond 2^22
 @pytest.mark.parametrize("n_t,n_fft,precision,n_side", [
     (256, 0, "fp64", 6), (300, 0, "fp64", 6), (300, 2048, "mixed", 6), (200, 0, "mixed_twosum", 6),
-    (3000, 0, "fp64", 6), (300, 8192, "mixed", 6), (300, 1 << 21, "mixed_twosum", 2),
+    (3000, 0, "fp64", 6), (3000, 0, "mixed_twosum", 6), (300, 8192, "mixed", 6),
+    (300, 1 << 21, "mixed_twosum", 2),
     (300, 1 << 22, "fp64", 2), (300, 1 << 23, "fp64", 2)])
 def test_spectrum_matches_oracle(radio, n_t, n_fft, precision, n_side):
     import torch
