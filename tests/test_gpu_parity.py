@@ -338,6 +338,40 @@ def test_time_slices_equal_whole_chunk(radio, precision, options):
         check_parity(Es, Bs, Eo, Bo, TOLS[precision], f"time slices vs oracle {precision}")
 
 
+def test_time_slices_with_particle_parts(radio):
+    """Time slices of a chunk on few tiles, where each slice's work items also cut
+    the sorted particles into parts: 5 x 10^4 particles on 8 x 8 cells (4 tiles,
+    800 kB per order), so a 1 MiB budget holds one order and the ten runs go in
+    five slices of two.  Same result as the whole chunk, and the oracle's."""
+    import torch
+    chunk = W.random_chunk(50000, 150, seed=43, dt=0.05, gamma_max=10.0)
+    cells = W.plane_cells([0, 0, 30.0], [1, 0, 0], [0, 1, 0], 8, 8, 6.0, 6.0)
+    t0, dtd = W.arrival_window(cells, chunk, 400, pad_frac=0.05,
+                               cell_index=W.grid_corner_cells(8, 8), seed=43)
+    spec = W.DetectorSpec(cells=cells, t0=t0, dt_det=dtd, n_t=400)
+
+    def run():
+        det = radio.Detector.from_spec(spec, precision="fp64")
+        det.deposit(radio.Chunk.from_numpy(chunk))
+        E, B = det.read()
+        torch.cuda.synchronize()
+        slices = det.stats()["slices"]
+        det.close()
+        return E.cpu().numpy(), B.cpu().numpy(), slices
+
+    cur = radio.get_tuning()
+    try:
+        Ew, Bw, n_whole = run()
+        radio.set_tuning(order_budget_mib=1)
+        Es, Bs, n_sliced = run()
+    finally:
+        radio.set_tuning(**cur)
+    assert (n_whole, n_sliced) == (1, 5)
+    check_parity(Es, Bs, Ew, Bw, 1e-13, "time slices with particle parts vs whole chunk")
+    Eo, Bo, _ = oracle_deposit(spec, chunk)
+    check_parity(Es, Bs, Eo, Bo, TOL_FP64, "time slices with particle parts vs oracle")
+
+
 def test_chunk_split_and_superposition(radio):
     chunk = W.random_chunk(23, 150, seed=12, dt=0.04, gamma_max=20.0)
     cells = W.plane_cells([0, 3.0, 40.0], [1, 0, 0], [0, 1, 0], 13, 11, 8.0, 8.0)
