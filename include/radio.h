@@ -156,9 +156,9 @@ typedef struct radio_stats {
     int64_t bytes;        /* device bytes held by the detector (with its workspace) */
     int64_t bypassed;     /* slot updates that missed the on-chip slot window and went
                              straight to device memory (a performance counter) */
-    int64_t slices;       /* deposit launches made for those chunks: a single deposit
-                             of a long chunk runs as time slices (radio_tuning), a
-                             batched one as one job per chunk */
+    int64_t slices;       /* deposit launches made for those chunks: a long chunk runs
+                             as time slices (radio_tuning), alone or in a batch; any
+                             other batched chunk as one job of the batch's launch */
 } radio_stats;
 
 /*
@@ -190,8 +190,11 @@ RADIO_API int radio_deposit_trajectory_chunk(radio_detector* det, const radio_ch
  * range of runs), ordered longest first, and taken by resident workgroups
  * from a device counter.  The result equals n separate
  * radio_deposit_trajectory_chunk calls (up to the order of floating-point
- * additions).  All detectors must live on the current device; a detector may
- * appear more than once.  On any invalid pair nothing is enqueued.  Batch
+ * additions).  A pair whose particle orders would not fit the order budget
+ * (radio_tuning) is deposited after the persistent launch, in the time slices
+ * of a single deposit.  All detectors must live on the current device; a
+ * detector may appear more than once.  On any invalid pair nothing is
+ * enqueued; RADIO_ENOMEM leaves every detector unchanged.  Batch
  * workspaces are shared by the device's batches, two in turn: a call waits
  * (on the host) for the batch enqueued two calls earlier on that device to
  * finish, so one batch can run while the next is prepared.
@@ -212,8 +215,9 @@ RADIO_API int radio_deposit_batch(radio_detector* const* dets, const radio_chunk
  *   order_budget_mib     device memory (MiB) the per-tile particle orders of one
  *                        deposit may take; 0, the default, allows the size of the
  *                        chunk's state records and at least 1 GiB.  A single
- *                        deposit keeps each order to at most two runs of 16
- *                        segments (arrival offsets drift apart along a chunk);
+ *                        deposit, alone or batched, keeps each order to at most
+ *                        two runs of 16 segments (arrival offsets drift apart
+ *                        along a chunk);
  *                        a chunk whose orders exceed the budget is deposited in
  *                        time slices that fit it, with the same result up to
  *                        summation order

@@ -296,7 +296,7 @@ bool far_geometry(const std::vector<double>& cells, std::vector<double>& far)
     return true;
 }
 
-radio::DepositJob make_job(radio_detector* det, const radio_chunk* k)
+radio::DepositJob make_job(const radio_detector* det, const radio_chunk* k)
 {
     radio::DepositJob J{};
     J.cells = det->d_cells;
@@ -376,36 +376,64 @@ int grow(T** p, size_t* cap, size_t need)
     return RADIO_OK;
 }
 
+// The time slices of one deposit: a chunk whose particle orders of at most
+// kRunsPerGroup runs would not fit the order budget is deposited in time slices
+// that each do.  The slices share the state-time origin and read their
+// neighbour states, so that the sum of their deposits is the chunk's, up to
+// summation order.  The first slice is the largest.
+struct SlicePlan {
+    radio::DepositJob W;  // the whole chunk
+    int64_t max_groups = 0;
+    int64_t n_slices = 1;
+    int64_t runs_each = 0;
+};
+
+SlicePlan plan_slices(const radio_detector* det, const radio_chunk* k)
+{
+    SlicePlan P;
+    P.W = make_job(det, k);
+    P.max_groups = radio::max_order_groups(P.W, radio::rec_bytes(det->precision),
+                                           current_tuning().order_budget_mib);
+    const bool slice = P.W.n_p >= radio::kMinGroupParticles &&
+                       P.W.runs_per_group > radio::kRunsPerGroup;
+    const int64_t slice_runs = slice ? P.max_groups * radio::kRunsPerGroup : P.W.n_runs;
+    P.n_slices = (P.W.n_runs + slice_runs - 1) / slice_runs;
+    P.runs_each = (P.W.n_runs + P.n_slices - 1) / P.n_slices;
+    return P;
+}
+
+radio::DepositJob plan_slice(const radio_detector* det, const SlicePlan& P, int64_t r_a)
+{
+    if (P.n_slices == 1)
+        return P.W;
+    return slice_job(det, P.W, r_a, std::min(r_a + P.runs_each, P.W.n_runs), P.max_groups);
+}
+
+// Grow the detector's workspaces to hold slice job J.
+int reserve(radio_detector* det, const radio::DepositJob& J)
+{
+    int rc = grow(&det->d_recs, &det->recs_cap,
+                  (size_t)(J.n_p * (J.n_s + 1)) * radio::rec_bytes(det->precision));
+    if (rc == RADIO_OK)
+        rc = grow(&det->d_perm, &det->perm_cap, (size_t)(J.n_groups * J.n_tiles * J.n_p));
+    if (rc == RADIO_OK)
+        rc = grow(&det->d_sel, &det->sel_cap, (size_t)J.n_tiles);
+    return rc;
+}
+
+// Enqueue a deposit in its time slices.  Only the first (largest) slice can
+// grow the workspaces, so a later one cannot fail for memory after earlier
+// ones were enqueued.
 int enqueue_deposit(radio_detector* det, const radio_chunk* k, hipStream_t s)
 {
     if (k->n_particles == 0 || k->n_steps == 0)
         return RADIO_OK;
     if (k->n_particles > INT32_MAX || k->n_steps > INT32_MAX - 1)
         return RADIO_EINVAL;
-    const radio::DepositJob W = make_job(det, k);
-    // Particle orders of at most kRunsPerGroup runs: a chunk whose orders would
-    // not fit the budget is deposited in time slices that each do.  The slices
-    // share the state-time origin and read their neighbour states, so that the
-    // sum of their deposits is the chunk's, up to summation order.  The first
-    // slice is the largest, so only it can grow the workspaces: a later one
-    // cannot fail for memory after earlier ones were enqueued.
-    const int64_t max_groups = radio::max_order_groups(W, radio::rec_bytes(det->precision),
-                                                       current_tuning().order_budget_mib);
-    const bool slice = W.n_p >= radio::kMinGroupParticles &&
-                       W.runs_per_group > radio::kRunsPerGroup;
-    const int64_t slice_runs = slice ? max_groups * radio::kRunsPerGroup : W.n_runs;
-    const int64_t n_slices = (W.n_runs + slice_runs - 1) / slice_runs;
-    const int64_t runs_each = (W.n_runs + n_slices - 1) / n_slices;
-    for (int64_t r_a = 0; r_a < W.n_runs; r_a += runs_each) {
-        const int64_t r_b = std::min(r_a + runs_each, W.n_runs);
-        radio::DepositJob J = n_slices == 1 ? W : slice_job(det, W, r_a, r_b, max_groups);
-        int rc = grow(&det->d_recs, &det->recs_cap,
-                      (size_t)(J.n_p * (J.n_s + 1)) * radio::rec_bytes(det->precision));
-        if (rc != RADIO_OK)
-            return rc;
-        rc = grow(&det->d_perm, &det->perm_cap, (size_t)(J.n_groups * J.n_tiles * J.n_p));
-        if (rc == RADIO_OK)
-            rc = grow(&det->d_sel, &det->sel_cap, (size_t)J.n_tiles);
+    const SlicePlan P = plan_slices(det, k);
+    for (int64_t r_a = 0; r_a < P.W.n_runs; r_a += P.runs_each) {
+        radio::DepositJob J = plan_slice(det, P, r_a);
+        const int rc = reserve(det, J);
         if (rc != RADIO_OK)
             return rc;
         J.recs = det->d_recs;
@@ -479,16 +507,28 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
             return RADIO_EDEVICE;
         A->pending = false;
     }
-    // plan every nonempty pair
+    // Plan every nonempty pair.  A pair whose particle orders would not fit the
+    // order budget is deposited after the persistent launch, in the time slices
+    // of a single deposit on its detector's own workspaces; those are grown
+    // here, before anything is enqueued, so that a memory error leaves every
+    // detector as it was.
     const radio_tuning tun = current_tuning();
-    std::vector<int> idx;
+    std::vector<int> idx, sliced;
     size_t recs_need = 0, perm_need = 0, sel_need = 0;
     A->h_jobs.clear();
     for (int i = 0; i < n; ++i) {
         const radio_chunk* k = &chunks[i];
         if (k->n_particles == 0 || k->n_steps == 0)
             continue;
-        radio::DepositJob J = make_job(dets[i], k);
+        const SlicePlan P = plan_slices(dets[i], k);
+        if (P.n_slices > 1) {
+            const int rc = reserve(dets[i], plan_slice(dets[i], P, 0));
+            if (rc != RADIO_OK)
+                return rc;
+            sliced.push_back(i);
+            continue;
+        }
+        const radio::DepositJob& J = P.W;
         recs_need += (size_t)(J.n_p * (J.n_s + 1)) * radio::rec_bytes(dets[i]->precision);
         perm_need += (size_t)(J.n_groups * J.n_tiles * J.n_p);
         sel_need += (size_t)J.n_tiles;
@@ -496,6 +536,11 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
         idx.push_back(i);
     }
     if (idx.empty()) {
+        for (int i : sliced) {
+            const int rc = enqueue_deposit(dets[i], &chunks[i], s);
+            if (rc != RADIO_OK)
+                return rc;
+        }
         for (int i = 0; i < n; ++i)
             dets[i]->chunks += 1;
         return RADIO_OK;
@@ -589,6 +634,11 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
         const radio_chunk* k = &chunks[idx[j]];
         dets[idx[j]]->interactions += k->n_particles * k->n_steps * dets[idx[j]]->n_c;
         dets[idx[j]]->slices += 1;
+    }
+    for (int i : sliced) {
+        rc = enqueue_deposit(dets[i], &chunks[i], s);
+        if (rc != RADIO_OK)
+            return rc;
     }
     for (int i = 0; i < n; ++i)
         dets[i]->chunks += 1;

@@ -99,6 +99,76 @@ def test_batch_mixed_modes_duplicates_and_empty(radio, sets):
         d.close()
 
 
+def test_batch_time_slices_long_chunks(radio, sets):
+    """A batched pair whose particle orders exceed the order budget is deposited in
+    the time slices of a single deposit, after the persistent launch; the other
+    pairs stay in the launch.  Here the long chunk (2000 particles x 150 steps on
+    32 x 32 cells) goes twice to one detector, in three slices each under a 1 MiB
+    budget.  Every detector equals its whole-chunk deposits, counts the slices a
+    single deposit would make, and the long chunk's detector matches the oracle
+    on sampled cells."""
+    import torch
+    long = W.random_chunk(2000, 150, seed=41, dt=0.05, gamma_max=10.0)
+    cells = W.plane_cells([0, 0, 30.0], [1, 0, 0], [0, 1, 0], 32, 32, 6.0, 6.0)
+    t0, dtd = W.arrival_window(cells, long, 400, pad_frac=0.05,
+                               cell_index=W.grid_corner_cells(32, 32), seed=41)
+    spec = W.DetectorSpec(cells=cells, t0=t0, dt_det=dtd, n_t=400)
+    c_long = radio.Chunk.from_numpy(long)
+    short = sets[:3]
+    c_short = [radio.Chunk.from_numpy(wl.chunk) for wl in short]
+    # whole-chunk references at the default budget
+    ref_long = radio.Detector.from_spec(spec, precision="fp64")
+    ref_long.deposit(c_long)
+    ref_long.deposit(c_long)
+    refs = []
+    for wl, c in zip(short, c_short):
+        r = radio.Detector.from_spec(wl.detector, precision="fp64")
+        r.deposit(c)
+        refs.append(r)
+    torch.cuda.synchronize()
+    cur = radio.get_tuning()
+    try:
+        radio.set_tuning(order_budget_mib=1)
+        d_long = radio.Detector.from_spec(spec, precision="fp64")
+        d_short = [radio.Detector.from_spec(wl.detector, precision="fp64") for wl in short]
+        radio.deposit_batch([d_short[0], d_long, d_short[1], d_long, d_short[2]],
+                            [c_short[0], c_long, c_short[1], c_long, c_short[2]])
+        # slices of single deposits under the same budget
+        single = []
+        for wl, c in zip(short, c_short):
+            d = radio.Detector.from_spec(wl.detector, precision="fp64")
+            d.deposit(c)
+            torch.cuda.synchronize()
+            single.append(d.stats()["slices"])
+            d.close()
+    finally:
+        radio.set_tuning(**cur)
+    st = d_long.stats()
+    assert (st["chunks"], st["slices"]) == (2, 6)
+    assert st["interactions"] == 2 * 2000 * 150 * 1024
+    E, B = _read(d_long)
+    Er, Br = _read(ref_long)
+    e = max(rel_l2(E, Er), rel_l2(B, Br))
+    print(f"[batch] long chunk twice in time slices vs whole relL2 {e:.3e}", flush=True)
+    assert e <= 1e-13
+    idx = [0, 31, 500, 992, 1023]
+    D = oracle.deposit_workload(spec, long, cell_index=idx)
+    Eo, Bo = oracle.read(D)
+    eo = max(rel_l2(E[idx], 2.0 * Eo), rel_l2(B[idx], 2.0 * Bo))
+    print(f"[batch] long chunk twice in time slices vs oracle relL2 {eo:.3e}", flush=True)
+    assert eo <= 1e-12
+    for wl, d, r, n_single in zip(short, d_short, refs, single):
+        E, B = _read(d)
+        Er, Br = _read(r)
+        e = max(rel_l2(E, Er), rel_l2(B, Br))
+        print(f"[batch] {wl.name} beside the sliced pairs: relL2 {e:.3e}, slices "
+              f"{d.stats()['slices']} (single deposit {n_single})", flush=True)
+        assert e <= 1e-13
+        assert d.stats()["slices"] == n_single
+    for d in [d_long, ref_long] + d_short + refs:
+        d.close()
+
+
 def test_batch_rejects_invalid_pairs_without_work(radio, sets):
     wl = sets[1]
     det = radio.Detector.from_spec(wl.detector)
