@@ -55,6 +55,9 @@ def parse():
                     help="skip the run-time (push and deposit) leg")
     ap.add_argument("--serve-chunks", type=int, default=30,
                     help="timed chunks of the streaming leg (after a fifth as many warm-up)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="bound on the streaming leg's offered stream (fewer chunks when "
+                         "the device is slow)")
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="offered load as a fraction of the measured single-chunk throughput")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -187,7 +190,7 @@ def batch_leg(radio, W, precision, steps, warmup):
             "speedup": ms_sep / ms_batch, "autotuned": tuned}
 
 
-def serve_leg(radio, W, precisions, n_chunks, load):
+def serve_leg(radio, W, precisions, n_chunks, load, seconds=60.0):
     """Streaming service: 8 plasma-mirror detectors (256 x 256 cells, 4096 slots each)
     resident in HBM, fed by a Poisson stream of chunks of 1-64 steps x 10^3-10^5
     fresh particles.  The arrival rate is load x X / E[work], where X is the
@@ -228,8 +231,8 @@ def serve_leg(radio, W, precisions, n_chunks, load):
         x_rate = sum(c.n_particles * c.n_steps * cells for c in probe) / (time.perf_counter() - t)
         det.close()
         rate = load * x_rate / mean_work
-        # keep the stream to about a minute: fewer chunks when the device is slow
-        n_use = int(min(n_all, max(10, rate * 60.0)))
+        # keep the stream to about `seconds`: fewer chunks when the device is slow
+        n_use = int(min(n_all, max(10, rate * seconds)))
         n_skip = max(1, n_use * n_warm // n_all)
         offsets = poisson_arrivals(rate, n_use, seed=W.BASE_SEED + 501)
         print(f"[bench] serve ({prec}): X = {x_rate:.3e} I/s, {rate:.2f} chunks/s, "
@@ -587,7 +590,8 @@ def main():
         out["runtime"] = runtime_leg(radio, W, args.precision)
     if not args.no_serve:
         precs = [args.precision] + (["fp64"] if args.precision != "fp64" and not args.no_fp64 else [])
-        out["serve"] = serve_leg(radio, W, precs, args.serve_chunks, args.serve_load)
+        out["serve"] = serve_leg(radio, W, precs, args.serve_chunks, args.serve_load,
+                                 args.serve_seconds)
     if atomics is not None:
         out["atomics"] = atomics
     if valu is not None:
