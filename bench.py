@@ -562,7 +562,7 @@ def main():
     }
     # ceilings of the interaction rate at F_int flops per interaction: double at the FP64
     # vector peak; mixed as its 25 double + 59 single flops at the two vector peaks
-    # (single at the packed rate), and with every flop at 78.6 (this build runs no
+    # (single at the packed rate), and with every flop at 78.6 (the library is compiled without
     # packed single-precision instructions)
     fp64_ceiling = PEAK_TFLOPS["fp64"] * 1e12 / FLOPS_PER_INTERACTION
     blended = 1.0 / (25.0 / (PEAK_TFLOPS["fp64"] * 1e12) + 59.0 / (PEAK_TFLOPS["mixed"] * 1e12))
