@@ -99,7 +99,8 @@ def test_batch_mixed_modes_duplicates_and_empty(radio, sets):
         d.close()
 
 
-def test_batch_time_slices_long_chunks(radio, sets):
+@pytest.mark.parametrize("precision", ["fp64", "mixed_twosum"])
+def test_batch_time_slices_long_chunks(radio, sets, precision):
     """A batched pair whose particle orders exceed the order budget is deposited in
     the time slices of a single deposit, after the persistent launch; the other
     pairs stay in the launch.  Here the long chunk (2000 particles x 150 steps on
@@ -108,6 +109,8 @@ def test_batch_time_slices_long_chunks(radio, sets):
     single deposit would make, and the long chunk's detector matches the oracle
     on sampled cells."""
     import torch
+    tol_whole = 1e-13 if precision == "fp64" else 1e-6
+    tol_or = 1e-12 if precision == "fp64" else 1e-5
     long = W.random_chunk(2000, 150, seed=41, dt=0.05, gamma_max=10.0)
     cells = W.plane_cells([0, 0, 30.0], [1, 0, 0], [0, 1, 0], 32, 32, 6.0, 6.0)
     t0, dtd = W.arrival_window(cells, long, 400, pad_frac=0.05,
@@ -117,26 +120,26 @@ def test_batch_time_slices_long_chunks(radio, sets):
     short = sets[:3]
     c_short = [radio.Chunk.from_numpy(wl.chunk) for wl in short]
     # whole-chunk references at the default budget
-    ref_long = radio.Detector.from_spec(spec, precision="fp64")
+    ref_long = radio.Detector.from_spec(spec, precision=precision)
     ref_long.deposit(c_long)
     ref_long.deposit(c_long)
     refs = []
     for wl, c in zip(short, c_short):
-        r = radio.Detector.from_spec(wl.detector, precision="fp64")
+        r = radio.Detector.from_spec(wl.detector, precision=precision)
         r.deposit(c)
         refs.append(r)
     torch.cuda.synchronize()
     cur = radio.get_tuning()
     try:
         radio.set_tuning(order_budget_mib=1)
-        d_long = radio.Detector.from_spec(spec, precision="fp64")
-        d_short = [radio.Detector.from_spec(wl.detector, precision="fp64") for wl in short]
+        d_long = radio.Detector.from_spec(spec, precision=precision)
+        d_short = [radio.Detector.from_spec(wl.detector, precision=precision) for wl in short]
         radio.deposit_batch([d_short[0], d_long, d_short[1], d_long, d_short[2]],
                             [c_short[0], c_long, c_short[1], c_long, c_short[2]])
         # slices of single deposits under the same budget
         single = []
         for wl, c in zip(short, c_short):
-            d = radio.Detector.from_spec(wl.detector, precision="fp64")
+            d = radio.Detector.from_spec(wl.detector, precision=precision)
             d.deposit(c)
             torch.cuda.synchronize()
             single.append(d.stats()["slices"])
@@ -149,21 +152,23 @@ def test_batch_time_slices_long_chunks(radio, sets):
     E, B = _read(d_long)
     Er, Br = _read(ref_long)
     e = max(rel_l2(E, Er), rel_l2(B, Br))
-    print(f"[batch] long chunk twice in time slices vs whole relL2 {e:.3e}", flush=True)
-    assert e <= 1e-13
+    print(f"[batch] long chunk twice in time slices vs whole {precision} relL2 {e:.3e}",
+          flush=True)
+    assert e <= tol_whole
     idx = [0, 31, 500, 992, 1023]
     D = oracle.deposit_workload(spec, long, cell_index=idx)
     Eo, Bo = oracle.read(D)
     eo = max(rel_l2(E[idx], 2.0 * Eo), rel_l2(B[idx], 2.0 * Bo))
-    print(f"[batch] long chunk twice in time slices vs oracle relL2 {eo:.3e}", flush=True)
-    assert eo <= 1e-12
+    print(f"[batch] long chunk twice in time slices vs oracle {precision} relL2 {eo:.3e}",
+          flush=True)
+    assert eo <= tol_or
     for wl, d, r, n_single in zip(short, d_short, refs, single):
         E, B = _read(d)
         Er, Br = _read(r)
         e = max(rel_l2(E, Er), rel_l2(B, Br))
-        print(f"[batch] {wl.name} beside the sliced pairs: relL2 {e:.3e}, slices "
+        print(f"[batch] {wl.name} beside the sliced pairs {precision}: relL2 {e:.3e}, slices "
               f"{d.stats()['slices']} (single deposit {n_single})", flush=True)
-        assert e <= 1e-13
+        assert e <= tol_whole
         assert d.stats()["slices"] == n_single
     for d in [d_long, ref_long] + d_short + refs:
         d.close()
