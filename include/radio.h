@@ -319,6 +319,20 @@ RADIO_API int radio_spectrum(radio_detector* det, int64_t n_fft, const double* w
 RADIO_API int radio_arrival_times(const double* cells, const double* points, const double* t, int64_t n,
                         double c, double* out, void* stream);
 
+/*
+ * Slot coordinates (t + |x_cell - x|/c - t0) / dt_det of n explicit (cell,
+ * point, time) triples: the arrival time of Eq. 2 in units of slots from the
+ * start of a time array (t0, dt_det), whose integer part is the slot Alg. 2
+ * deposits into.  Evaluated on the device with exactly the rounding of the
+ * double-precision deposit: the arrival time as radio_arrival_times, then the
+ * correctly rounded quotient.  DEVICE arrays cells[n][3], points[n][3], t[n],
+ * out[n].  RADIO_EINVAL for c or dt_det not positive and finite (or 1/dt_det
+ * not finite), t0 not finite, or a NULL array with n > 0.
+ */
+RADIO_API int radio_slot_coordinates(const double* cells, const double* points, const double* t,
+                                     int64_t n, double c, double t0, double dt_det, double* out,
+                                     void* stream);
+
 /* Human-readable text for a status code (static storage). */
 RADIO_API const char* radio_status_string(int status);
 

@@ -10,6 +10,8 @@ Functions and the passages they follow:
   kinematics(u)            Alg. 1: beta = p / sqrt(|p|^2 + 1), 1/gamma^2
   arrival(x_cell, x, t, c) Eq. 2: t_det = t + |x_part - x_cell| / c
                            (far=True: Eq. 3, t + R_cell/c - x_part . n_cell / c)
+  slot_of(tau, t0, dt_det) Alg. 2's slot function before the floor:
+                           (tau - t0) / dt_det
   field(...)               Eq. 1: Lienard-Wiechert E and B = n x E (options:
                            FAR_FIELD geometry, ACCEL_ONLY second term)
   deposit(...)             Alg. 1 + Alg. 2 with the integrator-detector
@@ -70,6 +72,8 @@ def _load():
         lib.radio_oracle_arrival.restype = ctypes.c_double
         lib.radio_oracle_arrival_far.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double]
         lib.radio_oracle_arrival_far.restype = ctypes.c_double
+        lib.radio_oracle_slot_of.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        lib.radio_oracle_slot_of.restype = ctypes.c_double
         lib.radio_oracle_field_opts.argtypes = [dp, dp, dp, ctypes.c_double, dp, ctypes.c_double,
                                                 ctypes.c_double, ctypes.c_int, dp, dp]
         lib.radio_oracle_field_opts.restype = None
@@ -103,6 +107,12 @@ def kinematics(u) -> Tuple[np.ndarray, float]:
 def arrival(x_cell, x_part, t: float, c: float = 1.0, far: bool = False) -> float:
     f = _load().radio_oracle_arrival_far if far else _load().radio_oracle_arrival
     return f(_dptr(_f64(x_cell)), _dptr(_f64(x_part)), float(t), float(c))
+
+
+def slot_of(tau: float, t0: float, dt_det: float) -> float:
+    """Slot coordinate (tau - t0) / dt_det of an arrival time (Alg. 2's slot
+    function before the floor), one correctly rounded division."""
+    return _load().radio_oracle_slot_of(float(tau), float(t0), float(dt_det))
 
 
 def field(x_cell, x_part, beta, inv_gamma2: float, betadot, q: float = -1.0,

@@ -39,9 +39,10 @@
  *   |v|^2 = (v0*v0 + v1*v1) + v2*v2 ;  g = |u|^2 + 1 ;  beta_k = u_k / sqrt(g)
  *   t_s  = t_first + (double)(first_step + s) * dt ;  R = sqrt(|x_c - x_s|^2)
  *   tau  = t_s + R * (1/c)          ;  n_k = d_k * (1/R)
- *   slot coordinate (tau - t0) * (1/dt_det): the time in units of slots, whose
- *   integer part is the slot of Alg. 2 (a segment much shorter than a slot
- *   changes length by ulp(coordinate)/length if rounded differently)
+ *   slot coordinate (tau - t0) / dt_det, one correctly rounded division: the
+ *   time in units of slots, whose integer part is the slot of Alg. 2 (a
+ *   segment much shorter than a slot changes length by ulp(coordinate)/length
+ *   if rounded differently)
  *   kappa = (|n - beta|^2 + 1/g) / 2, which equals 1 - n.beta exactly for a
  *   unit n (|n - beta|^2 = 1 - 2 n.beta + |beta|^2 and 1 - |beta|^2 = 1/g)
  *   but has no cancellation as beta -> 1.
@@ -114,6 +115,14 @@ EXPORT double radio_oracle_arrival(const double x_cell[3], const double x_part[3
     double d2 = x_cell[2] - x_part[2];
     double R = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
     return t + R * (1.0 / c);
+}
+
+/* Slot coordinate of an arrival time: (tau - t0) / dt_det, the time since the
+   start of the detector's time array in units of its slot width, whose integer
+   part is the slot Alg. 2 deposits into (Sec. 3.2). */
+EXPORT double radio_oracle_slot_of(double tau, double t0, double dt_det)
+{
+    return (tau - t0) / dt_det;
 }
 
 /* The cell's distance from the origin and its direction (the far-field
@@ -300,7 +309,6 @@ EXPORT int radio_oracle_deposit(const double* cells, int64_t n_cells, double t0,
     if (!cells || !x || !u || !D || !(dt > 0.0))
         return -1;
     const int64_t n_states = n_steps + 1;
-    const double inv_dt_det = 1.0 / dt_det;
     int64_t clipped = 0, nonmono = 0;
     if (n_threads < 1)
         n_threads = 1;
@@ -360,8 +368,8 @@ EXPORT int radio_oracle_deposit(const double* cells, int64_t n_cells, double t0,
                     radio_oracle_field_opts(xc, x_cur, beta, g2, betadot, qp, c, options, F,
                                             F + 3);
                 }
-                double a = (tau_prev - t0) * inv_dt_det;
-                double b = (tau - t0) * inv_dt_det;
+                double a = radio_oracle_slot_of(tau_prev, t0, dt_det);
+                double b = radio_oracle_slot_of(tau, t0, dt_det);
                 double lo = a < b ? a : b;
                 double hi = a < b ? b : a;
                 if (b < a)

@@ -31,7 +31,7 @@ EXPORTS = (
     "radio_deposit_trajectory_chunk", "radio_deposit_batch", "radio_read_detector",
     "radio_detector_stats", "radio_detector_shape", "radio_detector_cells",
     "radio_arrival_times", "radio_status_string", "radio_set_tuning", "radio_get_tuning",
-    "radio_spectrum", "radio_push",
+    "radio_spectrum", "radio_push", "radio_slot_coordinates",
 )
 
 
@@ -112,6 +112,8 @@ def _lib():
                                              ctypes.POINTER(ctypes.c_int32)]
         lib.radio_detector_cells.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         lib.radio_arrival_times.argtypes = [vp, vp, vp, i64, ctypes.c_double, vp, vp]
+        lib.radio_slot_coordinates.argtypes = [vp, vp, vp, i64, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_double, vp, vp]
         lib.radio_spectrum.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double), vp, vp, vp, vp]
         lib.radio_push.argtypes = [ctypes.POINTER(_Push), i64, i64, ctypes.c_double, i64, vp, vp,
                                    vp]
@@ -421,4 +423,19 @@ def arrival_times(cells, points, t, c: float = 1.0, stream=None):
     out = torch.empty(n, dtype=torch.float64, device=t.device)
     _check(_lib().radio_arrival_times(cells.data_ptr(), points.data_ptr(), t.data_ptr(), n, float(c),
                                       out.data_ptr(), _stream(stream)), "radio_arrival_times")
+    return out
+
+
+def slot_coordinates(cells, points, t, t0: float, dt_det: float, c: float = 1.0, stream=None):
+    """(t + |cells - points|/c - t0) / dt_det on the device, rounded as the double
+    deposit rounds it, for (n, 3), (n, 3), (n,) float64 tensors."""
+    import torch
+    n = int(t.shape[0])
+    _dev_f64(cells, (n, 3), "cells")
+    _dev_f64(points, (n, 3), "points")
+    _dev_f64(t, (n,), "t")
+    out = torch.empty(n, dtype=torch.float64, device=t.device)
+    _check(_lib().radio_slot_coordinates(cells.data_ptr(), points.data_ptr(), t.data_ptr(), n,
+                                         float(c), float(t0), float(dt_det), out.data_ptr(),
+                                         _stream(stream)), "radio_slot_coordinates")
     return out

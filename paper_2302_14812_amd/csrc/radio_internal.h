@@ -94,7 +94,11 @@ struct DepositJob {
     int64_t xs_stride;              // elements between the components of x and u
     int64_t s_before, s_after;      // states x and u hold before state 0 and after state n_s
                                     // (a time slice of a longer chunk: its neighbours)
-    double t0, inv_dt_det;          // slot coordinate (t_det - t0) * inv_dt_det
+    double t0, inv_dt_det;          // slot coordinate (t_det - t0) / dt_det, inv_dt_det =
+                                    // RN(1/dt_det)
+    double dt_det;
+    int64_t slot_div;               // 1: the double slot coordinate divides (the divisor
+                                    // fails the check of slot_quotient_corrects)
     double inv_c, c;
     // work decomposition, filled by plan_job()
     int64_t n_tiles;                // tiles of kTileCells cells
@@ -191,5 +195,13 @@ hipError_t launch_push(const PushParams& P, int64_t n_p, int64_t n_s, double t_f
                        int64_t first_step, double* x, double* u, hipStream_t s);
 hipError_t launch_arrival(const double* cells, const double* pts, const double* t, int64_t n,
                           double inv_c, double* out, hipStream_t s);
+hipError_t launch_slot_coords(const double* cells, const double* pts, const double* t, int64_t n,
+                              double inv_c, double t0, double dt_det, double inv_dt_det,
+                              bool slot_div, double* out, hipStream_t s);
+// Whether the double deposit's slot coordinate, (t_det - t0) / dt_det formed from
+// RN(1/dt_det) with two corrections, is correctly rounded for every numerator
+// with this divisor (|b RN(1/b) - 1| B < 1 - 2^-45, B the significand of b as
+// an integer); if not, the kernels divide.
+bool slot_quotient_corrects(double dt_det);
 
 }  // namespace radio

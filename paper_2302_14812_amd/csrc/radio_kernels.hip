@@ -127,11 +127,35 @@ __device__ __forceinline__ double canon_arrival(double t, double R, double inv_c
     return t + R * inv_c;
 }
 
-// slot coordinate (t_det - t0) / dt_det, as a product with 1/dt_det
-__device__ __forceinline__ double canon_slot(double tau, double t0, double inv_dt_det)
+// The slot coordinate (t_det - t0) / dt_det, correctly rounded, as the one IEEE
+// division that defines it, without a division per state.  With the divisor b =
+// dt_det, its correctly rounded reciprocal y = RN(1/b) from the host and the
+// numerator x = t_det - t0:
+//   q0 = RN(x y)                         within 2.5 ulp of z = x/b
+//   q1 = RN(q0 + RN(x - b q0) y)         within ulp/2 + 10 u ulp   (u = 2^-53)
+//   q2 = RN(q1 + (x - b q1) y)           (x - b q1 is exact here)
+// Two corrections in the manner of Markstein's theorem.  q1 + (x - b q1) y =
+// z + (z - q1) e with e = b y - 1, and |z - q1| <= (1/2 + 10 u) ulp(z).  A
+// quotient of two doubles is never a rounding midpoint, and x - b m for a
+// midpoint m is a nonzero multiple of ulp(b) ulp(z)/2, so z lies at least
+// ulp(z)/(2 B) from every midpoint, B being b's significand as an integer in
+// [2^52, 2^53).  q2 is therefore RN(z) whenever |e| B (1 + 20 u) < 1: true for
+// most divisors (|e| <= B 2^-106) and checked for each detector on the host
+// (slot_div = 0).  For the divisors where it is not, the kernels divide.
+// Valid for normal x and z away from overflow and underflow (|x| >= 2^-900),
+// which physical arrival times are; a non-finite x gives NaN (a dropped segment).
+__device__ __forceinline__ double canon_slot(double tau, double t0, double dt_det,
+                                             double inv_dt_det, bool slot_div)
 {
 #pragma clang fp contract(off)
-    return (tau - t0) * inv_dt_det;
+    const double x = tau - t0;
+    if (slot_div)
+        return x / dt_det;
+    double q = x * inv_dt_det;
+    double r = fma(-q, dt_det, x);
+    q = fma(r, inv_dt_det, q);
+    r = fma(-q, dt_det, x);
+    return fma(r, inv_dt_det, q);
 }
 
 // n = d/R as d * (1/R) and w = n - beta
@@ -547,8 +571,15 @@ __device__ __forceinline__ void add_segment_linear(Carry<T>& C, const Sink& sink
 
 struct Consts {
     double t0, inv_dt_det, inv_c;
-    double kR;  // inv_c * inv_dt_det: slots per unit of distance (mixed modes)
+    double kR;      // inv_c * inv_dt_det: slots per unit of distance (mixed modes)
+    double dt_det;  // the slot width (the divisor of the double slot coordinate)
+    bool slot_div;  // the double slot coordinate takes a division (see canon_slot)
 };
+
+__device__ __forceinline__ double canon_slot(double tau, const Consts& K)
+{
+    return canon_slot(tau, K.t0, K.dt_det, K.inv_dt_det, K.slot_div);
+}
 
 // E and B of Eq. 1 from the unit vector n to the cell, w = n - beta, 1/kappa,
 // 1/R and the state's 1/gamma^2 and betadot, for a charge with qc = q/c and
@@ -611,7 +642,7 @@ __device__ __forceinline__ double field_fp64(const double xc[3], const RecF64& s
         recip(0.5 * fma(w[0], w[0], fma(w[1], w[1], fma(w[2], w[2], st.g2i))));
     const double nwk = (n[0] * w[0] + n[1] * w[1] + n[2] * w[2]) * kinv;
     lw_fields<double>(n, w, kinv, rinv, st.g2i, st.bd, qc, qv, nwk, F);
-    return canon_slot(tau, K.t0, K.inv_dt_det);
+    return canon_slot(tau, K);
 }
 
 // R = |d| and 1/R from one hardware reciprocal square root (about 23 correct
@@ -712,7 +743,7 @@ __device__ __forceinline__ double slot_far_mixed(const double fc[4], const doubl
 __device__ __forceinline__ double slot_far_fp64(const double fc[4], const double x[3], double t_s,
                                                 const Consts& K)
 {
-    return canon_slot(canon_far_arrival(t_s, fc, x, K.inv_c), K.t0, K.inv_dt_det);
+    return canon_slot(canon_far_arrival(t_s, fc, x, K.inv_c), K);
 }
 
 // Eq. 1 with the far-field geometry n = n_cell, R = R_cell; Rinv = 1/R_cell
@@ -780,7 +811,7 @@ __device__ __forceinline__ double slot_coord_fp64(const double xc[3], const doub
 {
     double d[3] = {xc[0] - x[0], xc[1] - x[1], xc[2] - x[2]};
     const double R = canon_sqrt(canon_norm2(d[0], d[1], d[2]));
-    return canon_slot(canon_arrival(t_s, R, K.inv_c), K.t0, K.inv_dt_det);
+    return canon_slot(canon_arrival(t_s, R, K.inv_c), K);
 }
 
 // ub = (t_s - t0) / dt_det, as for field_mixed
@@ -1089,7 +1120,10 @@ struct DepositShared {
 // HOLD: which field a segment holds (0 the current state's, 1 the previous
 // state's, 2 the linear interpolation between the two)
 // G: bit 0 the far-field geometry, bit 1 potentials instead of fields
-template <int M, int R, int G, int HOLD>
+// DIV: the double slot coordinate divides (a divisor that fails the host check
+// of canon_slot's corrections); a compile-time choice, so that the state loop
+// carries no branch for it.
+template <int M, int R, int G, int HOLD, bool DIV>
 __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, int64_t split,
                                              int64_t part, DepositShared<M, R>& sh)
 {
@@ -1109,7 +1143,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
     const int64_t row_i = tile * kTileCells + cl;  // internal (tile-ordered) cell row
     const bool active = row_i < J.n_c;
     const int n_t = (int)J.n_t;
-    const Consts K{J.t0, J.inv_dt_det, J.inv_c, J.inv_c * J.inv_dt_det};
+    const Consts K{J.t0, J.inv_dt_det, J.inv_c, J.inv_c * J.inv_dt_det, J.dt_det, DIV};
     const double ntd = (double)n_t;
     // the time argument of the field and slot functions for state index sk: the
     // state time t_s (double mode, canonical rounding), or (t_s - t0) / dt_det
@@ -1478,6 +1512,22 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
                                __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// deposit_item with the slot-coordinate form of the job (the single-precision
+// modes have one)
+template <int M, int R, int G, int HOLD>
+__device__ __forceinline__ void deposit_item_of(const DepositJob& J, int64_t tile, int64_t split,
+                                                int64_t part, DepositShared<M, R>& sh)
+{
+    if constexpr (M == kModeF64) {
+        if (J.slot_div)
+            deposit_item<M, R, G, HOLD, true>(J, tile, split, part, sh);
+        else
+            deposit_item<M, R, G, HOLD, false>(J, tile, split, part, sh);
+    } else {
+        deposit_item<M, R, G, HOLD, false>(J, tile, split, part, sh);
+    }
+}
+
 // The work items item0 + [0, gridDim.x) of a single deposit, item =
 // split * n_tiles + tile, one per workgroup (gridDim.x is a multiple of
 // kXcds); items whose tile takes the other ring size leave at once.
@@ -1488,14 +1538,16 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
 // one; the far-field, acceleration-only and held-field kernels go a few
 // registers over, and keeping them at five waves (at the cost of a few spilled
 // words in the hold kernels) is 4-6% faster on the undulator ensemble.  The
-// double kernels are held to four workgroups per CU by their LDS; the
-// previous-state hold fits the matching 128 VGPRs without spilling (6% faster),
-// the linear hold would spill and gains nothing.
+// double kernels are held to four workgroups per CU by their LDS; with both
+// forms of the slot coordinate compiled in (see deposit_item_of) the default
+// and previous-state kernels go a few registers over 128 by themselves and fit
+// them on request (the previous-state hold with two spilled words), the linear
+// hold would spill heavily and is left alone.
 template <int M, int R, int G, int HOLD>
 constexpr int kMinWaves =
     R != kRingSmall                      ? 1
     : M != kModeF64 && (G != 0 || HOLD != 0) ? 5
-    : M == kModeF64 && HOLD == 1         ? 4
+    : M == kModeF64 && HOLD != 2         ? 4
                                          : 1;
 
 template <int M, int R, int G, int HOLD>
@@ -1517,7 +1569,7 @@ __attribute__((amdgpu_waves_per_eu(kMinWaves<M, R, G, HOLD>))) void deposit_kern
     if (gptr(J.ring_sel)[tile] != (R == kRingLarge ? 1 : 0))
         return;
     const int64_t rest = logical / J.n_tiles;  // split-major, then part
-    deposit_item<M, R, G, HOLD>(J, tile, rest / J.n_parts, rest % J.n_parts, sh);
+    deposit_item_of<M, R, G, HOLD>(J, tile, rest / J.n_parts, rest % J.n_parts, sh);
 }
 
 // Persistent workgroups for many independent deposits: each takes the next work
@@ -1549,7 +1601,7 @@ deposit_persistent_kernel(
         const DepositJob J = jobs[w.job];
         if (gptr(J.ring_sel)[w.tile] != (R == kRingLarge ? 1 : 0))
             continue;
-        deposit_item<M, R, G, HOLD>(J, w.tile, w.split, w.part, sh);
+        deposit_item_of<M, R, G, HOLD>(J, w.tile, w.split, w.part, sh);
     }
 }
 
@@ -1616,6 +1668,22 @@ __global__ void arrival_kernel(const double* cells, const double* pts, const dou
         double d1 = cells[3 * i + 1] - pts[3 * i + 1];
         double d2 = cells[3 * i + 2] - pts[3 * i + 2];
         out[i] = canon_arrival(t[i], canon_sqrt(canon_norm2(d0, d1, d2)), inv_c);
+    }
+}
+
+// slot coordinates (t + |x_cell - x|/c - t0) / dt_det of explicit triples, as the
+// double deposit rounds them
+__global__ void slot_coord_kernel(const double* cells, const double* pts, const double* t,
+                                  int64_t n, double inv_c, double t0, double dt_det,
+                                  double inv_dt_det, int slot_div, double* out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) {
+        double d0 = cells[3 * i] - pts[3 * i];
+        double d1 = cells[3 * i + 1] - pts[3 * i + 1];
+        double d2 = cells[3 * i + 2] - pts[3 * i + 2];
+        const double tau = canon_arrival(t[i], canon_sqrt(canon_norm2(d0, d1, d2)), inv_c);
+        out[i] = canon_slot(tau, t0, dt_det, inv_dt_det, slot_div != 0);
     }
 }
 
@@ -1883,6 +1951,17 @@ hipError_t launch_arrival(const double* cells, const double* pts, const double* 
         return hipSuccess;
     hipLaunchKernelGGL(arrival_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cells,
                        pts, t, n, inv_c, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_coords(const double* cells, const double* pts, const double* t, int64_t n,
+                              double inv_c, double t0, double dt_det, double inv_dt_det,
+                              bool slot_div, double* out, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(slot_coord_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cells,
+                       pts, t, n, inv_c, t0, dt_det, inv_dt_det, slot_div ? 1 : 0, out);
     return hipGetLastError();
 }
 

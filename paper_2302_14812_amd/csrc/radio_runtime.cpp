@@ -320,7 +320,9 @@ radio::DepositJob make_job(const radio_detector* det, const radio_chunk* k)
     J.potentials = (det->options & RADIO_POTENTIALS) ? 1 : 0;
     J.dt = k->dt;
     J.t0 = det->t0;
-    J.inv_dt_det = 1.0 / det->dt_det;
+    J.inv_dt_det = 1.0 / det->dt_det;  // correctly rounded (host IEEE division)
+    J.dt_det = det->dt_det;
+    J.slot_div = radio::slot_quotient_corrects(det->dt_det) ? 0 : 1;
     J.inv_c = 1.0 / det->c;
     J.c = det->c;
     const int per_cu =
@@ -647,6 +649,21 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
 
 }  // namespace
 
+namespace radio {
+
+bool slot_quotient_corrects(double b)
+{
+    if (!(b >= 0x1p-900 && b <= 0x1p900))
+        return false;
+    const double y = 1.0 / b;                // RN(1/b)
+    const double e = std::fma(b, y, -1.0);   // b y - 1, exact
+    int ex = 0;
+    const double B = std::ldexp(std::frexp(b, &ex), 53);  // integer in [2^52, 2^53)
+    return std::fabs(e) * B < 1.0 - 0x1p-45;
+}
+
+}  // namespace radio
+
 extern "C" {
 
 const char* radio_status_string(int status)
@@ -946,6 +963,23 @@ int radio_arrival_times(const double* cells, const double* points, const double*
         return RADIO_EINVAL;
     if (radio::launch_arrival(cells, points, t, n, 1.0 / c, out, (hipStream_t)stream) !=
         hipSuccess)
+        return RADIO_EDEVICE;
+    return RADIO_OK;
+}
+
+int radio_slot_coordinates(const double* cells, const double* points, const double* t, int64_t n,
+                           double c, double t0, double dt_det, double* out, void* stream)
+{
+    if (n < 0 || !std::isfinite(c) || !(c > 0.0) || !std::isfinite(t0) ||
+        !std::isfinite(dt_det) || !(dt_det > 0.0) || !std::isfinite(1.0 / dt_det))
+        return RADIO_EINVAL;
+    if (n == 0)
+        return RADIO_OK;
+    if (!cells || !points || !t || !out)
+        return RADIO_EINVAL;
+    if (radio::launch_slot_coords(cells, points, t, n, 1.0 / c, t0, dt_det, 1.0 / dt_det,
+                                  !radio::slot_quotient_corrects(dt_det), out,
+                                  (hipStream_t)stream) != hipSuccess)
         return RADIO_EDEVICE;
     return RADIO_OK;
 }

@@ -112,6 +112,9 @@ def test_invalid_arguments_rejected_before_any_device_work():
     assert lib.radio_deposit_batch(None, None, 0, None) == radio.OK
     assert lib.radio_arrival_times(None, None, None, 5, 1.0, None, None) == radio.EINVAL
     assert lib.radio_arrival_times(None, None, None, 0, 0.0, None, None) == radio.EINVAL
+    assert lib.radio_slot_coordinates(None, None, None, 5, 1.0, 0.0, 0.1, None, None) == radio.EINVAL
+    assert lib.radio_slot_coordinates(None, None, None, 0, 1.0, 0.0, 0.0, None, None) == radio.EINVAL
+    assert lib.radio_slot_coordinates(None, None, None, 0, 1.0, 0.0, 0.1, None, None) == radio.OK
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

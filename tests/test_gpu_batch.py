@@ -11,6 +11,8 @@ from paper_2302_14812_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
+from parity import check_parity  # noqa: E402
+
 
 @pytest.fixture(scope="module")
 def radio():
@@ -64,9 +66,7 @@ def test_batch_equals_separate_and_oracle(radio, sets, precision):
                                 replace=False).tolist())
         D = oracle.deposit_workload(wl.detector, wl.chunk, cell_index=idx)
         Eo, Bo = oracle.read(D)
-        eo = max(rel_l2(Eb[idx], Eo), rel_l2(Bb[idx], Bo))
-        print(f"[batch] {wl.name} {precision}: batch vs oracle relL2 {eo:.3e}", flush=True)
-        assert eo <= tol_or, (wl.name, eo)
+        check_parity(Eb[idx], Bb[idx], Eo, Bo, tol_or, f"batch {wl.name} {precision} vs oracle")
         ds.close()
         db.close()
 
@@ -158,10 +158,8 @@ def test_batch_time_slices_long_chunks(radio, sets, precision):
     idx = [0, 31, 500, 992, 1023]
     D = oracle.deposit_workload(spec, long, cell_index=idx)
     Eo, Bo = oracle.read(D)
-    eo = max(rel_l2(E[idx], 2.0 * Eo), rel_l2(B[idx], 2.0 * Bo))
-    print(f"[batch] long chunk twice in time slices vs oracle {precision} relL2 {eo:.3e}",
-          flush=True)
-    assert eo <= tol_or
+    check_parity(E[idx], B[idx], 2.0 * Eo, 2.0 * Bo, tol_or,
+                 f"batch long chunk twice in time slices vs oracle {precision}")
     for wl, d, r, n_single in zip(short, d_short, refs, single):
         E, B = _read(d)
         Er, Br = _read(r)

@@ -16,9 +16,8 @@ from paper_2302_14812_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TOL_FP64 = 1e-12
-TOL_MIXED = 1e-5
-TOLS = {"fp64": TOL_FP64, "mixed": TOL_MIXED, "mixed_twosum": TOL_MIXED}
+from parity import TOL_FP64, TOL_MIXED, TOLS, check_parity, rel_l2  # noqa: E402
+
 PRECISIONS = pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_twosum"])
 
 
@@ -30,11 +29,6 @@ def radio():
     import paper_2302_14812_amd as radio
     radio._lib()  # a missing library raises here: no fallback
     return radio
-
-
-def rel_l2(a, b):
-    nb = float(np.linalg.norm(b))
-    return float(np.linalg.norm(a - b)) / (nb if nb > 0 else 1.0)
 
 
 def gpu_deposit(radio, spec, chunks, precision="fp64"):
@@ -56,12 +50,6 @@ def oracle_deposit(spec, chunk, cell_index=None):
     D = oracle.deposit_workload(spec, chunk, cell_index=cell_index, counters=cnt)
     E, B = oracle.read(D)
     return E, B, cnt
-
-
-def check_parity(Eg, Bg, Eo, Bo, tol, what):
-    eE, eB = rel_l2(Eg, Eo), rel_l2(Bg, Bo)
-    print(f"[parity] {what}: relL2 E={eE:.3e} B={eB:.3e}", flush=True)
-    assert max(eE, eB) <= tol, (what, eE, eB)
 
 
 def _window(cells, chunk, n_t, pad=0.05):
@@ -112,6 +100,61 @@ def test_arrival_times_bit_exact_hard_cases(radio, oracle_mod):
     ref = np.array([oracle_mod.arrival(cells[i], pts[i], t[i], 1.0) for i in range(3 * n)])
     bad = np.flatnonzero(out != ref)
     assert bad.size == 0, (bad[:5], out[bad[:5]] - ref[bad[:5]])
+
+
+@pytest.mark.parametrize("dt_det", [1.2e-4, 0.0438, 0.04, 2.0 ** -10,
+                                    # a significand of all ones (the host check sends
+                                    # it to a division) and one unit below it (not)
+                                    float(np.nextafter(2.0, 0.0)) * 2.0 ** -12,
+                                    float(np.nextafter(np.nextafter(2.0, 0.0), 0.0)) * 2.0 ** -4])
+def test_slot_coordinates_bit_exact(radio, oracle_mod, dt_det):
+    """The slot coordinate (t_det - t0) / dt_det of the double deposit equals the
+    oracle's correctly rounded division bit for bit: arrival times at the
+    workloads' distances, and numerators that put the quotient within an ulp of
+    a rounding midpoint (cell and point coincide, so t_det = t exactly)."""
+    import torch
+    from fractions import Fraction
+    rng = np.random.Generator(np.random.PCG64(17))
+    n = 4000
+    cells = rng.normal(size=(n, 3)) * (10.0 ** rng.uniform(2, 5, size=(n, 1)))
+    pts = rng.normal(size=(n, 3)) * rng.uniform(0, 30, size=(n, 1))
+    t = rng.uniform(-50, 500, size=n)
+    t0 = float(np.linalg.norm(cells, axis=1).min()) - 100.0
+    out = radio.slot_coordinates(torch.from_numpy(cells).cuda(), torch.from_numpy(pts).cuda(),
+                                 torch.from_numpy(t).cuda(), t0, dt_det).cpu().numpy()
+    ref = np.array([oracle_mod.slot_of(oracle_mod.arrival(cells[i], pts[i], t[i]), t0, dt_det)
+                    for i in range(n)])
+    bad = np.flatnonzero(out != ref)
+    assert bad.size == 0, (dt_det, bad[:5], out[bad[:5]] - ref[bad[:5]])
+    # quotients next to rounding midpoints: x = RN(dt_det (q + ulp(q)/2)), +- an ulp
+    m = 3000
+    q = np.ldexp(1.0 + rng.uniform(size=m), rng.integers(-3, 20, size=m))
+    half = 0.5 * (np.nextafter(q, np.inf) - q)
+    x = np.array([float(Fraction(dt_det) * (Fraction(float(a)) + Fraction(float(h))))
+                  for a, h in zip(q, half)])
+    k = rng.integers(-1, 2, size=m)
+    x = np.where(k > 0, np.nextafter(x, np.inf), np.where(k < 0, np.nextafter(x, -np.inf), x))
+    p = rng.normal(size=(m, 3)) * 10.0
+    out = radio.slot_coordinates(torch.from_numpy(p).cuda(), torch.from_numpy(p).cuda(),
+                                 torch.from_numpy(x).cuda(), 0.0, dt_det).cpu().numpy()
+    ref = np.array([oracle_mod.slot_of(v, 0.0, dt_det) for v in x])
+    bad = np.flatnonzero(out != ref)
+    assert bad.size == 0, (dt_det, bad[:5], out[bad[:5]] - ref[bad[:5]])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_parity_divisor_sent_to_division(radio, precision):
+    """A slot width whose significand is all ones fails the host check of the
+    two-correction quotient, so the double kernels divide: parity as usual."""
+    chunk = W.random_chunk(29, 70, seed=13, dt=0.07, gamma_max=20.0, t_first=0.2)
+    cells = W.plane_cells([1.0, -2.0, 30.0], [1, 0.2, 0], [0, 1, 0.1], 9, 7, 12.0, 9.0)
+    t0, dtd0 = _window(cells, chunk, 180)
+    dtd = float(np.ldexp(np.nextafter(2.0, 0.0), int(np.floor(np.log2(dtd0))) - 1))
+    n_t = int(np.ceil(180 * dtd0 / dtd))
+    spec = W.DetectorSpec(cells=cells, t0=t0, dt_det=dtd, n_t=n_t)
+    Eg, Bg, _ = gpu_deposit(radio, spec, chunk, precision)
+    Eo, Bo, _ = oracle_deposit(spec, chunk)
+    check_parity(Eg, Bg, Eo, Bo, TOLS[precision], f"divided slot coordinate {precision}")
 
 
 @PRECISIONS
@@ -440,16 +483,17 @@ def test_full_size_undulator_sampled_cells(radio, precision):
     check_parity(Eg, Bg, Eo, Bo, TOLS[precision], f"{wl.name} sampled {precision}")
 
 
-def test_plasma_mirror_full_detector_sampled_cells(radio):
+@PRECISIONS
+def test_plasma_mirror_full_detector_sampled_cells(radio, precision):
     """The plasma-mirror configuration at its full detector (256 x 256 cells, 4096
     slots) and length (1000 steps over 10 laser periods), with 2 x 10^4 of its
-    2 x 10^5 electrons, mixed precision, compared on sampled cells.  Its particle
-    orders at two runs each exceed the default budget, so the chunk runs as time
-    slices (here eleven)."""
+    2 x 10^5 electrons, in every precision, compared on sampled cells.  Its
+    particle orders at two runs each exceed the default budget, so the chunk runs
+    as time slices (here eleven)."""
     import time
     import torch
-    wl = W.plasma_mirror_workload(n_particles=20_000, n_steps=1000)
-    det = radio.Detector.from_spec(wl.detector, precision="mixed")
+    wl = _plasma_full()
+    det = radio.Detector.from_spec(wl.detector, precision=precision)
     ch = radio.Chunk.from_numpy(wl.chunk)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -462,17 +506,31 @@ def test_plasma_mirror_full_detector_sampled_cells(radio):
           f"(first call), bypassed/int {st['bypassed'] / st['interactions']:.2e}", flush=True)
     assert st["slices"] > 1
     n1, n2 = wl.detector.grid
-    rng = np.random.Generator(np.random.PCG64(98))
-    idx = sorted(set(W.grid_corner_cells(n1, n2)) | set(rng.choice(n1 * n2, 3, replace=False).tolist()))
-    Eg = E[idx].cpu().numpy()
-    Bg = B[idx].cpu().numpy()
+    Eg = E[list(_PM_CELLS)].cpu().numpy()
+    Bg = B[list(_PM_CELLS)].cpu().numpy()
     del E, B, ch
     det.close()
-    Eo, Bo, _ = oracle_deposit(wl.detector, wl.chunk, cell_index=idx)
-    check_parity(Eg, Bg, Eo, Bo, TOL_MIXED, f"{wl.name} sampled mixed")
+    Eo, Bo, _ = _plasma_oracle()
+    check_parity(Eg, Bg, Eo, Bo, TOLS[precision], f"{wl.name} sampled {precision}")
 
 
 _CACHE = {}
+# sampled cells of the 256 x 256 plasma-mirror detector: corners, centre, and a seeded set
+_PM_CELLS = tuple(sorted(set(W.grid_corner_cells(256, 256)) | set(
+    np.random.Generator(np.random.PCG64(98)).choice(256 * 256, 11, replace=False).tolist())))
+
+
+def _plasma_full():
+    if "pm" not in _CACHE:
+        _CACHE["pm"] = W.plasma_mirror_workload(n_particles=20_000, n_steps=1000)
+    return _CACHE["pm"]
+
+
+def _plasma_oracle():
+    if "pm_oracle" not in _CACHE:
+        wl = _plasma_full()
+        _CACHE["pm_oracle"] = oracle_deposit(wl.detector, wl.chunk, cell_index=list(_PM_CELLS))
+    return _CACHE["pm_oracle"]
 
 
 def _undulator_full():

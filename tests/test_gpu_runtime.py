@@ -11,6 +11,8 @@ from paper_2302_14812_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
+from parity import check_parity  # noqa: E402
+
 WAVE = {"wave_amplitude": 1.5, "wave_dir": [1.0, 0.0, 0.0], "wave_pol": [0.0, 1.0, 0.0],
         "wave_omega": 1.0, "wave_phase": 0.3}
 
@@ -98,8 +100,8 @@ def test_runtime_blocks_equal_one_shot_and_oracle(radio):
     for d, tol in zip(dets, (1e-12, 1e-5)):
         Ed, Bd = d.read()
         torch.cuda.synchronize()
-        e = max(rel_l2(Ed.cpu().numpy(), Eo), rel_l2(Bd.cpu().numpy(), Bo))
-        print(f"[runtime] {d.precision} vs oracle relL2 {e:.2e}", flush=True)
-        assert np.abs(Eo).max() > 0 and e <= tol
+        assert np.abs(Eo).max() > 0
+        check_parity(Ed.cpu().numpy(), Bd.cpu().numpy(), Eo, Bo, tol,
+                     f"runtime {d.precision} vs oracle")
     for d in dets + [one]:
         d.close()
