@@ -355,27 +355,40 @@ radio::DepositJob slice_job(const radio_detector* det, const radio::DepositJob& 
     return J;
 }
 
-// Grow a device workspace to hold at least `need` elements (the device is
-// synchronised before an old buffer is released).
+// Grow a device workspace to hold at least `need` elements, in stream order on
+// s: the old buffer is released with hipFreeAsync once s has passed the work
+// already enqueued on it (the previous user of a detector's workspace is
+// ordered before s by the caller; a batch arena's previous batch has been
+// waited for), and the new one comes from the device's stream-ordered pool.
+// Nothing waits on the host and no other stream is stalled.
 template <typename T>
-int grow(T** p, size_t* cap, size_t need)
+int grow(T** p, size_t* cap, size_t need, hipStream_t s)
 {
     if (need <= *cap)
         return RADIO_OK;
     if (*p) {
-        if (hipDeviceSynchronize() != hipSuccess)
+        if (hipFreeAsync(*p, s) != hipSuccess)
             return RADIO_EDEVICE;
-        (void)hipFree(*p);
         *p = nullptr;
         *cap = 0;
     }
-    if (hipMalloc((void**)p, need * sizeof(T)) != hipSuccess) {
+    if (hipMallocAsync((void**)p, need * sizeof(T), s) != hipSuccess) {
         (void)hipGetLastError();
         *p = nullptr;
         return RADIO_ENOMEM;
     }
     *cap = need;
     return RADIO_OK;
+}
+
+// Release a workspace of grow() (the device is idle: destroy synchronises first).
+template <typename T>
+void release(T** p, size_t* cap)
+{
+    if (*p)
+        (void)hipFreeAsync(*p, nullptr);
+    *p = nullptr;
+    *cap = 0;
 }
 
 // The time slices of one deposit: a chunk whose particle orders of at most
@@ -411,15 +424,15 @@ radio::DepositJob plan_slice(const radio_detector* det, const SlicePlan& P, int6
     return slice_job(det, P.W, r_a, std::min(r_a + P.runs_each, P.W.n_runs), P.max_groups);
 }
 
-// Grow the detector's workspaces to hold slice job J.
-int reserve(radio_detector* det, const radio::DepositJob& J)
+// Grow the detector's workspaces to hold slice job J (stream-ordered on s).
+int reserve(radio_detector* det, const radio::DepositJob& J, hipStream_t s)
 {
     int rc = grow(&det->d_recs, &det->recs_cap,
-                  (size_t)(J.n_p * (J.n_s + 1)) * radio::rec_bytes(det->precision));
+                  (size_t)(J.n_p * (J.n_s + 1)) * radio::rec_bytes(det->precision), s);
     if (rc == RADIO_OK)
-        rc = grow(&det->d_perm, &det->perm_cap, (size_t)(J.n_groups * J.n_tiles * J.n_p));
+        rc = grow(&det->d_perm, &det->perm_cap, (size_t)(J.n_groups * J.n_tiles * J.n_p), s);
     if (rc == RADIO_OK)
-        rc = grow(&det->d_sel, &det->sel_cap, (size_t)J.n_tiles);
+        rc = grow(&det->d_sel, &det->sel_cap, (size_t)J.n_tiles, s);
     return rc;
 }
 
@@ -435,7 +448,7 @@ int enqueue_deposit(radio_detector* det, const radio_chunk* k, hipStream_t s)
     const SlicePlan P = plan_slices(det, k);
     for (int64_t r_a = 0; r_a < P.W.n_runs; r_a += P.runs_each) {
         radio::DepositJob J = plan_slice(det, P, r_a);
-        const int rc = reserve(det, J);
+        const int rc = reserve(det, J, s);
         if (rc != RADIO_OK)
             return rc;
         J.recs = det->d_recs;
@@ -524,7 +537,7 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
             continue;
         const SlicePlan P = plan_slices(dets[i], k);
         if (P.n_slices > 1) {
-            const int rc = reserve(dets[i], plan_slice(dets[i], P, 0));
+            const int rc = reserve(dets[i], plan_slice(dets[i], P, 0), s);
             if (rc != RADIO_OK)
                 return rc;
             sliced.push_back(i);
@@ -547,13 +560,13 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
             dets[i]->chunks += 1;
         return RADIO_OK;
     }
-    int rc = grow(&A->d_recs, &A->recs_cap, recs_need);
+    int rc = grow(&A->d_recs, &A->recs_cap, recs_need, s);
     if (rc == RADIO_OK)
-        rc = grow(&A->d_perm, &A->perm_cap, perm_need);
+        rc = grow(&A->d_perm, &A->perm_cap, perm_need, s);
     if (rc == RADIO_OK)
-        rc = grow(&A->d_sel, &A->sel_cap, sel_need);
+        rc = grow(&A->d_sel, &A->sel_cap, sel_need, s);
     if (rc == RADIO_OK)
-        rc = grow(&A->d_jobs, &A->jobs_cap, A->h_jobs.size());
+        rc = grow(&A->d_jobs, &A->jobs_cap, A->h_jobs.size(), s);
     if (rc != RADIO_OK)
         return rc;
     // work items: a per-pair split chosen so that items carry similar work, longest first
@@ -609,7 +622,7 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
     A->h_items.resize(items.size());
     for (size_t i = 0; i < items.size(); ++i)
         A->h_items[i] = items[i].w;
-    rc = grow(&A->d_items, &A->items_cap, A->h_items.size());
+    rc = grow(&A->d_items, &A->items_cap, A->h_items.size(), s);
     if (rc != RADIO_OK)
         return rc;
     if (hipMemcpyAsync(A->d_jobs, A->h_jobs.data(), A->h_jobs.size() * sizeof(radio::DepositJob),
@@ -797,16 +810,14 @@ int radio_detector_destroy(radio_detector* det)
             (void)hipFree(det->d_user_index);
         if (det->d_counters)
             (void)hipFree(det->d_counters);
-        if (det->d_recs)
-            (void)hipFree(det->d_recs);
-        if (det->d_perm)
-            (void)hipFree(det->d_perm);
-        if (det->d_sel)
-            (void)hipFree(det->d_sel);
-        if (det->d_spec)
-            (void)hipFree(det->d_spec);
+        release(&det->d_recs, &det->recs_cap);
+        release(&det->d_perm, &det->perm_cap);
+        release(&det->d_sel, &det->sel_cap);
+        release(&det->d_spec, &det->spec_cap);
         if (det->d_far)
             (void)hipFree(det->d_far);
+        if (hipStreamSynchronize(nullptr) != hipSuccess)
+            rc = RADIO_EDEVICE;
     }
     delete det;
     return rc;
@@ -1045,7 +1056,7 @@ int radio_spectrum(radio_detector* det, int64_t n_fft, const double* weights, do
     int rc = RADIO_OK;
     if (d2I || dIdw) {
         // the two work arrays, kept by the detector for later spectra
-        rc = grow(&det->d_spec, &det->spec_cap, (size_t)(4 * G * N + radio::kSpecTableValues));
+        rc = grow(&det->d_spec, &det->spec_cap, (size_t)(4 * G * N + radio::kSpecTableValues), s);
         w0 = det->d_spec;
         w1 = det->d_spec + 2 * G * N;
     }

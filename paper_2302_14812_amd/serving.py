@@ -181,10 +181,13 @@ class DepositServer:
     """Threads around the library: a scheduler loop and a completion watcher.
 
     specs: detector id -> workloads.DetectorSpec.  memory_budget: bytes of
-    device memory the resident detectors may hold (default: 90% of the free
-    memory at start).  max_batch_work: interactions per batch.  max_inflight:
-    batches enqueued on the device at once; while that many run, arriving
-    chunks wait and join the next batch (continuous batching).
+    device memory the service may hold (default: 90% of the free memory at
+    start): the two batch workspaces of the library (reserved up front for
+    batches of max_batch_work interactions, arena_bytes) and the resident
+    detectors, each with its accumulator and the workspaces its own deposits
+    may grow (resident_bytes).  max_batch_work: interactions per batch.
+    max_inflight: batches enqueued on the device at once; while that many run,
+    arriving chunks wait and join the next batch (continuous batching).
     """
 
     def __init__(self, specs: Dict[int, object], precision: str = "mixed",
@@ -203,11 +206,17 @@ class DepositServer:
         if memory_budget is None:
             free, _ = torch.cuda.mem_get_info()
             memory_budget = int(0.9 * free)
-        self.sched = Scheduler({d: detector_bytes(s) for d, s in self.specs.items()},
-                               {d: s.n_cells for d, s in self.specs.items()},
-                               memory_budget, max_batch_work)
         self.max_inflight = int(max_inflight)
         self.piece_work = float(max_batch_work / 2 if piece_work is None else piece_work)
+        self.memory_budget = int(memory_budget)
+        self.arena_reserve = 2 * arena_bytes(self.specs.values(), max_batch_work)
+        if self.arena_reserve >= self.memory_budget:
+            raise ValueError(f"the batch workspaces ({self.arena_reserve} bytes) leave no room for "
+                             f"detectors in a budget of {self.memory_budget} bytes")
+        self.sched = Scheduler({d: resident_bytes(s, self.piece_work)
+                                for d, s in self.specs.items()},
+                               {d: s.n_cells for d, s in self.specs.items()},
+                               self.memory_budget - self.arena_reserve, max_batch_work)
         self.detectors: Dict[int, object] = {}
         self.stream = torch.cuda.Stream()  # default priority
         self.requests: List[Request] = []
@@ -392,9 +401,47 @@ class DepositServer:
 
 
 def detector_bytes(spec) -> int:
-    """Device bytes a resident detector holds: six accumulator words per
+    """Device bytes of a detector's state: six accumulator words per
     (cell, slot) and the cell positions with their index map."""
     return int(spec.n_cells) * int(spec.n_t) * 48 + int(spec.n_cells) * 32
+
+
+# the library's deposit shape: cells per tile, segments per run, runs per
+# particle order, and the largest state record (double precision)
+_TILE_CELLS, _RUN_L, _RUNS_PER_ORDER, _REC_BYTES = 16, 16, 2, 80
+
+
+def workspace_bytes(spec, piece_work: float) -> int:
+    """Upper bound of the workspaces a detector's own deposits grow (state records,
+    one particle order, ring choices).  In a batch a part runs in the batch's
+    workspaces unless its particle orders exceed the library's order budget;
+    it then runs in time slices of at most two runs on the detector's own
+    workspaces, which needs more than two runs (33 states) and so at most
+    piece_work / (33 n_cells) particles."""
+    n_c = int(spec.n_cells)
+    tiles = -(-n_c // _TILE_CELLS)
+    n_p = int(math.ceil(piece_work / (33.0 * n_c)))
+    states = _RUNS_PER_ORDER * _RUN_L + 1
+    return tiles * n_p * 4 + n_p * states * _REC_BYTES + tiles
+
+
+def resident_bytes(spec, piece_work: float) -> int:
+    """Device bytes admission counts for a resident detector: its state and the
+    workspaces its deposits may grow."""
+    return detector_bytes(spec) + workspace_bytes(spec, piece_work)
+
+
+def arena_bytes(specs, max_batch_work: float) -> int:
+    """Upper bound of one batch workspace of the library for batches of up to
+    max_batch_work interactions on these detectors: per interaction at most
+    4 ceil(n_c/16) / n_c bytes of particle order (one step, one order) and
+    2 * 80 / n_c bytes of state records, plus ring choices and descriptors."""
+    specs = list(specs)
+    if not specs:
+        return 0
+    per_int = max((4.0 * -(-int(sp.n_cells) // _TILE_CELLS) + 2.0 * _REC_BYTES) / int(sp.n_cells)
+                  for sp in specs)
+    return int(math.ceil(1.1 * per_int * float(max_batch_work))) + (64 << 20)
 
 
 def summarize(requests: Sequence[Request], skip: int = 0, sched: Optional[Scheduler] = None

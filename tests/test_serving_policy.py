@@ -107,6 +107,23 @@ def test_detector_bytes_counts_accumulator_and_cells():
     assert detector_bytes(spec) == 12 * 100 * 48 + 12 * 32
 
 
+def test_admission_counts_workspaces():
+    """Admission counts each detector's own deposit workspaces beside its state,
+    and the service reserves the two batch workspaces: for the plasma-mirror
+    detector (65536 cells) and batches of 4e10 interactions, about 1e10 bytes
+    of particle orders per batch workspace."""
+    from paper_2302_14812_amd.serving import arena_bytes, resident_bytes, workspace_bytes
+    spec = W.DetectorSpec(cells=np.zeros((65536, 3)), t0=0.0, dt_det=1.0, n_t=4096)
+    ws = workspace_bytes(spec, 2e10)
+    n_p = -(-int(2e10) // (33 * 65536))
+    assert ws >= 4096 * n_p * 4 + n_p * 33 * 64
+    assert resident_bytes(spec, 2e10) == detector_bytes(spec) + ws
+    a = arena_bytes([spec], 4e10)
+    assert 1.0e10 <= a <= 1.2e10
+    # a one-step chunk of 10^5 particles: one order of 4096 tiles x 10^5 particles
+    assert a >= 4096 * 100_000 * 4 * (4e10 / (100_000 * 65536))
+
+
 def _stream(n, rate, seed, n_det=4, cells=256):
     offs = poisson_arrivals(rate, n, seed)
     sched_rows = list(W.stream_schedule(n, n_det, seed, max_log_particles=4.0))
