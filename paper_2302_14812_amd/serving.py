@@ -81,18 +81,21 @@ class Scheduler:
     detectors that do not fit wait (and do not block requests for resident
     detectors behind them).  A batch visits the pending requests of resident
     detectors in arrival order and takes the next part of each, round after
-    round, until max_batch_work interactions (a batch takes at least one
-    part): a request cut into many parts advances by a part per round and
-    never holds back the requests that arrived after it for longer than a
-    batch.
+    round, until max_batch_work interactions or max_batch_segments particle
+    segments (a batch takes at least one part; the segments bound the state
+    records and particle orders of the batch's workspace on small detectors):
+    a request cut into many parts advances by a part per round and never
+    holds back the requests that arrived after it for longer than a batch.
     """
 
     def __init__(self, detector_bytes: Dict[int, int], cells: Dict[int, int], budget: int,
-                 max_batch_work: float):
+                 max_batch_work: float, max_batch_segments: Optional[float] = None):
         self.detector_bytes = dict(detector_bytes)
         self.cells = dict(cells)
         self.budget = int(budget)
         self.max_batch_work = float(max_batch_work)
+        self.max_batch_segments = float("inf") if max_batch_segments is None else float(
+            max_batch_segments)
         self.resident: Dict[int, int] = {}
         self.finished: set = set()
         self.pending: Deque[Request] = collections.deque()
@@ -145,6 +148,7 @@ class Scheduler:
         """The next batch as (request, part index) pairs."""
         batch: List[Tuple[Request, int]] = []
         work = 0.0
+        segs = 0.0
         progress = True
         while progress:
             progress = False
@@ -153,10 +157,13 @@ class Scheduler:
                     continue
                 k = req.next_piece
                 w = req.pieces[k][1]
-                if batch and work + w > self.max_batch_work:
+                g = w / max(1, self.cells[req.det_id])  # particle segments of the part
+                if batch and (work + w > self.max_batch_work or
+                              segs + g > self.max_batch_segments):
                     continue
                 batch.append((req, k))
                 work += w
+                segs += g
                 req.next_piece += 1
                 req.open_pieces += 1
                 req.batch = self.n_batches
@@ -183,9 +190,13 @@ class DepositServer:
     specs: detector id -> workloads.DetectorSpec.  memory_budget: bytes of
     device memory the service may hold (default: 90% of the free memory at
     start): the two batch workspaces of the library (reserved up front for
-    batches of max_batch_work interactions, arena_bytes) and the resident
-    detectors, each with its accumulator and the workspaces its own deposits
-    may grow (resident_bytes).  max_batch_work: interactions per batch.
+    batches of max_batch_work interactions and max_batch_segments particle
+    segments, arena_bytes) and the resident detectors, each with its
+    accumulator and the workspaces its own deposits may grow (resident_bytes).
+    max_batch_work: interactions per batch; max_batch_segments: particle
+    segments per batch (default max_batch_work / 4096: binding only for
+    detectors of fewer than 4096 cells).  Chunks are cut into parts of at most
+    piece_work interactions (default half a batch) and half a batch's segments.
     max_inflight: batches enqueued on the device at once; while that many run,
     arriving chunks wait and join the next batch (continuous batching).
     """
@@ -193,6 +204,7 @@ class DepositServer:
     def __init__(self, specs: Dict[int, object], precision: str = "mixed",
                  memory_budget: Optional[int] = None, max_batch_work: float = 4e10,
                  piece_work: Optional[float] = None, max_inflight: int = 2,
+                 max_batch_segments: Optional[float] = None,
                  clock: Callable[[], float] = time.perf_counter):
         import torch
 
@@ -208,15 +220,19 @@ class DepositServer:
             memory_budget = int(0.9 * free)
         self.max_inflight = int(max_inflight)
         self.piece_work = float(max_batch_work / 2 if piece_work is None else piece_work)
+        self.max_batch_segments = float(max_batch_work / 4096 if max_batch_segments is None
+                                        else max_batch_segments)
+        self.piece_segments = self.max_batch_segments / 2
         self.memory_budget = int(memory_budget)
-        self.arena_reserve = 2 * arena_bytes(self.specs.values(), max_batch_work)
+        self.arena_reserve = 2 * arena_bytes(max_batch_work, self.max_batch_segments)
         if self.arena_reserve >= self.memory_budget:
             raise ValueError(f"the batch workspaces ({self.arena_reserve} bytes) leave no room for "
                              f"detectors in a budget of {self.memory_budget} bytes")
         self.sched = Scheduler({d: resident_bytes(s, self.piece_work)
                                 for d, s in self.specs.items()},
                                {d: s.n_cells for d, s in self.specs.items()},
-                               self.memory_budget - self.arena_reserve, max_batch_work)
+                               self.memory_budget - self.arena_reserve, max_batch_work,
+                               self.max_batch_segments)
         self.detectors: Dict[int, object] = {}
         self.stream = torch.cuda.Stream()  # default priority
         self.requests: List[Request] = []
@@ -241,8 +257,9 @@ class DepositServer:
         arrival = self.clock()
         if det_id not in self.specs:
             raise KeyError(f"unknown detector {det_id}")
-        plan = plan_pieces(chunk.n_particles, chunk.n_steps, self.specs[det_id].n_cells,
-                           self.piece_work)
+        n_c = self.specs[det_id].n_cells
+        plan = plan_pieces(chunk.n_particles, chunk.n_steps, n_c,
+                           min(self.piece_work, self.piece_segments * n_c))
         if len(plan) == 1:
             pieces = [chunk]
         else:  # device copies, ordered on the caller's stream before the event below
@@ -431,17 +448,20 @@ def resident_bytes(spec, piece_work: float) -> int:
     return detector_bytes(spec) + workspace_bytes(spec, piece_work)
 
 
-def arena_bytes(specs, max_batch_work: float) -> int:
-    """Upper bound of one batch workspace of the library for batches of up to
-    max_batch_work interactions on these detectors: per interaction at most
-    4 ceil(n_c/16) / n_c bytes of particle order (one step, one order) and
-    2 * 80 / n_c bytes of state records, plus ring choices and descriptors."""
-    specs = list(specs)
-    if not specs:
-        return 0
-    per_int = max((4.0 * -(-int(sp.n_cells) // _TILE_CELLS) + 2.0 * _REC_BYTES) / int(sp.n_cells)
-                  for sp in specs)
-    return int(math.ceil(1.1 * per_int * float(max_batch_work))) + (64 << 20)
+def arena_bytes(max_batch_work: float, max_batch_segments: float) -> int:
+    """Upper bound of one batch workspace of the library for batches of up to W =
+    max_batch_work interactions and S = max_batch_segments particle segments.
+    A pair of n_p particles, n_s segments and n_c cells holds at most n_s
+    particle orders (one per two runs of 16 segments) of ceil(n_c/16) n_p
+    entries of 4 bytes, <= W/4 + 4 S over the batch; state records of at most
+    80 bytes for n_p (n_s + 1) <= 2 n_p n_s states, <= 160 S; ring choices of
+    ceil(n_c/16) bytes, <= W/16 + one per pair; and its job and work items.
+    A quarter on top covers the last two, plus 64 MiB."""
+    W, S = float(max_batch_work), float(max_batch_segments)
+    orders = 4.0 * W / _TILE_CELLS + 4.0 * S
+    records = 2.0 * _REC_BYTES * S
+    choices = W / _TILE_CELLS
+    return int(math.ceil(1.25 * (orders + records + choices))) + (64 << 20)
 
 
 def summarize(requests: Sequence[Request], skip: int = 0, sched: Optional[Scheduler] = None
@@ -485,8 +505,9 @@ def simulate(sched: Scheduler, requests: Sequence[Request],
     for r in arrivals:
         if piece_work is not None and r.pieces is None:
             n_c = sched.cells[r.det_id]
+            limit = min(piece_work, sched.max_batch_segments / 2 * n_c)
             r.pieces = [(None, (p1 - p0) * (b - a) * n_c)
-                        for a, b, p0, p1 in plan_pieces(r.n_particles, r.n_steps, n_c, piece_work)]
+                        for a, b, p0, p1 in plan_pieces(r.n_particles, r.n_steps, n_c, limit)]
     i = 0
     now = 0.0
     device_free = 0.0

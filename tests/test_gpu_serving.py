@@ -102,7 +102,8 @@ def test_memory_budget_admits_three_at_a_time(radio, stream):
     spec = W.plasma_mirror_detector(n_side=8, n_t=128, sample_particles=16)
     specs5 = {d: spec for d in range(5)}
     work = 4e10  # the server's default batch size; parts of half of it
-    budget = 3 * resident_bytes(spec, work / 2) + 2 * arena_bytes([spec], work) + 100
+    arenas = 2 * arena_bytes(work, work / 4096)
+    budget = 3 * resident_bytes(spec, work / 2) + arenas + 100
     chunks = [radio.Chunk.from_numpy(c) for _, c in host[:10]]
     order = [0, 1, 2, 0, 1, 2, 3, 4, 3, 4]
     with DepositServer(specs5, precision="fp64", memory_budget=budget) as srv:
@@ -113,7 +114,7 @@ def test_memory_budget_admits_three_at_a_time(radio, stream):
         res = {d: srv.finish(d, timeout=60) for d in (2, 3, 4)}
         st = srv.summary()
     print(f"[serve] budget: {st}", flush=True)
-    assert st["peak_resident"] == 3 and st["peak_bytes"] <= budget - 2 * arena_bytes([spec], work)
+    assert st["peak_resident"] == 3 and st["peak_bytes"] <= budget - arenas
     assert st["chunks"] == 10
     for d in range(2, 5):
         mine = [c for dd, c in zip(order, chunks) if dd == d]

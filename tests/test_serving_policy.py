@@ -118,10 +118,28 @@ def test_admission_counts_workspaces():
     n_p = -(-int(2e10) // (33 * 65536))
     assert ws >= 4096 * n_p * 4 + n_p * 33 * 64
     assert resident_bytes(spec, 2e10) == detector_bytes(spec) + ws
-    a = arena_bytes([spec], 4e10)
-    assert 1.0e10 <= a <= 1.2e10
-    # a one-step chunk of 10^5 particles: one order of 4096 tiles x 10^5 particles
-    assert a >= 4096 * 100_000 * 4 * (4e10 / (100_000 * 65536))
+    a = arena_bytes(4e10, 4e10 / 4096)
+    assert 1.2e10 <= a <= 2.0e10
+    # a batch of one-step chunks of 10^5 particles on that detector: 4e10 / 6.5e9 of
+    # them, each with one order of 4096 tiles x 10^5 particles and 2 x 10^5 records
+    n = 4e10 / (100_000 * 65536)
+    assert a >= n * (4096 * 100_000 * 4 + 2 * 100_000 * 80)
+    # on a one-tile detector the segment bound holds the records: 4e10 / 4096 segments
+    # of one-step chunks need 2 x 80 bytes each
+    assert a >= 4e10 / 4096 * 160
+
+
+def test_batches_respect_the_segment_bound():
+    """On a detector of 16 cells a batch of 1e9 interactions would hold 6e7 particle
+    segments; with a bound of 1e6 segments batches stop there."""
+    s = Scheduler({0: 1}, {0: 16}, 10, 1e9, max_batch_segments=1e6)
+    for k in range(8):
+        s.add(Request(0, 100_000, 4, float(k)))  # 4e5 segments, 6.4e6 interactions each
+    sizes = []
+    while s.pending:
+        s.admit()
+        sizes.append(len(s.next_batch()))
+    assert sizes == [2, 2, 2, 2]
 
 
 def _stream(n, rate, seed, n_det=4, cells=256):
