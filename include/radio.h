@@ -48,6 +48,8 @@ extern "C" {
 #define RADIO_ENOMEM (-2)  /* device or host allocation failed */
 #define RADIO_EDEVICE (-3) /* a HIP call or kernel launch failed */
 #define RADIO_ESTATE (-4)  /* object in the wrong state (e.g. wrong device) */
+#define RADIO_ETOOBIG (-5) /* a chunk needs more than the fixed scratch of
+                              radio_deposit_trajectory_chunk_noalloc */
 
 /* arithmetic of the deposit */
 #define RADIO_FP64 0         /* every step in IEEE double */
@@ -183,6 +185,27 @@ RADIO_API int radio_detector_reset(radio_detector* det, void* stream);
  * dropped deposits, never out-of-bounds writes.
  */
 RADIO_API int radio_deposit_trajectory_chunk(radio_detector* det, const radio_chunk* chunk, void* stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the deposit
+ * of radio_deposit_trajectory_chunk, same arguments and result up to the order
+ * of floating-point additions, with every workspace in one fixed device array
+ * of radio_noalloc_scratch_bytes() bytes (256 MiB) per GPU, held by the
+ * library from its first use on that GPU until the process ends.  It calls no
+ * allocation or release routine.  The chunk runs as time slices of whole runs
+ * sized so that a slice's state records, particle orders (one per two runs of
+ * 16 segments: 4 * ceil(n_cells / 16) * n_particles bytes each) and ring choices
+ * fit the array; RADIO_ETOOBIG (nothing enqueued) when even one run does not.
+ * All calls on one GPU share the array: calls on one stream follow each other,
+ * calls that overlap on one GPU from different streams race and must not be
+ * made.  Argument checks and other errors as radio_deposit_trajectory_chunk.
+ */
+RADIO_API int radio_deposit_trajectory_chunk_noalloc(radio_detector* det, const radio_chunk* chunk,
+                                                     void* stream);
+
+/* The size of the non-allocating deposit's scratch per GPU, in bytes. */
+RADIO_API int radio_noalloc_scratch_bytes(int64_t* bytes);
 
 /*
  * Deposit n independent (detector, chunk) pairs in one persistent launch per

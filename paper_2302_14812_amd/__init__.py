@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libradio.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ETOOBIG = 0, -1, -2, -3, -4, -5
 FP64, MIXED, MIXED_TWOSUM = 0, 1, 2
 GEOM_EXPLICIT, GEOM_PLANE, GEOM_SPHERE = 0, 1, 2
 # detector options (bit flags)
@@ -32,6 +32,7 @@ EXPORTS = (
     "radio_detector_stats", "radio_detector_shape", "radio_detector_cells",
     "radio_arrival_times", "radio_status_string", "radio_set_tuning", "radio_get_tuning",
     "radio_spectrum", "radio_push", "radio_slot_coordinates",
+    "radio_deposit_trajectory_chunk_noalloc", "radio_noalloc_scratch_bytes",
 )
 
 
@@ -104,6 +105,8 @@ def _lib():
         lib.radio_detector_destroy.argtypes = [vp]
         lib.radio_detector_reset.argtypes = [vp, vp]
         lib.radio_deposit_trajectory_chunk.argtypes = [vp, ctypes.POINTER(_Chunk), vp]
+        lib.radio_deposit_trajectory_chunk_noalloc.argtypes = [vp, ctypes.POINTER(_Chunk), vp]
+        lib.radio_noalloc_scratch_bytes.argtypes = [ctypes.POINTER(i64)]
         lib.radio_deposit_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Chunk),
                                             ctypes.c_int, vp]
         lib.radio_read_detector.argtypes = [vp, vp, vp, vp]
@@ -294,6 +297,14 @@ class Detector:
         c = chunk._c()
         _check(_lib().radio_deposit_trajectory_chunk(self.handle, ctypes.byref(c), _stream(stream)),
                "radio_deposit_trajectory_chunk")
+
+    def deposit_noalloc(self, chunk: Chunk, stream=None) -> None:
+        """The same deposit with every workspace in the library's fixed scratch
+        (no device allocation; RadioError ETOOBIG when the chunk does not fit)."""
+        c = chunk._c()
+        _check(_lib().radio_deposit_trajectory_chunk_noalloc(self.handle, ctypes.byref(c),
+                                                              _stream(stream)),
+               "radio_deposit_trajectory_chunk_noalloc")
 
     def read(self, E=None, B=None, stream=None) -> Tuple[object, object]:
         """Return (E, B) device tensors of shape (n_cells, n_t, 3)."""

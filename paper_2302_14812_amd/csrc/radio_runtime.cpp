@@ -465,6 +465,102 @@ int enqueue_deposit(radio_detector* det, const radio_chunk* k, hipStream_t s)
     return RADIO_OK;
 }
 
+// ---------------------------------------------------------------------------
+// The deposit that allocates nothing: its workspaces (state records, particle
+// orders, ring choices) live in one fixed device array per GPU, `scratch`.
+// Every call on a GPU shares that GPU's copy; calls on one stream follow each
+// other, calls that overlap on one GPU (different streams) race.  Nothing in it
+// needs clearing: each launch's kinematics, order and ring-choice kernels write
+// every word the deposit kernel of the same launch reads.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(256) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of this GPU's scratch, looked up once per device with that
+// device current (the array's name is no device address in host code).
+int scratch_of(int dev, char** out)
+{
+    if (dev < 0 || dev >= kMaxDevices)
+        return RADIO_ESTATE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return RADIO_EDEVICE;
+        }
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return RADIO_OK;
+}
+
+constexpr size_t align256(size_t n)
+{
+    return (n + 255) / 256 * 256;
+}
+
+// Bytes of the scratch a time slice of `runs` runs of job W takes: its records
+// (with their one-state overlap), one order per kRunsPerGroup runs, ring choices.
+size_t slice_scratch_bytes(const radio::DepositJob& W, int precision, int64_t runs)
+{
+    const int64_t states = std::min(runs * radio::kRunL, W.n_s) + 1;
+    const int64_t groups =
+        W.n_p < radio::kMinGroupParticles ? 1 : (runs + radio::kRunsPerGroup - 1) / radio::kRunsPerGroup;
+    return align256((size_t)(W.n_p * states) * radio::rec_bytes(precision)) +
+           align256((size_t)(groups * W.n_tiles * W.n_p) * sizeof(int32_t)) +
+           align256((size_t)W.n_tiles);
+}
+
+int enqueue_deposit_noalloc(radio_detector* det, const radio_chunk* k, hipStream_t s)
+{
+    if (k->n_particles == 0 || k->n_steps == 0)
+        return RADIO_OK;
+    if (k->n_particles > INT32_MAX || k->n_steps > INT32_MAX - 1)
+        return RADIO_EINVAL;
+    char* base = nullptr;
+    int rc = scratch_of(det->device, &base);
+    if (rc != RADIO_OK)
+        return rc;
+    const radio::DepositJob W = make_job(det, k);
+    if (slice_scratch_bytes(W, det->precision, 1) > kScratchBytes)
+        return RADIO_ETOOBIG;
+    // the longest time slices that fit the scratch
+    int64_t lo = 1, hi = W.n_runs;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (slice_scratch_bytes(W, det->precision, mid) <= kScratchBytes)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int64_t n_slices = (W.n_runs + lo - 1) / lo;
+    const int64_t runs_each = (W.n_runs + n_slices - 1) / n_slices;
+    const int64_t groups_each = (runs_each + radio::kRunsPerGroup - 1) / radio::kRunsPerGroup;
+    for (int64_t r_a = 0; r_a < W.n_runs; r_a += runs_each) {
+        radio::DepositJob J =
+            slice_job(det, W, r_a, std::min(r_a + runs_each, W.n_runs), groups_each);
+        const size_t rec_b = align256((size_t)(J.n_p * (J.n_s + 1)) * radio::rec_bytes(det->precision));
+        const size_t perm_b = align256((size_t)(J.n_groups * J.n_tiles * J.n_p) * sizeof(int32_t));
+        if (rec_b + perm_b + align256((size_t)J.n_tiles) > kScratchBytes)
+            return RADIO_ETOOBIG;  // not reached: the slices were sized to fit
+        J.recs = base;
+        J.perm = reinterpret_cast<int32_t*>(base + rec_b);
+        J.ring_sel = reinterpret_cast<uint8_t*>(base + rec_b + perm_b);
+        if (radio::launch_kinematics(J, det->precision, s) != hipSuccess ||
+            radio::launch_order(J, s) != hipSuccess ||
+            radio::launch_ring_choice(J, det->precision, s) != hipSuccess ||
+            radio::launch_deposit(J, det->precision, current_tuning().max_grid, s) != hipSuccess)
+            return RADIO_EDEVICE;
+        det->slices += 1;
+    }
+    det->interactions += k->n_particles * k->n_steps * det->n_c;
+    return RADIO_OK;
+}
+
 // Workspaces of batched deposits, per device: every pair of a batch needs its
 // own state records and particle orders until the persistent launch has run, so
 // they come from one arena; before the arena is reused the previous batch's
@@ -692,6 +788,8 @@ const char* radio_status_string(int status)
         return "device error";
     case RADIO_ESTATE:
         return "invalid state";
+    case RADIO_ETOOBIG:
+        return "chunk too large for the fixed scratch of the non-allocating deposit";
     default:
         return "unknown status";
     }
@@ -854,6 +952,31 @@ int radio_deposit_trajectory_chunk(radio_detector* det, const radio_chunk* chunk
     if (rc == RADIO_OK)
         det->chunks += 1;
     return rc;
+}
+
+int radio_deposit_trajectory_chunk_noalloc(radio_detector* det, const radio_chunk* chunk,
+                                           void* stream)
+{
+    if (!det)
+        return RADIO_EINVAL;
+    int rc = validate_chunk(chunk);
+    if (rc != RADIO_OK)
+        return rc;
+    DeviceGuard g(det->device);
+    if (!g.ok())
+        return RADIO_EDEVICE;
+    rc = enqueue_deposit_noalloc(det, chunk, (hipStream_t)stream);
+    if (rc == RADIO_OK)
+        det->chunks += 1;
+    return rc;
+}
+
+int radio_noalloc_scratch_bytes(int64_t* bytes)
+{
+    if (!bytes)
+        return RADIO_EINVAL;
+    *bytes = (int64_t)kScratchBytes;
+    return RADIO_OK;
 }
 
 int radio_deposit_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
