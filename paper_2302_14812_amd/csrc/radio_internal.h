@@ -56,7 +56,7 @@ static_assert(kGroups * kTileCells == kDepositThreads && (kGroups & (kGroups - 1
 constexpr int kRingMargin = 2;                          // ring slots kept below a batch's start
 constexpr int kXcds = 8;                                // accelerator dies sharing one L2 each
 
-// Slots per cell in the LDS ring (powers of two), 48 B per slot in every mode
+// Slots per cell in the LDS ring (the small one a power of two), 48 B per slot in every mode
 // (6 doubles, or 6 compensated single pairs).  Each tile takes the small ring
 // when the slots a batch touches fit it (four workgroups per CU), else the
 // large one (two per CU): slowly advancing arrivals, where many segments
@@ -68,8 +68,13 @@ constexpr int kXcds = 8;                                // accelerator dies shar
 #ifndef RADIO_RING_LARGE
 #define RADIO_RING_LARGE 64
 #endif
+// segments a large-ring workgroup stages per batch (a divisor of kRunL)
+#ifndef RADIO_LARGE_SUBRUN
+#define RADIO_LARGE_SUBRUN 16
+#endif
 constexpr int kRingSmall = RADIO_RING_SMALL;
 constexpr int kRingLarge = RADIO_RING_LARGE;
+constexpr int kLargeSubRun = RADIO_LARGE_SUBRUN;
 
 // One (detector, chunk) deposit as the kernels see it.  Sizes are 64-bit; the
 // host runtime has validated every pointer and size before filling this in.

@@ -253,6 +253,16 @@ __device__ __forceinline__ void global_add_pair(RADIO_GLOBAL float* row, int j, 
     }
 }
 
+// position of slot j >= 0 in a ring of R slots
+template <int R>
+__device__ __forceinline__ int ring_pos(int j)
+{
+    if constexpr ((R & (R - 1)) == 0)
+        return j & (R - 1);
+    else
+        return (int)((unsigned)j % (unsigned)R);
+}
+
 // One cell's ring of slots in LDS, covering slots [base, base + R); slot j lives
 // at position j mod R.  Emissions inside go to the ring (LDS atomic add: the
 // kGroups lanes of a cell share it), anything else straight to HBM.  The ring
@@ -282,7 +292,7 @@ struct CellSink<double, R> {
         for (int k = 0; k < 6; ++k)
             v[k] = (double)a[k];
         if ((unsigned)(j - base) < (unsigned)R) {
-            RADIO_LDS double* q = ring + (j & (R - 1)) * W;
+            RADIO_LDS double* q = ring + ring_pos<R>(j) * W;
 #pragma unroll
             for (int k = 0; k < 6; ++k)
                 __hip_atomic_fetch_add(q + k, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -304,7 +314,7 @@ struct CellSink<float, R> {
     __device__ __forceinline__ void flush(int j, const float a[6]) const
     {
         if ((unsigned)(j - base) < (unsigned)R) {
-            RADIO_LDS double* q = ring + (j & (R - 1)) * W;
+            RADIO_LDS double* q = ring + ring_pos<R>(j) * W;
 #pragma unroll
             for (int k = 0; k < 6; ++k)
                 __hip_atomic_fetch_add(q + k, (double)a[k], __ATOMIC_RELAXED,
@@ -1093,6 +1103,14 @@ struct ModeTypes {
     using Rec = typename std::conditional<MIX, RecMix, RecF64>::type;  // staged state record
 };
 
+// Segments a workgroup stages per batch: a whole run with the small ring, a
+// part of it with the large ring (tiles whose arrivals cross a slot every
+// segment or two), so that the large ring's span and its LDS stay small.
+template <int R>
+constexpr int kSubRun = R == kRingLarge ? kLargeSubRun : kRunL;
+static_assert(kRunL % kSubRun<kRingLarge> == 0 && kRunL % kSubRun<kRingSmall> == 0,
+              "a run is a whole number of staged parts");
+
 // LDS of one deposit workgroup with rings of R slots
 template <int M, int R>
 struct DepositShared {
@@ -1100,9 +1118,10 @@ struct DepositShared {
     // one cell's ring, padded by one word so that the rings of the kTileCells
     // cells, which one instruction updates together, start in different banks
     static constexpr int kStride = R * CellSink<Acc, R>::W + 1;
-    typename ModeTypes<M>::Rec rec[kGroups][kRunL + 1];  // staged batch: a run per group
+    static constexpr int L = kSubRun<R>;
+    typename ModeTypes<M>::Rec rec[kGroups][L + 1];  // staged batch: L segments per group
     double sq[kGroups];                 // its charges
-    double tk[kRunL + 1];               // its states' time arguments (the same for every lane)
+    double tk[L + 1];                   // its states' time arguments (the same for every lane)
     double ring[kTileCells * kStride];  // per-cell slot rings
     int nb[2][kTileCells];              // per cell: lowest start slot of a coming batch
     int ord[2][kGroups];                // particles of the staged rows, per batch parity
@@ -1198,10 +1217,15 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
     const int64_t bt_begin = part * J.batches_per_part;
     const int64_t bt_end = min(bt_begin + J.batches_per_part, (J.n_p + kGroups - 1) / kGroups);
     const int64_t n_batches = bt_end - bt_begin;  // per run
-    const int64_t rb_begin = split * J.runs_per_split;
-    const int64_t rb_end = min(rb_begin + J.runs_per_split, J.n_runs);
-    // The item's batches are taken run-major: run rb (states rb * kRunL ...)
-    // of the particles order[bt * kGroups ...], bt = bt_begin .. bt_end - 1.
+    // The item's runs [rb_begin, rb_end), staged in parts of L segments: part
+    // rb (states rb * L ... rb * L + L) of run rb / NS.
+    constexpr int L = kSubRun<R>;
+    constexpr int NS = kRunL / L;
+    const int64_t rb_begin = split * J.runs_per_split * NS;
+    const int64_t rb_end =
+        min(min(split * J.runs_per_split + J.runs_per_split, J.n_runs) * NS, (J.n_s + L - 1) / L);
+    // The item's batches are taken part-major: part rb of the particles
+    // order[bt * kGroups ...], bt = bt_begin .. bt_end - 1.
     // Before a batch is computed, one round of global loads brings its
     // records, its charges and the first positions of the next batch's
     // particles, whose lowest start slot per cell places the ring for that
@@ -1213,10 +1237,10 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
             ++rb_;
         }
     };
-    // the lane's particle of batch (rb_, bt_), or -1
+    // the lane's particle of batch (rb_, bt_), or -1 (the order of the part's run)
     auto lane_particle = [&](int64_t rb_, int64_t bt_, int lane_g) -> int {
         const int64_t i = bt_ * kGroups + lane_g;
-        return (rb_ < rb_end && i < J.n_p) ? (int)order_of(rb_)[i] : -1;
+        return (rb_ < rb_end && i < J.n_p) ? (int)order_of(rb_ / NS)[i] : -1;
     };
     // lowest start slot of the cell over a batch: the lane's particle starts at x
     // at state s_a (into nb[buf][cell])
@@ -1250,7 +1274,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
             if (new_base > base && new_base < base + R)
                 hi = new_base;
             for (int j = lo + g; j < hi; j += kGroups) {
-                RADIO_LDS double* q = my_ring + (j & (R - 1)) * RW;
+                RADIO_LDS double* q = my_ring + ring_pos<R>(j) * RW;
                 double a[RW];
                 bool nz = false;
 #pragma unroll
@@ -1298,9 +1322,9 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
     if (rb_begin < rb_end && n_batches > 0) {
         const int p0 = lane_particle(rb, bt, g);
         if (active && p0 >= 0) {
-            const RADIO_GLOBAL double* x = first_position(p0, rb * kRunL);
+            const RADIO_GLOBAL double* x = first_position(p0, rb * L);
             const double xs[3] = {x[0], x[1], x[2]};
-            scout(xs, rb * kRunL, 0);
+            scout(xs, rb * L, 0);
         }
         if constexpr (kStageDirect) {
             if (tid < kGroups)
@@ -1312,8 +1336,8 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
     }
     __syncthreads();
     for (int buf = 0; rb < rb_end && n_batches > 0; buf ^= 1) {
-        const int64_t s_a = rb * kRunL;
-        const int len = (int)min((int64_t)kRunL, J.n_s - s_a);
+        const int64_t s_a = rb * L;
+        const int len = (int)min((int64_t)L, J.n_s - s_a);
         const int64_t i0 = bt * kGroups;
         const int np = (int)min((int64_t)kGroups, J.n_p - i0);
         // slide the ring to this batch's earliest start (every lane of the
@@ -1339,7 +1363,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
             // batch's first positions for the ring.
             static_assert(sizeof(Rec) % 16 == 0, "records move in 16-byte pieces");
             constexpr int kPieces = (int)(sizeof(Rec) / 16);
-            constexpr int kPer = (kRunL + 1) * kPieces;  // pieces of a full row
+            constexpr int kPer = (L + 1) * kPieces;  // pieces of a full row
             constexpr int kWaves = kDepositThreads / 64;
             constexpr int kRowsPerWave = kGroups / kWaves;
             constexpr int kHalves = (kPer + 63) / 64;  // rounds per row
@@ -1373,7 +1397,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
             double xs[3] = {0.0, 0.0, 0.0};
             const bool scouting = active && p_scout >= 0;
             if (scouting) {
-                const RADIO_GLOBAL double* x = first_position(p_scout, rb1 * kRunL);
+                const RADIO_GLOBAL double* x = first_position(p_scout, rb1 * L);
                 xs[0] = x[0];
                 xs[1] = x[1];
                 xs[2] = x[2];
@@ -1384,14 +1408,14 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
             if (tid < kGroups)
                 sh.ord[buf ^ 1][tid] = ord_next;
             if (scouting)
-                scout(xs, rb1 * kRunL, buf ^ 1);
+                scout(xs, rb1 * L, buf ^ 1);
             p_scout = p_scout_next;
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the records are in LDS
         } else {
             // pieces of 16 bytes where the record size allows, else of 8
             using Piece = typename std::conditional<sizeof(Rec) % 16 == 0, v2i64, long long>::type;
             constexpr int kPieces = (int)(sizeof(Rec) / sizeof(Piece));
-            constexpr int kIter = ((kRunL + 1) * kPieces + kStageLanes - 1) / kStageLanes;
+            constexpr int kIter = ((L + 1) * kPieces + kStageLanes - 1) / kStageLanes;
             const int per = (len + 1) * kPieces;
             int t = t_stage;
             asm volatile("" : "+v"(t));
@@ -1415,7 +1439,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
             double xs[3] = {0.0, 0.0, 0.0};
             const bool scouting = active && p_scout >= 0;
             if (scouting) {
-                const RADIO_GLOBAL double* x = first_position(p_scout, rb1 * kRunL);
+                const RADIO_GLOBAL double* x = first_position(p_scout, rb1 * L);
                 xs[0] = x[0];
                 xs[1] = x[1];
                 xs[2] = x[2];
@@ -1432,7 +1456,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
                     sh.sq[gg] = qs;
             }
             if (scouting)
-                scout(xs, rb1 * kRunL, buf ^ 1);
+                scout(xs, rb1 * L, buf ^ 1);
             p_stage = p_stage_next;
             p_scout = p_scout_next;
         }
@@ -1579,10 +1603,17 @@ __attribute__((amdgpu_waves_per_eu(kMinWaves<M, R, G, HOLD>))) void deposit_kern
 // workgroup leaves once the counter passes n_items.
 // (The persistent loop costs registers: every single-precision variant with the
 // small ring goes over 96 VGPRs by itself, and five waves per SIMD, with a few
-// spilled words, make the 64-set batched benchmark 1.2% faster.)
+// spilled words, make the 64-set batched benchmark 1.2% faster; the double
+// small-ring variants are asked for the four waves their LDS allows.)
+template <int M, int R, int G, int HOLD>
+constexpr int kPersistentWaves = R != kRingSmall                      ? 1
+                                 : M != kModeF64                      ? 5
+                                 : HOLD != 2                          ? 4
+                                                                      : 1;
+
 template <int M, int R, int G, int HOLD>
 __global__ __launch_bounds__(kDepositThreads)
-__attribute__((amdgpu_waves_per_eu((M != kModeF64 && R == kRingSmall) ? 5 : 1))) void
+__attribute__((amdgpu_waves_per_eu(kPersistentWaves<M, R, G, HOLD>))) void
 deposit_persistent_kernel(
     const DepositJob* __restrict__ jobs, const WorkItem* __restrict__ items, int64_t n_items,
     unsigned long long* __restrict__ next)
