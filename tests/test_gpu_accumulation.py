@@ -1,0 +1,100 @@
+"""The compensated single-precision accumulator (RADIO_MIXED_TWOSUM) against
+plain single-precision accumulation, on a deposit that piles thousands of
+additions onto the same detector slots.
+
+The integrator detector of Sec. 3.2 accumulates every deposit into its slots;
+in run-time mode (Sec. 3.1) a detector takes one chunk per push step, so a
+slot in device memory receives one addition per chunk that reaches it.  Here
+one small chunk is deposited K = 6000 times into each detector: every slot is
+flushed from the on-chip ring at the end of each deposit (a ring bypass adds to
+it directly as well), so each device slot receives at least K additions of the
+same values.  In exact arithmetic the result is K times one deposit's.
+
+- RADIO_MIXED (double accumulation) and RADIO_MIXED_TWOSUM (single-precision
+  (hi, lo) pairs with two-sum) both stay within 1e-9 of K times one deposit,
+  and within the 1e-5 bar of K times the oracle's deposit.
+- Plain single-precision accumulation of the same K additions per slot,
+  replayed on the host (each addition rounded to single precision, as a
+  single-precision atomic add would), drifts by K x 2^-24 / 2 relative, about
+  4e-5 here: four times over the bar.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_14812_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+from parity import TOL_MIXED, check_parity, rel_l2  # noqa: E402
+
+K = 6000
+
+
+@pytest.fixture(scope="module")
+def radio():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2302_14812_amd as radio
+    radio._lib()
+    return radio
+
+
+def _case():
+    chunk = W.random_chunk(32, 16, seed=61, dt=0.05, gamma_max=6.0, t_first=0.2)
+    cells = W.plane_cells([0.0, 0.0, 40.0], [1, 0, 0], [0, 1, 0], 4, 4, 6.0, 6.0)
+    t0, dtd = W.arrival_window(cells, chunk, 24, pad_frac=0.05,
+                               cell_index=list(range(16)), max_particles=32, seed=61)
+    return W.DetectorSpec(cells=cells, t0=t0, dt_det=dtd, n_t=24), chunk
+
+
+def _repeat(radio, spec, dev, precision, k):
+    import torch
+    det = radio.Detector.from_spec(spec, precision=precision)
+    for _ in range(k):
+        det.deposit(dev)
+    E, B = det.read()
+    torch.cuda.synchronize()
+    st = det.stats()
+    det.close()
+    return E.cpu().numpy(), B.cpu().numpy(), st
+
+
+def _fp32_replay(v, k):
+    """k additions of v to a single-precision accumulator, each rounded to single."""
+    s = np.zeros(v.shape, dtype=np.float32)
+    vf = v.astype(np.float32)
+    for _ in range(k):
+        s = s + vf  # float32 + float32: one rounding per addition
+    return s.astype(np.float64)
+
+
+def test_compensated_accumulation_holds_where_single_precision_drifts(radio):
+    spec, chunk = _case()
+    dev = radio.Chunk.from_numpy(chunk)
+    E1, B1, st1 = _repeat(radio, spec, dev, "mixed", 1)
+    # slot updates that went to device memory directly rather than from the ring
+    print(f"[accumulation] one deposit: {st1['interactions']} interactions, "
+          f"{st1['bypassed']} ring bypasses", flush=True)
+    assert np.abs(E1).max() > 0.0
+    Em, Bm, stm = _repeat(radio, spec, dev, "mixed", K)
+    Et, Bt, stt = _repeat(radio, spec, dev, "mixed_twosum", K)
+    assert stm["chunks"] == stt["chunks"] == K
+    # double accumulation and compensated pairs against K times one deposit
+    for what, (E, B) in (("double", (Em, Bm)), ("compensated pairs", (Et, Bt))):
+        e = max(rel_l2(E, K * E1), rel_l2(B, K * B1))
+        print(f"[accumulation] {what}: {K} deposits vs {K} x one, relL2 {e:.3e}", flush=True)
+        assert e <= 1e-9, (what, e)
+    # the same additions in plain single precision
+    Ef, Bf = _fp32_replay(E1, K), _fp32_replay(B1, K)
+    ef = max(rel_l2(Ef, K * E1), rel_l2(Bf, K * B1))
+    print(f"[accumulation] plain single precision (host replay): relL2 {ef:.3e}", flush=True)
+    assert ef > 2.0 * TOL_MIXED
+    # against the oracle: the deposit is linear, K deposits are K times one
+    Eo, Bo = oracle.read(oracle.deposit_workload(spec, chunk))
+    check_parity(Et, Bt, K * Eo, K * Bo, TOL_MIXED, f"compensated pairs, {K} deposits, vs oracle")
+    check_parity(Em, Bm, K * Eo, K * Bo, TOL_MIXED, f"double accumulation, {K} deposits, vs oracle")
+    ef_o = max(rel_l2(_fp32_replay(E1, K), K * Eo), rel_l2(_fp32_replay(B1, K), K * Bo))
+    print(f"[accumulation] plain single precision vs oracle: relL2 {ef_o:.3e}", flush=True)
+    assert ef_o > TOL_MIXED

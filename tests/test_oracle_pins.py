@@ -472,6 +472,126 @@ def test_lienard_power_of_circular_motion(oracle_mod):
     assert abs(energy / expect - 1.0) < 2e-3, energy / expect
 
 
+def _schott(m, theta, beta, om):
+    """Time-averaged power per solid angle in harmonic m of a unit charge in circular
+    motion (speed beta, angular frequency om), theta from the orbit's axis: Schott's
+    series (Landau-Lifshitz vol. 2, Sec. 74; Jackson problem 14.15), c = 1:
+    m^2 om^2 / (2 pi) [cot^2 theta J_m(x)^2 + beta^2 J_m'(x)^2],  x = m beta sin theta."""
+    from scipy.special import jv, jvp
+    x = m * beta * math.sin(theta)
+    return m * m * om * om / (2 * math.pi) * ((math.cos(theta) / math.sin(theta)) ** 2 *
+                                              jv(m, x) ** 2 + beta * beta * jvp(m, x) ** 2)
+
+
+def test_schott_series_sums_to_lienard_power():
+    """The harmonic series used below, summed over harmonics and integrated over the
+    sphere, gives Lienard's power (2/3) gamma^4 beta^2 om^2 of circular motion."""
+    pytest.importorskip("scipy")
+    beta = 0.6
+    om = beta
+    x, w = np.polynomial.legendre.leggauss(200)
+    th = np.arccos(x)
+    tot = sum(2 * math.pi * sum(wi * _schott(m, t, beta, om) for t, wi in zip(th, w))
+              for m in range(1, 60))
+    expect = (2.0 / 3.0) * beta ** 2 * om ** 2 / (1 - beta ** 2) ** 2
+    assert abs(tot / expect - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("theta_deg", [20.0, 45.0, 70.0, 90.0])
+def test_schott_harmonics_of_circular_motion(oracle_mod, theta_deg):
+    """The synchrotron-like line spectrum of circular motion.  A charge at beta = 0.6
+    on a unit circle radiates only at harmonics m of the orbital frequency; the
+    detector signal at 1e5 in direction theta (from the orbit's axis), deposited
+    by the oracle over eight orbits and Fourier analysed over four whole periods
+    of detector time, carries in harmonic m the power per solid angle
+    R^2 / (2 pi) |E_m|^2, which must equal Schott's series.  The slot averaging
+    multiplies E_m by sinc(m om dt_det / 2), divided out.  With 8000 states per
+    orbit the lines agree to ~1e-6; the bar is 1e-4 of each line (of the
+    fundamental for lines far below it)."""
+    pytest.importorskip("scipy")
+    beta = 0.6
+    gamma = 1.0 / math.sqrt(1 - beta * beta)
+    om = beta  # radius 1
+    T = 2 * math.pi / om
+    per, S, slots = 8, 8000, 512
+    chunk = W.circular_orbit(gamma=gamma, radius=1.0, n_steps=per * S, dt=T / S, q=-1.0)
+    th = math.radians(theta_deg)
+    Rd = 1.0e5
+    cell = Rd * np.array([[math.sin(th), 0.0, math.cos(th)]])
+    dt_det = T / slots
+    t0 = Rd - 2.0
+    n_t = int((per * T + 4.0) / dt_det)
+    D = oracle_mod.deposit(cell, t0, dt_det, n_t, chunk.x, chunk.u, chunk.q, 0.0, chunk.dt)
+    E = D[0, :, :3]
+    # four whole periods of detector time away from the ends of the signal
+    j0 = 2 * slots
+    X = np.fft.fft(E[j0:j0 + 4 * slots], axis=0)
+    N = 4 * slots
+    for m in range(1, 5):
+        Em2 = (np.abs(X[4 * m]) ** 2).sum() / N ** 2
+        sinc = math.sin(m * om * dt_det / 2) / (m * om * dt_det / 2)
+        got = Rd ** 2 / (2 * math.pi) * Em2 / sinc ** 2
+        want = _schott(m, th, beta, om)
+        print(f"[schott] theta {theta_deg} m {m}: oracle {got:.6e} Schott {want:.6e} "
+              f"ratio {got / want:.6f}")
+        # lines far below the fundamental are held to the fundamental's absolute error
+        scale = max(want, 1e-3 * _schott(1, th, beta, om))
+        assert abs(got - want) <= 1e-4 * scale, (m, got, want)
+    # nothing between the lines
+    between = [k for k in range(1, 17) if k % 4]
+    leak = max(np.abs(X[k]).max() for k in between) / np.abs(X[4]).max()
+    assert leak < 1e-6, leak
+
+
+def test_on_axis_circular_orbit_bins_are_an_exact_sum(oracle_mod):
+    """On the orbit's axis R is the same for every state and n.beta = 0 exactly, so
+    kappa = 1, tau_s - tau_{s-1} = dt, and with betadot the chord of the rotating
+    beta, n.betadot = R^-1 r beta sin(om dt) / dt is the same for every segment:
+        E_s = q [ w_s / (gamma^2 R^2) + (w_s (n.betadot) - betadot_s) / R ],
+        w_s = n_s - beta_s,  betadot_s = (2 beta / dt) sin(om dt / 2)
+              (-cos(phi_s - om dt/2), -sin(phi_s - om dt/2), 0),
+    B_s = n_s x E_s.  Each slot is the sum of these closed forms times the
+    overlaps of [tau_{s-1}, tau_s] with it (arrival times from the oracle's own
+    arrival function, which is pinned separately), so the deposit is checked as
+    a sum of closed-form fields, to 1e-13 (the oracle's betadot is a difference of
+    two rounded velocities, good to ~eps / (om dt) each; the sum here lands at 2e-14)."""
+    gamma, r, q = 5.0, 1.0, -1.0
+    beta = math.sqrt(1 - 1 / gamma ** 2)
+    om = beta / r
+    dt, S = 0.01, 2000
+    chunk = W.circular_orbit(gamma=gamma, radius=r, n_steps=S, dt=dt, q=q)
+    Z = 1000.0
+    cell = np.array([0.0, 0.0, Z])
+    R = math.sqrt(r * r + Z * Z)
+    dt_det = 0.0438
+    t0 = R - 0.3
+    n_t = int((S * dt + 0.6) / dt_det)
+    D = oracle_mod.deposit(cell[None, :], t0, dt_det, n_t, chunk.x, chunk.u, chunk.q, 0.0, dt)[0]
+    ref = np.zeros((n_t, 6))
+    s = np.arange(S + 1)
+    phi = om * dt * s
+    tau = np.array([oracle_mod.arrival(cell, chunk.x[:, k, 0], k * dt) for k in s])
+    a = (tau - t0) / dt_det
+    k_nb = r * beta * math.sin(om * dt) / (R * dt)
+    for k in range(1, S + 1):
+        n = np.array([-r * math.cos(phi[k]), -r * math.sin(phi[k]), Z]) / R
+        b = beta * np.array([-math.sin(phi[k]), math.cos(phi[k]), 0.0])
+        h = phi[k] - om * dt / 2
+        bd = (2 * beta / dt) * math.sin(om * dt / 2) * np.array([-math.cos(h), -math.sin(h), 0.0])
+        w = n - b
+        E = q * (w / (gamma ** 2 * R * R) + (w * k_nb - bd) / R)
+        F = np.concatenate([E, np.cross(n, E)])
+        lo, hi = a[k - 1], a[k]
+        for j in range(int(math.floor(lo)), int(math.floor(hi)) + 1):
+            ov = min(hi, j + 1.0) - max(lo, float(j))
+            if 0 <= j < n_t and ov > 0:
+                ref[j] += F * ov
+    assert np.allclose(np.diff(tau), dt, rtol=0, atol=2e-12)  # tau steps by dt
+    err = np.linalg.norm(D - ref) / np.linalg.norm(ref)
+    print(f"[on-axis circular] relL2 {err:.2e}")
+    assert err < 1e-13
+
+
 def test_dipole_pattern_and_larmor(oracle_mod):
     """A slowly oscillating charge radiates (q^2/4pi)|betadot|^2 sin^2(Theta) per solid angle,
     with the field opposite to the acceleration at Theta = 90 degrees."""
