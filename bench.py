@@ -157,7 +157,9 @@ def batch_leg(radio, W, precision, steps, warmup):
     chunks = [radio.Chunk.from_numpy(wl.chunk) for wl in sets]
     dets = [radio.Detector.from_spec(wl.detector, precision=precision) for wl in sets]
     total = sum(wl.interactions for wl in sets)
+    defaults = radio.get_tuning()
     tuned = autotune.apply_batch([wl.detector for wl in sets], chunks)
+    shape = radio.get_tuning()["shape"]
     stream = torch.cuda.current_stream()
 
     def timed(fn):
@@ -189,6 +191,7 @@ def batch_leg(radio, W, precision, steps, warmup):
     ms_sep = timed(separate)
     print(f"[bench] batch ({precision}): 64 launches {ms_sep:.1f} ms", file=sys.stderr, flush=True)
     sizes = [wl.interactions for wl in sets]
+    radio.set_tuning(**defaults)
     for d in dets:
         d.close()
     return {"workload": "64 uneven sets (batched-launch recipe, particle counts x 0.02, sides "
@@ -198,7 +201,8 @@ def batch_leg(radio, W, precision, steps, warmup):
             "one_launch_ms": ms_batch, "separate_launches_ms": ms_sep,
             "one_launch_value": total / (ms_batch * 1e-3),
             "separate_value": total / (ms_sep * 1e-3),
-            "speedup": ms_sep / ms_batch, "autotuned": tuned}
+            "speedup": ms_sep / ms_batch, "autotuned": tuned,
+            "workgroup_shape": list(radio.SHAPES[shape])}
 
 
 def plasma_leg(radio, W, precisions, n_particles, n_steps=1000, fp64_steps=1000):
@@ -229,13 +233,19 @@ def plasma_leg(radio, W, precisions, n_particles, n_steps=1000, fp64_steps=1000)
            "n_cells": spec.n_cells, "n_t": spec.n_t, "interactions": inter}
     fields = {}
     full = chunk_dev
+    from paper_2302_14812_amd import autotune
+    defaults = radio.get_tuning()
     for prec in precisions:
         # the double run may take the first fp64_steps steps only (same motion, shorter)
         chunk = full
         if prec == "fp64" and fp64_steps < full.n_steps:
             chunk = full.slice_steps(0, fp64_steps)
         inter = chunk.n_particles * chunk.n_steps * spec.n_cells
-        print(f"[bench] plasma ({prec}): {chunk.n_steps} steps, {inter:.3e} interactions",
+        radio.set_tuning(**defaults)
+        tuned = autotune.apply_single(spec, chunk, prec)
+        shape = radio.get_tuning()["shape"]
+        print(f"[bench] plasma ({prec}): {chunk.n_steps} steps, {inter:.3e} interactions, "
+              f"shape {radio.SHAPES[shape]}{' (tuned)' if tuned else ''}",
               file=sys.stderr, flush=True)
         det = radio.Detector.from_spec(spec, precision=prec)
         det.deposit(warm, stream)
@@ -256,9 +266,11 @@ def plasma_leg(radio, W, precisions, n_particles, n_steps=1000, fp64_steps=1000)
         kms = a.elapsed_time(b)
         st = det.stats()
         det.close()
+        radio.set_tuning(**defaults)
         flops = inter * FLOPS_PER_INTERACTION
         out[prec] = {"value": inter / (ms * 1e-3), "ms_per_step": ms, "deposit_kernel_ms": kms,
-                     "n_steps": chunk.n_steps, "interactions": inter,
+                     "n_steps": chunk.n_steps, "interactions": inter, "autotuned": tuned,
+                     "workgroup_shape": list(radio.SHAPES[shape]),
                      "deposit_launches_per_step": st["slices"],
                      "bypassed_per_interaction": st["bypassed"] / max(1, st["interactions"]),
                      "roofline": {"bound": "alu", "achieved": flops / (kms * 1e-3) / 1e12,
@@ -608,11 +620,19 @@ def main():
     # the headline leg takes the requested steps; the others three (after one warm-up),
     # so that every leg fits the run
     sec_steps, sec_warm = min(args.steps, 3), min(args.warmup, 1)
+    from paper_2302_14812_amd import autotune
+    defaults = radio.get_tuning()
+    tuned = {}
     for prec in order:
         main = prec == args.precision
+        # the tuned workgroup shape and split for this workload, where the cache has them
+        radio.set_tuning(**defaults)
+        tuned[prec] = autotune.apply_single(wl.detector, wl.chunk, prec)
         ms, kms, fields[prec] = time_precision(radio, wl, chunk_dev, prec,
                                                args.steps if main else sec_steps,
                                                args.warmup if main else sec_warm, keep=True)
+        shape = radio.get_tuning()["shape"]
+        radio.set_tuning(**defaults)
         flops = inter * FLOPS_PER_INTERACTION
         # the deposit call of a step is `launches` deposit-kernel launches of equal
         # work (time slices); flops / time is the same per launch and per step, and
@@ -620,6 +640,7 @@ def main():
         legs[prec] = {
             "value": inter / (ms * 1e-3), "ms_per_step": ms, "deposit_kernel_ms": kms,
             "steps": args.steps if main else sec_steps,
+            "autotuned": tuned[prec], "shape": radio.SHAPES[shape],
             "deposit_launches_per_step": time_precision.launches,
             "roofline": {"bound": "alu", "achieved": flops / (kms * 1e-3) / 1e12,
                          "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
@@ -666,6 +687,10 @@ def main():
         "roofline": main_leg["roofline"],
         "deposit_launches_per_step": main_leg["deposit_launches_per_step"],
         "rel_l2_vs_fp64_path": main_leg.get("rel_l2_vs_fp64_path"),
+        "autotuned": main_leg["autotuned"],
+        "workgroup_shape": {"cells_per_tile": main_leg["shape"][0],
+                            "particles_per_batch": main_leg["shape"][1],
+                            "segments_per_run": main_leg["shape"][2]},
     }
     # ceilings of the interaction rate at F_int flops per interaction: double at the FP64
     # vector peak; mixed as its 25 double + 59 single flops at the two vector peaks

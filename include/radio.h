@@ -239,17 +239,24 @@ RADIO_API int radio_deposit_batch(radio_detector* const* dets, const radio_chunk
  *                        deposit may take; 0, the default, allows the size of the
  *                        chunk's state records and at least 1 GiB.  A single
  *                        deposit, alone or batched, keeps each order to at most
- *                        two runs of 16 segments (arrival offsets drift apart
- *                        along a chunk);
+ *                        two runs (arrival offsets drift apart along a chunk);
  *                        a chunk whose orders exceed the budget is deposited in
  *                        time slices that fit it, with the same result up to
  *                        summation order
+ *   shape                workgroup shape of the deposit of detectors with the
+ *                        default options (0 for the others): 0 = tiles of 16
+ *                        cells against batches of 16 particles and runs of 16
+ *                        segments (the default), 1 = 8 cells x 32 particles x
+ *                        16 segments, 2 = 16 cells x 16 particles x 8 segments.
+ *                        Every shape gives the same result up to summation
+ *                        order; the autotuner picks the fastest per workload
  */
 typedef struct radio_tuning {
     int32_t target_blocks;
     int32_t items_per_workgroup;
     int32_t max_grid;
     int32_t order_budget_mib;
+    int32_t shape;
 } radio_tuning;
 
 RADIO_API int radio_set_tuning(const radio_tuning* t);

@@ -77,7 +77,14 @@ class _Push(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("target_blocks", ctypes.c_int32), ("items_per_workgroup", ctypes.c_int32),
-                ("max_grid", ctypes.c_int32), ("order_budget_mib", ctypes.c_int32)]
+                ("max_grid", ctypes.c_int32), ("order_budget_mib", ctypes.c_int32),
+                ("shape", ctypes.c_int32)]
+
+
+# workgroup shapes of the deposit (radio_tuning.shape): cells per tile, particles
+# per batch, segments per run
+SHAPES = {0: (16, 16, 16), 1: (8, 32, 16), 2: (16, 16, 8)}
+_TUNING_FIELDS = ("target_blocks", "items_per_workgroup", "max_grid", "order_budget_mib", "shape")
 
 
 class _Stats(ctypes.Structure):
@@ -390,18 +397,17 @@ def deposit_batch(detectors: Sequence[Detector], chunks: Sequence[Chunk], stream
 def get_tuning() -> dict:
     t = _Tuning()
     _check(_lib().radio_get_tuning(ctypes.byref(t)), "radio_get_tuning")
-    return {"target_blocks": int(t.target_blocks), "items_per_workgroup": int(t.items_per_workgroup),
-            "max_grid": int(t.max_grid), "order_budget_mib": int(t.order_budget_mib)}
+    return {k: int(getattr(t, k)) for k in _TUNING_FIELDS}
 
 
 def set_tuning(target_blocks: Optional[int] = None, items_per_workgroup: Optional[int] = None,
-               max_grid: Optional[int] = None, order_budget_mib: Optional[int] = None) -> None:
+               max_grid: Optional[int] = None, order_budget_mib: Optional[int] = None,
+               shape: Optional[int] = None) -> None:
     """Set the launch tunables (radio_tuning); unnamed ones keep their values."""
     cur = get_tuning()
     new = {"target_blocks": target_blocks, "items_per_workgroup": items_per_workgroup,
-           "max_grid": max_grid, "order_budget_mib": order_budget_mib}
-    t = _Tuning(*[int(new[k] if new[k] is not None else cur[k])
-                  for k in ("target_blocks", "items_per_workgroup", "max_grid", "order_budget_mib")])
+           "max_grid": max_grid, "order_budget_mib": order_budget_mib, "shape": shape}
+    t = _Tuning(*[int(new[k] if new[k] is not None else cur[k]) for k in _TUNING_FIELDS])
     _check(_lib().radio_set_tuning(ctypes.byref(t)), "radio_set_tuning")
 
 

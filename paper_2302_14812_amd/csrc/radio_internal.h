@@ -40,19 +40,36 @@ inline size_t rec_bytes(int mode)
     return mode == kModeF64 ? sizeof(RecF64) : sizeof(RecMix);
 }
 
-// workgroup shape of the deposit
-#ifndef RADIO_TILE_CELLS
-#define RADIO_TILE_CELLS 16
-#endif
-#ifndef RADIO_RUN_L
-#define RADIO_RUN_L 16
-#endif
-constexpr int kTileCells = RADIO_TILE_CELLS;            // cells per workgroup
+// Workgroup shapes of the deposit: 256 threads, a tile of `cells` detector cells,
+// 256 / cells particle lanes per cell (the particles of one staged batch), runs of
+// `run` segments.  Shape 0 is the default; the others are compiled for the
+// default detector options only, and the autotuner picks among them.
 constexpr int kDepositThreads = 256;
-constexpr int kGroups = kDepositThreads / kTileCells;   // particle lanes per cell
-constexpr int kRunL = RADIO_RUN_L;                      // segments per run
-static_assert(kGroups * kTileCells == kDepositThreads && (kGroups & (kGroups - 1)) == 0,
-              "tile shape");
+struct TileShape {
+    int cells;  // cells per tile
+    int run;    // segments per run
+};
+constexpr int kShapes = 3;
+constexpr TileShape kShapeTable[kShapes] = {{16, 16}, {8, 16}, {16, 8}};
+constexpr int shape_cells(int s) { return kShapeTable[s].cells; }
+constexpr int shape_groups(int s) { return kDepositThreads / kShapeTable[s].cells; }
+constexpr int shape_run(int s) { return kShapeTable[s].run; }
+constexpr bool shapes_valid()
+{
+    for (int s = 0; s < kShapes; ++s) {
+        const int c = shape_cells(s), g = shape_groups(s);
+        if (c * g != kDepositThreads || (g & (g - 1)) != 0 || (c & (c - 1)) != 0 || g < 4 ||
+            g > 32 || shape_run(s) % 8 != 0)
+            return false;
+    }
+    return true;
+}
+static_assert(shapes_valid(), "tile shapes");
+// the default shape's constants (shape 0)
+constexpr int kTileCells = shape_cells(0);
+constexpr int kGroups = shape_groups(0);
+constexpr int kRunL = shape_run(0);
+constexpr int kMaxGroups = 32;                          // particles per batch, any shape
 constexpr int kRingMargin = 2;                          // ring slots kept below a batch's start
 constexpr int kXcds = 8;                                // accelerator dies sharing one L2 each
 
@@ -68,13 +85,13 @@ constexpr int kXcds = 8;                                // accelerator dies shar
 #ifndef RADIO_RING_LARGE
 #define RADIO_RING_LARGE 64
 #endif
-// segments a large-ring workgroup stages per batch (a divisor of kRunL)
-#ifndef RADIO_LARGE_SUBRUN
-#define RADIO_LARGE_SUBRUN 16
+// parts a large-ring workgroup stages each run in (1: whole runs)
+#ifndef RADIO_LARGE_SUBRUNS
+#define RADIO_LARGE_SUBRUNS 1
 #endif
 constexpr int kRingSmall = RADIO_RING_SMALL;
 constexpr int kRingLarge = RADIO_RING_LARGE;
-constexpr int kLargeSubRun = RADIO_LARGE_SUBRUN;
+constexpr int kLargeParts = RADIO_LARGE_SUBRUNS;
 
 // One (detector, chunk) deposit as the kernels see it.  Sizes are 64-bit; the
 // host runtime has validated every pointer and size before filling this in.
@@ -105,12 +122,15 @@ struct DepositJob {
     int64_t slot_div;               // 1: the double slot coordinate divides (the divisor
                                     // fails the check of slot_quotient_corrects)
     double inv_c, c;
+    // workgroup shape (kShapeTable): its index, cells per tile, particles per batch
+    // (groups) and segments per run
+    int32_t shape, tile_cells, groups, run_l;
     // work decomposition, filled by plan_job()
-    int64_t n_tiles;                // tiles of kTileCells cells
-    int64_t n_runs;                 // runs of kRunL segments
+    int64_t n_tiles;                // tiles of tile_cells cells
+    int64_t n_runs;                 // runs of run_l segments
     int64_t runs_per_split;         // runs per work item
     int64_t n_splits;               // run ranges per tile
-    int64_t batches_per_part;       // batches of kGroups particles per work item
+    int64_t batches_per_part;       // batches of `groups` particles per work item
     int64_t n_parts;                // particle ranges per tile and run range
     int64_t runs_per_group;         // runs sharing one particle order per tile (a power of 2)
     int64_t group_shift;            // log2(runs_per_group)
@@ -126,11 +146,13 @@ struct WorkItem {
 };
 
 // Work items are kept short (a run, or the few runs that make at least this
-// many batches of kGroups particles): workgroups running at the same time then
+// many batches of particles): workgroups running at the same time then
 // stream the records of few runs, which stay in cache for the many tiles that
 // read them.
 constexpr int64_t kMinItemBatches = 64;
 
+// Set the job's workgroup shape (its tile, batch and run sizes).
+void set_shape(DepositJob& job, int shape);
 // Split the runs of a job into work items: until tiles x splits reaches
 // target_blocks when it is positive, else into short items (a run or a few)
 // while at least `capacity` items (the workgroups resident at once) remain;
@@ -149,9 +171,12 @@ int64_t max_order_groups(const DepositJob& job, size_t rec_bytes, int64_t budget
 void set_groups(DepositJob& job, int64_t max_groups);
 // Runs per order group that a deposit keeps to, by depositing a longer chunk
 // in time slices whose orders fit the budget; particles below which a chunk
-// keeps a single order (16 batches).
+// keeps a single order (16 batches of the job's shape).
 constexpr int64_t kRunsPerGroup = 2;
-constexpr int64_t kMinGroupParticles = 16 * kGroups;
+inline int64_t min_group_particles(const DepositJob& job)
+{
+    return 16 * (int64_t)job.groups;
+}
 
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
@@ -159,11 +184,16 @@ hipError_t launch_kinematics(const DepositJob& job, int mode, hipStream_t s);
 hipError_t launch_order(const DepositJob& job, hipStream_t s);
 hipError_t launch_ring_choice(const DepositJob& job, int mode, hipStream_t s);
 hipError_t launch_deposit(const DepositJob& job, int mode, int64_t max_grid, hipStream_t s);
-// Deposit kernel variants: v = mode + 3 * (G + 4 * hold), G = far + 2 * potentials.
-constexpr int kKernelVariants = 36;
+// Deposit kernel variants: for shape 0, v = mode + 3 * (G + 4 * hold) with
+// G = far + 2 * potentials (36); for the other shapes, the default options only:
+// v = 36 + 3 * (shape - 1) + mode.
+constexpr int kOptionVariants = 36;
+constexpr int kKernelVariants = kOptionVariants + 3 * (kShapes - 1);
 inline int kernel_variant(int mode, const DepositJob& J)
 {
     const int G = (J.far ? 1 : 0) + (J.potentials ? 2 : 0);
+    if (J.shape != 0)
+        return (G == 0 && J.hold == 0) ? kOptionVariants + 3 * (J.shape - 1) + mode : -1;
     return mode + 3 * (G + 4 * (int)J.hold);
 }
 // next: two work counters (small-ring and large-ring workgroups)

@@ -919,7 +919,7 @@ constexpr int kOrderBins = 4096;
 
 __global__ __launch_bounds__(256) void order_kernel(const double* __restrict__ x, int64_t n_p,
                                                     int64_t n_s, int64_t xs_stride,
-                                                    int64_t n_tiles,
+                                                    int64_t n_tiles, int64_t tile_cells,
                                                     int64_t steps_per_group,
                                                     const double* __restrict__ cells, int64_t n_c,
                                                     double inv_c, double inv_dt_det,
@@ -933,8 +933,8 @@ __global__ __launch_bounds__(256) void order_kernel(const double* __restrict__ x
     const int64_t group = blockIdx.x / n_tiles;
     // the group's middle state
     const int64_t s_key = min(n_s, group * steps_per_group + steps_per_group / 2);
-    const int64_t c0 = tile * kTileCells;
-    const int64_t c1 = min(c0 + (int64_t)kTileCells, n_c);
+    const int64_t c0 = tile * tile_cells;
+    const int64_t c1 = min(c0 + tile_cells, n_c);
     if (tid < 3) {
         double s = 0.0;
         for (int64_t c = c0; c < c1; ++c)
@@ -1009,7 +1009,6 @@ __global__ __launch_bounds__(256) void order_kernel(const double* __restrict__ x
 // and counts the slots a lane would emit outside it.  Above kRingBypassLimit
 // such emissions per interaction the tile takes the large ring.  Only speed
 // depends on this choice: emissions outside a ring go to HBM directly.
-constexpr int kChoiceBatches = 8;           // sampled batches per sampled run
 constexpr double kRingBypassLimit = 0.05;   // emissions to HBM per interaction
 
 __global__ __launch_bounds__(256) void ring_choice_kernel(const char* __restrict__ recs,
@@ -1022,31 +1021,34 @@ __global__ __launch_bounds__(256) void ring_choice_kernel(const char* __restrict
                                                           int64_t n_runs, double t_first,
                                                           int64_t s0, double dt, double t0,
                                                           double inv_dt_det, double inv_c,
-                                                          int64_t n_t, uint8_t* __restrict__ sel)
+                                                          int64_t n_t, int tile_cells, int groups,
+                                                          int run_l, uint8_t* __restrict__ sel)
 {
-    constexpr int kSamples = 2 * kChoiceBatches;
-    static_assert(kSamples * kGroups <= 256, "one thread per sampled particle");
-    __shared__ int start[kSamples];
+    // one thread per sampled particle: 256 / groups sampled batches, half of them
+    // in the first run and half in the middle one
+    const int n_samples = 256 / groups;
+    const int kChoiceBatches = n_samples / 2;
+    __shared__ int start[64];
     __shared__ unsigned out_count, segs;
     const int tid = threadIdx.x;
     const int64_t tile = blockIdx.x;
-    const int64_t c0 = tile * kTileCells;
-    if (tid < kSamples)
+    const int64_t c0 = tile * tile_cells;
+    if (tid < n_samples)
         start[tid] = INT_MAX;
     if (tid == 0) {
         out_count = 0u;
         segs = 0u;
     }
-    const int smp = tid / kGroups;  // sampled batch
-    const int gg = tid % kGroups;   // particle within it
+    const int smp = tid / groups;  // sampled batch
+    const int gg = tid % groups;   // particle within it
     const int64_t n_states = n_s + 1;
-    const int64_t n_batches = (n_p + kGroups - 1) / kGroups;
+    const int64_t n_batches = (n_p + groups - 1) / groups;
     const int64_t run = (smp < kChoiceBatches) ? 0 : n_runs / 2;
     const int64_t bt = (2 * (int64_t)(smp % kChoiceBatches) + 1) * n_batches / (2 * kChoiceBatches);
-    const int64_t pi = bt * kGroups + gg;
-    const int64_t s_a = run * kRunL;
-    const int len = (int)min((int64_t)kRunL, n_s - s_a);
-    const bool on = smp < kSamples && pi < n_p && len > 0;
+    const int64_t pi = bt * groups + gg;
+    const int64_t s_a = run * run_l;
+    const int len = (int)min((int64_t)run_l, n_s - s_a);
+    const bool on = smp < n_samples && pi < n_p && len > 0;
     const double* xc = cells + 3 * c0;
     const double* fc = far ? far + 4 * c0 : nullptr;
     const int32_t* order = perm + ((run / runs_per_group) * n_tiles + tile) * n_p;  // once a thread
@@ -1103,28 +1105,28 @@ struct ModeTypes {
     using Rec = typename std::conditional<MIX, RecMix, RecF64>::type;  // staged state record
 };
 
-// Segments a workgroup stages per batch: a whole run with the small ring, a
-// part of it with the large ring (tiles whose arrivals cross a slot every
-// segment or two), so that the large ring's span and its LDS stay small.
-template <int R>
-constexpr int kSubRun = R == kRingLarge ? kLargeSubRun : kRunL;
-static_assert(kRunL % kSubRun<kRingLarge> == 0 && kRunL % kSubRun<kRingSmall> == 0,
-              "a run is a whole number of staged parts");
+// Segments a workgroup of shape SH stages per batch: a whole run with the small
+// ring, a part of it (kLargeParts parts) with the large ring.
+template <int R, int SH>
+constexpr int kSubRun = R == kRingLarge ? shape_run(SH) / kLargeParts : shape_run(SH);
 
-// LDS of one deposit workgroup with rings of R slots
-template <int M, int R>
+// LDS of one deposit workgroup of shape SH with rings of R slots
+template <int M, int R, int SH>
 struct DepositShared {
     using Acc = typename ModeTypes<M>::Acc;
-    // one cell's ring, padded by one word so that the rings of the kTileCells
+    static constexpr int TC = shape_cells(SH);   // cells per tile
+    static constexpr int GR = shape_groups(SH);  // particles per batch
+    // one cell's ring, padded by one word so that the rings of the tile's
     // cells, which one instruction updates together, start in different banks
     static constexpr int kStride = R * CellSink<Acc, R>::W + 1;
-    static constexpr int L = kSubRun<R>;
-    typename ModeTypes<M>::Rec rec[kGroups][L + 1];  // staged batch: L segments per group
-    double sq[kGroups];                 // its charges
+    static constexpr int L = kSubRun<R, SH>;
+    static_assert(shape_run(SH) % L == 0, "a run is a whole number of staged parts");
+    typename ModeTypes<M>::Rec rec[GR][L + 1];  // staged batch: L segments per group
+    double sq[GR];                      // its charges
     double tk[L + 1];                   // its states' time arguments (the same for every lane)
-    double ring[kTileCells * kStride];  // per-cell slot rings
-    int nb[2][kTileCells];              // per cell: lowest start slot of a coming batch
-    int ord[2][kGroups];                // particles of the staged rows, per batch parity
+    double ring[TC * kStride];          // per-cell slot rings
+    int nb[2][TC];                      // per cell: lowest start slot of a coming batch
+    int ord[2][GR];                     // particles of the staged rows, per batch parity
     unsigned long long cnt[3];          // clipped, nonmonotone, bypassed
 };
 
@@ -1142,10 +1144,13 @@ struct DepositShared {
 // DIV: the double slot coordinate divides (a divisor that fails the host check
 // of canon_slot's corrections); a compile-time choice, so that the state loop
 // carries no branch for it.
-template <int M, int R, int G, int HOLD, bool DIV>
+template <int M, int R, int G, int HOLD, int SH, bool DIV>
 __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, int64_t split,
-                                             int64_t part, DepositShared<M, R>& sh)
+                                             int64_t part, DepositShared<M, R, SH>& sh)
 {
+    constexpr int kTileCells = shape_cells(SH);  // this shape's tile, batch and run
+    constexpr int kGroups = shape_groups(SH);
+    constexpr int kRunL = shape_run(SH);
     constexpr bool FAR = (G & 1) != 0;
     constexpr bool POT = (G & 2) != 0;
     constexpr bool MIX = ModeTypes<M>::MIX;
@@ -1198,7 +1203,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         else
             return MIX ? slot_coord_mixed(xc, st.x, tk, K) : slot_coord_fp64(xc, st.x, tk, K);
     };
-    RADIO_LDS double* my_ring = (RADIO_LDS double*)&sh.ring[cl * DepositShared<M, R>::kStride];
+    RADIO_LDS double* my_ring = (RADIO_LDS double*)&sh.ring[cl * DepositShared<M, R, SH>::kStride];
     RADIO_LDS int* nb = (RADIO_LDS int*)&sh.nb[0][0];
     for (int i = g; i < R * RW; i += kGroups)
         my_ring[i] = 0.0;
@@ -1219,7 +1224,7 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
     const int64_t n_batches = bt_end - bt_begin;  // per run
     // The item's runs [rb_begin, rb_end), staged in parts of L segments: part
     // rb (states rb * L ... rb * L + L) of run rb / NS.
-    constexpr int L = kSubRun<R>;
+    constexpr int L = kSubRun<R, SH>;
     constexpr int NS = kRunL / L;
     const int64_t rb_begin = split * J.runs_per_split * NS;
     const int64_t rb_end =
@@ -1538,17 +1543,17 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
 
 // deposit_item with the slot-coordinate form of the job (the single-precision
 // modes have one)
-template <int M, int R, int G, int HOLD>
+template <int M, int R, int G, int HOLD, int SH>
 __device__ __forceinline__ void deposit_item_of(const DepositJob& J, int64_t tile, int64_t split,
-                                                int64_t part, DepositShared<M, R>& sh)
+                                                int64_t part, DepositShared<M, R, SH>& sh)
 {
     if constexpr (M == kModeF64) {
         if (J.slot_div)
-            deposit_item<M, R, G, HOLD, true>(J, tile, split, part, sh);
+            deposit_item<M, R, G, HOLD, SH, true>(J, tile, split, part, sh);
         else
-            deposit_item<M, R, G, HOLD, false>(J, tile, split, part, sh);
+            deposit_item<M, R, G, HOLD, SH, false>(J, tile, split, part, sh);
     } else {
-        deposit_item<M, R, G, HOLD, false>(J, tile, split, part, sh);
+        deposit_item<M, R, G, HOLD, SH, false>(J, tile, split, part, sh);
     }
 }
 
@@ -1566,20 +1571,23 @@ __device__ __forceinline__ void deposit_item_of(const DepositJob& J, int64_t til
 // forms of the slot coordinate compiled in (see deposit_item_of) the default
 // and previous-state kernels go a few registers over 128 by themselves and fit
 // them on request (the previous-state hold with two spilled words), the linear
-// hold would spill heavily and is left alone.
-template <int M, int R, int G, int HOLD>
+// hold would spill heavily and is left alone.  The other shapes: the 16-cell
+// tile with runs of 8 segments has the LDS for five (single) or four (double)
+// waves and is asked for them; the 8-cell tile's LDS allows three.
+template <int M, int R, int G, int HOLD, int SH>
 constexpr int kMinWaves =
     R != kRingSmall                      ? 1
-    : M != kModeF64 && (G != 0 || HOLD != 0) ? 5
+    : SH == 1                            ? 1
+    : M != kModeF64 && (G != 0 || HOLD != 0 || SH == 2) ? 5
     : M == kModeF64 && HOLD != 2         ? 4
                                          : 1;
 
-template <int M, int R, int G, int HOLD>
+template <int M, int R, int G, int HOLD, int SH>
 __global__ __launch_bounds__(kDepositThreads)
-__attribute__((amdgpu_waves_per_eu(kMinWaves<M, R, G, HOLD>))) void deposit_kernel(
+__attribute__((amdgpu_waves_per_eu(kMinWaves<M, R, G, HOLD, SH>))) void deposit_kernel(
     DepositJob J, int64_t item0)
 {
-    __shared__ __align__(16) DepositShared<M, R> sh;
+    __shared__ __align__(16) DepositShared<M, R, SH> sh;
     // Workgroups are dealt round-robin over the XCDs; give each XCD a contiguous
     // range of items, so that the workgroups resident on one XCD work on
     // neighbouring tiles of the same runs, whose records and particle orders
@@ -1593,7 +1601,7 @@ __attribute__((amdgpu_waves_per_eu(kMinWaves<M, R, G, HOLD>))) void deposit_kern
     if (gptr(J.ring_sel)[tile] != (R == kRingLarge ? 1 : 0))
         return;
     const int64_t rest = logical / J.n_tiles;  // split-major, then part
-    deposit_item_of<M, R, G, HOLD>(J, tile, rest / J.n_parts, rest % J.n_parts, sh);
+    deposit_item_of<M, R, G, HOLD, SH>(J, tile, rest / J.n_parts, rest % J.n_parts, sh);
 }
 
 // Persistent workgroups for many independent deposits: each takes the next work
@@ -1605,20 +1613,20 @@ __attribute__((amdgpu_waves_per_eu(kMinWaves<M, R, G, HOLD>))) void deposit_kern
 // small ring goes over 96 VGPRs by itself, and five waves per SIMD, with a few
 // spilled words, make the 64-set batched benchmark 1.2% faster; the double
 // small-ring variants are asked for the four waves their LDS allows.)
-template <int M, int R, int G, int HOLD>
-constexpr int kPersistentWaves = R != kRingSmall                      ? 1
+template <int M, int R, int G, int HOLD, int SH>
+constexpr int kPersistentWaves = R != kRingSmall || SH == 1           ? 1
                                  : M != kModeF64                      ? 5
                                  : HOLD != 2                          ? 4
                                                                       : 1;
 
-template <int M, int R, int G, int HOLD>
+template <int M, int R, int G, int HOLD, int SH>
 __global__ __launch_bounds__(kDepositThreads)
-__attribute__((amdgpu_waves_per_eu(kPersistentWaves<M, R, G, HOLD>))) void
+__attribute__((amdgpu_waves_per_eu(kPersistentWaves<M, R, G, HOLD, SH>))) void
 deposit_persistent_kernel(
     const DepositJob* __restrict__ jobs, const WorkItem* __restrict__ items, int64_t n_items,
     unsigned long long* __restrict__ next)
 {
-    __shared__ __align__(16) DepositShared<M, R> sh;
+    __shared__ __align__(16) DepositShared<M, R, SH> sh;
     __shared__ int64_t cur;
     for (;;) {
         __syncthreads();  // everyone has read the previous `cur`
@@ -1632,7 +1640,7 @@ deposit_persistent_kernel(
         const DepositJob J = jobs[w.job];
         if (gptr(J.ring_sel)[w.tile] != (R == kRingLarge ? 1 : 0))
             continue;
-        deposit_item_of<M, R, G, HOLD>(J, w.tile, w.split, w.part, sh);
+        deposit_item_of<M, R, G, HOLD, SH>(J, w.tile, w.split, w.part, sh);
     }
 }
 
@@ -1722,10 +1730,18 @@ __global__ void slot_coord_kernel(const double* cells, const double* pts, const 
 
 constexpr int64_t kMaxDepositGrid = int64_t(1) << 22;  // workgroups of one deposit launch
 
+void set_shape(DepositJob& job, int shape)
+{
+    job.shape = shape;
+    job.tile_cells = shape_cells(shape);
+    job.groups = shape_groups(shape);
+    job.run_l = shape_run(shape);
+}
+
 void plan_job(DepositJob& job, int target_blocks, int64_t capacity)
 {
-    job.n_runs = (job.n_s + kRunL - 1) / kRunL;
-    job.n_tiles = (job.n_c + kTileCells - 1) / kTileCells;
+    job.n_runs = (job.n_s + job.run_l - 1) / job.run_l;
+    job.n_tiles = (job.n_c + job.tile_cells - 1) / job.tile_cells;
     int64_t splits = 1;
     if (target_blocks > 0) {
         splits = (target_blocks + job.n_tiles - 1) / job.n_tiles;
@@ -1733,7 +1749,7 @@ void plan_job(DepositJob& job, int target_blocks, int64_t capacity)
         // short items (at least kMinItemBatches batches, so that an item's
         // set-up and final ring flush stay small), unless that leaves fewer
         // items than the device holds at once
-        const int64_t n_batches = std::max<int64_t>((job.n_p + kGroups - 1) / kGroups, 1);
+        const int64_t n_batches = std::max<int64_t>((job.n_p + job.groups - 1) / job.groups, 1);
         const int64_t rps = std::max<int64_t>(1, (kMinItemBatches + n_batches - 1) / n_batches);
         splits = (job.n_runs + rps - 1) / rps;
         if (job.n_tiles * splits < capacity)
@@ -1746,7 +1762,7 @@ void plan_job(DepositJob& job, int target_blocks, int64_t capacity)
     job.runs_per_split = (job.n_runs + splits - 1) / splits;
     job.n_splits = (job.n_runs + job.runs_per_split - 1) / job.runs_per_split;
     // few runs (a short chunk): ranges of the sorted particles as well
-    const int64_t n_batches = std::max<int64_t>((job.n_p + kGroups - 1) / kGroups, 1);
+    const int64_t n_batches = std::max<int64_t>((job.n_p + job.groups - 1) / job.groups, 1);
     int64_t parts = 1;
     const int64_t items = job.n_tiles * job.n_splits;
     if (target_blocks <= 0 && items < 2 * capacity) {
@@ -1770,7 +1786,7 @@ void set_groups(DepositJob& job, int64_t max_groups)
 {
     int64_t groups = std::min(job.n_runs, std::max<int64_t>(1, max_groups));
     // a few batches gain nothing from re-sorting, and each order costs a histogram
-    if (job.n_p < kMinGroupParticles)
+    if (job.n_p < min_group_particles(job))
         groups = 1;
     groups = std::max<int64_t>(1, groups);
     const int64_t want = (job.n_runs + groups - 1) / groups;
@@ -1783,7 +1799,7 @@ void set_groups(DepositJob& job, int64_t max_groups)
 
 void set_parts(DepositJob& job, int64_t parts)
 {
-    const int64_t n_batches = std::max<int64_t>((job.n_p + kGroups - 1) / kGroups, 1);
+    const int64_t n_batches = std::max<int64_t>((job.n_p + job.groups - 1) / job.groups, 1);
     parts = std::max<int64_t>(1, std::min<int64_t>(parts, n_batches));
     job.batches_per_part = (n_batches + parts - 1) / parts;
     job.n_parts = (n_batches + job.batches_per_part - 1) / job.batches_per_part;
@@ -1830,7 +1846,7 @@ hipError_t launch_order(const DepositJob& job, hipStream_t s)
 {
     hipLaunchKernelGGL(order_kernel, dim3((unsigned)(job.n_tiles * job.n_groups)), dim3(256), 0, s,
                        job.x, job.n_p, job.n_s, job.xs_stride, job.n_tiles,
-                       job.runs_per_group * kRunL,
+                       (int64_t)job.tile_cells, job.runs_per_group * job.run_l,
                        job.cells, job.n_c, job.inv_c, job.inv_dt_det, job.perm);
     return hipGetLastError();
 }
@@ -1844,29 +1860,35 @@ hipError_t launch_ring_choice(const DepositJob& job, int mode, hipStream_t s)
                        job.perm, job.n_tiles, job.runs_per_group, job.cells, job.far, job.n_c,
                        job.n_p, job.n_s, job.n_runs,
                        job.t_first,
-                       job.s0, job.dt, job.t0, job.inv_dt_det, job.inv_c, job.n_t, job.ring_sel);
+                       job.s0, job.dt, job.t0, job.inv_dt_det, job.inv_c, job.n_t,
+                       (int)job.tile_cells, (int)job.groups, (int)job.run_l, job.ring_sel);
     return hipGetLastError();
 }
 
-// kernel variants: precision mode x ring size x geometry/quantity (far field,
-// potentials) x hold rule
-template <int M, int G, int HOLD>
-static void launch_deposit_v(const DepositJob& job, dim3 grid, hipStream_t s)
-{
-    // more items than one launch holds run in several launches
-    const int64_t n_items = job.n_tiles * job.n_splits * job.n_parts;
-    for (int64_t item0 = 0; item0 < n_items; item0 += grid.x)
-        hipLaunchKernelGGL((deposit_kernel<M, kRingSmall, G, HOLD>), grid, dim3(kDepositThreads),
-                           0, s, job, item0);
-    for (int64_t item0 = 0; item0 < n_items; item0 += grid.x)
-        hipLaunchKernelGGL((deposit_kernel<M, kRingLarge, G, HOLD>), grid, dim3(kDepositThreads),
-                           0, s, job, item0);
-}
+// kernel variants (kernel_variant): precision mode x geometry/quantity (far
+// field, potentials) x hold rule for the default shape; precision mode for the
+// other shapes with the default options; each with both ring sizes
+template <int V>
+struct VariantOf {
+    static constexpr bool kOpt = V < kOptionVariants;
+    static constexpr int M = kOpt ? V % 3 : (V - kOptionVariants) % 3;
+    static constexpr int G = kOpt ? (V / 3) % 4 : 0;
+    static constexpr int HOLD = kOpt ? V / 12 : 0;
+    static constexpr int SH = kOpt ? 0 : 1 + (V - kOptionVariants) / 3;
+};
 
 template <int V>
 static void launch_deposit_index(const DepositJob& job, dim3 grid, hipStream_t s)
 {
-    launch_deposit_v<V % 3, (V / 3) % 4, V / 12>(job, grid, s);
+    using K = VariantOf<V>;
+    // more items than one launch holds run in several launches
+    const int64_t n_items = job.n_tiles * job.n_splits * job.n_parts;
+    for (int64_t item0 = 0; item0 < n_items; item0 += grid.x)
+        hipLaunchKernelGGL((deposit_kernel<K::M, kRingSmall, K::G, K::HOLD, K::SH>), grid,
+                           dim3(kDepositThreads), 0, s, job, item0);
+    for (int64_t item0 = 0; item0 < n_items; item0 += grid.x)
+        hipLaunchKernelGGL((deposit_kernel<K::M, kRingLarge, K::G, K::HOLD, K::SH>), grid,
+                           dim3(kDepositThreads), 0, s, job, item0);
 }
 
 template <int V>
@@ -1874,11 +1896,11 @@ static void launch_persistent_index(const DepositJob* jobs, const WorkItem* item
                                     int64_t n_items, unsigned long long* next, int blocks_small,
                                     int blocks_large, hipStream_t s)
 {
-    constexpr int M = V % 3, G = (V / 3) % 4, HOLD = V / 12;
-    hipLaunchKernelGGL((deposit_persistent_kernel<M, kRingSmall, G, HOLD>),
+    using K = VariantOf<V>;
+    hipLaunchKernelGGL((deposit_persistent_kernel<K::M, kRingSmall, K::G, K::HOLD, K::SH>),
                        dim3((unsigned)blocks_small), dim3(kDepositThreads), 0, s, jobs, items,
                        n_items, next);
-    hipLaunchKernelGGL((deposit_persistent_kernel<M, kRingLarge, G, HOLD>),
+    hipLaunchKernelGGL((deposit_persistent_kernel<K::M, kRingLarge, K::G, K::HOLD, K::SH>),
                        dim3((unsigned)blocks_large), dim3(kDepositThreads), 0, s, jobs, items,
                        n_items, next + 1);
 }
@@ -1887,10 +1909,13 @@ template <int V>
 static int blocks_per_cu_index(bool large_ring)
 {
     int n = 0;
-    constexpr int M = V % 3, G = (V / 3) % 4, HOLD = V / 12;
+    using K = VariantOf<V>;
     const void* f =
-        large_ring ? reinterpret_cast<const void*>(deposit_persistent_kernel<M, kRingLarge, G, HOLD>)
-                   : reinterpret_cast<const void*>(deposit_persistent_kernel<M, kRingSmall, G, HOLD>);
+        large_ring
+            ? reinterpret_cast<const void*>(
+                  deposit_persistent_kernel<K::M, kRingLarge, K::G, K::HOLD, K::SH>)
+            : reinterpret_cast<const void*>(
+                  deposit_persistent_kernel<K::M, kRingSmall, K::G, K::HOLD, K::SH>);
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kDepositThreads, 0);
     return (e == hipSuccess && n > 0) ? n : 1;
 }

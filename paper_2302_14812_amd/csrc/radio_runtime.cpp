@@ -54,7 +54,7 @@ namespace {
 
 // launch tunables (radio_set_tuning)
 std::mutex g_tuning_mu;
-radio_tuning g_tuning = {0, 4, 1 << 22, 0};
+radio_tuning g_tuning = {0, 4, 1 << 22, 0, 0};
 
 radio_tuning current_tuning()
 {
@@ -325,6 +325,10 @@ radio::DepositJob make_job(const radio_detector* det, const radio_chunk* k)
     J.slot_div = radio::slot_quotient_corrects(det->dt_det) ? 0 : 1;
     J.inv_c = 1.0 / det->c;
     J.c = det->c;
+    // the tuned workgroup shape, for detectors with the default options (the
+    // other shapes are compiled for those only)
+    const int shape = current_tuning().shape;
+    radio::set_shape(J, (det->options == 0 && shape > 0 && shape < radio::kShapes) ? shape : 0);
     const int per_cu =
         radio::persistent_blocks_per_cu(radio::kernel_variant(det->precision, J), false);
     radio::plan_job(J, current_tuning().target_blocks, (int64_t)det->n_cus * per_cu);
@@ -340,8 +344,8 @@ radio::DepositJob slice_job(const radio_detector* det, const radio::DepositJob& 
                             int64_t r_b, int64_t max_groups)
 {
     radio::DepositJob J = W;
-    const int64_t a = r_a * radio::kRunL;
-    const int64_t b = std::min(r_b * radio::kRunL, W.n_s);
+    const int64_t a = r_a * W.run_l;
+    const int64_t b = std::min(r_b * W.run_l, W.n_s);
     J.x = W.x + a * W.n_p;
     J.u = W.u + a * W.n_p;
     J.n_s = b - a;
@@ -409,7 +413,7 @@ SlicePlan plan_slices(const radio_detector* det, const radio_chunk* k)
     P.W = make_job(det, k);
     P.max_groups = radio::max_order_groups(P.W, radio::rec_bytes(det->precision),
                                            current_tuning().order_budget_mib);
-    const bool slice = P.W.n_p >= radio::kMinGroupParticles &&
+    const bool slice = P.W.n_p >= radio::min_group_particles(P.W) &&
                        P.W.runs_per_group > radio::kRunsPerGroup;
     const int64_t slice_runs = slice ? P.max_groups * radio::kRunsPerGroup : P.W.n_runs;
     P.n_slices = (P.W.n_runs + slice_runs - 1) / slice_runs;
@@ -507,9 +511,10 @@ constexpr size_t align256(size_t n)
 // (with their one-state overlap), one order per kRunsPerGroup runs, ring choices.
 size_t slice_scratch_bytes(const radio::DepositJob& W, int precision, int64_t runs)
 {
-    const int64_t states = std::min(runs * radio::kRunL, W.n_s) + 1;
-    const int64_t groups =
-        W.n_p < radio::kMinGroupParticles ? 1 : (runs + radio::kRunsPerGroup - 1) / radio::kRunsPerGroup;
+    const int64_t states = std::min(runs * W.run_l, W.n_s) + 1;
+    const int64_t groups = W.n_p < radio::min_group_particles(W)
+                               ? 1
+                               : (runs + radio::kRunsPerGroup - 1) / radio::kRunsPerGroup;
     return align256((size_t)(W.n_p * states) * radio::rec_bytes(precision)) +
            align256((size_t)(groups * W.n_tiles * W.n_p) * sizeof(int32_t)) +
            align256((size_t)W.n_tiles);
@@ -691,9 +696,9 @@ int enqueue_batch(radio_detector* const* dets, const radio_chunk* chunks, int n,
         ro += (size_t)(J.n_p * (J.n_s + 1)) * radio::rec_bytes(prec);
         po += (size_t)(J.n_groups * J.n_tiles * J.n_p);
         so += (size_t)J.n_tiles;
-        const double run_work = (double)radio::kTileCells * (double)J.n_p * (double)radio::kRunL;
+        const double run_work = (double)J.tile_cells * (double)J.n_p * (double)J.run_l;
         // items of similar work, and short (see kMinItemBatches)
-        const int64_t n_batches = (J.n_p + radio::kGroups - 1) / radio::kGroups;
+        const int64_t n_batches = (J.n_p + J.groups - 1) / J.groups;
         const int64_t rps_short = (radio::kMinItemBatches + n_batches - 1) / n_batches;
         int64_t rps = std::min<int64_t>((int64_t)std::ceil(item_work / run_work), rps_short);
         rps = std::max<int64_t>(1, std::min<int64_t>(rps, J.n_runs));
@@ -1007,7 +1012,7 @@ int radio_set_tuning(const radio_tuning* t)
 {
     if (!t || t->target_blocks < 0 || t->target_blocks > (1 << 24) || t->items_per_workgroup < 1 ||
         t->items_per_workgroup > 4096 || t->max_grid < 1 || t->max_grid > (1 << 22) ||
-        t->order_budget_mib < 0)
+        t->order_budget_mib < 0 || t->shape < 0 || t->shape >= radio::kShapes)
         return RADIO_EINVAL;
     std::lock_guard<std::mutex> lk(g_tuning_mu);
     g_tuning = *t;

@@ -10,9 +10,11 @@ flushed from the on-chip ring at the end of each deposit (a ring bypass adds to
 it directly as well), so each device slot receives at least K additions of the
 same values.  In exact arithmetic the result is K times one deposit's.
 
-- RADIO_MIXED (double accumulation) and RADIO_MIXED_TWOSUM (single-precision
-  (hi, lo) pairs with two-sum) both stay within 1e-9 of K times one deposit,
-  and within the 1e-5 bar of K times the oracle's deposit.
+- RADIO_MIXED (double accumulation) stays within 1e-12 of K times one deposit
+  and RADIO_MIXED_TWOSUM (single-precision (hi, lo) pairs with two-sum) within
+  1e-8 (the pair carries ~48 bits; its lo word sums in single precision, so its
+  own roundings add up to ~K |lo| 2^-24: 1.6e-9 measured), and both within the
+  1e-5 bar of K times the oracle's deposit.
 - Plain single-precision accumulation of the same K additions per slot,
   replayed on the host (each addition rounded to single precision, as a
   single-precision atomic add would), drifts by K x 2^-24 / 2 relative, about
@@ -82,10 +84,10 @@ def test_compensated_accumulation_holds_where_single_precision_drifts(radio):
     Et, Bt, stt = _repeat(radio, spec, dev, "mixed_twosum", K)
     assert stm["chunks"] == stt["chunks"] == K
     # double accumulation and compensated pairs against K times one deposit
-    for what, (E, B) in (("double", (Em, Bm)), ("compensated pairs", (Et, Bt))):
+    for what, (E, B), bar in (("double", (Em, Bm), 1e-12), ("compensated pairs", (Et, Bt), 1e-8)):
         e = max(rel_l2(E, K * E1), rel_l2(B, K * B1))
         print(f"[accumulation] {what}: {K} deposits vs {K} x one, relL2 {e:.3e}", flush=True)
-        assert e <= 1e-9, (what, e)
+        assert e <= bar, (what, e)
     # the same additions in plain single precision
     Ef, Bf = _fp32_replay(E1, K), _fp32_replay(B1, K)
     ef = max(rel_l2(Ef, K * E1), rel_l2(Bf, K * B1))

@@ -186,10 +186,12 @@ def test_batch_rejects_invalid_pairs_without_work(radio, sets):
 
 def test_tuning_roundtrip(radio):
     cur = radio.get_tuning()
-    radio.set_tuning(target_blocks=1024, items_per_workgroup=2)
+    radio.set_tuning(target_blocks=1024, items_per_workgroup=2, shape=2)
     assert radio.get_tuning() == {"target_blocks": 1024, "items_per_workgroup": 2,
                                   "max_grid": cur["max_grid"],
-                                  "order_budget_mib": cur["order_budget_mib"]}
+                                  "order_budget_mib": cur["order_budget_mib"], "shape": 2}
+    with pytest.raises(radio.RadioError):
+        radio.set_tuning(shape=len(radio.SHAPES))
     with pytest.raises(radio.RadioError):
         radio.set_tuning(order_budget_mib=-1)
     with pytest.raises(radio.RadioError):
@@ -212,17 +214,20 @@ def test_autotuner_picks_a_candidate_and_caches(radio, sets, tmp_path):
     before = radio.get_tuning()
     rb = autotune.tune_batch(specs, chunks, precision="fp64", candidates=(1, 4), repeats=1,
                              cache=cache)
-    assert rb["items_per_workgroup"] in (1, 4) and len(rb["timings_ms"]) == 2
+    # every shape timed at the current items per workgroup, then both candidates
+    assert rb["items_per_workgroup"] in (1, 4, before["items_per_workgroup"])
+    assert rb["shape"] in radio.SHAPES and len(rb["timings_ms"]) >= len(radio.SHAPES) + 1
     rs = autotune.tune_single(specs[0], chunks[0], precision="fp64", candidates=(256, 1024),
                               repeats=1, cache=cache)
-    assert rs["target_blocks"] in (256, 1024)
+    assert rs["target_blocks"] in (256, 1024) and rs["shape"] in radio.SHAPES
     assert radio.get_tuning() == before  # tuning restores the caller's settings
     path = str(tmp_path / "tune.json")
     autotune.save_cache(cache, path)
-    loaded = autotune.load_cache(path)
+    loaded = autotune.load_cache(path, shipped=False)
     assert loaded == json_roundtrip(cache)
     assert autotune.apply_batch(specs, chunks, cache=loaded)
-    assert radio.get_tuning()["items_per_workgroup"] == rb["items_per_workgroup"]
+    t = radio.get_tuning()
+    assert (t["items_per_workgroup"], t["shape"]) == (rb["items_per_workgroup"], rb["shape"])
     radio.set_tuning(**before)
 
 

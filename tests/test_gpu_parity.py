@@ -192,6 +192,62 @@ def test_parity_random_ragged(radio, precision, seed, n_p, n_s, n_side, n_t, cli
         assert cnt[0] > 0
 
 
+@pytest.mark.parametrize("shape", [1, 2])
+@PRECISIONS
+def test_workgroup_shapes_match_oracle(radio, precision, shape):
+    """The other workgroup shapes (8 cells x 32 particles x runs of 16; 16 cells x 16
+    particles x runs of 8) on ragged random, clipped, undulator and plasma-mirror
+    cases, single deposits and a batch, against the oracle; a detector with
+    options keeps the default shape."""
+    cur = radio.get_tuning()
+    cases = []
+    for seed, n_p, n_s, side, n_t, clip in ((1, 37, 77, (20, 15), 333, False),
+                                            (5, 33, 95, (17, 31), 200, True)):
+        chunk = W.random_chunk(n_p, n_s, seed=seed, dt=0.07, gamma_max=30.0, t_first=0.3 * seed)
+        cells = W.plane_cells([1.0, -2.0, 30.0], [1, 0.2, 0], [0, 1, 0.1], side[0], side[1],
+                              12.0, 9.0)
+        t0, dtd = _window(cells, chunk, n_t)
+        if clip:
+            t0 += 0.2 * n_t * dtd
+            dtd *= 0.6
+        cases.append((f"random seed={seed}", W.DetectorSpec(cells=cells, t0=t0, dt_det=dtd, n_t=n_t),
+                      chunk))
+    und = W.undulator_workload(n_particles=300, n_steps=200, n_side=24, n_t=512)
+    pm = W.plasma_mirror_workload(n_particles=400, n_steps=150, n_side=16, n_t=1024)
+    cases += [(und.name, und.detector, und.chunk), (pm.name, pm.detector, pm.chunk)]
+    try:
+        radio.set_tuning(shape=shape)
+        for name, spec, chunk in cases:
+            Eg, Bg, st = gpu_deposit(radio, spec, chunk, precision)
+            Eo, Bo, cnt = oracle_deposit(spec, chunk)
+            check_parity(Eg, Bg, Eo, Bo, TOLS[precision], f"shape {shape} {name} {precision}")
+            assert st["clipped"] == cnt[0] and st["nonmonotone"] == cnt[1]
+        # the same cases in one batch
+        import torch
+        dets = [radio.Detector.from_spec(spec, precision=precision) for _, spec, _ in cases]
+        radio.deposit_batch(dets, [radio.Chunk.from_numpy(c) for _, _, c in cases])
+        for d, (name, spec, chunk) in zip(dets, cases):
+            E, B = d.read()
+            torch.cuda.synchronize()
+            Eo, Bo, _ = oracle_deposit(spec, chunk)
+            check_parity(E.cpu().numpy(), B.cpu().numpy(), Eo, Bo, TOLS[precision],
+                         f"shape {shape} batch {name} {precision}")
+            d.close()
+        # a detector with options takes the default shape and stays correct
+        name, spec, chunk = cases[1]
+        det = radio.Detector.from_spec(spec, precision=precision, options=radio.HOLD_LINEAR)
+        det.deposit(radio.Chunk.from_numpy(chunk))
+        E, B = det.read()
+        torch.cuda.synchronize()
+        det.close()
+        Do = oracle.deposit_workload(spec, chunk, options=oracle.HOLD_LINEAR)
+        Eo, Bo = oracle.read(Do)
+        check_parity(E.cpu().numpy(), B.cpu().numpy(), Eo, Bo, TOLS[precision],
+                     f"shape {shape} with options (default shape) {precision}")
+    finally:
+        radio.set_tuning(**cur)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_deposit_in_several_launches(radio, precision):
     """Work items beyond one launch's grid (max_grid) run as further launches with
