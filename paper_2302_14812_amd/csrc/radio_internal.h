@@ -85,13 +85,14 @@ constexpr int kXcds = 8;                                // accelerator dies shar
 #ifndef RADIO_RING_LARGE
 #define RADIO_RING_LARGE 64
 #endif
-// parts a large-ring workgroup stages each run in (1: whole runs)
-#ifndef RADIO_LARGE_SUBRUNS
-#define RADIO_LARGE_SUBRUNS 1
+// segments a large-ring workgroup stages at most per batch (longer runs are
+// staged in parts of this length): what the large ring's span allows
+#ifndef RADIO_LARGE_STAGE
+#define RADIO_LARGE_STAGE 16
 #endif
 constexpr int kRingSmall = RADIO_RING_SMALL;
 constexpr int kRingLarge = RADIO_RING_LARGE;
-constexpr int kLargeParts = RADIO_LARGE_SUBRUNS;
+constexpr int kLargeStage = RADIO_LARGE_STAGE;
 
 // One (detector, chunk) deposit as the kernels see it.  Sizes are 64-bit; the
 // host runtime has validated every pointer and size before filling this in.

@@ -1106,9 +1106,11 @@ struct ModeTypes {
 };
 
 // Segments a workgroup of shape SH stages per batch: a whole run with the small
-// ring, a part of it (kLargeParts parts) with the large ring.
+// ring; with the large ring at most kLargeStage (a run of more is staged in
+// parts), because the arrivals of a batch must fit the ring's span.
 template <int R, int SH>
-constexpr int kSubRun = R == kRingLarge ? shape_run(SH) / kLargeParts : shape_run(SH);
+constexpr int kSubRun =
+    (R == kRingLarge && shape_run(SH) > kLargeStage) ? kLargeStage : shape_run(SH);
 
 // LDS of one deposit workgroup of shape SH with rings of R slots
 template <int M, int R, int SH>
