@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-launch leg (64 uneven sets, one persistent launch "
                          "vs 64 separate launches)")
+    ap.add_argument("--batch-scale", type=float, default=0.02,
+                    help="particle counts of the batched leg as a fraction of the recipe's")
     ap.add_argument("--no-serve", action="store_true", help="skip the streaming-service leg")
     ap.add_argument("--no-options", action="store_true",
                     help="skip the detector-options leg (far field, hold rules)")
@@ -147,13 +149,14 @@ def options_leg(radio, wl, chunk_dev, precision, steps, warmup):
     return out
 
 
-def batch_leg(radio, W, precision, steps, warmup):
-    """64 independent uneven sets: one persistent batched launch vs 64 launches."""
+def batch_leg(radio, W, precision, steps, warmup, scale=0.02):
+    """64 independent uneven sets of the batched-launch recipe (detectors of 32^2 to
+    256^2 cells with 256 to 4096 slots, 500-4000 steps, helical or planar motion),
+    particle counts times `scale`: one persistent batched launch vs 64 launches."""
     import torch
 
     from paper_2302_14812_amd import autotune
-    sets = W.batched_sets(n_sets=64, scale=0.02, sides=(32, 64, 128),
-                          n_t_choices=(256, 512, 1024, 2048))
+    sets = W.batched_sets(n_sets=64, scale=scale)
     chunks = [radio.Chunk.from_numpy(wl.chunk) for wl in sets]
     dets = [radio.Detector.from_spec(wl.detector, precision=precision) for wl in sets]
     total = sum(wl.interactions for wl in sets)
@@ -194,8 +197,10 @@ def batch_leg(radio, W, precision, steps, warmup):
     radio.set_tuning(**defaults)
     for d in dets:
         d.close()
-    return {"workload": "64 uneven sets (batched-launch recipe, particle counts x 0.02, sides "
-                        "32-128, 256-2048 slots)",
+    det_bytes = sum(wl.detector.n_cells * wl.detector.n_t * 48 for wl in sets)
+    return {"workload": f"64 uneven sets (batched-launch recipe: sides 32-256, 256-4096 slots, "
+                        f"500-4000 steps; particle counts x {scale:g})",
+            "detector_bytes": det_bytes,
             "interactions": total, "precision": precision,
             "smallest_set": min(sizes), "largest_set": max(sizes),
             "one_launch_ms": ms_batch, "separate_launches_ms": ms_sep,
@@ -222,7 +227,7 @@ def plasma_leg(radio, W, precisions, n_particles, n_steps=1000, fp64_steps=1000)
     chunk_dev = radio.Chunk.from_numpy(wl.chunk)
     inter_all = wl.chunk.n_particles * wl.chunk.n_steps * wl.detector.n_cells
     torch.cuda.synchronize()
-    spec, inter = wl.detector, inter_all
+    spec, inter, spec_name = wl.detector, inter_all, wl.name
     name = wl.name if n_steps >= 1000 else f"{wl.name} (first {n_steps} steps)"
     del wl
     print(f"[bench] plasma: {name} generated and copied in {time.perf_counter() - t:.1f} s "
@@ -268,6 +273,9 @@ def plasma_leg(radio, W, precisions, n_particles, n_steps=1000, fp64_steps=1000)
         det.close()
         radio.set_tuning(**defaults)
         flops = inter * FLOPS_PER_INTERACTION
+        # roofline.traffic is per launch: bytes per interaction x the mean launch's interactions
+        bpi = measured_traffic_per_interaction(prec, spec_name, radio.SHAPES[shape])
+        traffic = None if bpi is None else bpi * inter / max(1, st["slices"])
         out[prec] = {"value": inter / (ms * 1e-3), "ms_per_step": ms, "deposit_kernel_ms": kms,
                      "n_steps": chunk.n_steps, "interactions": inter, "autotuned": tuned,
                      "workgroup_shape": list(radio.SHAPES[shape]),
@@ -276,7 +284,7 @@ def plasma_leg(radio, W, precisions, n_particles, n_steps=1000, fp64_steps=1000)
                      "roofline": {"bound": "alu", "achieved": flops / (kms * 1e-3) / 1e12,
                                   "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
                                   "frac": flops / (kms * 1e-3) / 1e12 / PEAK_TFLOPS[prec],
-                                  "traffic": None}}
+                                  "traffic": traffic}}
         if chunk is full:
             fields[prec] = (E, B)
         else:
@@ -481,23 +489,40 @@ def runtime_leg(radio, W, precision):
             "value": inter / (ms * 1e-3)}
 
 
-def measured_traffic(precision, workload):
-    """HBM bytes per deposit launch from the committed rocprofv3 counter summary, or None
-    when it was taken on another workload or on a different kernel source."""
+def _traffic_record(name, workload):
+    """A committed rocprofv3 counter summary (profiles/<name>), or None when it was
+    taken on another workload or on a different kernel source."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "deposit_traffic_undulator_10000e_4096steps.json")
+    path = os.path.join(ROOT, "profiles", name)
     src = os.path.join(ROOT, "paper_2302_14812_amd", "csrc", "radio_kernels.hip")
     try:
         with open(path) as f:
             rec = json.load(f)
         with open(src, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()[:16]
-    except OSError:
+    except (OSError, ValueError):
         return None
     if rec.get("kernel_source_sha256_16") != sha or rec.get("workload") != workload:
         return None
-    leg = rec.get("per_launch", {}).get(precision)
+    return rec
+
+
+def measured_traffic(precision, workload):
+    """HBM bytes per deposit launch of the undulator benchmark from its counter summary."""
+    rec = _traffic_record("deposit_traffic_undulator_10000e_4096steps.json", workload)
+    leg = None if rec is None else rec.get("per_launch", {}).get(precision)
     return None if leg is None else leg["hbm_bytes"]
+
+
+def measured_traffic_per_interaction(precision, workload, shape):
+    """HBM bytes per interaction of the plasma-mirror deposit from its counter summary
+    (taken on equal time slices, so it carries over to any launch of the same slicing),
+    or None when the summary was taken with another workgroup shape."""
+    rec = _traffic_record("deposit_traffic_plasma_mirror_200000e_256x256_4096bins.json", workload)
+    leg = None if rec is None else rec.get("per_interaction", {}).get(precision)
+    if leg is None or tuple(leg["workgroup_shape"]) != tuple(shape):
+        return None
+    return leg["hbm_bytes_per_interaction"]
 
 
 def measurement_program(name):
@@ -666,7 +691,8 @@ def main():
     main_leg = legs[args.precision]
     opts = None if args.no_options else options_leg(radio, wl, chunk_dev, args.precision, 1, 1)
     del chunk_dev
-    batch = None if args.no_batch else batch_leg(radio, W, args.precision, sec_steps, sec_warm)
+    batch = None if args.no_batch else batch_leg(radio, W, args.precision, sec_steps, sec_warm,
+                                                 args.batch_scale)
     out = {
         "metric": "LW interactions/s (particle-step x cell)",
         "value": main_leg["value"],

@@ -227,8 +227,7 @@ def ship(path: str = SHIPPED_CACHE, repeats: int = 2) -> Dict[str, dict]:
     rec = tune_single(pm.detector, chunk, "mixed", candidates=(0,), repeats=1, cache=cache)
     print(f"[tune] {pm.name} (first 200 steps) mixed: {rec}", file=sys.stderr, flush=True)
     del chunk, pm
-    sets = W.batched_sets(n_sets=64, scale=0.02, sides=(32, 64, 128),
-                          n_t_choices=(256, 512, 1024, 2048))
+    sets = W.batched_sets(n_sets=64, scale=0.02)
     chunks = [radio.Chunk.from_numpy(s.chunk) for s in sets]
     rec = tune_batch([s.detector for s in sets], chunks, "mixed", candidates=(2, 4, 8, 16),
                      repeats=repeats, cache=cache)
