@@ -437,27 +437,18 @@ def runtime_leg(radio, W, precision):
     """The run-time mode: 10^4 electrons in a plane wave (a = 1.5, omega = 1, along +x)
     pushed on the device by radio_push 16 steps at a time (dt = 0.05, 1024 steps) and
     each block deposited right away into a 128 x 128 cap at 1e4 about +x with 2048
-    slots; nothing leaves device memory."""
-    import numpy as np
+    slots; nothing leaves device memory.  Each block is a one-pair batched deposit,
+    with the launch settings the tuning cache holds for such blocks."""
     import torch
 
-    from paper_2302_14812_amd.runtime import RunTimeDiagnostic
+    from paper_2302_14812_amd import autotune
+    from paper_2302_14812_amd.runtime import RunTimeDiagnostic, plane_wave_electrons
     n_p, block, n_blocks, dt = 10000, 16, 64, 0.05
-    rng = np.random.Generator(np.random.PCG64(W.BASE_SEED + 700))
-    x0 = rng.uniform(-2.0, 2.0, size=(3, n_p))
-    u0 = np.zeros((3, n_p))
-    wave = {"qm": -1.0, "wave_amplitude": 1.5, "wave_dir": [1.0, 0.0, 0.0],
-            "wave_pol": [0.0, 1.0, 0.0], "wave_omega": 1.0, "wave_phase": 0.0}
-    # window from a sample pushed by the oracle-free device pusher itself
-    xs = torch.zeros((3, block * n_blocks + 1, 64), dtype=torch.float64, device="cuda")
-    us = torch.zeros_like(xs)
-    xs[:, 0] = torch.from_numpy(x0[:, :64]).cuda()
-    sample = radio.push(radio.Chunk(xs, us, None, 0.0, dt), **wave)
-    cells = W.sphere_cap_cells(1e4, [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], 128, 128, 0.3, 0.3)
-    host = W.Chunk(x=sample.x.cpu().numpy(), u=sample.u.cpu().numpy(), q=np.full(64, -1.0),
-                   t_first=0.0, dt=dt)
-    t0, dtd = W.arrival_window(cells, host, 2048, pad_frac=0.05)
-    det = radio.Detector(cells, t0=t0, dt_det=dtd, n_t=2048, precision=precision)
+    cells, t0, dtd, n_t, x0, u0, wave = plane_wave_electrons(n_p, block, n_blocks, dt)
+    det = radio.Detector(cells, t0=t0, dt_det=dtd, n_t=n_t, precision=precision)
+    defaults = radio.get_tuning()
+    tuned = autotune.apply_runtime(det, n_p, block, precision)
+    shape = radio.get_tuning()["shape"]
     rt = RunTimeDiagnostic([det], x0, u0, None, dt=dt, block_steps=block, fields=wave)
     rt.advance(1)  # warm
     torch.cuda.synchronize()
@@ -480,13 +471,15 @@ def runtime_leg(radio, W, precision):
     push_ms = c.elapsed_time(d)
     inter = n_p * block * n_blocks * det.n_cells
     det.close()
+    radio.set_tuning(**defaults)
     print(f"[bench] runtime ({precision}): {ms:.1f} ms for {n_blocks} push-deposit blocks, "
-          f"push {push_ms:.1f} ms, {inter / (ms * 1e-3):.3e} interactions/s", file=sys.stderr,
-          flush=True)
+          f"push {push_ms:.1f} ms, {inter / (ms * 1e-3):.3e} interactions/s, shape "
+          f"{radio.SHAPES[shape]}{' (tuned)' if tuned else ''}", file=sys.stderr, flush=True)
     return {"workload": "1e4 electrons in a plane wave (a 1.5), 1024 steps in blocks of 16; "
                         "128x128 cap at 1e4, 2048 slots", "precision": precision,
             "total_ms": ms, "push_ms": push_ms, "interactions": inter,
-            "value": inter / (ms * 1e-3)}
+            "value": inter / (ms * 1e-3), "autotuned": tuned,
+            "workgroup_shape": list(radio.SHAPES[shape])}
 
 
 def _traffic_record(name, workload):

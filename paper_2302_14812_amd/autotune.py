@@ -205,11 +205,38 @@ def apply_batch(specs: Sequence, chunks: Sequence, cache: Optional[Dict[str, dic
     return bool(rec)
 
 
+def runtime_key(n_particles: int, block_steps: int, n_cells: int, precision: str) -> str:
+    return (f"runtime/{precision}/p{_bucket(n_particles)}/s{_bucket(block_steps)}"
+            f"/c{_bucket(n_cells)}")
+
+
+def tune_runtime(spec, block: "radio.Chunk", precision: str = "mixed",
+                 cache: Optional[Dict[str, dict]] = None, **kw) -> dict:
+    """Pick the workgroup shape and items_per_workgroup for run-time deposits: one
+    block of pushed steps into one detector per call, a one-pair batch."""
+    rec = tune_batch([spec], [block], precision, cache=None, **kw)
+    if cache is not None:
+        cache[runtime_key(block.n_particles, block.n_steps, spec.n_cells, precision)] = rec
+    return rec
+
+
+def apply_runtime(det, n_particles: int, block_steps: int, precision: str,
+                  cache: Optional[Dict[str, dict]] = None) -> bool:
+    """Set the shape and items_per_workgroup for run-time blocks like these from the
+    cache; True if such blocks were tuned."""
+    cache = load_cache() if cache is None else cache
+    rec = cache.get(runtime_key(n_particles, block_steps, det.n_cells, precision))
+    if rec:
+        radio.set_tuning(items_per_workgroup=rec["items_per_workgroup"], shape=rec.get("shape", 0))
+    return bool(rec)
+
+
 def ship(path: str = SHIPPED_CACHE, repeats: int = 2) -> Dict[str, dict]:
     """Tune the benchmark's workloads and write the shipped cache: the planar
     undulator ensemble (single deposits, both precisions), the plasma-mirror sheet
     (2e5 electrons; its first 200 steps, which share the bucket of the whole run;
-    mixed) and the 64 uneven sets of the batched-launch benchmark (mixed)."""
+    mixed), the 64 uneven sets of the batched-launch benchmark (mixed) and the
+    run-time mode's 16-step blocks of plane-wave electrons (mixed)."""
     import sys
 
     import torch
@@ -233,6 +260,19 @@ def ship(path: str = SHIPPED_CACHE, repeats: int = 2) -> Dict[str, dict]:
                      repeats=repeats, cache=cache)
     print(f"[tune] 64 batched sets mixed: {rec}", file=sys.stderr, flush=True)
     del chunks
+    # run-time blocks: a 16-step block from the middle of the plane-wave run
+    from paper_2302_14812_amd.runtime import plane_wave_electrons
+    cells, t0, dtd, n_t, x0, u0, wave = plane_wave_electrons()
+    xs = torch.zeros((3, 1025, x0.shape[1]), dtype=torch.float64, device="cuda")
+    us = torch.zeros_like(xs)
+    xs[:, 0] = torch.from_numpy(x0).cuda()
+    us[:, 0] = torch.from_numpy(u0).cuda()
+    run = radio.push(radio.Chunk(xs, us, None, 0.0, 0.05), **wave)
+    spec = W.DetectorSpec(cells=cells, t0=t0, dt_det=dtd, n_t=n_t)
+    rec = tune_runtime(spec, run.slice_steps(512, 528), "mixed", candidates=(2, 4, 8),
+                       repeats=repeats, cache=cache)
+    print(f"[tune] run-time blocks mixed: {rec}", file=sys.stderr, flush=True)
+    del run, xs, us
     torch.cuda.synchronize()
     save_cache(cache, path)
     return cache

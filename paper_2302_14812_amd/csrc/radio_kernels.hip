@@ -1317,14 +1317,61 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
     // the latter the thread index passes through an empty asm so that what is
     // derived from it is recomputed per batch instead of being held in
     // registers across the field loop.
-    constexpr bool kStageDirect = MIX;
+    // Large-ring workgroups (two per CU: their LDS allows no more) have too
+    // few neighbours to hide a batch's loads, so they prefetch: the next
+    // batch's records, charges and first positions are loaded into registers
+    // while the current batch is computed, and written to LDS after it.
+    constexpr bool kPrefetch = (R == kRingLarge);
+    constexpr bool kStageDirect = MIX && !kPrefetch;
     constexpr int kStageLanes = kDepositThreads / kGroups;
     int t_stage = tid;
     asm volatile("" : "+v"(t_stage));
+    // register staging: a thread holds pieces r0, r0 + kStageLanes, ... of the
+    // records of particle t_stage / kStageLanes of the batch (pieces of 16
+    // bytes where the record size allows, else of 8)
+    using Piece = typename std::conditional<sizeof(Rec) % 16 == 0, v2i64, long long>::type;
+    constexpr int kPieces = (int)(sizeof(Rec) / sizeof(Piece));
+    constexpr int kIter = ((L + 1) * kPieces + kStageLanes - 1) / kStageLanes;
+    // the records (states s_a .. s_a + L, contiguous) and the charge of particle p
+    auto load_records = [&](int p, int64_t s_a_, Piece(&v)[kIter], double& qs) {
+        const int per = (int)(min((int64_t)L, J.n_s - s_a_) + 1) * kPieces;
+        int t = t_stage;
+        asm volatile("" : "+v"(t));
+        const int r0 = t % kStageLanes;
+        if (p >= 0) {
+            const RADIO_GLOBAL Piece* src =
+                gptr(reinterpret_cast<const Piece*>(recs + (int64_t)p * n_states + s_a_));
+#pragma unroll
+            for (int j = 0; j < kIter; ++j)
+                if (r0 + j * kStageLanes < per)
+                    v[j] = src[r0 + j * kStageLanes];
+            if (r0 == 0)
+                qs = charges ? charges[p] : -1.0;
+        }
+    };
+    auto store_records = [&](int p, int len_, const Piece(&v)[kIter], double qs) {
+        const int per = (len_ + 1) * kPieces;
+        int t = t_stage;
+        asm volatile("" : "+v"(t));
+        const int gg = t / kStageLanes;
+        const int r0 = t % kStageLanes;
+        if (p >= 0) {
+            Piece* dst = reinterpret_cast<Piece*>(&sh.rec[gg][0]);
+#pragma unroll
+            for (int j = 0; j < kIter; ++j)
+                if (r0 + j * kStageLanes < per)
+                    dst[r0 + j * kStageLanes] = v[j];
+            if (r0 == 0)
+                sh.sq[gg] = qs;
+        }
+    };
     int64_t rb = rb_begin, bt = bt_begin;  // the current batch
     int64_t rb1 = rb, bt1 = bt;     // the next one
     advance(rb1, bt1);
     int p_stage = -1, p_scout = -1;  // this thread's particle to stage; the lane's to scout
+    int p_next = -1;                 // prefetch: this thread's particle of the next batch
+    Piece v_pre[kPrefetch ? kIter : 1];  // prefetch: the records in flight
+    double q_pre = 0.0;
     __syncthreads();  // rings and start slots cleared
     if (rb_begin < rb_end && n_batches > 0) {
         const int p0 = lane_particle(rb, bt, g);
@@ -1338,6 +1385,10 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
                 sh.ord[0][tid] = lane_particle(rb, bt, tid);
         } else {
             p_stage = lane_particle(rb, bt, t_stage / kStageLanes);
+        }
+        if constexpr (kPrefetch) {
+            load_records(p_stage, rb * L, v_pre, q_pre);
+            p_next = lane_particle(rb1, bt1, t_stage / kStageLanes);
         }
         p_scout = lane_particle(rb1, bt1, g);
     }
@@ -1418,11 +1469,10 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
                 scout(xs, rb1 * L, buf ^ 1);
             p_scout = p_scout_next;
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the records are in LDS
+        } else if constexpr (kPrefetch) {
+            // this batch's records came into registers while the previous one was computed
+            store_records(p_stage, len, v_pre, q_pre);
         } else {
-            // pieces of 16 bytes where the record size allows, else of 8
-            using Piece = typename std::conditional<sizeof(Rec) % 16 == 0, v2i64, long long>::type;
-            constexpr int kPieces = (int)(sizeof(Rec) / sizeof(Piece));
-            constexpr int kIter = ((L + 1) * kPieces + kStageLanes - 1) / kStageLanes;
             const int per = (len + 1) * kPieces;
             int t = t_stage;
             asm volatile("" : "+v"(t));
@@ -1472,6 +1522,24 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         __syncthreads();
         if (tid < kTileCells)  // read by every lane before the barrier; next used two batches on
             nb[buf * kTileCells + tid] = INT_MAX;
+        // prefetch: in flight while this batch is computed, the next batch's
+        // records and charges, its first positions (for its ring placement) and
+        // the order entries of the batch after it
+        double xs_next[3] = {0.0, 0.0, 0.0};
+        bool scout_next = false;
+        int p_stage_after = -1, p_scout_after = -1;
+        if constexpr (kPrefetch) {
+            load_records(p_next, rb1 * L, v_pre, q_pre);
+            scout_next = active && p_scout >= 0;
+            if (scout_next) {
+                const RADIO_GLOBAL double* x = first_position(p_scout, rb1 * L);
+                xs_next[0] = x[0];
+                xs_next[1] = x[1];
+                xs_next[2] = x[2];
+            }
+            p_stage_after = lane_particle(rb2, bt2, t_stage / kStageLanes);
+            p_scout_after = lane_particle(rb2, bt2, g);
+        }
         if (active && g < np) {
             Sink sink{my_ring, row, base, n_t, &n_bypass};
             const double q = sh.sq[g];
@@ -1506,9 +1574,10 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
             const bool inside = u_prev >= -1.0 && u_prev < ntd + 1.0;
             carry_open(C, inside ? floor(u_prev) : (double)(INT_MIN / 2));
             C.lim = fast_limit(C.J1 - 1.0, u_prev, ntd);
-            for (int k = 1; k <= len; ++k) {
+            // segment k: the field of state k, held (or interpolated) over its arrivals
+            auto segment = [&](const Rec& st, double tk) {
                 T F[6];
-                const double uk = field_at(sh.rec[g][k], sh.tk[k], F);
+                const double uk = field_at(st, tk, F);
                 if constexpr (HOLD == 0) {
                     add_segment(C, sink, n_t, u_prev, uk, F, n_back, n_clip);
                 } else {
@@ -1521,8 +1590,32 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
                         Fp[c] = F[c];
                 }
                 u_prev = uk;
+            };
+            if constexpr (kPrefetch) {
+                // the next state's record is read from LDS while this one is
+                // worked on (two waves per SIMD hide little of the LDS latency)
+                Rec cur = sh.rec[g][1];
+                double t_cur = sh.tk[1];
+                for (int k = 1; k <= len; ++k) {
+                    const int kn = min(k + 1, len);
+                    const Rec nxt = sh.rec[g][kn];
+                    const double t_nxt = sh.tk[kn];
+                    segment(cur, t_cur);
+                    cur = nxt;
+                    t_cur = t_nxt;
+                }
+            } else {
+                for (int k = 1; k <= len; ++k)
+                    segment(sh.rec[g][k], sh.tk[k]);
             }
             sink.flush((int)(C.J1 - 1.0), C.V);
+        }
+        if constexpr (kPrefetch) {
+            if (scout_next)
+                scout(xs_next, rb1 * L, buf ^ 1);
+            p_stage = p_next;
+            p_next = p_stage_after;
+            p_scout = p_scout_after;
         }
         __syncthreads();  // records and rings are free for the next batch
         rb = rb1;

@@ -423,9 +423,16 @@ def detector_bytes(spec) -> int:
     return int(spec.n_cells) * int(spec.n_t) * 48 + int(spec.n_cells) * 32
 
 
-# the library's deposit shape: cells per tile, segments per run, runs per
-# particle order, and the largest state record (double precision)
-_TILE_CELLS, _RUN_L, _RUNS_PER_ORDER, _REC_BYTES = 16, 16, 2, 80
+# The library's deposit plan, for bounds that hold in every workgroup shape
+# (radio_tuning.shape): the smallest tile (cells) and run (segments) of the
+# shapes, runs per particle order, and the largest state record (double).
+def _shape_minima():
+    import paper_2302_14812_amd as radio
+    return (min(c for c, _, _ in radio.SHAPES.values()),
+            min(r for _, _, r in radio.SHAPES.values()))
+
+
+(_TILE_CELLS, _RUN_L), _RUNS_PER_ORDER, _REC_BYTES = _shape_minima(), 2, 80
 
 
 def workspace_bytes(spec, piece_work: float) -> int:
@@ -433,12 +440,14 @@ def workspace_bytes(spec, piece_work: float) -> int:
     one particle order, ring choices).  In a batch a part runs in the batch's
     workspaces unless its particle orders exceed the library's order budget;
     it then runs in time slices of at most two runs on the detector's own
-    workspaces, which needs more than two runs (33 states) and so at most
-    piece_work / (33 n_cells) particles."""
+    workspaces, which needs more than two runs (2 L + 1 states for runs of L
+    segments) and so at most piece_work / ((2 L + 1) n_cells) particles.
+    Taken with the smallest tile and run of any shape, this bounds each shape's
+    orders (tiles x particles) and records (particles x states)."""
     n_c = int(spec.n_cells)
     tiles = -(-n_c // _TILE_CELLS)
-    n_p = int(math.ceil(piece_work / (33.0 * n_c)))
     states = _RUNS_PER_ORDER * _RUN_L + 1
+    n_p = int(math.ceil(piece_work / (float(states) * n_c)))
     return tiles * n_p * 4 + n_p * states * _REC_BYTES + tiles
 
 
@@ -452,11 +461,12 @@ def arena_bytes(max_batch_work: float, max_batch_segments: float) -> int:
     """Upper bound of one batch workspace of the library for batches of up to W =
     max_batch_work interactions and S = max_batch_segments particle segments.
     A pair of n_p particles, n_s segments and n_c cells holds at most n_s
-    particle orders (one per two runs of 16 segments) of ceil(n_c/16) n_p
-    entries of 4 bytes, <= W/4 + 4 S over the batch; state records of at most
-    80 bytes for n_p (n_s + 1) <= 2 n_p n_s states, <= 160 S; ring choices of
-    ceil(n_c/16) bytes, <= W/16 + one per pair; and its job and work items.
-    A quarter on top covers the last two, plus 64 MiB."""
+    particle orders (one per two runs) of ceil(n_c/C) n_p entries of 4 bytes
+    for tiles of C cells, <= 4 W/C + 4 S over the batch; state records of at
+    most 80 bytes for n_p (n_s + 1) <= 2 n_p n_s states, <= 160 S; ring choices
+    of ceil(n_c/C) bytes, <= W/C + one per pair; and its job and work items.
+    C is the smallest tile of any workgroup shape.  A quarter on top covers the
+    last two, plus 64 MiB."""
     W, S = float(max_batch_work), float(max_batch_segments)
     orders = 4.0 * W / _TILE_CELLS + 4.0 * S
     records = 2.0 * _REC_BYTES * S

@@ -109,21 +109,27 @@ def test_detector_bytes_counts_accumulator_and_cells():
 
 def test_admission_counts_workspaces():
     """Admission counts each detector's own deposit workspaces beside its state,
-    and the service reserves the two batch workspaces: for the plasma-mirror
-    detector (65536 cells) and batches of 4e10 interactions, about 1e10 bytes
-    of particle orders per batch workspace."""
+    and the service reserves the two batch workspaces, bounded for every
+    workgroup shape: for the plasma-mirror detector (65536 cells) and batches
+    of 4e10 interactions, about 2e10 bytes of particle orders per batch
+    workspace with the 8-cell tiles of shape 1."""
+    import paper_2302_14812_amd as radio
     from paper_2302_14812_amd.serving import arena_bytes, resident_bytes, workspace_bytes
     spec = W.DetectorSpec(cells=np.zeros((65536, 3)), t0=0.0, dt_det=1.0, n_t=4096)
     ws = workspace_bytes(spec, 2e10)
-    n_p = -(-int(2e10) // (33 * 65536))
-    assert ws >= 4096 * n_p * 4 + n_p * 33 * 64
     assert resident_bytes(spec, 2e10) == detector_bytes(spec) + ws
     a = arena_bytes(4e10, 4e10 / 4096)
-    assert 1.2e10 <= a <= 2.0e10
-    # a batch of one-step chunks of 10^5 particles on that detector: 4e10 / 6.5e9 of
-    # them, each with one order of 4096 tiles x 10^5 particles and 2 x 10^5 records
-    n = 4e10 / (100_000 * 65536)
-    assert a >= n * (4096 * 100_000 * 4 + 2 * 100_000 * 80)
+    assert 2.4e10 <= a <= 3.5e10
+    for cells, groups, run in radio.SHAPES.values():
+        # a detector's time slices: two runs of the shape, particles as many as
+        # make piece_work with more than two runs
+        n_p = -(-int(2e10) // ((2 * run + 1) * 65536))
+        assert ws >= (65536 // cells) * n_p * 4 + n_p * (2 * run + 1) * 80
+        # a batch of one-step chunks of 10^5 particles on that detector: 4e10 / 6.5e9
+        # of them, each with one order of 65536 / cells tiles x 10^5 particles and
+        # 2 x 10^5 records
+        n = 4e10 / (100_000 * 65536)
+        assert a >= n * ((65536 // cells) * 100_000 * 4 + 2 * 100_000 * 80)
     # on a one-tile detector the segment bound holds the records: 4e10 / 4096 segments
     # of one-step chunks need 2 x 80 bytes each
     assert a >= 4e10 / 4096 * 160
