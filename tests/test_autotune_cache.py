@@ -37,7 +37,16 @@ def test_shipped_cache_entries():
     import paper_2302_14812_amd as radio
     shipped = autotune.load_cache(path="/nonexistent/none.json")
     for key, rec in shipped.items():
-        assert key.startswith(("single/", "batch/"))
+        assert key.startswith(("single/", "batch/", "runtime/"))
         assert rec["shape"] in radio.SHAPES
         assert ("target_blocks" in rec) if key.startswith("single/") else (
             "items_per_workgroup" in rec)
+
+
+def test_runtime_keys():
+    """Run-time blocks have their own bucket: a one-pair batch of a 16-step block
+    is not the 64-set batch, nor a single deposit of the whole run."""
+    k = autotune.runtime_key(10000, 16, 16384, "mixed")
+    assert k == "runtime/mixed/p13/s4/c14"
+    assert k != autotune.single_key(10000, 16, 16384, "mixed")
+    assert autotune.runtime_key(10000, 16, 16384, "fp64") != k
