@@ -28,7 +28,7 @@ from __future__ import annotations
 import json
 import math
 import os
-from typing import Dict, Iterable, List, Optional, Sequence
+from typing import Callable, Dict, Iterable, List, Optional, Sequence
 
 import paper_2302_14812_amd as radio
 
@@ -113,9 +113,11 @@ def _shapes_for(specs, shapes: Iterable[int]) -> List[int]:
 def tune_single(spec, chunk: "radio.Chunk", precision: str = "mixed",
                 candidates: Iterable[int] = (0, 768, 1536, 3072, 6144, 12288), repeats: int = 2,
                 cache: Optional[Dict[str, dict]] = None,
-                shapes: Iterable[int] = tuple(radio.SHAPES)) -> dict:
+                shapes: Iterable[int] = tuple(radio.SHAPES),
+                progress: Optional[Callable[[str], None]] = None) -> dict:
     """Pick the workgroup shape and target_blocks for deposits like (spec, chunk):
-    the shapes at the first candidate, then the candidates at the best shape."""
+    the shapes at the first candidate, then the candidates at the best shape.
+    progress, if given, receives a line per timed configuration."""
     det = radio.Detector.from_spec(spec, precision=precision)
     saved = radio.get_tuning()
     candidates = [int(c) for c in candidates]
@@ -126,6 +128,8 @@ def tune_single(spec, chunk: "radio.Chunk", precision: str = "mixed",
         key = f"{shape}/{tb}"
         if key not in results:
             results[key] = _time_ms(lambda: (det.reset(), det.deposit(chunk)), repeats)
+            if progress:
+                progress(f"shape {shape} target_blocks {tb}: {results[key]:.1f} ms")
         return results[key]
 
     try:
@@ -146,10 +150,11 @@ def tune_single(spec, chunk: "radio.Chunk", precision: str = "mixed",
 def tune_batch(specs: Sequence, chunks: Sequence["radio.Chunk"], precision: str = "mixed",
                candidates: Iterable[int] = (1, 2, 4, 8, 16), repeats: int = 2,
                cache: Optional[Dict[str, dict]] = None,
-               shapes: Iterable[int] = tuple(radio.SHAPES)) -> dict:
+               shapes: Iterable[int] = tuple(radio.SHAPES),
+               progress: Optional[Callable[[str], None]] = None) -> dict:
     """Pick the workgroup shape and items_per_workgroup for batches like (specs,
     chunks): the shapes at the current items_per_workgroup, then the candidates at
-    the best shape."""
+    the best shape.  progress, if given, receives a line per timed configuration."""
     dets = [radio.Detector.from_spec(s, precision=precision) for s in specs]
     saved = radio.get_tuning()
     results = {}
@@ -164,6 +169,8 @@ def tune_batch(specs: Sequence, chunks: Sequence["radio.Chunk"], precision: str 
         key = f"{shape}/{k}"
         if key not in results:
             results[key] = _time_ms(run, repeats)
+            if progress:
+                progress(f"shape {shape} items_per_workgroup {k}: {results[key]:.1f} ms")
         return results[key]
 
     try:
@@ -235,7 +242,7 @@ def ship(path: str = SHIPPED_CACHE, repeats: int = 2) -> Dict[str, dict]:
     """Tune the benchmark's workloads and write the shipped cache: the planar
     undulator ensemble (single deposits, both precisions), the plasma-mirror sheet
     (2e5 electrons; its first 200 steps, which share the bucket of the whole run;
-    mixed), the 64 uneven sets of the batched-launch benchmark (mixed) and the
+    both precisions), the 64 uneven sets of the batched-launch benchmark (mixed) and the
     run-time mode's 16-step blocks of plane-wave electrons (mixed)."""
     import sys
 
@@ -243,21 +250,28 @@ def ship(path: str = SHIPPED_CACHE, repeats: int = 2) -> Dict[str, dict]:
 
     from paper_2302_14812_amd import workloads as W
     cache: Dict[str, dict] = {}
+
+    def note(line):
+        print(f"[tune]   {line}", file=sys.stderr, flush=True)
+
     wl = W.undulator_workload()
     chunk = radio.Chunk.from_numpy(wl.chunk)
     for prec in ("mixed", "fp64"):
-        rec = tune_single(wl.detector, chunk, prec, candidates=(0,), repeats=repeats, cache=cache)
+        rec = tune_single(wl.detector, chunk, prec, candidates=(0,), repeats=repeats, cache=cache,
+                          progress=note)
         print(f"[tune] {wl.name} {prec}: {rec}", file=sys.stderr, flush=True)
     del chunk
     pm = W.plasma_mirror_workload(n_particles=200_000)
     chunk = radio.Chunk.from_numpy(pm.chunk.slice_steps(0, 200))
-    rec = tune_single(pm.detector, chunk, "mixed", candidates=(0,), repeats=1, cache=cache)
-    print(f"[tune] {pm.name} (first 200 steps) mixed: {rec}", file=sys.stderr, flush=True)
+    for prec in ("mixed", "fp64"):
+        rec = tune_single(pm.detector, chunk, prec, candidates=(0,), repeats=1, cache=cache,
+                          progress=note)
+        print(f"[tune] {pm.name} (first 200 steps) {prec}: {rec}", file=sys.stderr, flush=True)
     del chunk, pm
     sets = W.batched_sets(n_sets=64, scale=0.02)
     chunks = [radio.Chunk.from_numpy(s.chunk) for s in sets]
     rec = tune_batch([s.detector for s in sets], chunks, "mixed", candidates=(2, 4, 8, 16),
-                     repeats=repeats, cache=cache)
+                     repeats=repeats, cache=cache, progress=note)
     print(f"[tune] 64 batched sets mixed: {rec}", file=sys.stderr, flush=True)
     del chunks
     # run-time blocks: a 16-step block from the middle of the plane-wave run
@@ -270,7 +284,7 @@ def ship(path: str = SHIPPED_CACHE, repeats: int = 2) -> Dict[str, dict]:
     run = radio.push(radio.Chunk(xs, us, None, 0.0, 0.05), **wave)
     spec = W.DetectorSpec(cells=cells, t0=t0, dt_det=dtd, n_t=n_t)
     rec = tune_runtime(spec, run.slice_steps(512, 528), "mixed", candidates=(2, 4, 8),
-                       repeats=repeats, cache=cache)
+                       repeats=repeats, cache=cache, progress=note)
     print(f"[tune] run-time blocks mixed: {rec}", file=sys.stderr, flush=True)
     del run, xs, us
     torch.cuda.synchronize()
