@@ -149,6 +149,15 @@ def options_leg(radio, wl, chunk_dev, precision, steps, warmup):
     return out
 
 
+def _alu_roofline(interactions, ms, precision):
+    """The ALU roofline of a leg's deposits: FLOPS_PER_INTERACTION per interaction over
+    its time (deposits with whatever else the leg's timed region holds) against the
+    vector peak of its precision."""
+    achieved = interactions * FLOPS_PER_INTERACTION / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[precision],
+            "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[precision], "traffic": None}
+
+
 def batch_leg(radio, W, precision, steps, warmup, scale=0.02):
     """64 independent uneven sets of the batched-launch recipe (detectors of 32^2 to
     256^2 cells with 256 to 4096 slots, 500-4000 steps, helical or planar motion),
@@ -207,7 +216,8 @@ def batch_leg(radio, W, precision, steps, warmup, scale=0.02):
             "one_launch_value": total / (ms_batch * 1e-3),
             "separate_value": total / (ms_sep * 1e-3),
             "speedup": ms_sep / ms_batch, "autotuned": tuned,
-            "workgroup_shape": list(radio.SHAPES[shape])}
+            "workgroup_shape": list(radio.SHAPES[shape]),
+            "roofline": _alu_roofline(total, ms_batch, precision)}
 
 
 def plasma_leg(radio, W, precisions, n_particles, n_steps=1000, fp64_steps=1000):
@@ -281,6 +291,7 @@ def plasma_leg(radio, W, precisions, n_particles, n_steps=1000, fp64_steps=1000)
                      "workgroup_shape": list(radio.SHAPES[shape]),
                      "deposit_launches_per_step": st["slices"],
                      "bypassed_per_interaction": st["bypassed"] / max(1, st["interactions"]),
+                     "large_ring_fraction": st["large_ring"] / max(1, st["interactions"]),
                      "roofline": {"bound": "alu", "achieved": flops / (kms * 1e-3) / 1e12,
                                   "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
                                   "frac": flops / (kms * 1e-3) / 1e12 / PEAK_TFLOPS[prec],
@@ -479,7 +490,8 @@ def runtime_leg(radio, W, precision):
                         "128x128 cap at 1e4, 2048 slots", "precision": precision,
             "total_ms": ms, "push_ms": push_ms, "interactions": inter,
             "value": inter / (ms * 1e-3), "autotuned": tuned,
-            "workgroup_shape": list(radio.SHAPES[shape])}
+            "workgroup_shape": list(radio.SHAPES[shape]),
+            "roofline": _alu_roofline(inter, ms, precision)}
 
 
 def _traffic_record(name, workload):

@@ -161,6 +161,9 @@ typedef struct radio_stats {
     int64_t slices;       /* deposit launches made for those chunks: a long chunk runs
                              as time slices (radio_tuning), alone or in a batch; any
                              other batched chunk as one job of the batch's launch */
+    int64_t large_ring;   /* of the interactions, those deposited by tiles that took the
+                             large on-chip slot ring (arrivals crossing slots often; a
+                             performance counter) */
 } radio_stats;
 
 /*

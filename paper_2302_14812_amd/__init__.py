@@ -89,7 +89,8 @@ _TUNING_FIELDS = ("target_blocks", "items_per_workgroup", "max_grid", "order_bud
 
 class _Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
-                ("interactions", "clipped", "nonmonotone", "chunks", "bytes", "bypassed", "slices")]
+                ("interactions", "clipped", "nonmonotone", "chunks", "bytes", "bypassed", "slices",
+                 "large_ring")]
 
 
 _LIB = None

@@ -72,6 +72,7 @@ constexpr int kRunL = shape_run(0);
 constexpr int kMaxGroups = 32;                          // particles per batch, any shape
 constexpr int kRingMargin = 2;                          // ring slots kept below a batch's start
 constexpr int kXcds = 8;                                // accelerator dies sharing one L2 each
+constexpr int kCounters = 4;  // a detector's device counters (DepositJob::counters)
 
 // Slots per cell in the LDS ring (the small one a power of two), 48 B per slot in every mode
 // (6 doubles, or 6 compensated single pairs).  Each tile takes the small ring
@@ -100,7 +101,8 @@ struct DepositJob {
     const double* cells;            // [n_c][3], internal (tile-ordered) rows
     double* acc;                    // [n_c][n_t][6] doubles, or [n_c][n_t][12] floats (hi, lo)
                                     // for the compensated single mode
-    unsigned long long* counters;   // [3]: clipped, nonmonotone, ring bypasses
+    unsigned long long* counters;   // [kCounters]: clipped, nonmonotone, ring bypasses,
+                                    // interactions deposited through the large ring
     const double* x;                // state 0 of [3][...][n_p] (components xs_stride apart)
     const double* u;                // the same for u
     const double* q;                // [n_p] or nullptr (all -1)

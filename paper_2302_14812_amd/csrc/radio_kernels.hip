@@ -1129,7 +1129,7 @@ struct DepositShared {
     double ring[TC * kStride];          // per-cell slot rings
     int nb[2][TC];                      // per cell: lowest start slot of a coming batch
     int ord[2][GR];                     // particles of the staged rows, per batch parity
-    unsigned long long cnt[3];          // clipped, nonmonotone, bypassed
+    unsigned long long cnt[kCounters];  // clipped, nonmonotone, bypassed, large-ring interactions
 };
 
 // One work item: a tile of kTileCells cells against the runs
@@ -1209,12 +1209,13 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
     RADIO_LDS int* nb = (RADIO_LDS int*)&sh.nb[0][0];
     for (int i = g; i < R * RW; i += kGroups)
         my_ring[i] = 0.0;
-    if (tid < 3)
+    if (tid < kCounters)
         sh.cnt[tid] = 0;
     if (tid < 2 * kTileCells)
         nb[tid] = INT_MAX;
     int base = 0;  // the ring covers [base, base + R), 0 <= base <= max(n_t - R, 0)
     unsigned n_clip = 0, n_back = 0, n_bypass = 0;
+    unsigned n_large = 0;  // large ring: the lane's segments (its interactions)
     // the tile's particle order for run rb (one order per group of runs)
     auto order_of = [&](int64_t rb_) {
         return gptr(J.perm + ((rb_ >> J.group_shift) * J.n_tiles + tile) * J.n_p);
@@ -1541,6 +1542,8 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
             p_scout_after = lane_particle(rb2, bt2, g);
         }
         if (active && g < np) {
+            if constexpr (R == kRingLarge)
+                n_large += (unsigned)len;
             Sink sink{my_ring, row, base, n_t, &n_bypass};
             const double q = sh.sq[g];
             // (the mixed records carry q/c in their betadot)
@@ -1630,8 +1633,10 @@ __device__ __forceinline__ void deposit_item(const DepositJob& J, int64_t tile, 
         atomicAdd(&sh.cnt[1], (unsigned long long)n_back);
     if (n_bypass)
         atomicAdd(&sh.cnt[2], (unsigned long long)n_bypass);
+    if (n_large)
+        atomicAdd(&sh.cnt[3], (unsigned long long)n_large);
     __syncthreads();
-    if (tid < 3 && sh.cnt[tid])
+    if (tid < kCounters && sh.cnt[tid])
         __hip_atomic_fetch_add(gptr(J.counters) + tid, sh.cnt[tid], __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -29,7 +29,8 @@ struct radio_detector {
     double* d_cells = nullptr;        // internal (tile-ordered) rows
     int64_t* d_user_index = nullptr;  // internal row -> caller's cell index
     double* d_acc = nullptr;
-    unsigned long long* d_counters = nullptr;  // [3] clipped, nonmonotone, ring bypasses
+    unsigned long long* d_counters = nullptr;  // [kCounters]: clipped, nonmonotone, ring
+                                               // bypasses, large-ring interactions
     char* d_recs = nullptr;                    // workspace (state records), grown on demand
     size_t recs_cap = 0;                       // in bytes
     int32_t* d_perm = nullptr;                 // workspace, grown on demand
@@ -861,7 +862,7 @@ int radio_detector_create(const radio_detector_desc* desc, void* stream, radio_d
     }
     if (hipMalloc((void**)&det->d_cells, (size_t)n_c * 3 * sizeof(double)) != hipSuccess ||
         hipMalloc((void**)&det->d_user_index, (size_t)n_c * sizeof(int64_t)) != hipSuccess ||
-        hipMalloc((void**)&det->d_counters, 3 * sizeof(unsigned long long)) != hipSuccess) {
+        hipMalloc((void**)&det->d_counters, radio::kCounters * sizeof(unsigned long long)) != hipSuccess) {
         (void)hipGetLastError();
         radio_detector_destroy(det);
         return RADIO_ENOMEM;
@@ -885,7 +886,7 @@ int radio_detector_create(const radio_detector_desc* desc, void* stream, radio_d
         hipMemcpyAsync(det->d_user_index, user.data(), (size_t)n_c * sizeof(int64_t),
                        hipMemcpyHostToDevice, s) != hipSuccess ||
         radio::launch_zero(det->d_acc, n_c * det->n_t * 6, s) != hipSuccess ||
-        radio::launch_zero_u64(det->d_counters, 3, s) != hipSuccess ||
+        radio::launch_zero_u64(det->d_counters, radio::kCounters, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {  // the host vectors are pageable: finish
         radio_detector_destroy(det);
         return RADIO_EDEVICE;
@@ -935,7 +936,7 @@ int radio_detector_reset(radio_detector* det, void* stream)
         return RADIO_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
     if (radio::launch_zero(det->d_acc, det->n_c * det->n_t * 6, s) != hipSuccess ||
-        radio::launch_zero_u64(det->d_counters, 3, s) != hipSuccess)
+        radio::launch_zero_u64(det->d_counters, radio::kCounters, s) != hipSuccess)
         return RADIO_EDEVICE;
     det->interactions = 0;
     det->chunks = 0;
@@ -1050,7 +1051,7 @@ int radio_detector_stats(const radio_detector* det, radio_stats* out)
     DeviceGuard g(det->device);
     if (!g.ok())
         return RADIO_EDEVICE;
-    unsigned long long cnt[3] = {0, 0, 0};
+    unsigned long long cnt[radio::kCounters] = {0, 0, 0, 0};
     if (hipDeviceSynchronize() != hipSuccess ||
         hipMemcpy(cnt, det->d_counters, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess)
         return RADIO_EDEVICE;
@@ -1058,12 +1059,13 @@ int radio_detector_stats(const radio_detector* det, radio_stats* out)
     out->clipped = (int64_t)cnt[0];
     out->nonmonotone = (int64_t)cnt[1];
     out->bypassed = (int64_t)cnt[2];
+    out->large_ring = (int64_t)cnt[3];
     out->chunks = det->chunks;
     out->slices = det->slices;
     out->bytes = (int64_t)(det->n_c * det->n_t * 6 * (int64_t)sizeof(double) +
                            det->n_c * 3 * (int64_t)sizeof(double) +
                            det->n_c * (int64_t)sizeof(int64_t) +
-                           3 * (int64_t)sizeof(unsigned long long) +
+                           radio::kCounters * (int64_t)sizeof(unsigned long long) +
                            (int64_t)det->recs_cap +
                            (int64_t)(det->perm_cap * sizeof(int32_t)) + (int64_t)det->sel_cap);
     return RADIO_OK;
