@@ -570,6 +570,46 @@ def test_plasma_mirror_full_detector_sampled_cells(radio, precision):
     check_parity(Eg, Bg, Eo, Bo, TOLS[precision], f"{wl.name} sampled {precision}")
 
 
+@pytest.mark.parametrize("precision,n_steps", [("mixed", 1000), ("fp64", 500)])
+def test_plasma_mirror_full_size_as_benchmarked(radio, precision, n_steps):
+    """The plasma-mirror configuration at its stated size -- 2 x 10^5 electrons, 256 x
+    256 cells, 4096 slots; all 1000 steps in mixed precision and the first 500 in
+    double, as the benchmark runs them -- in the launch configuration the benchmark
+    times (the shipped tuning: the 8 x 32 x 16 workgroup shape; time slices of its
+    particle orders, 1.6e9 entries per order of two runs over the 8192 tiles),
+    compared with the oracle on sampled cells."""
+    import torch
+
+    from paper_2302_14812_amd import autotune
+    wl = W.plasma_mirror_workload(n_particles=200_000, n_steps=1000)
+    if n_steps < wl.chunk.n_steps:
+        wl.chunk = wl.chunk.slice_steps(0, n_steps)
+    cur = radio.get_tuning()
+    try:
+        ch = radio.Chunk.from_numpy(wl.chunk)
+        tuned = autotune.apply_single(wl.detector, ch, precision)
+        det = radio.Detector.from_spec(wl.detector, precision=precision)
+        det.deposit(ch)
+        E, B = det.read()
+        torch.cuda.synchronize()
+        st = det.stats()
+        print(f"[parity] plasma mirror 2e5 e- x {n_steps} steps {precision}: shape "
+              f"{radio.SHAPES[radio.get_tuning()['shape']]}{' (tuned)' if tuned else ''}, "
+              f"{st['slices']} slices, large ring {st['large_ring'] / st['interactions']:.3f}",
+              flush=True)
+        Eg = E[list(_PM_CELLS)].cpu().numpy()
+        Bg = B[list(_PM_CELLS)].cpu().numpy()
+        del E, B, ch
+        det.close()
+    finally:
+        radio.set_tuning(**cur)
+    assert st["interactions"] == 200_000 * n_steps * 65536
+    assert st["slices"] > 1
+    Eo, Bo, _ = oracle_deposit(wl.detector, wl.chunk, cell_index=list(_PM_CELLS))
+    del wl
+    check_parity(Eg, Bg, Eo, Bo, TOLS[precision], f"plasma mirror full size sampled {precision}")
+
+
 _CACHE = {}
 # sampled cells of the 256 x 256 plasma-mirror detector: corners, centre, and a seeded set
 _PM_CELLS = tuple(sorted(set(W.grid_corner_cells(256, 256)) | set(
