@@ -375,6 +375,97 @@ __global__ __launch_bounds__(kFftThreads) void spec_rows_q_kernel(const double2*
     }
 }
 
+// In-register radix-2 transform (decimation in time) of 2^LG values loaded in
+// bit-reversed order, leaving them in natural order.  W[j] = exp(-2 pi i j /
+// 2^LG), j < 2^(LG-1), read with uniform addresses (scalar loads: the same
+// twiddles for every lane); the j = 0 butterflies take no product.
+template <int LG>
+__device__ __forceinline__ void reg_fft(double2 (&v)[1 << LG], const double2* __restrict__ W)
+{
+#pragma unroll
+    for (int s = 0; s < LG; ++s) {
+        const int h = 1 << s;
+#pragma unroll
+        for (int j = 0; j < h; ++j) {
+            const double2 w = j == 0 ? make_double2(1.0, 0.0) : W[j << (LG - 1 - s)];
+#pragma unroll
+            for (int blk = 0; blk < (1 << LG); blk += 2 * h) {
+                const double2 a = v[blk + j];
+                const double2 t = j == 0 ? v[blk + j + h] : cmul(v[blk + j + h], w);
+                v[blk + j] = make_double2(a.x + t.x, a.y + t.y);
+                v[blk + j + h] = make_double2(a.x - t.x, a.y - t.y);
+            }
+        }
+    }
+}
+
+constexpr int kRow32 = 32;  // N2 = 1024 = 32 x 32
+
+// The second step for rows of N2 = 1024, held in registers instead of LDS
+// passes: a row is a 32 x 32 four-step transform (n = 32 a + b, k = c + 32 d),
+//     X[c + 32 d] = sum_b W_32^(b d) W_1024^(b c) sum_a x[32 a + b] W_32^(a c).
+// One wavefront per row k1 of a cell: lanes 0-31 take signal Z1, lanes 32-63
+// signal Z2.  Lane b loads x[32 a + b] (a = 0 .. 31, coalesced over the lanes),
+// transforms over a in registers, multiplies by W_1024^(b c) and writes the 32
+// values to LDS; lane c then reads A[b][c] (b = 0 .. 31) and transforms over b.
+// Q = |Z1|^2 + |Z2|^2 is folded through LDS and stored row-major at
+// Qt[g][1024 k1 + c + 32 d], as spec_rows_q_kernel stores it.
+__global__ __launch_bounds__(64) void spec_rows_q32_kernel(const double2* __restrict__ Y,
+                                                           int64_t G, int lg1,
+                                                           const double2* __restrict__ tab,
+                                                           double* __restrict__ Q)
+{
+    __shared__ double2 T[2][kRow32][kRow32 + 1];  // A[b][c] per signal, rows padded
+    const int lane = threadIdx.x;
+    const int sig = lane >> 5;
+    const int b = lane & (kRow32 - 1);
+    const int64_t N1 = (int64_t)1 << lg1;
+    const int64_t N = N1 * (kRow32 * kRow32);
+    const int64_t g = blockIdx.x >> lg1;
+    const int64_t k1 = blockIdx.x & (N1 - 1);
+    if (g >= G)
+        return;
+    // exp(-2 pi i j / 32) = tab[64 j] (tab[k] = exp(-2 pi i k / kFftTile))
+    static_assert(kFftTile == 64 * kRow32, "32-point twiddles from the LDS-transform table");
+    double2 w32[kRow32 / 2];
+#pragma unroll
+    for (int j = 0; j < kRow32 / 2; ++j)
+        w32[j] = tab[64 * j];
+    const double2* y = Y + (2 * g + sig) * N + (kRow32 * kRow32) * k1;
+    double2 v[kRow32];
+#pragma unroll
+    for (int a = 0; a < kRow32; ++a)
+        v[bitrev(a, 5)] = y[kRow32 * a + b];
+    reg_fft<5>(v, w32);
+#pragma unroll
+    for (int c = 0; c < kRow32; ++c) {
+        // W_1024^m = tab[2 m] for m < 512, -tab[2 m - 1024] above
+        const int m = (b * c) & 1023;
+        const double2 t = tab[(2 * m) & 1023];
+        const double2 w = m < 512 ? t : make_double2(-t.x, -t.y);
+        T[sig][c][b] = c == 0 ? v[0] : cmul(v[c], w);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int bb = 0; bb < kRow32; ++bb)
+        v[bitrev(bb, 5)] = T[sig][b][bb];
+    reg_fft<5>(v, w32);
+    __syncthreads();  // T is reused for |Z2|^2
+    double* P = reinterpret_cast<double*>(&T[0][0][0]);  // [32][33] doubles
+    if (sig == 1) {
+#pragma unroll
+        for (int d = 0; d < kRow32; ++d)
+            P[d * (kRow32 + 1) + b] = v[d].x * v[d].x + v[d].y * v[d].y;
+    }
+    __syncthreads();
+    if (sig == 0) {
+        double* q = Q + g * N + (kRow32 * kRow32) * k1;
+#pragma unroll
+        for (int d = 0; d < kRow32; ++d)
+            q[b + kRow32 * d] = (v[d].x * v[d].x + v[d].y * v[d].y) + P[d * (kRow32 + 1) + b];
+    }
+}
+
 template <bool PAIRS>
 __global__ __launch_bounds__(256) void spec_load_kernel(const double* __restrict__ acc,
                                                         int64_t n_t, int64_t r0, int64_t G,
@@ -727,7 +818,12 @@ hipError_t launch_spectrum_group(const double* acc, bool pairs, int64_t n_t, int
         int lg_q1 = 0;
         if (lg2 > 0) {
             const size_t lds_b = ((size_t)kFftTile + ((size_t)1 << lg2) / 2) * sizeof(double2);
-            if (lg2 < kFftTileLg) {
+            if (lg2 == 10) {
+                // rows of 1024 in registers, one wavefront per row of a cell
+                hipLaunchKernelGGL(spec_rows_q32_kernel, dim3((unsigned)(G << lg1)), dim3(64), 0,
+                                   s, work0, G, lg1, tables, reinterpret_cast<double*>(work1));
+                lg_q1 = lg1;
+            } else if (lg2 < kFftTileLg) {
                 const int64_t tiles = G * ((int64_t)1 << (lg1 - (kFftTileLg - 1 - lg2)));
                 hipLaunchKernelGGL(spec_rows_q_kernel, dim3((unsigned)tiles), dim3(kFftThreads),
                                    lds_b, s, work0, G, lg1, lg2, tables,

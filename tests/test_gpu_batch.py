@@ -71,6 +71,46 @@ def test_batch_equals_separate_and_oracle(radio, sets, precision):
         db.close()
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_batch_as_benchmarked(radio, precision):
+    """The batched-launch benchmark's 64 uneven sets as it runs them (the recipe's
+    sides of 32^2 to 256^2 cells and 256 to 4096 slots, particle counts x 0.02, one
+    launch with the shipped tuning), each set against the oracle on its grid
+    corners and two seeded cells."""
+    import torch
+
+    from paper_2302_14812_amd import autotune
+    sets = W.batched_sets(n_sets=64, scale=0.02)
+    chunks = [radio.Chunk.from_numpy(wl.chunk) for wl in sets]
+    dets = [radio.Detector.from_spec(wl.detector, precision=precision) for wl in sets]
+    cur = radio.get_tuning()
+    try:
+        tuned = autotune.apply_batch([wl.detector for wl in sets], chunks)
+        radio.deposit_batch(dets, chunks)
+        torch.cuda.synchronize()
+    finally:
+        radio.set_tuning(**cur)
+    print(f"[batch] 64 benchmark sets {precision}: tuned {tuned}, "
+          f"{sum(wl.interactions for wl in sets):.3e} interactions", flush=True)
+    rng = np.random.Generator(np.random.PCG64(64))
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    worst = 0.0
+    for wl, d in zip(sets, dets):
+        n1, n2 = wl.detector.grid
+        idx = sorted(set(W.grid_corner_cells(n1, n2)) |
+                     set(rng.choice(n1 * n2, 2, replace=False).tolist()))
+        E, B = d.read()
+        torch.cuda.synchronize()
+        Eg, Bg = E[idx].cpu().numpy(), B[idx].cpu().numpy()
+        assert d.stats()["interactions"] == wl.interactions
+        d.close()
+        Eo, Bo = oracle.read(oracle.deposit_workload(wl.detector, wl.chunk, cell_index=idx))
+        check_parity(Eg, Bg, Eo, Bo, tol, f"benchmark set {wl.name} {precision}")
+        worst = max(worst, rel_l2(Eg, Eo), rel_l2(Bg, Bo))
+    print(f"[batch] 64 benchmark sets {precision}: worst relL2 against the oracle {worst:.3e}",
+          flush=True)
+
+
 def test_batch_mixed_modes_duplicates_and_empty(radio, sets):
     import torch
     wl = sets[0]
