@@ -223,34 +223,37 @@ __device__ __forceinline__ void global_add(RADIO_GLOBAL double* row, int j, cons
         __hip_atomic_fetch_add(q + k, a[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Compensated single-precision adds into the HBM pair (hi[6], lo[6]) of slot j:
+// the six returning adds to hi are issued together, so that their round trips
+// overlap, then the lo words take each add's rounding error.  A zero component
+// adds exactly nothing (old + 0 is exact, its error 0), so no component is
+// skipped: a branch per component would put the round trips in sequence.
 __device__ __forceinline__ void global_add(RADIO_GLOBAL float* row, int j, const float a[6])
 {
     RADIO_GLOBAL float* q = row + (int64_t)j * 12;
+    float old[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        if (a[k] != 0.0f) {
-            const float old =
-                __hip_atomic_fetch_add(q + k, a[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(q + 6 + k, two_sum_err(old, a[k], old + a[k]), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+    for (int k = 0; k < 6; ++k)
+        old[k] = __hip_atomic_fetch_add(q + k, a[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        __hip_atomic_fetch_add(q + 6 + k, two_sum_err(old[k], a[k], old[k] + a[k]),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// a compensated pair (hi, lo) into the HBM pair
+// a compensated pair (hi, lo) into the HBM pair, the same way
 __device__ __forceinline__ void global_add_pair(RADIO_GLOBAL float* row, int j, const float hi[6],
                                                 const float lo[6])
 {
     RADIO_GLOBAL float* q = row + (int64_t)j * 12;
+    float old[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        if (hi[k] != 0.0f || lo[k] != 0.0f) {
-            const float old =
-                __hip_atomic_fetch_add(q + k, hi[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(q + 6 + k, two_sum_err(old, hi[k], old + hi[k]) + lo[k],
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+    for (int k = 0; k < 6; ++k)
+        old[k] = __hip_atomic_fetch_add(q + k, hi[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        __hip_atomic_fetch_add(q + 6 + k, two_sum_err(old[k], hi[k], old[k] + hi[k]) + lo[k],
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // position of slot j >= 0 in a ring of R slots
