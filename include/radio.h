@@ -272,6 +272,23 @@ RADIO_API int radio_get_tuning(radio_tuning* t);
  */
 RADIO_API int radio_read_detector(const radio_detector* det, double* E, double* B, void* stream);
 
+/*
+ * Replace the detector's fields with E and B, DEVICE arrays [n_cells][n_t][3]
+ * (double) in the layout radio_read_detector writes: the inverse of a read, so
+ * that a snapshot read from a detector and loaded into a detector of the same
+ * description (cells, t0, dt_det, n_t, precision, options) resumes its
+ * accumulation -- a checkpoint.  The slot array is the detector's only state
+ * (the integrator detector of Sec. 3.2; chunks carry their previous state,
+ * Sec. 3.1), so later deposits add to the loaded fields as they would have to
+ * the original ones.  Exact for RADIO_FP64 and RADIO_MIXED; RADIO_MIXED_TWOSUM
+ * stores each value as a (hi, lo) single-precision pair, to about 2^-48 of it.
+ * Statistics (radio_detector_stats) are not changed.  Both pointers are
+ * required (RADIO_EINVAL otherwise); the arrays are read by work enqueued on
+ * `stream` and must stay valid until it has run.
+ */
+RADIO_API int radio_detector_load(radio_detector* det, const double* E, const double* B,
+                                  void* stream);
+
 /* Statistics; synchronises the device to read the counters. */
 RADIO_API int radio_detector_stats(const radio_detector* det, radio_stats* out);
 

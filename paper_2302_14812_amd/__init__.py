@@ -29,6 +29,7 @@ _PRECISIONS = {"fp64": FP64, "mixed": MIXED, "mixed_twosum": MIXED_TWOSUM}
 EXPORTS = (
     "radio_detector_create", "radio_detector_destroy", "radio_detector_reset",
     "radio_deposit_trajectory_chunk", "radio_deposit_batch", "radio_read_detector",
+    "radio_detector_load",
     "radio_detector_stats", "radio_detector_shape", "radio_detector_cells",
     "radio_arrival_times", "radio_status_string", "radio_set_tuning", "radio_get_tuning",
     "radio_spectrum", "radio_push", "radio_slot_coordinates",
@@ -118,6 +119,7 @@ def _lib():
         lib.radio_deposit_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Chunk),
                                             ctypes.c_int, vp]
         lib.radio_read_detector.argtypes = [vp, vp, vp, vp]
+        lib.radio_detector_load.argtypes = [vp, vp, vp, vp]
         lib.radio_detector_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
         lib.radio_detector_shape.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                              ctypes.POINTER(ctypes.c_int32)]
@@ -327,6 +329,16 @@ class Detector:
         _check(_lib().radio_read_detector(self.handle, E.data_ptr(), B.data_ptr(), _stream(stream)),
                "radio_read_detector")
         return E, B
+
+    def load(self, E, B, stream=None) -> None:
+        """Replace the detector's fields with (E, B) device tensors of shape (n_cells,
+        n_t, 3), as read() returns them: restores a snapshot, so that later deposits
+        add to it (radio_detector_load)."""
+        shape = (self.n_cells, self.n_t, 3)
+        _dev_f64(E, shape, "E")
+        _dev_f64(B, shape, "B")
+        _check(_lib().radio_detector_load(self.handle, E.data_ptr(), B.data_ptr(), _stream(stream)),
+               "radio_detector_load")
 
     def spectrum(self, n_fft: int = 0, weights=None, stream=None, d2I: bool = True,
                  dIdw: bool = True, dIdO: bool = True):

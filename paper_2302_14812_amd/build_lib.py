@@ -23,7 +23,8 @@ COMMON = [
     "-Wall", "-Wno-unused-result",
 ]
 
-SOURCES = ["radio_kernels.hip", "radio_spectrum.hip", "radio_push.hip", "radio_runtime.cpp"]
+SOURCES = ["radio_kernels.hip", "radio_spectrum.hip", "radio_push.hip", "radio_io.hip",
+           "radio_runtime.cpp"]
 # measurement programs run by bench.py: floating-point atomic-add throughput,
 # issue cost of the vector instructions the deposit uses
 ATOMICS_BENCH = os.path.join(HERE, "radio_atomics_bench")

@@ -206,6 +206,10 @@ hipError_t launch_deposit_batch(const DepositJob* jobs, const WorkItem* items, i
 int persistent_blocks_per_cu(int variant, bool large_ring);
 hipError_t launch_readout(const double* acc, int64_t n_c, int64_t n_t, const int64_t* user_index,
                           bool pairs, double* E, double* B, hipStream_t s);
+// E and B [n_c][n_t][3] in the caller's cell order into the accumulator (the
+// inverse of launch_readout)
+hipError_t launch_load(double* acc, int64_t n_c, int64_t n_t, const int64_t* user_index,
+                       bool pairs, const double* E, const double* B, hipStream_t s);
 // spectral post-processing (radio_spectrum.hip): one group of G cells (internal
 // rows r0 ..) through load, FFT passes and power; work0/work1 hold 2 G N values,
 // tables kSpecTableValues (twiddle tables, rewritten by each call).  Where the

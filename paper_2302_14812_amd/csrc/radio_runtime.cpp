@@ -1044,6 +1044,20 @@ int radio_read_detector(const radio_detector* det, double* E, double* B, void* s
     return RADIO_OK;
 }
 
+int radio_detector_load(radio_detector* det, const double* E, const double* B, void* stream)
+{
+    if (!det || !E || !B)
+        return RADIO_EINVAL;
+    DeviceGuard g(det->device);
+    if (!g.ok())
+        return RADIO_EDEVICE;
+    if (radio::launch_load(det->d_acc, det->n_c, det->n_t, det->d_user_index,
+                           det->precision == RADIO_MIXED_TWOSUM, E, B,
+                           (hipStream_t)stream) != hipSuccess)
+        return RADIO_EDEVICE;
+    return RADIO_OK;
+}
+
 int radio_detector_stats(const radio_detector* det, radio_stats* out)
 {
     if (!det || !out)

@@ -106,6 +106,7 @@ def test_invalid_arguments_rejected_before_any_device_work():
     ch = radio._Chunk(1, 1, 0.0, 0.1, 0, None, None, None)
     assert lib.radio_deposit_trajectory_chunk(None, ctypes.byref(ch), None) == radio.EINVAL
     assert lib.radio_read_detector(None, None, None, None) == radio.EINVAL
+    assert lib.radio_detector_load(None, None, None, None) == radio.EINVAL
     assert lib.radio_detector_reset(None, None) == radio.EINVAL
     assert lib.radio_detector_destroy(None) == radio.OK
     assert lib.radio_deposit_batch(None, None, -1, None) == radio.EINVAL

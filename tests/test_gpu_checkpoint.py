@@ -1,0 +1,93 @@
+"""Checkpoint and resume: a detector's fields read after some chunks and loaded
+into a fresh detector of the same description continue the accumulation as the
+original would (the slot array is the detector's only state: Sec. 3.2's
+integrator detector, with chunks carrying their own previous state, Sec. 3.1)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_14812_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+from parity import TOLS, check_parity, rel_l2  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def radio():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2302_14812_amd as radio
+    radio._lib()
+    return radio
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_twosum"])
+def test_resume_from_a_snapshot(radio, precision):
+    import torch
+    wl = W.plasma_mirror_workload(n_particles=200, n_steps=300, n_side=12, n_t=768)
+    ch = radio.Chunk.from_numpy(wl.chunk)
+    first, second = ch.slice_steps(0, 120), ch.slice_steps(120, 300)
+    # uninterrupted
+    ref = radio.Detector.from_spec(wl.detector, precision=precision)
+    ref.deposit(first)
+    ref.deposit(second)
+    Er, Br = ref.read()
+    # interrupted after the first part: snapshot, new detector, load, continue
+    a = radio.Detector.from_spec(wl.detector, precision=precision)
+    a.deposit(first)
+    Es, Bs = a.read()
+    a.close()
+    b = radio.Detector.from_spec(wl.detector, precision=precision)
+    b.load(Es, Bs)
+    E0, B0 = b.read()
+    torch.cuda.synchronize()
+    # the snapshot itself comes back (exactly, but for the compensated pairs)
+    if precision == "mixed_twosum":
+        assert max(rel_l2(E0.cpu().numpy(), Es.cpu().numpy()),
+                   rel_l2(B0.cpu().numpy(), Bs.cpu().numpy())) <= 1e-14
+    else:
+        assert torch.equal(E0, Es) and torch.equal(B0, Bs)
+    b.deposit(second)
+    Eb, Bb = b.read()
+    torch.cuda.synchronize()
+    e = max(rel_l2(Eb.cpu().numpy(), Er.cpu().numpy()), rel_l2(Bb.cpu().numpy(), Br.cpu().numpy()))
+    print(f"[checkpoint] {precision}: resumed vs uninterrupted relL2 {e:.3e}", flush=True)
+    assert e <= (1e-13 if precision == "fp64" else 1e-7)
+    Eo, Bo = oracle.read(oracle.deposit_workload(wl.detector, wl.chunk))
+    check_parity(Eb.cpu().numpy(), Bb.cpu().numpy(), Eo, Bo, TOLS[precision],
+                 f"resumed detector {precision}")
+    ref.close()
+    b.close()
+
+
+def test_load_rejects_wrong_shapes(radio):
+    import torch
+    wl = W.plasma_mirror_workload(n_particles=10, n_steps=20, n_side=4, n_t=64)
+    det = radio.Detector.from_spec(wl.detector)
+    E = torch.zeros((det.n_cells, det.n_t + 1, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises((ValueError, radio.RadioError)):
+        det.load(E, E)
+    det.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_twosum"])
+def test_repeated_runs_agree(radio, precision):
+    """Determinism: the same chunk deposited into fresh detectors three times.  The
+    slot updates are atomic adds whose order varies from run to run, so results may
+    differ in the last bits, never by more than 1e-12."""
+    import torch
+    wl = W.undulator_workload(n_particles=200, n_steps=400, n_side=16, n_t=512)
+    ch = radio.Chunk.from_numpy(wl.chunk)
+    runs = []
+    for _ in range(3):
+        det = radio.Detector.from_spec(wl.detector, precision=precision)
+        det.deposit(ch)
+        E, B = det.read()
+        torch.cuda.synchronize()
+        runs.append((E.cpu().numpy(), B.cpu().numpy()))
+        det.close()
+    e = max(max(rel_l2(E, runs[0][0]), rel_l2(B, runs[0][1])) for E, B in runs[1:])
+    print(f"[determinism] {precision}: largest relL2 between runs {e:.3e}", flush=True)
+    assert e <= 1e-12
