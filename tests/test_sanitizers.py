@@ -20,6 +20,8 @@ import subprocess
 
 import pytest
 
+from paper_2302_14812_amd import build_lib
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SAN_ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:halt_on_error=1:abort_on_error=0",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1", LC_ALL="C")
@@ -145,6 +147,7 @@ int main(void) {
     EXPECT(radio_deposit_batch(none, ks, 2, NULL), RADIO_EDEVICE);
     EXPECT(radio_read_detector(NULL, NULL, NULL, NULL), RADIO_EINVAL);
     EXPECT(radio_detector_reset(NULL, NULL), RADIO_EINVAL);
+    EXPECT(radio_detector_load(NULL, cells, cells, NULL), RADIO_EINVAL);
     EXPECT(radio_detector_destroy(NULL), RADIO_OK);
     radio_stats s;
     EXPECT(radio_detector_stats(NULL, &s), RADIO_EINVAL);
@@ -218,7 +221,8 @@ def test_host_runtime_under_address_and_undefined_sanitizers(tmp_path):
               os.path.join(ROOT, "include"), "-I", csrc]
     objs = []
     procs = []
-    for src in ("radio_kernels.hip", "radio_spectrum.hip", "radio_push.hip", "radio_runtime.cpp"):
+    # every source of the library, as its build compiles them
+    for src in build_lib.SOURCES:
         obj = tmp_path / (src.split(".")[0] + ".o")
         procs.append(subprocess.Popen([HIPCC] + common + san + ["-x", "hip", "-c",
                                                                 os.path.join(csrc, src), "-o",
