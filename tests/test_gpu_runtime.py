@@ -11,7 +11,7 @@ from paper_2302_14812_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-from parity import check_parity  # noqa: E402
+from parity import TOLS, check_parity  # noqa: E402
 
 WAVE = {"wave_amplitude": 1.5, "wave_dir": [1.0, 0.0, 0.0], "wave_pol": [0.0, 1.0, 0.0],
         "wave_omega": 1.0, "wave_phase": 0.3}
@@ -105,3 +105,61 @@ def test_runtime_blocks_equal_one_shot_and_oracle(radio):
                      f"runtime {d.precision} vs oracle")
     for d in dets + [one]:
         d.close()
+
+
+# sampled cells of the 128 x 128 cap: centre, corners and a seeded set
+_RT_CELLS = tuple(sorted(set(W.grid_corner_cells(128, 128)) | set(
+    np.random.Generator(np.random.PCG64(71)).choice(128 * 128, 11, replace=False).tolist())))
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_runtime_as_benchmarked(radio, precision):
+    """The run-time mode at the size and in the launch configuration the benchmark
+    times: 10^4 electrons in the plane wave pushed 16 steps at a time for 64 blocks,
+    each block deposited into the 128 x 128 cap (2048 slots) with the shipped
+    run-time tuning, compared on sampled cells with the oracle's deposit of the
+    same trajectory (one push of the whole run, equal to the blocks' pushes)."""
+    import torch
+
+    from paper_2302_14812_amd import autotune
+    from paper_2302_14812_amd.runtime import RunTimeDiagnostic, plane_wave_electrons
+    n_p, block, n_blocks, dt = 10000, 16, 64, 0.05
+    cells, t0, dtd, n_t, x0, u0, wave = plane_wave_electrons(n_p, block, n_blocks, dt)
+    cur = radio.get_tuning()
+    try:
+        det = radio.Detector(cells, t0=t0, dt_det=dtd, n_t=n_t, precision=precision)
+        tuned = autotune.apply_runtime(det, n_p, block, precision)
+        rt = RunTimeDiagnostic([det], x0, u0, None, dt=dt, block_steps=block, fields=wave)
+        rt.advance(n_blocks)
+        E, B = det.read()
+        torch.cuda.synchronize()
+        st = det.stats()
+        print(f"[runtime] as benchmarked {precision}: shape "
+              f"{radio.SHAPES[radio.get_tuning()['shape']]}{' (tuned)' if tuned else ''}, "
+              f"large ring {st['large_ring'] / st['interactions']:.3f}, "
+              f"clipped {st['clipped']}", flush=True)
+        Eg = E[list(_RT_CELLS)].cpu().numpy()
+        Bg = B[list(_RT_CELLS)].cpu().numpy()
+        xe, ue = rt.state()
+        xe, ue = xe.cpu().numpy(), ue.cpu().numpy()
+        del E, B
+        det.close()
+    finally:
+        radio.set_tuning(**cur)
+    assert st["interactions"] == n_p * block * n_blocks * 128 * 128
+    n_s = block * n_blocks
+    x = torch.zeros((3, n_s + 1, n_p), dtype=torch.float64, device="cuda")
+    u = torch.zeros_like(x)
+    x[:, 0] = torch.from_numpy(x0).cuda()
+    u[:, 0] = torch.from_numpy(u0).cuda()
+    whole = radio.push(radio.Chunk(x, u, None, 0.0, dt), **wave)
+    host = W.Chunk(x=whole.x.cpu().numpy(), u=whole.u.cpu().numpy(), q=np.full(n_p, -1.0),
+                   t_first=0.0, dt=dt)
+    del x, u, whole
+    # the blocks pushed exactly what one push of the whole run gives
+    np.testing.assert_array_equal(xe, host.x[:, -1])
+    np.testing.assert_array_equal(ue, host.u[:, -1])
+    spec = W.DetectorSpec(cells=cells, t0=t0, dt_det=dtd, n_t=n_t)
+    Eo, Bo = oracle.read(oracle.deposit_workload(spec, host, cell_index=list(_RT_CELLS)))
+    assert np.abs(Eo).max() > 0
+    check_parity(Eg, Bg, Eo, Bo, TOLS[precision], f"runtime as benchmarked {precision} sampled")
