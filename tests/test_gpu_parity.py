@@ -539,6 +539,41 @@ def test_full_size_undulator_sampled_cells(radio, precision):
     check_parity(Eg, Bg, Eo, Bo, TOLS[precision], f"{wl.name} sampled {precision}")
 
 
+@pytest.mark.parametrize("names", ["FAR_FIELD", "FAR_FIELD ACCEL_ONLY", "HOLD_PREVIOUS",
+                                   "HOLD_LINEAR"])
+def test_full_size_undulator_options_sampled_cells(radio, names):
+    """The detector options as the benchmark's options leg runs them: the full
+    undulator workload in mixed precision with the far field (Eq. 3), the far field
+    with the acceleration term alone, the previous state's field held and the
+    linear interpolation, each compared with the oracle under the same option on
+    sampled cells."""
+    import dataclasses
+    import torch
+    wl = _undulator_full()
+    options = 0
+    for n in names.split():
+        options |= getattr(radio, n)
+    det = radio.Detector.from_spec(wl.detector, precision="mixed", options=options)
+    ch = radio.Chunk.from_numpy(wl.chunk)
+    det.deposit(ch)
+    E, B = det.read()
+    torch.cuda.synchronize()
+    idx = list(_OPT_CELLS)
+    Eg = E[idx].cpu().numpy()
+    Bg = B[idx].cpu().numpy()
+    del E, B, ch
+    det.close()
+    spec = dataclasses.replace(wl.detector, options=options)
+    Eo, Bo, _ = oracle_deposit(spec, wl.chunk, cell_index=idx)
+    check_parity(Eg, Bg, Eo, Bo, TOLS["mixed"], f"{wl.name} options={options} sampled mixed")
+
+
+# sampled cells of the 128 x 128 undulator detector for the options: centre and corners,
+# and a seeded set
+_OPT_CELLS = tuple(sorted(set(W.grid_corner_cells(128, 128)) | set(
+    np.random.Generator(np.random.PCG64(97)).choice(128 * 128, 5, replace=False).tolist())))
+
+
 @PRECISIONS
 def test_plasma_mirror_full_detector_sampled_cells(radio, precision):
     """The plasma-mirror configuration at its full detector (256 x 256 cells, 4096
