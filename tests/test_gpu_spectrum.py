@@ -96,3 +96,28 @@ def test_device_benchmark_spectrum_follows_eq8(radio):
     print("[spectrum] device integrated / Eq. 8:", np.round(ratio, 3), flush=True)
     assert np.abs(ratio - 1).max() < 0.06
     det.close()
+
+
+def test_spectrum_as_benchmarked(radio):
+    """The spectral leg at the size the benchmark times: one electron on the
+    sinusoidal orbit (gamma 50, K 10, 37699 steps) seen by a line of 512 cells at
+    1e5 with 131072 slots (N = 2^17, four groups of 128 cells); the device's
+    deposit and spectrum against the oracle's deposit and spectrum of the same
+    trajectory."""
+    chunk = W.sinusoidal_orbit(37699)
+    n_c, n_t = 512, 131072
+    cells = W.line_cells(1e5, n_c, 0.1)
+    t0, dtd = W.arrival_window(cells, chunk, n_t, pad_frac=0.01)
+    det = radio.Detector(cells, t0=t0, dt_det=dtd, n_t=n_t, precision="fp64")
+    det.deposit(radio.Chunk.from_numpy(chunk))
+    om, d2, dw, dO = det.spectrum()
+    d2, dw, dO = d2.cpu().numpy(), dw.cpu().numpy(), dO.cpu().numpy()
+    det.close()
+    D = oracle.deposit(cells, t0, dtd, n_t, chunk.x, chunk.u, chunk.q, chunk.t_first, chunk.dt)
+    omo, d2o, dwo, dOo = oracle.spectrum(oracle.read(D)[0], dtd, cells)
+    del D
+    np.testing.assert_allclose(om, omo, rtol=1e-15)
+    errs = (rel_l2(d2, d2o), rel_l2(dw, dwo), rel_l2(dO, dOo))
+    print(f"[spectrum] as benchmarked (512 x 131072): relL2 d2I {errs[0]:.2e} "
+          f"dIdw {errs[1]:.2e} dIdO {errs[2]:.2e}", flush=True)
+    assert max(errs) <= 1e-12
