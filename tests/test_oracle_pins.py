@@ -424,6 +424,31 @@ def test_time_shift_moves_slots(oracle_mod):
     assert np.abs(b[:, :m]).max() == 0.0
 
 
+def test_rigid_translation_changes_nothing(oracle_mod):
+    """Eq. 1 and Eq. 2 depend on positions only through d = x_cell - x_part, so
+    moving particles and cells together leaves the detector unchanged.  The
+    translated coordinates are rounded once more (up to ulp(40) ~ 7e-15 each),
+    which moves an arrival time by ~1e-14 and a slot boundary crossing by that
+    over dt_det: ~1e-12 of a slot value here, so the bar is 1e-10.  A field or
+    arrival time formed from absolute positions would change by O(1)."""
+    chunk = W.random_chunk(6, 80, seed=23, dt=0.04, gamma_max=10.0)
+    cells = W.plane_cells([0, 0, 40.0], [1, 0, 0], [0, 1, 0], 4, 3, 10.0, 8.0)
+    t0, dt_det, n_t = _window_for(cells, chunk, n_t=300)
+    args = dict(t0=t0, dt_det=dt_det, n_t=n_t, u=chunk.u, q=chunk.q, t_first=chunk.t_first,
+                dt=chunk.dt)
+    ref = oracle_mod.deposit(cells, x=chunk.x, **args)
+    scale = float(np.linalg.norm(ref))
+    assert scale > 0
+    for shift in ([0.5, -0.25, 0.75], [3.0, 7.0, -11.0]):
+        T = np.asarray(shift)
+        moved = oracle_mod.deposit(cells + T[None, :], x=chunk.x + T[:, None, None], **args)
+        assert float(np.linalg.norm(moved - ref)) <= 1e-10 * scale
+    # moving the particles alone does change it
+    off = oracle_mod.deposit(cells, x=chunk.x + np.array([0.5, -0.25, 0.75])[:, None, None],
+                             **args)
+    assert float(np.linalg.norm(off - ref)) > 1e-3 * scale
+
+
 def test_counters_report_clipping_and_reversal(oracle_mod):
     # charge moving away from the cell faster than ... cannot happen; build a reversed
     # arrival sequence by stepping positions faster than light (invalid input, counted)
@@ -647,6 +672,38 @@ def test_undulator_resonance_on_axis(oracle_mod):
         return spec[max(k - 3, 0):k + 4].max()
 
     assert band(3 * w1) > 10 * band(2 * w1)
+
+
+def test_helical_resonance_on_axis(oracle_mod):
+    """The paper's helical example (gamma 57.3, K 0.8, omega_0 = 1): on the helix
+    axis R is constant and n.beta = beta_parallel, so the field is a vector of fixed
+    length rotating at the Doppler-compressed frequency 2 gamma^2 omega_0 / (1 + K^2):
+    one spectral line, the same amplitude in x and y, no harmonics.  Its period,
+    1.57e-3 / omega_0, is the ~2e-3 the paper quotes for this trajectory."""
+    gamma, K, periods = 57.3, 0.8, 24
+    chunk = W.helical_undulator(1, 200 * periods, periods, gamma, 0.0, K, 0.0, seed=1)
+    cells = np.array([[0.0, 0.0, 1.0e4]])
+    t0, dt_det, n_t = _window_for(cells, chunk, n_t=4096, pad=0.002)
+    D = oracle_mod.deposit(cells, t0, dt_det, n_t, chunk.x, chunk.u, chunk.q, 0.0, chunk.dt)
+    w1 = 2 * gamma ** 2 / (1 + K ** 2)
+    assert 1e-3 < 2 * math.pi / w1 < 3e-3
+    win = np.hanning(n_t)
+    sx = np.abs(np.fft.rfft(D[0, :, 0] * win))
+    sy = np.abs(np.fft.rfft(D[0, :, 1] * win))
+    freqs = 2 * math.pi * np.fft.rfftfreq(n_t, dt_det)
+    df = freqs[1]
+    k_peak = int(np.argmax(sx[5:])) + 5
+    assert abs(freqs[k_peak] - w1) < 1.5 * df + 0.01 * w1, (freqs[k_peak], w1)
+
+    def band(spec, w):
+        k = int(round(w / df))
+        return spec[max(k - 3, 0):k + 4].max()
+
+    # circular polarisation: equal x and y lines
+    assert abs(band(sy, w1) / band(sx, w1) - 1.0) < 0.02
+    # on axis a helix radiates the fundamental only
+    for m in (2, 3):
+        assert band(sx, m * w1) < 1e-2 * band(sx, w1), m
 
 
 def test_coherent_vs_incoherent_emitters(oracle_mod):
