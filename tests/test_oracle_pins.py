@@ -675,7 +675,7 @@ def test_undulator_resonance_on_axis(oracle_mod):
 
 
 def test_helical_resonance_on_axis(oracle_mod):
-    """The paper's helical example (gamma 57.3, K 0.8, omega_0 = 1): on the helix
+    """The helical example of Sec. 3.3 (gamma 57.3, K 0.8, omega_0 = 1): on the helix
     axis R is constant and n.beta = beta_parallel, so the field is a vector of fixed
     length rotating at the Doppler-compressed frequency 2 gamma^2 omega_0 / (1 + K^2):
     one spectral line, the same amplitude in x and y, no harmonics.  Its period,
