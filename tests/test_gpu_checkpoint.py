@@ -2,7 +2,6 @@
 into a fresh detector of the same description continue the accumulation as the
 original would (the slot array is the detector's only state: Sec. 3.2's
 integrator detector, with chunks carrying their own previous state, Sec. 3.1)."""
-import numpy as np
 import pytest
 
 import oracle

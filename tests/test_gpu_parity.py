@@ -6,7 +6,6 @@ coordinate amplifies, must match the oracle bit for bit.
 """
 import math
 import os
-import sys
 
 import numpy as np
 import pytest
@@ -16,7 +15,7 @@ from paper_2302_14812_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-from parity import TOL_FP64, TOL_MIXED, TOLS, check_parity, rel_l2  # noqa: E402
+from parity import TOL_FP64, TOLS, check_parity, rel_l2  # noqa: E402
 
 PRECISIONS = pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_twosum"])
 

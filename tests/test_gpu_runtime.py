@@ -1,7 +1,6 @@
 """The run-time mode on the device: the Boris push (radio_push) against the
 oracle's pusher, and push-deposit blocks against one push and one deposit of
 the whole run, and against the oracle's deposit of the same trajectory."""
-import math
 
 import numpy as np
 import pytest

@@ -2,7 +2,6 @@
 import math
 
 import numpy as np
-import pytest
 
 
 def test_uniform_electric_field_is_exact_for_momentum(oracle_mod):
